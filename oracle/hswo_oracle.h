@@ -1,0 +1,81 @@
+/*
+ * hswo_oracle.h -- plain FP64 CPU oracle for HSWO / HSEG / RHSEG.
+ *
+ * TEST INFRASTRUCTURE ONLY. This library exists to check the GPU library
+ * (libhswo). Only the test suite, the smoke check and the benchmark's CPU
+ * baseline may load it; no product code path calls into it.
+ *
+ * Method (Section 4.1 of the paper):
+ *   HSEG loop (the four numbered steps of Section 4.1): every pixel starts
+ *   as a region; each iteration finds the spatially adjacent pair with the
+ *   smallest dissimilarity, and (spectral clustering) the smallest
+ *   non-adjacent pair; the non-adjacent pair is merged instead when it is
+ *   smaller than the adjacent minimum, weighted by the spectral clustering
+ *   weight; stop at the requested region count.
+ *   RHSEG: the image is split into 4^(L-1) sections, HSEG runs on the
+ *   deepest sections, the four sections of a parent are reassembled with
+ *   8-neighbourhood links across the split lines (Figure 4.4), and HSEG
+ *   runs again on the parent, up to level 1.
+ *   Criterion (Equation 1): sqrt( n_i n_j / (n_i + n_j) * sum_b (mu_ib - mu_jb)^2 ).
+ *   The oracle ranks on the squared value D2 (sqrt is monotone).
+ *
+ * Readings taken where the paper is silent (listed in the design doc):
+ *   one merge per iteration; the non-adjacent pair wins iff
+ *   D2_na < w^2 * D2_adj (strict); spectral stage active iff w > 0 and
+ *   R <= spclust_max; ties broken lexicographically on (D2, lo, hi) where
+ *   lo < hi are region labels; a region's label is its smallest row-major
+ *   pixel index; canonical FP64 criterion with fixed operation order and no
+ *   fused multiply-add.
+ */
+#ifndef HSWO_ORACLE_H
+#define HSWO_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct oracle_params {
+    int32_t connectivity;       /* 4 or 8, inside a section */
+    int32_t seam_connectivity;  /* 4 or 8, across RHSEG split lines */
+    float spclust_wght;         /* spectral clustering weight w in [0,1] */
+    int32_t spclust_max;        /* spectral stage active iff R <= this (0: never) */
+    int32_t target_regions;     /* stop count of the top pass */
+    int32_t section_regions;    /* stop count of non-top passes (0: max(target, spclust_max/4)) */
+    int32_t rnb_levels;         /* L >= 1 */
+    int32_t n_levels;           /* number of label snapshots */
+    const int32_t* level_counts;/* strictly decreasing, last == target */
+    int32_t brute;              /* 1: recompute every pair every iteration */
+    int32_t n_threads;          /* worker threads over independent sections */
+} oracle_params;
+
+typedef struct oracle_merge {
+    int32_t lo, hi;     /* region labels, lo < hi; lo survives */
+    int32_t kind;       /* 0 adjacent, 1 non-adjacent (spectral) */
+    int32_t r_after;    /* live regions in the section after this merge */
+    double d2;          /* canonical FP64 squared criterion */
+} oracle_merge;
+
+/* Canonical squared criterion of Equation 1 from band sums and counts. */
+double oracle_d2(const double* Si, const double* Sj, int64_t ni, int64_t nj, int32_t B);
+
+/*
+ * Run RHSEG (HSWO/HSEG when rnb_levels == 1) on a float32 H x W x B cube
+ * (band-interleaved by pixel, host memory).
+ *   labels   : [n_levels][H][W] int32 output (required)
+ *   log      : optional, capacity H*W records; merges in level order,
+ *              sections of a level in quadtree order (TL, TR, BL, BR, recursively)
+ *   n_log    : optional, number of records written
+ *   out_*    : optional final regions of the top pass: up to H*W entries
+ * Returns 0 on success, -1 on invalid parameters.
+ */
+int oracle_rhseg(const float* cube, int32_t H, int32_t W, int32_t B, const oracle_params* p,
+                 int32_t* labels, oracle_merge* log, int64_t* n_log,
+                 int32_t* out_R, int32_t* out_label, int64_t* out_n, double* out_S);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,164 @@
+"""Independent pure-Python HSEG/RHSEG for tiny images (a third opinion).
+
+Written separately from the C++ oracle and sharing nothing with it: each
+iteration re-derives the regions, their band sums, their pixel counts and
+their spatial adjacency from the current label map, instead of maintaining
+them through merges. It follows the HSEG steps of Section 4.1 and
+Equation 1 under the same readings as the oracle (one merge per iteration,
+non-adjacent pair wins iff D2_na < w^2 D2_adj, lexicographic (D2, lo, hi)
+tie-break, smaller label survives, RHSEG quadrant split at floor(h/2),
+floor(w/2), reassembly links under the seam connectivity).
+
+``exact=True`` evaluates Equation 1 in rational arithmetic (fractions), so
+its decisions are the mathematically exact ones; otherwise the squared
+criterion is evaluated in IEEE double in the canonical order (band sums,
+then per-band means, squared differences accumulated band by band, then the
+size factor).
+"""
+from __future__ import annotations
+
+from fractions import Fraction
+from typing import Dict, List, Sequence, Tuple
+
+
+def _quadrants(r0, c0, h, w):
+    h0, w0 = h // 2, w // 2
+    return [(r0, c0, h0, w0), (r0, c0 + w0, h0, w - w0), (r0 + h0, c0, h - h0, w0),
+            (r0 + h0, c0 + w0, h - h0, w - w0)]
+
+
+def _leaf_map(H, W, L):
+    """Leaf-section id of every pixel."""
+    leaf = [[-1] * W for _ in range(H)]
+    rects = [(0, 0, H, W)]
+    for _ in range(L - 1):
+        rects = [q for r in rects for q in _quadrants(*r)]
+    for k, (r0, c0, h, w) in enumerate(rects):
+        for r in range(r0, r0 + h):
+            for c in range(c0, c0 + w):
+                leaf[r][c] = k
+    return leaf
+
+
+def _criterion(xs_i, xs_j, exact):
+    """Equation 1 squared, from the two regions' pixel vectors."""
+    ni, nj = len(xs_i), len(xs_j)
+    B = len(xs_i[0])
+    if exact:
+        Si = [sum(Fraction(x[b]) for x in xs_i) for b in range(B)]
+        Sj = [sum(Fraction(x[b]) for x in xs_j) for b in range(B)]
+        acc = sum((Si[b] / ni - Sj[b] / nj) ** 2 for b in range(B))
+        return Fraction(ni * nj, ni + nj) * acc
+    # band sums of quantised inputs are exact in double whatever the order
+    Si = [float(sum(Fraction(x[b]) for x in xs_i)) for b in range(B)]
+    Sj = [float(sum(Fraction(x[b]) for x in xs_j)) for b in range(B)]
+    fac = (float(ni) * float(nj)) / float(ni + nj)
+    acc = 0.0
+    for b in range(B):
+        d = Si[b] / float(ni) - Sj[b] / float(nj)
+        acc = acc + d * d
+    return fac * acc
+
+
+def _hseg_pass(cube, lab, rect, leaf, conn, seam, w, kmax, stop, log, snaps, counts, top):
+    r0, c0, h, wd = rect
+    H = len(cube)
+    W = len(cube[0])
+    pix = [(r, c) for r in range(r0, r0 + h) for c in range(c0, c0 + wd)]
+    w2 = float(w) * float(w)
+
+    def regions():
+        reg: Dict[int, List] = {}
+        for (r, c) in pix:
+            reg.setdefault(lab[r][c], []).append(cube[r][c])
+        return reg
+
+    def adjacency():
+        adj = set()
+        for (r, c) in pix:
+            for dr, dc in ((0, 1), (1, 0), (1, 1), (1, -1)):
+                r2, c2 = r + dr, c + dc
+                if not (r0 <= r2 < r0 + h and c0 <= c2 < c0 + wd):
+                    continue
+                if dr != 0 and dc != 0:
+                    need8 = conn if leaf[r][c] == leaf[r2][c2] else seam
+                    if need8 != 8:
+                        continue
+                a, b = lab[r][c], lab[r2][c2]
+                if a != b:
+                    adj.add((min(a, b), max(a, b)))
+        return adj
+
+    def snap(R):
+        for li, cnt in enumerate(counts):
+            if cnt == R:
+                snaps[li] = [row[:] for row in lab]
+
+    reg = regions()
+    R = len(reg)
+    if top:
+        for li, cnt in enumerate(counts):
+            if cnt >= R:
+                snaps[li] = [row[:] for row in lab]
+    while R > stop:
+        reg = regions()
+        adj = adjacency()
+        labels = sorted(reg)
+        spectral = w > 0 and R <= kmax
+        A = None
+        N = None
+        for i_idx, i in enumerate(labels):
+            for j in labels[i_idx + 1:]:
+                isadj = (i, j) in adj
+                if not isadj and not spectral:
+                    continue
+                v = _criterion(reg[i], reg[j], exact=log.exact)
+                key = (v, i, j)
+                if isadj:
+                    if A is None or key < A:
+                        A = key
+                else:
+                    if N is None or key < N:
+                        N = key
+        if spectral and N is not None and (A is None or N[0] < (w2 * A[0] if not log.exact else Fraction(w) ** 2 * A[0])):
+            win, kind = N, 1
+        elif A is not None:
+            win, kind = A, 0
+        else:
+            break
+        _, lo, hi = win
+        for (r, c) in pix:
+            if lab[r][c] == hi:
+                lab[r][c] = lo
+        R -= 1
+        log.append((lo, hi, kind, R, win[0]))
+        if top:
+            snap(R)
+
+
+class _Log(list):
+    exact = False
+
+
+def rhseg(cube, *, connectivity=4, seam_connectivity=8, spclust_wght=0.0, spclust_max=0,
+          target_regions=1, section_regions=0, rnb_levels=1, level_counts=None, exact=False, **_):
+    """cube: nested lists or an array H x W x B. Returns (labels per level, log)."""
+    cube = [[[float(v) for v in px] for px in row] for row in (cube.tolist() if hasattr(cube, "tolist") else cube)]
+    H, W = len(cube), len(cube[0])
+    counts = list(level_counts) if level_counts is not None else [target_regions]
+    S = section_regions if section_regions > 0 else max(target_regions, spclust_max // 4)
+    L = rnb_levels
+    lab = [[r * W + c for c in range(W)] for r in range(H)]
+    leaf = _leaf_map(H, W, L)
+    levels = [[(0, 0, H, W)]]
+    for _ in range(L - 1):
+        levels.append([q for r in levels[-1] for q in _quadrants(*r)])
+    log = _Log()
+    log.exact = exact
+    snaps = [None] * len(counts)
+    for d in range(L - 1, -1, -1):
+        top = d == 0
+        for rect in levels[d]:
+            _hseg_pass(cube, lab, rect, leaf, connectivity, seam_connectivity, spclust_wght,
+                       spclust_max, target_regions if top else S, log, snaps, counts, top)
+    return snaps, list(log)

@@ -1,0 +1,91 @@
+"""The oracle's pins have teeth: plant one plausible mistake at a time in a
+temporary copy of the oracle source (on the CPU), rebuild it, and check that
+the pins reject every mutant. The committed oracle itself is never changed."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.oracle import _SRC
+from paper_2106_12942_amd import synth
+from tests import pybrute
+from tests.invariants import check_partition_levels, sse_of_partition
+from tests.test_oracle_pins import GOLDEN_CASES
+
+MUTANTS = {
+    "size_factor": ("const double fac = (dni * dnj) / (double)(ni + nj);",
+                    "const double fac = (dni * dnj) / (double)(ni + nj + 1);"),
+    "mean_of_j": ("const double d = Si[b] / dni - Sj[b] / dnj;",
+                  "const double d = Si[b] / dni - Sj[b] / dni;"),
+    "weight_not_squared": ("w2_ = (double)p.spclust_wght * (double)p.spclust_wght;",
+                           "w2_ = (double)p.spclust_wght;"),
+    "ties_prefer_nonadjacent": ("N.d2 < w2_ * A.d2", "N.d2 <= w2_ * A.d2"),
+    "tiebreak_on_hi": ("if (a.lo != b.lo) return a.lo < b.lo;\n    return a.hi < b.hi;",
+                       "if (a.hi != b.hi) return a.hi < b.hi;\n    return a.lo < b.lo;"),
+    "sum_overwritten": ("for (int b = 0; b < st_.B; ++b) Slo[b] = Slo[b] + Shi[b];",
+                        "for (int b = 0; b < st_.B; ++b) Slo[b] = Shi[b];"),
+    "count_not_added": ("st_.n[lo] += st_.n[hi];", "st_.n[lo] += 0;"),
+    "adjacency_not_inherited": ("                st_.adj[x][lo] = 0.0;\n                st_.adj[lo][x] = 0.0;",
+                                "                (void)0;"),
+    "seam_ignores_diagonals": ("const int nf = forward_offsets(p->seam_connectivity, dr, dc);",
+                               "const int nf = forward_offsets(4, dr, dc);"),
+    "split_rounds_up": ("const int h0 = r.h / 2, w0 = r.w / 2;\n    q[0]",
+                        "const int h0 = (r.h + 1) / 2, w0 = (r.w + 1) / 2;\n    q[0]"),
+    "snapshot_one_late": ("if (snap_->counts[l] == R) write_level(l);",
+                          "if (snap_->counts[l] == R + 1) write_level(l);"),
+    "spectral_threshold_strict": ("R <= p_.spclust_max;", "R < p_.spclust_max;"),
+}
+
+
+def _run_pins(lib):
+    """A compact pass over the pins; returns the name of the first that fails."""
+    for case in GOLDEN_CASES:
+        res = oracle.rhseg(case["cube"], **case["params"], lib=lib)
+        got = [(int(m["lo"]), int(m["hi"]), int(m["kind"]), int(m["r_after"]), float(m["d2"])) for m in res.log]
+        want = [(lo, hi, k, r, float(d)) for (lo, hi, k, r, d) in case["merges"]]
+        if len(got) != len(want) or any(g[:4] != w[:4] or abs(g[4] - w[4]) > 1e-12 * max(1, w[4])
+                                        for g, w in zip(got, want)):
+            return "golden:" + case["name"]
+    rng = np.random.default_rng(11)
+    grid = [dict(connectivity=4, seam_connectivity=8, spclust_wght=0.5, spclust_max=12, rnb_levels=2,
+                 section_regions=3),
+            dict(connectivity=8, seam_connectivity=8, spclust_wght=0.21, spclust_max=20, rnb_levels=1)]
+    for t in range(8):
+        p = grid[t % 2]
+        H, W = int(rng.integers(3, 7)), int(rng.integers(3, 7))
+        cube = synth.random_cube(H, W, 3, seed=40 + t, kind="integer" if t % 3 == 0 else "continuous")
+        counts = [max(2, H * W // 2), 2]
+        res = oracle.rhseg(cube, **p, target_regions=2, level_counts=counts, lib=lib)
+        snaps, log = pybrute.rhseg(cube, **p, target_regions=2, level_counts=counts)
+        got = [(int(m["lo"]), int(m["hi"]), int(m["kind"]), int(m["r_after"]), float(m["d2"])) for m in res.log]
+        if got != [tuple(x) for x in log]:
+            return "python brute force"
+        if not all(np.array_equal(res.labels[i], np.array(snaps[i])) for i in range(2)):
+            return "python brute force labels"
+        try:
+            check_partition_levels(res.labels, counts)
+        except AssertionError:
+            return "partition"
+        csum = np.concatenate([[0.0], np.cumsum(res.log["d2"])])
+        for i in range(2):
+            k = H * W - len(np.unique(res.labels[i]))
+            if abs(csum[k] - sse_of_partition(cube.astype(np.float64), res.labels[i])) > 1e-9 * (1 + csum[k]):
+                return "sse identity"
+    return None
+
+
+def test_unmutated_oracle_passes_the_compact_pins():
+    assert _run_pins(None) is None
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_reject_mutant(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(_SRC).read()
+    assert src.count(old) == 1, f"mutation site for {name} not found exactly once"
+    path = tmp_path / "mutant.cpp"
+    path.write_text(src.replace(old, new))
+    lib = oracle.build(src=str(path), out=str(tmp_path / f"liboracle_{name}.so"))
+    assert _run_pins(lib) is not None, f"mutant {name} survived every pin"
