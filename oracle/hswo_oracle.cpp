@@ -27,17 +27,28 @@
 
 namespace {
 
-/* ---- Equation 1, squared, canonical operation order --------------------- */
+/* ---- Equation 1, squared, canonical operation order --------------------- *
+ * fac = (n_i * n_j) / (n_i + n_j); per band d = S_i/n_i - S_j/n_j and d*d;
+ * the band terms are added as a pairwise tree over the band index, padded
+ * with zeros to the next power of two (adding +0.0 is exact, so the padding
+ * changes nothing); D2 = fac * sum. */
+double pairwise_sum(const double* v, int n /* a power of two */) {
+    if (n == 1) return v[0];
+    return pairwise_sum(v, n / 2) + pairwise_sum(v + n / 2, n / 2);
+}
+
 double criterion(const double* Si, const double* Sj, int64_t ni, int64_t nj, int B) {
     const double dni = (double)ni, dnj = (double)nj;
     const double fac = (dni * dnj) / (double)(ni + nj);
-    double acc = 0.0;
+    int P = 1;
+    while (P < B) P *= 2;
+    double sq[4096];  /* B <= 4096 is validated on entry */
+    for (int b = 0; b < P; ++b) sq[b] = 0.0;
     for (int b = 0; b < B; ++b) {
         const double d = Si[b] / dni - Sj[b] / dnj;
-        const double sq = d * d;
-        acc = acc + sq;
+        sq[b] = d * d;
     }
-    return fac * acc;
+    return fac * pairwise_sum(sq, P);
 }
 
 /* ---- merge key: (D2, lo, hi), compared lexicographically (tie-break) ----- */
@@ -371,13 +382,14 @@ void parallel_for(int n, int n_threads, F f) {
 }  // namespace
 
 extern "C" double oracle_d2(const double* Si, const double* Sj, int64_t ni, int64_t nj, int32_t B) {
+    if (B < 1 || B > 4096) return std::numeric_limits<double>::quiet_NaN();
     return criterion(Si, Sj, ni, nj, B);
 }
 
 extern "C" int oracle_rhseg(const float* cube, int32_t H, int32_t W, int32_t B, const oracle_params* p,
                             int32_t* labels, oracle_merge* log, int64_t* n_log, int32_t* out_R,
                             int32_t* out_label, int64_t* out_n, double* out_S) {
-    if (!cube || !p || !labels || H < 1 || W < 1 || B < 1) return -1;
+    if (!cube || !p || !labels || H < 1 || W < 1 || B < 1 || B > 4096) return -1;
     if ((int64_t)H * W >= (int64_t)1 << 31) return -1;
     if (p->connectivity != 4 && p->connectivity != 8) return -1;
     if (p->seam_connectivity != 4 && p->seam_connectivity != 8) return -1;

@@ -24,8 +24,8 @@
  *   D2_na < w^2 * D2_adj (strict); spectral stage active iff w > 0 and
  *   R <= spclust_max; ties broken lexicographically on (D2, lo, hi) where
  *   lo < hi are region labels; a region's label is its smallest row-major
- *   pixel index; canonical FP64 criterion with fixed operation order and no
- *   fused multiply-add.
+ *   pixel index; canonical FP64 criterion with fixed operation order (band
+ *   terms summed as a zero-padded pairwise tree) and no fused multiply-add.
  */
 #ifndef HSWO_ORACLE_H
 #define HSWO_ORACLE_H

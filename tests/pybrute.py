@@ -12,8 +12,8 @@ floor(w/2), reassembly links under the seam connectivity).
 ``exact=True`` evaluates Equation 1 in rational arithmetic (fractions), so
 its decisions are the mathematically exact ones; otherwise the squared
 criterion is evaluated in IEEE double in the canonical order (band sums,
-then per-band means, squared differences accumulated band by band, then the
-size factor).
+then per-band means and squared differences, summed as a pairwise tree over
+the band index zero-padded to a power of two, then the size factor).
 """
 from __future__ import annotations
 
@@ -53,10 +53,16 @@ def _criterion(xs_i, xs_j, exact):
     Si = [float(sum(Fraction(x[b]) for x in xs_i)) for b in range(B)]
     Sj = [float(sum(Fraction(x[b]) for x in xs_j)) for b in range(B)]
     fac = (float(ni) * float(nj)) / float(ni + nj)
-    acc = 0.0
+    terms = []
     for b in range(B):
         d = Si[b] / float(ni) - Sj[b] / float(nj)
-        acc = acc + d * d
+        terms.append(d * d)
+    # pairwise tree over the band index, zero-padded to a power of two
+    while len(terms) & (len(terms) - 1):
+        terms.append(0.0)
+    while len(terms) > 1:
+        terms = [terms[2 * k] + terms[2 * k + 1] for k in range(len(terms) // 2)]
+    acc = terms[0]
     return fac * acc
 
 

@@ -19,6 +19,8 @@ MUTANTS = {
                     "const double fac = (dni * dnj) / (double)(ni + nj + 1);"),
     "mean_of_j": ("const double d = Si[b] / dni - Sj[b] / dnj;",
                   "const double d = Si[b] / dni - Sj[b] / dni;"),
+    "last_band_dropped": ("for (int b = 0; b < B; ++b) {\n        const double d",
+                          "for (int b = 0; b < B - 1; ++b) {\n        const double d"),
     "weight_not_squared": ("w2_ = (double)p.spclust_wght * (double)p.spclust_wght;",
                            "w2_ = (double)p.spclust_wght;"),
     "ties_prefer_nonadjacent": ("N.d2 < w2_ * A.d2", "N.d2 <= w2_ * A.d2"),
