@@ -1,0 +1,182 @@
+/*
+ * hswo.h -- C ABI of libhswo: hierarchical step-wise optimisation (HSWO /
+ * HSEG) region merging and its recursive approximation RHSEG on MI355X
+ * (gfx950), for hyperspectral cubes.
+ *
+ * Method (Section 4.1 of the paper):
+ *   Every pixel starts as a region. Each iteration evaluates the
+ *   dissimilarity of every spatially adjacent region pair, and -- when
+ *   spectral clustering is on -- of every non-adjacent pair; the most similar
+ *   pair is merged (the four HSEG steps of Section 4.1). RHSEG splits the
+ *   image into 4^(L-1) sections, runs HSEG on the deepest sections,
+ *   reassembles each group of four with links across the split lines
+ *   (Figure 4.4) and runs HSEG again on the reassembled section, up to the
+ *   whole image.
+ *   Dissimilarity: square root of the band-sum MSE, Equation 1,
+ *     sqrt( n_i n_j / (n_i + n_j) * sum_b (mu_ib - mu_jb)^2 ).
+ *
+ * Readings where the paper is silent (the same in the CPU oracle):
+ *   - One merge per iteration. The best non-adjacent pair N is merged instead
+ *     of the best adjacent pair A iff D2(N) < w^2 * D2(A) (D2 = the squared
+ *     criterion, w = spclust_wght), strict, so A wins exact ties.
+ *   - The spectral (non-adjacent) stage of a section is active iff w > 0 and
+ *     the section's live region count R <= spclust_max.
+ *   - Ties are broken on the lexicographic key (D2, lo, hi) with lo < hi the
+ *     two region labels. The merged region keeps label lo.
+ *   - A region's label is its smallest row-major pixel index (0-based); the
+ *     output label maps hold these values.
+ *   - D2 is decided in IEEE FP64 with one fixed operation order:
+ *       fac = (n_i * n_j) / (n_i + n_j)
+ *       d_b = S_ib / n_i - S_jb / n_j;  q_b = d_b * d_b
+ *       acc = pairwise tree sum of q_0..q_{B-1} zero-padded to a power of two
+ *       D2  = fac * acc
+ *     with S the FP64 band sums, no fused multiply-add. Lower precisions are
+ *     used only as screens with certified error bounds; every decision is
+ *     re-checked with the formula above, so the merge sequence and the label
+ *     maps do not depend on the screen's precision.
+ *   - RHSEG splits a section at floor(h/2), floor(w/2) into TL, TR, BL, BR.
+ *     Inside a leaf, pixels are linked under `connectivity`; at every
+ *     reassembly, pixel pairs across the split lines are linked under
+ *     `seam_connectivity` (8 follows the paper's 8-neighbourhood).
+ *   - A non-top pass stops at section_regions regions; the top pass stops at
+ *     target_regions and writes the label maps of the requested levels.
+ *
+ * Conventions for every entry point:
+ *   - Device pointers are HIP device memory of the current device. The cube
+ *     and every output are owned by the caller. The library keeps no state
+ *     between calls and allocates no device memory: the scratch it needs is
+ *     the caller's `workspace`, at least hswo_workspace_bytes() bytes, 256-byte
+ *     aligned.
+ *   - Work is enqueued on `hip_stream` (a hipStream_t; NULL = the null
+ *     stream). Outputs are valid once that stream has completed. When `stats`
+ *     is non-NULL the call synchronises the stream before returning to fill
+ *     it in.
+ *   - Parameters are validated on the host before anything is enqueued; on
+ *     error nothing is written and the error code is returned, with a message
+ *     available from hswo_last_error(). No C++ exception crosses the ABI.
+ */
+#ifndef HSWO_H
+#define HSWO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HSWO_VERSION 10000 /* 1.0.0 */
+
+/* return codes */
+#define HSWO_OK 0
+#define HSWO_E_INVAL (-1)       /* invalid argument */
+#define HSWO_E_NOMEM (-2)       /* workspace too small (see hswo_workspace_bytes) */
+#define HSWO_E_DEVICE (-3)      /* a HIP call failed */
+#define HSWO_E_NONFINITE (-4)   /* reserved: non-finite input found by a caller-side check */
+#define HSWO_E_UNSUPPORTED (-5) /* valid request this build does not implement */
+
+/* cube element types */
+#define HSWO_F32 0
+#define HSWO_F16 1
+
+/* screening precision for the non-adjacent (spectral) stage */
+#define HSWO_PREC_FP32 0      /* plain: FP32 vector ALU screen */
+#define HSWO_PREC_SCREEN_BF16 1 /* Gram cross-term on BF16 matrix cores, FP32 accumulate */
+#define HSWO_PREC_SCREEN_FP16 2 /* Gram cross-term on FP16 matrix cores, FP32 accumulate */
+
+/* flags */
+#define HSWO_FLAG_MERGE_LOG 1 /* fill merge_log (must be non-NULL) */
+
+typedef struct hswo_params {
+    int32_t connectivity;       /* 4 or 8: pixel links inside a leaf section */
+    int32_t seam_connectivity;  /* 4 or 8: pixel links across RHSEG split lines */
+    float spclust_wght;         /* spectral clustering weight w, 0 <= w <= 1 (not NaN) */
+    int32_t spclust_max;        /* spectral stage iff R <= spclust_max; 0 = never; <= 65535 */
+    int32_t target_regions;     /* >= 1: stop count of the top pass */
+    int32_t section_regions;    /* stop count of non-top passes; 0 = max(target, spclust_max/4) */
+    int32_t rnb_levels;         /* L >= 1 recursion levels (4^(L-1) leaf sections) */
+    int32_t n_levels;           /* number of label maps to output, >= 1 */
+    const int32_t* level_counts;/* HOST pointer, n_levels entries, strictly decreasing,
+                                   all >= target_regions, last == target_regions */
+    int32_t precision;          /* HSWO_PREC_* */
+    int32_t flags;              /* HSWO_FLAG_* */
+} hswo_params;
+
+typedef struct hswo_merge_rec {
+    int32_t lo, hi;   /* labels of the merged regions, lo < hi; lo survives */
+    int32_t kind;     /* 0 adjacent (spatial stage), 1 non-adjacent (spectral stage) */
+    int32_t r_after;  /* live regions in the section after the merge */
+    double d2;        /* the canonical FP64 squared criterion of the merge */
+} hswo_merge_rec;     /* 24 bytes */
+
+typedef struct hswo_stats {
+    int64_t merges;              /* merges performed */
+    int64_t iterations;          /* merge-loop iterations over all sections */
+    int64_t adjacent_pairs;      /* adjacent pairs screened (summed over iterations) */
+    int64_t spectral_pairs;      /* unordered pairs screened in the spectral stage */
+    int64_t exact_rechecks;      /* pairs re-scored in canonical FP64 */
+    int64_t tile_rescans;        /* spectral tiles re-screened to collect candidates */
+    double ms_total;             /* device time of the call (hipEvents), ms */
+} hswo_stats;
+
+/* One independent section for hswo_run_batch. */
+typedef struct hswo_section {
+    const void* cube;   /* device, H x W x B, band-interleaved by pixel, dtype of the call */
+    int32_t H, W, B;
+    int32_t* labels;    /* device, [n_levels][H][W] int32; labels are local pixel indices */
+    hswo_merge_rec* merge_log; /* device, H*W - target records, or NULL */
+} hswo_section;
+
+/* Library version (HSWO_VERSION). */
+int hswo_version(void);
+
+/* Message of the last error returned on the calling thread ("" if none). */
+const char* hswo_last_error(void);
+
+/* Workspace needed by hswo_run / rhseg_segment for this shape and parameters
+   (rnb_levels taken from p). Returns 0 if the parameters are invalid. */
+size_t hswo_workspace_bytes(int32_t H, int32_t W, int32_t B, int32_t dtype, const hswo_params* p);
+
+/*
+ * HSEG on the whole image as one section (RHSEG with L = 1; Section 4.1,
+ * the four HSEG steps). p->rnb_levels must be 1.
+ *   cube       device, H x W x B (band-interleaved by pixel), dtype HSWO_F32 or
+ *              HSWO_F16, finite values, 16-byte aligned
+ *   labels     device, [p->n_levels][H][W] int32 output
+ *   merge_log  device, (H*W - target) records in merge order, or NULL
+ *   stats      host, optional (synchronises the stream)
+ *   workspace  device scratch, ws_bytes >= hswo_workspace_bytes(...)
+ */
+int hswo_run(const void* cube, int32_t H, int32_t W, int32_t B, int32_t dtype, const hswo_params* p,
+             int32_t* labels, hswo_merge_rec* merge_log, hswo_stats* stats, void* workspace,
+             size_t ws_bytes, void* hip_stream);
+
+/*
+ * RHSEG (Section 4.1, recursive approximation of HSEG, Figures 4.3 and 4.4)
+ * with rnb_levels = L. Arguments as hswo_run. The merge log lists the merges
+ * of the deepest level first, the sections of a level in quadtree order (TL,
+ * TR, BL, BR, recursively), merges of a section in order.
+ */
+int rhseg_segment(const void* cube, int32_t H, int32_t W, int32_t B, int32_t dtype,
+                  const hswo_params* p, int32_t rnb_levels, int32_t* labels,
+                  hswo_merge_rec* merge_log, hswo_stats* stats, void* workspace, size_t ws_bytes,
+                  void* hip_stream);
+
+/*
+ * Many independent sections, each segmented as its own top pass (HSEG on a
+ * section, Section 4.1; sections are independent, as RHSEG's sections of one
+ * level are), all in one persistent launch. Every section uses the same
+ * parameters (p->rnb_levels must be 1) and the same dtype; H, W, B may
+ * differ. Labels are local pixel indices of each section.
+ */
+size_t hswo_batch_workspace_bytes(int32_t n_sections, const hswo_section* sections, int32_t dtype,
+                                  const hswo_params* p);
+int hswo_run_batch(int32_t n_sections, const hswo_section* sections, int32_t dtype,
+                   const hswo_params* p, hswo_stats* stats, void* workspace, size_t ws_bytes,
+                   void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSWO_H */

@@ -1,0 +1,110 @@
+// hswo_internal.h -- device-side descriptors shared by the host runtime
+// (hswo_api.cpp) and the kernels (hswo_kernels.hip). Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "hswo.h"
+
+namespace hswo {
+
+constexpr int NT = 512;          // threads per section-driver workgroup (8 wave64)
+constexpr int NWAVE = NT / 64;
+constexpr int TILE = 64;         // spectral tile edge (pairs TILE x TILE)
+constexpr int BK = 32;           // band chunk staged in LDS; mean rows padded to a multiple
+constexpr int CAND_CAP = 10240;  // candidate list capacity (LDS)
+constexpr int MAX_B = 4096;
+
+// counters accumulated per call (device, u64)
+enum Counter {
+    C_MERGES = 0,
+    C_ITERS,
+    C_ADJ_PAIRS,
+    C_SPEC_PAIRS,
+    C_RECHECKS,
+    C_RESCANS,
+    C_COUNT
+};
+
+// One section of one recursion level (or one independent batch section).
+struct SecDev {
+    int32_t R0;      // slot capacity (regions at the start of the pass, upper bound)
+    int32_t B;       // bands
+    int32_t Bp;      // float row stride: B rounded up to a multiple of BK
+    int32_t Ecap;    // edge capacity
+    int32_t stop;    // stop count of this pass
+    int32_t top;     // 1: top pass (merge times recorded for the level snapshots)
+    int32_t log_base;// index of this section's first merge record
+    int32_t tiles;   // capacity of tstat (spectral tiles)
+    int32_t* label;  // [R0] region label (smallest pixel index of the region)
+    int32_t* npix;   // [R0] pixel count
+    double* sums;    // [R0][B] FP64 band sums
+    float* mean;     // [R0][Bp] FP32 mean spectrum (screen copy), zero padded
+    float* norm;     // [R0] upper bound of the L2 norm of the FP32 mean row
+    int32_t* mark;   // [R0] per-iteration marks for edge de-duplication
+    int2* edges;     // [Ecap] adjacent slot pairs
+    float2* escr;    // [Ecap] per-edge screen bounds (lower, upper)
+    float2* tstat;   // [tiles] per-tile bounds (min lower, min upper)
+    int32_t* st;     // state: [0] R, [1] E, [2] R at pass start, [3] merges done
+    int32_t* parent; // label-indexed union-find parent (image or batch section)
+    int32_t* mtime;  // label-indexed merge time: -1 non-top merge, k top merge, INT_MAX alive
+    hswo_merge_rec* log;  // section merge log base (may be null)
+};
+
+// Leaf initialisation: where a section's pixels come from.
+struct InitDev {
+    const void* cube;  // image (rhseg) or section cube (batch)
+    int32_t img_w;     // row length of the cube in pixels
+    int32_t r0, c0, h, w;  // section rectangle inside the cube
+    int32_t label_w;   // labels are (r0+r)*label_w + (c0+c)
+    int32_t conn;      // 4 or 8
+};
+
+// Reassembly of four children into a parent section.
+struct AsmDev {
+    int32_t child0;    // index of the first of the four children in the child level's SecDev array
+    int32_t r0, c0, h, w;  // parent rectangle (image coordinates)
+    int32_t img_w;
+    int32_t seam_conn;
+    int32_t hash_cap;  // power of two
+    unsigned long long* hash;
+};
+
+// Label snapshot of one top pass.
+struct SnapDev {
+    const int32_t* st;     // top section state (R at pass start in st[2])
+    const int32_t* parent;
+    const int32_t* mtime;
+    int32_t* labels;       // [n_levels][H][W]
+    int32_t img_w;         // width of the parent/mtime index space
+    int32_t r0, c0, h, w;  // pixels covered
+    int32_t label_w;       // labels are (r0+r)*label_w + (c0+c) in parent/mtime
+};
+
+struct LoopParams {
+    double w2;        // spclust_wght^2 in FP64
+    int32_t spectral; // w > 0
+    int32_t kmax;     // spectral stage iff R <= kmax
+    int32_t precision;
+    int32_t pad;
+    unsigned long long* counters;  // [C_COUNT]
+};
+
+// kernel launchers (hswo_kernels.hip)
+hipError_t launch_init_pixels(int32_t* parent, int32_t* mtime, int64_t n, hipStream_t s);
+hipError_t launch_init_leaves(const SecDev* secs, const InitDev* init, int n, int dtype, int max_pixels,
+                              hipStream_t s);
+hipError_t launch_section_driver(const SecDev* secs, int n, const LoopParams& lp, hipStream_t s);
+hipError_t launch_compress(int32_t* parent, int64_t n, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s);
+hipError_t launch_assemble(const SecDev* parents, const SecDev* children, const AsmDev* asm_, int n,
+                           int32_t* slotmap, int max_cap, hipStream_t s);
+hipError_t launch_seam(const SecDev* parents, const AsmDev* asm_, int n, const int32_t* slotmap,
+                       int max_seam, hipStream_t s);
+hipError_t launch_snapshot(const SnapDev* snaps, int n, const int32_t* counts, int n_levels, int max_pixels,
+                           hipStream_t s);
+
+}  // namespace hswo

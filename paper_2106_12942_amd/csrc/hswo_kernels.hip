@@ -1,0 +1,907 @@
+// hswo_kernels.hip -- CDNA4 (gfx950) kernels of the HSWO / HSEG / RHSEG hot path.
+//
+// The method is the HSEG loop of Section 4.1 of the paper: every iteration
+// scores all spatially adjacent region pairs and, when spectral clustering is
+// on, all non-adjacent pairs with Equation 1, takes the minimum, merges that
+// pair and updates the region statistics and adjacency. Here one workgroup
+// owns one section and runs the whole loop on the device (no host round trip
+// per merge, unlike the paper's CPU-side merge of Section 4.2):
+//
+//   adjacent stage   16 lanes per edge stream the two FP32 mean rows (float4,
+//                    coalesced), an FP32 sum of squares with a certified
+//                    error bound; per-edge (lower, upper) bounds go to scratch.
+//   spectral stage   all pairs i < j in 64 x 64 tiles staged through LDS,
+//                    FP32, with per-tile (min lower, min upper).
+//   decision         every pair whose lower bound can reach the minimum is
+//                    re-scored with the canonical FP64 formula (one wavefront
+//                    per pair, fixed pairwise band tree), and the exact
+//                    lexicographic minimum (D2, lo, hi) decides.
+//   merge            FP64 band sums, counts, FP32 mean row and norm of the
+//                    survivor; swap-remove of the dead slot; one block pass
+//                    relabels, de-duplicates and compacts the edge list.
+//
+// The spectral stage scores all pairs without masking adjacent ones: if the
+// overall minimum M is below w^2 * D2(A) (A the best adjacent pair) it cannot
+// be adjacent, because every adjacent pair has D2 >= D2(A) >= w^2 D2(A); and
+// if it is not below, no non-adjacent pair is. So the merge chosen is the one
+// the paper's step 3 chooses, with no adjacency test inside the tiles.
+//
+// Compiled with -ffp-contract=off: every FP64 operation of the re-check is a
+// single IEEE round-to-nearest operation in the order written; FMAs in the
+// screens are written explicitly (fmaf).
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+
+#include "hswo_internal.h"
+
+namespace hswo {
+
+namespace {
+
+constexpr float U32 = 5.9604645e-08f;  // 2^-24, unit roundoff of FP32
+
+struct KeyD {
+    double d2;
+    int lo, hi;  // labels, lo < hi
+    int si, sj;  // slots of lo and hi
+};
+
+__device__ __forceinline__ KeyD key_none() {
+    KeyD k;
+    k.d2 = __builtin_huge_val();
+    k.lo = INT_MAX;
+    k.hi = INT_MAX;
+    k.si = -1;
+    k.sj = -1;
+    return k;
+}
+
+__device__ __forceinline__ bool key_less(const KeyD& a, const KeyD& b) {
+    if (a.d2 != b.d2) return a.d2 < b.d2;
+    if (a.lo != b.lo) return a.lo < b.lo;
+    return a.hi < b.hi;
+}
+
+__device__ __forceinline__ bool key_exists(const KeyD& k) { return k.lo != INT_MAX; }
+
+struct Smem {
+    float As[BK][TILE + 4];
+    float Cs[BK][TILE + 4];
+    int cand[CAND_CAP];
+    float redf[2][NWAVE];
+    int redi[NWAVE];
+    double redd[NWAVE];
+    KeyD redk[NWAVE];
+    double csum[NWAVE][16];
+    int ncand;
+    int bcast_i[4];
+};
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
+
+__device__ __forceinline__ float wave_min_f(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+    return v;
+}
+
+// minimum of two floats over the block; every thread gets both results
+__device__ __forceinline__ float2 block_min_f2(Smem& sh, float a, float b) {
+    a = wave_min_f(a);
+    b = wave_min_f(b);
+    if (lane_id() == 0) {
+        sh.redf[0][wave_id()] = a;
+        sh.redf[1][wave_id()] = b;
+    }
+    __syncthreads();
+    float ra = sh.redf[0][0], rb = sh.redf[1][0];
+#pragma unroll
+    for (int w = 1; w < NWAVE; ++w) {
+        ra = fminf(ra, sh.redf[0][w]);
+        rb = fminf(rb, sh.redf[1][w]);
+    }
+    __syncthreads();
+    return make_float2(ra, rb);
+}
+
+__device__ __forceinline__ double block_sum_d(Smem& sh, double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    if (lane_id() == 0) sh.redd[wave_id()] = v;
+    __syncthreads();
+    double r = 0.0;
+#pragma unroll
+    for (int w = 0; w < NWAVE; ++w) r += sh.redd[w];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ KeyD shfl_key(const KeyD& k, int o) {
+    KeyD r;
+    r.d2 = __shfl_xor(k.d2, o);
+    r.lo = __shfl_xor(k.lo, o);
+    r.hi = __shfl_xor(k.hi, o);
+    r.si = __shfl_xor(k.si, o);
+    r.sj = __shfl_xor(k.sj, o);
+    return r;
+}
+
+__device__ KeyD block_min_key(Smem& sh, KeyD k) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        KeyD x = shfl_key(k, o);
+        if (key_less(x, k)) k = x;
+    }
+    if (lane_id() == 0) sh.redk[wave_id()] = k;
+    __syncthreads();
+    KeyD r = sh.redk[0];
+#pragma unroll
+    for (int w = 1; w < NWAVE; ++w)
+        if (key_less(sh.redk[w], r)) r = sh.redk[w];
+    __syncthreads();
+    return r;
+}
+
+// exclusive prefix of a 0/1 flag over the block; returns the prefix, *total set
+__device__ __forceinline__ int block_scan_flag(Smem& sh, bool f, int* total) {
+    const unsigned long long m = __ballot(f);
+    const int lane = lane_id();
+    const int below = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) sh.redi[wave_id()] = __popcll(m);
+    __syncthreads();
+    int before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < NWAVE; ++w) {
+        const int c = sh.redi[w];
+        if (w < wave_id()) before += c;
+        tot += c;
+    }
+    __syncthreads();
+    *total = tot;
+    return before + below;
+}
+
+// Certified bounds on the canonical D2 of a pair from its FP32 screen.
+//   s      FP32 sum over bands of (m_a - m_b)^2, FMA accumulated
+//   na,nb  pixel counts; Na,Nb upper bounds of the FP32 mean-row norms
+//   gam    accumulation bound ~ (2B + 32) u
+// m_a = fl32(fl64(S_a / n_a)) is within ~u|mu_a| of the true mean per band and
+// the per-band difference rounds once, so ||d~ - d|| <= ~2u(Na + Nb); the
+// computed s is within gam of ||d~||^2. The FP64 canonical value differs from
+// the real value by far less than the 32u margin.
+__device__ __forceinline__ float2 screen_bounds(float s, int na, int nb, float Na, float Nb, float gam) {
+    const float fa = (float)na, fb = (float)nb;
+    const float w = (fa * fb) / (fa + fb);
+    const float r = sqrtf(s);
+    const float eta = 3.0f * U32 * (Na + Nb);
+    const float rl = fmaxf(r * (1.0f - gam) - eta, 0.0f);
+    const float rh = r * (1.0f + gam) + eta;
+    return make_float2(w * rl * rl * (1.0f - 32.0f * U32), w * rh * rh * (1.0f + 32.0f * U32));
+}
+
+// Canonical FP64 squared criterion, evaluated by one whole wavefront (all 64
+// lanes must call it with the same arguments; every lane gets the result).
+//   fac = (n_i n_j)/(n_i + n_j); d_b = S_ib/n_i - S_jb/n_j; q_b = d_b*d_b;
+//   acc = pairwise tree over b of q_b, zero-padded to a power of two.
+// Lane l holds bands 4l..4l+3 of each 256-band chunk: two in-register levels,
+// six butterfly levels across lanes (a+b == b+a bitwise, so both lanes of a
+// pair hold the same sum). Chunk sums are parked in LDS and combined by a
+// 16-leaf tree (again butterflies, over lanes 0..15). Zero padding beyond
+// the next power of two only adds +0.0, which is exact.
+__device__ double exact_d2_wave(Smem& sh, const SecDev& s, int si, int sj) {
+    const int lane = lane_id();
+    const int B = s.B;
+    const int n_i = s.npix[si], n_j = s.npix[sj];
+    const double dni = (double)n_i, dnj = (double)n_j;
+    const double* Si = s.sums + (size_t)si * B;
+    const double* Sj = s.sums + (size_t)sj * B;
+    const int nch = (B + 255) >> 8;
+    double* cs = sh.csum[wave_id()];
+    for (int c = 0; c < nch; ++c) {
+        double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
+        const int b = (c << 8) + (lane << 2);
+        if (b + 3 < B) {
+            double d;
+            d = Si[b] / dni - Sj[b] / dnj; q0 = d * d;
+            d = Si[b + 1] / dni - Sj[b + 1] / dnj; q1 = d * d;
+            d = Si[b + 2] / dni - Sj[b + 2] / dnj; q2 = d * d;
+            d = Si[b + 3] / dni - Sj[b + 3] / dnj; q3 = d * d;
+        } else {
+            double d;
+            if (b < B) { d = Si[b] / dni - Sj[b] / dnj; q0 = d * d; }
+            if (b + 1 < B) { d = Si[b + 1] / dni - Sj[b + 1] / dnj; q1 = d * d; }
+            if (b + 2 < B) { d = Si[b + 2] / dni - Sj[b + 2] / dnj; q2 = d * d; }
+        }
+        double t = (q0 + q1) + (q2 + q3);
+        t = t + __shfl_xor(t, 1);
+        t = t + __shfl_xor(t, 2);
+        t = t + __shfl_xor(t, 4);
+        t = t + __shfl_xor(t, 8);
+        t = t + __shfl_xor(t, 16);
+        t = t + __shfl_xor(t, 32);
+        if (lane == 0) cs[c] = t;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    double u = (lane < nch) ? cs[lane] : 0.0;
+    u = u + __shfl_xor(u, 1);
+    u = u + __shfl_xor(u, 2);
+    u = u + __shfl_xor(u, 4);
+    u = u + __shfl_xor(u, 8);
+    const double acc = __shfl(u, 0);
+    const double fac = (dni * dnj) / (double)(n_i + n_j);
+    return fac * acc;
+}
+
+// Exact lexicographic minimum over the first n entries of the LDS candidate
+// list. Adjacent mode: entries are edge indices; spectral mode: (i<<16)|j.
+__device__ KeyD exact_best_of_list(Smem& sh, const SecDev& s, int n, bool edge_mode) {
+    KeyD best = key_none();
+    for (int c = wave_id(); c < n; c += NWAVE) {
+        const int ent = sh.cand[c];
+        int a, b;
+        if (edge_mode) {
+            const int2 e = s.edges[ent];
+            a = e.x;
+            b = e.y;
+        } else {
+            a = (int)((unsigned)ent >> 16);
+            b = (int)((unsigned)ent & 0xffffu);
+        }
+        int la = s.label[a], lb = s.label[b];
+        if (la > lb) {
+            const int t = a; a = b; b = t;
+            const int u = la; la = lb; lb = u;
+        }
+        KeyD k;
+        k.d2 = exact_d2_wave(sh, s, a, b);
+        k.lo = la;
+        k.hi = lb;
+        k.si = a;
+        k.sj = b;
+        if (key_less(k, best)) best = k;
+    }
+    return block_min_key(sh, best);
+}
+
+// Flush the candidate list into `best` when it is fuller than `keep_room`
+// allows. Must be called by the whole block at a point where all appends of
+// the current round are done.
+__device__ void flush_candidates(Smem& sh, const SecDev& s, KeyD& best, int& nchk, bool edge_mode,
+                                 int keep_room) {
+    __syncthreads();
+    const int n = sh.ncand;
+    __syncthreads();  // every thread has read n before anyone appends again
+    if (n > CAND_CAP - keep_room) {
+        const int m = n < CAND_CAP ? n : CAND_CAP;
+        const KeyD k = exact_best_of_list(sh, s, m, edge_mode);
+        if (key_less(k, best)) best = k;
+        nchk += m;
+        if (threadIdx.x == 0) sh.ncand = 0;
+        __syncthreads();
+    }
+}
+
+// 64 x 64 FP32 spectral tile: thread (ty, tx) of 16 x 32 accumulates the
+// 4 x 2 pairs rows ib*64+4ty+{0..3}, cols jb*64+2tx+{0,1}.
+__device__ void tile_sums_fp32(Smem& sh, const SecDev& s, int ib, int jb, int R, float acc[4][2]) {
+    const int tid = threadIdx.x;
+    const int ty = tid >> 5, tx = tid & 31;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) acc[a][0] = acc[a][1] = 0.0f;
+    const int lrow = tid >> 3, lb = (tid & 7) << 2;
+    const int ia = ib * TILE + lrow, ic = jb * TILE + lrow;
+    for (int k0 = 0; k0 < s.Bp; k0 += BK) {
+        float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vc = va;
+        if (ia < R) va = *reinterpret_cast<const float4*>(s.mean + (size_t)ia * s.Bp + k0 + lb);
+        if (ic < R) vc = *reinterpret_cast<const float4*>(s.mean + (size_t)ic * s.Bp + k0 + lb);
+        sh.As[lb + 0][lrow] = va.x;
+        sh.As[lb + 1][lrow] = va.y;
+        sh.As[lb + 2][lrow] = va.z;
+        sh.As[lb + 3][lrow] = va.w;
+        sh.Cs[lb + 0][lrow] = vc.x;
+        sh.Cs[lb + 1][lrow] = vc.y;
+        sh.Cs[lb + 2][lrow] = vc.z;
+        sh.Cs[lb + 3][lrow] = vc.w;
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < BK; ++kk) {
+            const float4 a = *reinterpret_cast<const float4*>(&sh.As[kk][ty * 4]);
+            const float2 c = *reinterpret_cast<const float2*>(&sh.Cs[kk][tx * 2]);
+            float d;
+            d = a.x - c.x; acc[0][0] = fmaf(d, d, acc[0][0]);
+            d = a.x - c.y; acc[0][1] = fmaf(d, d, acc[0][1]);
+            d = a.y - c.x; acc[1][0] = fmaf(d, d, acc[1][0]);
+            d = a.y - c.y; acc[1][1] = fmaf(d, d, acc[1][1]);
+            d = a.z - c.x; acc[2][0] = fmaf(d, d, acc[2][0]);
+            d = a.z - c.y; acc[2][1] = fmaf(d, d, acc[2][1]);
+            d = a.w - c.x; acc[3][0] = fmaf(d, d, acc[3][0]);
+            d = a.w - c.y; acc[3][1] = fmaf(d, d, acc[3][1]);
+        }
+        __syncthreads();
+    }
+}
+
+// One merge (Section 4.1: the merged region replaces both). lo_s keeps the
+// region; the slot hi_s is freed and the last live slot R-1 moves into it.
+__device__ void merge_pair(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int& E, int stamp,
+                           int kind, double d2) {
+    const int tid = threadIdx.x;
+    const int B = s.B, Bp = s.Bp;
+    const int lo_l = s.label[lo_s], hi_l = s.label[hi_s];
+    const int n_new = s.npix[lo_s] + s.npix[hi_s];
+    const double dn = (double)n_new;
+    double* Slo = s.sums + (size_t)lo_s * B;
+    const double* Shi = s.sums + (size_t)hi_s * B;
+    float* Mlo = s.mean + (size_t)lo_s * Bp;
+    double nrm = 0.0;
+    for (int b = tid; b < B; b += NT) {
+        const double v = Slo[b] + Shi[b];
+        Slo[b] = v;
+        const float m = (float)(v / dn);
+        Mlo[b] = m;
+        nrm += (double)m * (double)m;
+    }
+    nrm = block_sum_d(sh, nrm);  // contains barriers: all reads of s.npix done
+    if (tid == 0) {
+        s.npix[lo_s] = n_new;
+        s.norm[lo_s] = (float)(sqrt(nrm) * (1.0 + 0x1p-20));
+        s.parent[hi_l] = lo_l;
+        const int k = s.st[3];
+        s.mtime[hi_l] = s.top ? k : -1;
+        if (s.log) {
+            hswo_merge_rec rec;
+            rec.lo = lo_l;
+            rec.hi = hi_l;
+            rec.kind = kind;
+            rec.r_after = R - 1;
+            rec.d2 = d2;
+            s.log[k] = rec;
+        }
+        s.st[3] = k + 1;
+    }
+    // mark the neighbours of the survivor
+    for (int e = tid; e < E; e += NT) {
+        const int2 ed = s.edges[e];
+        if (ed.x == lo_s) s.mark[ed.y] = stamp;
+        if (ed.y == lo_s) s.mark[ed.x] = stamp;
+    }
+    __syncthreads();
+    // relabel hi -> lo, drop the merged pair and duplicate (lo, x) edges,
+    // rename the moved slot, compact in place (writes never pass reads)
+    const int last = R - 1;
+    int newE = 0;
+    for (int e0 = 0; e0 < E; e0 += NT) {
+        const int e = e0 + tid;
+        bool keep = false;
+        int a = 0, b = 0;
+        if (e < E) {
+            const int2 ed = s.edges[e];
+            a = ed.x;
+            b = ed.y;
+            const bool hi_edge = (a == hi_s) || (b == hi_s);
+            if (a == hi_s) a = lo_s;
+            if (b == hi_s) b = lo_s;
+            keep = (a != b);
+            if (keep && hi_edge) {
+                const int other = (a == lo_s) ? b : a;
+                if (s.mark[other] == stamp) keep = false;
+            }
+            if (a == last) a = hi_s;
+            if (b == last) b = hi_s;
+        }
+        int tot;
+        const int pos = block_scan_flag(sh, keep, &tot);  // barrier: chunk fully read
+        if (keep) s.edges[newE + pos] = make_int2(a, b);
+        newE += tot;
+    }
+    E = newE;
+    __syncthreads();
+    // swap-remove: move the last live slot into the freed one
+    if (hi_s != last) {
+        const double* Ssrc = s.sums + (size_t)last * B;
+        double* Sdst = s.sums + (size_t)hi_s * B;
+        for (int b = tid; b < B; b += NT) Sdst[b] = Ssrc[b];
+        const float* Msrc = s.mean + (size_t)last * Bp;
+        float* Mdst = s.mean + (size_t)hi_s * Bp;
+        for (int b = tid; b < Bp; b += NT) Mdst[b] = Msrc[b];
+        if (tid == 0) {
+            s.label[hi_s] = s.label[last];
+            s.npix[hi_s] = s.npix[last];
+            s.norm[hi_s] = s.norm[last];
+            s.mark[hi_s] = s.mark[last];
+        }
+    }
+    __syncthreads();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// The section driver: one workgroup runs the whole HSEG loop of one section.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict__ secs, int n_sec,
+                                                       LoopParams lp) {
+    __shared__ Smem sh;
+    if ((int)blockIdx.x >= n_sec) return;
+    const SecDev s = secs[blockIdx.x];
+    const int tid = threadIdx.x;
+    int R = s.st[0];
+    int E = s.st[1];
+    const float gam = (float)(2 * s.B + 32) * U32;
+    unsigned long long c_adj = 0, c_spec = 0, c_chk = 0, c_resc = 0, c_it = 0;
+    int stamp = 0;
+    if (tid == 0) sh.ncand = 0;
+    __syncthreads();
+
+    while (R > s.stop) {
+        // ------------------------------------------------ adjacent stage
+        float myU = __builtin_huge_valf();
+        {
+            const int g = tid >> 4, gl = tid & 15;
+            const int nf4 = s.Bp >> 2;
+            for (int e0 = 0; e0 < E; e0 += NT / 16) {
+                const int e = e0 + g;
+                float acc = 0.0f;
+                int a = 0, b = 0;
+                if (e < E) {
+                    const int2 ed = s.edges[e];
+                    a = ed.x;
+                    b = ed.y;
+                    const float4* ra = reinterpret_cast<const float4*>(s.mean + (size_t)a * s.Bp);
+                    const float4* rb = reinterpret_cast<const float4*>(s.mean + (size_t)b * s.Bp);
+                    for (int c = gl; c < nf4; c += 16) {
+                        const float4 x = ra[c], y = rb[c];
+                        float d;
+                        d = x.x - y.x; acc = fmaf(d, d, acc);
+                        d = x.y - y.y; acc = fmaf(d, d, acc);
+                        d = x.z - y.z; acc = fmaf(d, d, acc);
+                        d = x.w - y.w; acc = fmaf(d, d, acc);
+                    }
+                }
+                acc += __shfl_xor(acc, 8);
+                acc += __shfl_xor(acc, 4);
+                acc += __shfl_xor(acc, 2);
+                acc += __shfl_xor(acc, 1);
+                if (e < E && gl == 0) {
+                    const float2 lu = screen_bounds(acc, s.npix[a], s.npix[b], s.norm[a], s.norm[b], gam);
+                    s.escr[e] = lu;
+                    myU = fminf(myU, lu.y);
+                }
+            }
+        }
+        const float Ua = block_min_f2(sh, myU, myU).x;
+        KeyD A = key_none();
+        int nchk = 0;
+        for (int e0 = 0; e0 < E; e0 += NT) {
+            const int e = e0 + tid;
+            if (e < E && s.escr[e].x <= Ua) {
+                const int k = atomicAdd(&sh.ncand, 1);
+                if (k < CAND_CAP) sh.cand[k] = e;
+            }
+            flush_candidates(sh, s, A, nchk, true, NT);
+        }
+        flush_candidates(sh, s, A, nchk, true, CAND_CAP);
+        c_adj += (unsigned long long)E;
+
+        // ------------------------------------------------ spectral stage
+        KeyD M = key_none();
+        const bool spectral = lp.spectral && R <= lp.kmax;
+        const double T = key_exists(A) ? lp.w2 * A.d2 : __builtin_huge_val();
+        if (spectral) {
+            const int nT = (R + TILE - 1) / TILE;
+            const int ty = tid >> 5, tx = tid & 31;
+            float Us = __builtin_huge_valf();
+            int t = 0;
+            for (int ib = 0; ib < nT; ++ib)
+                for (int jb = ib; jb < nT; ++jb, ++t) {
+                    float acc[4][2];
+                    tile_sums_fp32(sh, s, ib, jb, R, acc);
+                    float mL = __builtin_huge_valf(), mU = __builtin_huge_valf();
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            const int i = ib * TILE + ty * 4 + a, j = jb * TILE + tx * 2 + c;
+                            if (i < j && j < R) {
+                                const float2 lu = screen_bounds(acc[a][c], s.npix[i], s.npix[j], s.norm[i],
+                                                                s.norm[j], gam);
+                                mL = fminf(mL, lu.x);
+                                mU = fminf(mU, lu.y);
+                            }
+                        }
+                    const float2 lu = block_min_f2(sh, mL, mU);
+                    if (tid == 0) s.tstat[t] = lu;
+                    Us = fminf(Us, lu.y);
+                }
+            const double theta = fmin((double)Us, T);
+            int nresc = 0;
+            t = 0;
+            for (int ib = 0; ib < nT; ++ib)
+                for (int jb = ib; jb < nT; ++jb, ++t) {
+                    if (tid == 0) {
+                        const float tl = s.tstat[t].x;
+                        sh.bcast_i[0] = ((double)tl <= theta && (double)tl < T) ? 1 : 0;
+                    }
+                    __syncthreads();
+                    const int flagged = sh.bcast_i[0];
+                    __syncthreads();
+                    if (!flagged) continue;  // block-uniform via LDS
+                    ++nresc;
+                    float acc[4][2];
+                    tile_sums_fp32(sh, s, ib, jb, R, acc);
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            const int i = ib * TILE + ty * 4 + a, j = jb * TILE + tx * 2 + c;
+                            if (i < j && j < R) {
+                                const float lo = screen_bounds(acc[a][c], s.npix[i], s.npix[j], s.norm[i],
+                                                               s.norm[j], gam).x;
+                                if ((double)lo <= theta && (double)lo < T) {
+                                    const int k = atomicAdd(&sh.ncand, 1);
+                                    if (k < CAND_CAP) sh.cand[k] = (int)(((unsigned)i << 16) | (unsigned)j);
+                                }
+                            }
+                        }
+                    flush_candidates(sh, s, M, nchk, false, TILE * TILE);
+                }
+            flush_candidates(sh, s, M, nchk, false, CAND_CAP);
+            c_spec += (unsigned long long)R * (unsigned long long)(R - 1) / 2ull;
+            c_resc += (unsigned long long)nresc;
+        }
+
+        // ------------------------------------------------ decision
+        KeyD win;
+        int kind;
+        if (spectral && key_exists(M) && M.d2 < T) {
+            win = M;
+            kind = 1;
+        } else if (key_exists(A)) {
+            win = A;
+            kind = 0;
+        } else {
+            break;  // no pair left (cannot happen in a connected section)
+        }
+        c_chk += (unsigned long long)nchk;
+        c_it += 1ull;
+
+        // ------------------------------------------------ merge
+        merge_pair(sh, s, win.si, win.sj, R, E, stamp, kind, win.d2);
+        ++stamp;
+        --R;
+    }
+    if (tid == 0) {
+        s.st[0] = R;
+        s.st[1] = E;
+        if (lp.counters) {
+            atomicAdd(&lp.counters[C_ITERS], c_it);
+            atomicAdd(&lp.counters[C_MERGES], c_it);
+            atomicAdd(&lp.counters[C_ADJ_PAIRS], c_adj);
+            atomicAdd(&lp.counters[C_SPEC_PAIRS], c_spec);
+            atomicAdd(&lp.counters[C_RECHECKS], c_chk);
+            atomicAdd(&lp.counters[C_RESCANS], c_resc);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation, reassembly, compression and snapshots.
+// ---------------------------------------------------------------------------
+__global__ void k_init_pixels(int32_t* parent, int32_t* mtime, int64_t n) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        parent[p] = (int32_t)p;
+        mtime[p] = INT_MAX;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ float load_px(const void* cube, size_t idx) {
+    return (float)reinterpret_cast<const T*>(cube)[idx];
+}
+
+template <>
+__device__ __forceinline__ float load_px<__half>(const void* cube, size_t idx) {
+    return __half2float(reinterpret_cast<const __half*>(cube)[idx]);
+}
+
+// Every pixel of a leaf section becomes a region (HSEG step 1): label = its
+// pixel index, one pixel, band sums = its spectrum; plus the section's grid
+// edges under 4- or 8-connectivity.
+template <typename T>
+__global__ void k_init_leaves(const SecDev* __restrict__ secs, const InitDev* __restrict__ init) {
+    const SecDev s = secs[blockIdx.y];
+    const InitDev in = init[blockIdx.y];
+    const int h = in.h, w = in.w, B = s.B, Bp = s.Bp;
+    const int P = h * w;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // band sums and mean rows
+    for (int64_t idx = t0; idx < (int64_t)P * Bp; idx += stride) {
+        const int k = (int)(idx / Bp), b = (int)(idx % Bp);
+        const int r = k / w, c = k % w;
+        float v = 0.0f;
+        if (b < B) {
+            v = load_px<T>(in.cube, ((size_t)(in.r0 + r) * in.img_w + (in.c0 + c)) * B + b);
+            s.sums[(size_t)k * B + b] = (double)v;
+        }
+        s.mean[(size_t)k * Bp + b] = v;
+    }
+    // per-pixel region data
+    for (int64_t k = t0; k < P; k += stride) {
+        const int r = (int)k / w, c = (int)k % w;
+        s.label[k] = (in.r0 + r) * in.label_w + (in.c0 + c);
+        s.npix[k] = 1;
+        s.mark[k] = -1;
+        const size_t base = ((size_t)(in.r0 + r) * in.img_w + (in.c0 + c)) * B;
+        double nrm = 0.0;
+        for (int b = 0; b < B; ++b) {
+            const double v = (double)load_px<T>(in.cube, base + b);
+            nrm += v * v;
+        }
+        s.norm[k] = (float)(sqrt(nrm) * (1.0 + 0x1p-20));
+    }
+    // grid edges: horizontal, vertical, then (8-connectivity) both diagonals
+    const int64_t nh = (int64_t)h * (w - 1), nv = (int64_t)(h - 1) * w, nd = (int64_t)(h - 1) * (w - 1);
+    const int64_t E0 = nh + nv + (in.conn == 8 ? 2 * nd : 0);
+    for (int64_t e = t0; e < E0; e += stride) {
+        int a, b;
+        if (e < nh) {
+            const int r = (int)(e / (w - 1)), c = (int)(e % (w - 1));
+            a = r * w + c;
+            b = a + 1;
+        } else if (e < nh + nv) {
+            const int64_t f = e - nh;
+            const int r = (int)(f / w), c = (int)(f % w);
+            a = r * w + c;
+            b = a + w;
+        } else if (e < nh + nv + nd) {
+            const int64_t f = e - nh - nv;
+            const int r = (int)(f / (w - 1)), c = (int)(f % (w - 1));
+            a = r * w + c;
+            b = a + w + 1;
+        } else {
+            const int64_t f = e - nh - nv - nd;
+            const int r = (int)(f / (w - 1)), c = (int)(f % (w - 1)) + 1;
+            a = r * w + c;
+            b = a + w - 1;
+        }
+        s.edges[e] = make_int2(a, b);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        s.st[0] = P;
+        s.st[1] = (int)E0;
+        s.st[2] = P;
+        s.st[3] = 0;
+    }
+}
+
+// Path compression of the label union-find: parent[p] becomes p's root.
+// Concurrent updates only ever store an ancestor, so every walk still ends
+// at the root.
+__global__ void k_compress(int32_t* parent, int64_t n) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        int x = parent[p];
+        for (int64_t step = 0; step < n; ++step) {  // a chain is never longer than n
+            const int y = parent[x];
+            if (y == x) break;
+            x = y;
+        }
+        parent[p] = x;
+    }
+}
+
+__global__ void k_fill_u64(unsigned long long* p, size_t n, unsigned long long v) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Reassembly (Figure 4.4), part 1: the parent's regions are the live regions
+// of its four children in order TL, TR, BL, BR; children's edges are kept.
+__global__ void k_assemble(const SecDev* __restrict__ parents, const SecDev* __restrict__ children,
+                           const AsmDev* __restrict__ asm_, int32_t* slotmap) {
+    const SecDev p = parents[blockIdx.y];
+    const AsmDev a = asm_[blockIdx.y];
+    int off[5], eoff[5];
+    off[0] = 0;
+    eoff[0] = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        off[c + 1] = off[c] + children[a.child0 + c].st[0];
+        eoff[c + 1] = eoff[c] + children[a.child0 + c].st[1];
+    }
+    if (off[4] > p.R0 || eoff[4] > p.Ecap) {
+        // cannot happen when every child pass ran to its stop count (sections
+        // are connected); never write past the parent's capacity
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            p.st[0] = 0;
+            p.st[1] = 0;
+            p.st[2] = 0;
+            p.st[3] = 0;
+        }
+        return;
+    }
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int B = p.B, Bp = p.Bp;
+    for (int c = 0; c < 4; ++c) {
+        const SecDev ch = children[a.child0 + c];
+        const int Rc = off[c + 1] - off[c], Ec = eoff[c + 1] - eoff[c];
+        for (int64_t k = t0; k < Rc; k += stride) {
+            const int ps = off[c] + (int)k;
+            const int lab = ch.label[k];
+            p.label[ps] = lab;
+            p.npix[ps] = ch.npix[k];
+            p.norm[ps] = ch.norm[k];
+            p.mark[ps] = -1;
+            slotmap[lab] = ps;
+        }
+        for (int64_t idx = t0; idx < (int64_t)Rc * B; idx += stride)
+            p.sums[(size_t)off[c] * B + idx] = ch.sums[idx];
+        for (int64_t idx = t0; idx < (int64_t)Rc * Bp; idx += stride)
+            p.mean[(size_t)off[c] * Bp + idx] = ch.mean[idx];
+        for (int64_t e = t0; e < Ec; e += stride) {
+            const int2 ed = ch.edges[e];
+            p.edges[eoff[c] + e] = make_int2(ed.x + off[c], ed.y + off[c]);
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        p.st[0] = off[4];
+        p.st[1] = eoff[4];
+        p.st[2] = off[4];
+        p.st[3] = 0;
+    }
+}
+
+__device__ __forceinline__ unsigned long long mix64(unsigned long long x) {
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdull;
+    x ^= x >> 33;
+    x *= 0xc4ceb9fe1a85ec53ull;
+    x ^= x >> 33;
+    return x;
+}
+
+// Reassembly, part 2: link the regions on either side of the two split lines
+// (pixel pairs in different quadrants that are neighbours under the seam
+// connectivity), one edge per distinct region pair.
+__global__ void k_seam(const SecDev* __restrict__ parents, const AsmDev* __restrict__ asm_,
+                       const int32_t* __restrict__ slotmap) {
+    const SecDev p = parents[blockIdx.y];
+    const AsmDev a = asm_[blockIdx.y];
+    const int h0 = a.h / 2, w0 = a.w / 2;
+    const int rs = a.r0 + h0 - 1;      // row above the horizontal split
+    const int cs0 = a.c0 + w0 - 1;     // columns either side of the vertical split
+    const int ncand = a.w + 2 * a.h;   // candidate pixels: that row, those two columns
+    const int noff = a.seam_conn == 8 ? 4 : 2;
+    const int dr[4] = {0, 1, 1, 1};
+    const int dc[4] = {1, 0, 1, -1};
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (int64_t)ncand * noff;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int ci = (int)(idx / noff), o = (int)(idx % noff);
+        int r, c;
+        if (ci < a.w) {
+            r = rs;
+            c = a.c0 + ci;
+        } else {
+            const int k = ci - a.w;
+            r = a.r0 + (k >> 1);
+            c = cs0 + (k & 1);
+        }
+        if (r < a.r0 || c < a.c0 || c >= a.c0 + a.w) continue;
+        const int r2 = r + dr[o], c2 = c + dc[o];
+        if (r2 >= a.r0 + a.h || c2 < a.c0 || c2 >= a.c0 + a.w) continue;
+        const int q1 = (r - a.r0 >= h0 ? 2 : 0) + (c - a.c0 >= w0 ? 1 : 0);
+        const int q2 = (r2 - a.r0 >= h0 ? 2 : 0) + (c2 - a.c0 >= w0 ? 1 : 0);
+        if (q1 == q2) continue;
+        const int la = p.parent[(size_t)r * a.img_w + c];
+        const int lb = p.parent[(size_t)r2 * a.img_w + c2];
+        if (la == lb) continue;
+        int sa = slotmap[la], sb = slotmap[lb];
+        if (sa > sb) {
+            const int t = sa; sa = sb; sb = t;
+        }
+        const unsigned long long key = ((unsigned long long)(unsigned)sa << 32) | (unsigned)sb;
+        unsigned long long hsh = mix64(key) & (unsigned long long)(a.hash_cap - 1);
+        for (int probe = 0; probe < a.hash_cap; ++probe) {
+            const unsigned long long old = atomicCAS(&a.hash[hsh], ~0ull, key);
+            if (old == ~0ull) {
+                const int e = atomicAdd(&p.st[1], 1);
+                p.edges[e] = make_int2(sa, sb);
+                break;
+            }
+            if (old == key) break;
+            hsh = (hsh + 1) & (unsigned long long)(a.hash_cap - 1);
+        }
+    }
+}
+
+// Label maps of the requested hierarchy levels of a top pass. A level with
+// count c is the state after k = max(0, R_start - c) top-pass merges: walk
+// from the pixel's region at the start of the pass along merges made before k.
+__global__ void k_snapshot(const SnapDev* __restrict__ snaps, const int32_t* __restrict__ counts, int n_levels) {
+    const SnapDev sd = snaps[blockIdx.y];
+    const int P = sd.h * sd.w;
+    const int Rs = sd.st[2];
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (int64_t)P * n_levels;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int lvl = (int)(idx / P), k = (int)(idx % P);
+        const int r = k / sd.w, c = k % sd.w;
+        const int kcut = Rs - counts[lvl] > 0 ? Rs - counts[lvl] : 0;
+        int x = (sd.r0 + r) * sd.label_w + (sd.c0 + c);
+        int steps = 0;
+        while (sd.mtime[x] < kcut && steps <= P) {  // bounded: a valid chain is shorter than P
+            x = sd.parent[x];
+            ++steps;
+        }
+        sd.labels[idx] = steps > P ? -1 : x;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline int grid_for(int64_t n, int bs, int cap) {
+    int64_t g = (n + bs - 1) / bs;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+hipError_t launch_init_pixels(int32_t* parent, int32_t* mtime, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_pixels, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, parent, mtime, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_leaves(const SecDev* secs, const InitDev* init, int n, int dtype, int max_pixels,
+                              hipStream_t s) {
+    const dim3 grid(grid_for((int64_t)max_pixels * 8, 256, 1024), n);
+    if (dtype == HSWO_F16)
+        hipLaunchKernelGGL(k_init_leaves<__half>, grid, dim3(256), 0, s, secs, init);
+    else
+        hipLaunchKernelGGL(k_init_leaves<float>, grid, dim3(256), 0, s, secs, init);
+    return hipGetLastError();
+}
+
+hipError_t launch_section_driver(const SecDev* secs, int n, const LoopParams& lp, hipStream_t s) {
+    hipLaunchKernelGGL(k_section_driver, dim3(n), dim3(NT), 0, s, secs, n, lp);
+    return hipGetLastError();
+}
+
+hipError_t launch_compress(int32_t* parent, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_compress, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, parent, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for((int64_t)n, 256, 4096)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble(const SecDev* parents, const SecDev* children, const AsmDev* asm_, int n,
+                           int32_t* slotmap, int max_cap, hipStream_t s) {
+    const dim3 grid(grid_for((int64_t)max_cap * 64, 256, 512), n);
+    hipLaunchKernelGGL(k_assemble, grid, dim3(256), 0, s, parents, children, asm_, slotmap);
+    return hipGetLastError();
+}
+
+hipError_t launch_seam(const SecDev* parents, const AsmDev* asm_, int n, const int32_t* slotmap, int max_seam,
+                       hipStream_t s) {
+    const dim3 grid(grid_for((int64_t)max_seam * 4, 256, 256), n);
+    hipLaunchKernelGGL(k_seam, grid, dim3(256), 0, s, parents, asm_, slotmap);
+    return hipGetLastError();
+}
+
+hipError_t launch_snapshot(const SnapDev* snaps, int n, const int32_t* counts, int n_levels, int max_pixels,
+                           hipStream_t s) {
+    const dim3 grid(grid_for((int64_t)max_pixels * n_levels, 256, 4096), n);
+    hipLaunchKernelGGL(k_snapshot, grid, dim3(256), 0, s, snaps, counts, n_levels);
+    return hipGetLastError();
+}
+
+}  // namespace hswo

@@ -1,0 +1,216 @@
+"""Thin ctypes binding over libhswo (include/hswo.h).
+
+Argument marshalling only: every step of HSWO / HSEG / RHSEG runs in the HIP
+kernels of libhswo. PyTorch provides device memory and the stream. There is
+no fallback: if the library is missing, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhswo.so")
+
+HSWO_OK = 0
+HSWO_E_INVAL = -1
+HSWO_E_NOMEM = -2
+HSWO_E_DEVICE = -3
+HSWO_E_NONFINITE = -4
+HSWO_E_UNSUPPORTED = -5
+
+HSWO_F32 = 0
+HSWO_F16 = 1
+
+PREC = {"fp32": 0, "bf16": 1, "fp16": 2}
+HSWO_FLAG_MERGE_LOG = 1
+
+MERGE_DTYPE = np.dtype([("lo", "<i4"), ("hi", "<i4"), ("kind", "<i4"), ("r_after", "<i4"), ("d2", "<f8")])
+
+EXPORTS = ["hswo_version", "hswo_last_error", "hswo_workspace_bytes", "hswo_run", "rhseg_segment",
+           "hswo_batch_workspace_bytes", "hswo_run_batch"]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("connectivity", ctypes.c_int32),
+        ("seam_connectivity", ctypes.c_int32),
+        ("spclust_wght", ctypes.c_float),
+        ("spclust_max", ctypes.c_int32),
+        ("target_regions", ctypes.c_int32),
+        ("section_regions", ctypes.c_int32),
+        ("rnb_levels", ctypes.c_int32),
+        ("n_levels", ctypes.c_int32),
+        ("level_counts", ctypes.POINTER(ctypes.c_int32)),
+        ("precision", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("merges", ctypes.c_int64),
+        ("iterations", ctypes.c_int64),
+        ("adjacent_pairs", ctypes.c_int64),
+        ("spectral_pairs", ctypes.c_int64),
+        ("exact_rechecks", ctypes.c_int64),
+        ("tile_rescans", ctypes.c_int64),
+        ("ms_total", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Section(ctypes.Structure):
+    _fields_ = [
+        ("cube", ctypes.c_void_p),
+        ("H", ctypes.c_int32),
+        ("W", ctypes.c_int32),
+        ("B", ctypes.c_int32),
+        ("labels", ctypes.c_void_p),
+        ("merge_log", ctypes.c_void_p),
+    ]
+
+
+class HswoError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libhswo error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libhswo.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "or python -m paper_2106_12942_amd.build")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+        lib.hswo_version.restype = ctypes.c_int
+        lib.hswo_last_error.restype = ctypes.c_char_p
+        lib.hswo_workspace_bytes.restype = sz
+        lib.hswo_workspace_bytes.argtypes = [i32, i32, i32, i32, ctypes.POINTER(Params)]
+        lib.hswo_run.restype = ctypes.c_int
+        lib.hswo_run.argtypes = [vp, i32, i32, i32, i32, ctypes.POINTER(Params), vp, vp,
+                                 ctypes.POINTER(Stats), vp, sz, vp]
+        lib.rhseg_segment.restype = ctypes.c_int
+        lib.rhseg_segment.argtypes = [vp, i32, i32, i32, i32, ctypes.POINTER(Params), i32, vp, vp,
+                                      ctypes.POINTER(Stats), vp, sz, vp]
+        lib.hswo_batch_workspace_bytes.restype = sz
+        lib.hswo_batch_workspace_bytes.argtypes = [i32, ctypes.POINTER(Section), i32, ctypes.POINTER(Params)]
+        lib.hswo_run_batch.restype = ctypes.c_int
+        lib.hswo_run_batch.argtypes = [i32, ctypes.POINTER(Section), i32, ctypes.POINTER(Params),
+                                       ctypes.POINTER(Stats), vp, sz, vp]
+        _lib = lib
+    return _lib
+
+
+def last_error() -> str:
+    return load().hswo_last_error().decode()
+
+
+def make_params(*, connectivity=4, seam_connectivity=8, spclust_wght=0.0, spclust_max=0, target_regions=1,
+                section_regions=0, rnb_levels=1, level_counts: Optional[Sequence[int]] = None,
+                precision="fp32", merge_log=False, **_ignored):
+    counts = list(level_counts) if level_counts is not None else [target_regions]
+    arr = (ctypes.c_int32 * len(counts))(*counts)
+    p = Params(connectivity, seam_connectivity, spclust_wght, spclust_max, target_regions, section_regions,
+               rnb_levels, len(counts), ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32)),
+               PREC[precision] if isinstance(precision, str) else int(precision),
+               HSWO_FLAG_MERGE_LOG if merge_log else 0)
+    p._counts_keepalive = arr  # the struct holds a raw pointer into arr
+    return p
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float32:
+        return HSWO_F32
+    if t.dtype == torch.float16:
+        return HSWO_F16
+    raise TypeError(f"cube dtype must be float32 or float16, got {t.dtype}")
+
+
+def _check(rc: int):
+    if rc != HSWO_OK:
+        raise HswoError(rc, last_error())
+
+
+@dataclasses.dataclass
+class Result:
+    labels: "object"           # torch int32 [n_levels, H, W] on the device
+    log: Optional[np.ndarray]  # MERGE_DTYPE records (host copy) or None
+    stats: Optional[dict]
+
+
+def workspace_bytes(H, W, B, dtype_code, params: Params) -> int:
+    return int(load().hswo_workspace_bytes(H, W, B, dtype_code, ctypes.byref(params)))
+
+
+def _aligned_workspace(nbytes: int, device):
+    import torch
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf, buf.data_ptr() + off
+
+
+def _segment(entry: str, cube, rnb_levels: int, merge_log: bool, stats: bool, stream, params) -> Result:
+    import torch
+    if not cube.is_cuda:
+        raise ValueError("cube must be a device tensor")
+    cube = cube.contiguous()
+    H, W, B = cube.shape
+    code = _dtype_code(cube)
+    params = dict(params)
+    params["rnb_levels"] = rnb_levels
+    p = make_params(**params, merge_log=merge_log)
+    lib = load()
+    s = stream if stream is not None else torch.cuda.current_stream(cube.device)
+
+    def call(labels_ptr, log_ptr, st_ref, ws_ptr, nb):
+        if entry == "hswo_run":
+            return lib.hswo_run(cube.data_ptr(), H, W, B, code, ctypes.byref(p), labels_ptr, log_ptr, st_ref,
+                                ws_ptr, nb, s.cuda_stream)
+        return lib.rhseg_segment(cube.data_ptr(), H, W, B, code, ctypes.byref(p), rnb_levels, labels_ptr,
+                                 log_ptr, st_ref, ws_ptr, nb, s.cuda_stream)
+
+    nb = int(lib.hswo_workspace_bytes(H, W, B, code, ctypes.byref(p)))
+    if nb == 0:
+        _check(call(None, None, None, None, 0))  # the entry point reports why
+        raise HswoError(HSWO_E_INVAL, "workspace query failed")
+    ws, ws_ptr = _aligned_workspace(nb, cube.device)
+    labels = torch.empty((p.n_levels, H, W), dtype=torch.int32, device=cube.device)
+    n_merges = H * W - params.get("target_regions", 1)
+    log_t = torch.empty((max(n_merges, 1) * MERGE_DTYPE.itemsize,), dtype=torch.uint8, device=cube.device) \
+        if merge_log else None
+    st = Stats() if stats else None
+    _check(call(labels.data_ptr(), log_t.data_ptr() if log_t is not None else None,
+                ctypes.byref(st) if st is not None else None, ws_ptr, nb))
+    # keep the workspace alive until the stream has consumed it
+    ws.record_stream(s)
+    log = None
+    if log_t is not None:
+        s.synchronize()
+        log = np.frombuffer(log_t.cpu().numpy().tobytes(), dtype=MERGE_DTYPE)[:max(n_merges, 0)]
+    return Result(labels=labels, log=log, stats=st.as_dict() if st is not None else None)
+
+
+def rhseg_segment(cube, *, rnb_levels: int = 1, merge_log: bool = False, stats: bool = False, stream=None,
+                  **params) -> Result:
+    """RHSEG of a device cube H x W x B (C entry point rhseg_segment)."""
+    return _segment("rhseg_segment", cube, rnb_levels, merge_log, stats, stream, params)
+
+
+def hswo_run(cube, *, merge_log: bool = False, stats: bool = False, stream=None, **params) -> Result:
+    """HSEG on the whole image as one section (C entry point hswo_run)."""
+    params.pop("rnb_levels", None)
+    return _segment("hswo_run", cube, 1, merge_log, stats, stream, params)

@@ -1,0 +1,119 @@
+"""The C ABI on the CPU: the library loads, exports every symbol declared in
+include/hswo.h, sizes workspaces, and rejects bad arguments before it touches
+the device (so no GPU is needed for any of these)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2106_12942_amd import hswo
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hswo.h")
+
+# fake, never dereferenced: validation fails before any device access
+FAKE = 0x100000
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(\w+)\s*\(", src, flags=re.M)) -
+                  {"if", "while", "for", "return", "sizeof"})
+
+
+def test_library_exports_every_declared_symbol():
+    lib = hswo.load()
+    names = declared_functions()
+    assert set(hswo.EXPORTS) <= set(names)
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in hswo.h but not exported"
+
+
+def test_version_and_empty_error():
+    assert hswo.load().hswo_version() == 10000
+
+
+def test_struct_layouts_match_header():
+    assert ctypes.sizeof(hswo.Params) == 48
+    assert hswo.MERGE_DTYPE.itemsize == 24
+    assert ctypes.sizeof(hswo.Stats) == 56
+
+
+BASE = dict(connectivity=4, seam_connectivity=8, spclust_wght=0.5, spclust_max=256, target_regions=2,
+            level_counts=[8, 2])
+
+
+def ws(H, W, B, dtype=0, **kw):
+    p = dict(BASE)
+    p.update(kw)
+    return hswo.workspace_bytes(H, W, B, dtype, hswo.make_params(**p))
+
+
+def test_workspace_bytes_grows_with_the_problem():
+    a = ws(64, 64, 32)
+    b = ws(64, 64, 64)
+    c = ws(128, 128, 32)
+    assert 0 < a < b and a < c
+    assert ws(512, 512, 128, spclust_max=1024, section_regions=256, rnb_levels=4, target_regions=8,
+              level_counts=[1024, 8]) > 0
+
+
+@pytest.mark.parametrize("kw,frag", [
+    (dict(connectivity=6), "connectivity"),
+    (dict(seam_connectivity=5), "seam_connectivity"),
+    (dict(spclust_wght=1.5), "spclust_wght"),
+    (dict(spclust_wght=float("nan")), "spclust_wght"),
+    (dict(spclust_max=70000), "spclust_max"),
+    (dict(target_regions=0, level_counts=[0]), "target_regions"),
+    (dict(level_counts=[2, 8]), "decreasing"),
+    (dict(level_counts=[8, 4]), "last level"),
+    (dict(level_counts=[8, 1]), "below target"),
+    (dict(section_regions=-1), "section_regions"),
+    (dict(precision=7), "precision"),
+])
+def test_invalid_params_rejected_before_device(kw, frag):
+    p = dict(BASE)
+    p.update(kw)
+    params = hswo.make_params(**p)
+    assert hswo.workspace_bytes(64, 64, 32, 0, params) == 0
+    lib = hswo.load()
+    rc = lib.hswo_run(FAKE, 64, 64, 32, 0, ctypes.byref(params), FAKE, None, None, FAKE, 1 << 30, None)
+    assert rc == hswo.HSWO_E_INVAL
+    assert frag in hswo.last_error()
+
+
+@pytest.mark.parametrize("H,W,B,dtype", [(0, 4, 3, 0), (4, -1, 3, 0), (4, 4, 0, 0), (4, 4, 5000, 0),
+                                         (4, 4, 3, 9), (65536, 32768, 1, 0)])
+def test_invalid_shapes_rejected(H, W, B, dtype):
+    params = hswo.make_params(**BASE)
+    lib = hswo.load()
+    rc = lib.hswo_run(FAKE, H, W, B, dtype, ctypes.byref(params), FAKE, None, None, FAKE, 1 << 30, None)
+    assert rc == hswo.HSWO_E_INVAL
+
+
+def test_pointer_and_workspace_checks():
+    lib = hswo.load()
+    params = hswo.make_params(**BASE)
+    nb = hswo.workspace_bytes(16, 16, 4, 0, params)
+    assert lib.hswo_run(None, 16, 16, 4, 0, ctypes.byref(params), FAKE, None, None, FAKE, nb, None) == hswo.HSWO_E_INVAL
+    assert lib.hswo_run(FAKE + 4, 16, 16, 4, 0, ctypes.byref(params), FAKE, None, None, FAKE, nb, None) == hswo.HSWO_E_INVAL
+    assert "aligned" in hswo.last_error()
+    assert lib.hswo_run(FAKE, 16, 16, 4, 0, ctypes.byref(params), FAKE, None, None, None, nb, None) == hswo.HSWO_E_INVAL
+    assert lib.hswo_run(FAKE, 16, 16, 4, 0, ctypes.byref(params), FAKE, None, None, FAKE, nb - 1, None) == hswo.HSWO_E_NOMEM
+    assert "workspace too small" in hswo.last_error()
+    # merge-log flag without a log buffer
+    p2 = hswo.make_params(**BASE, merge_log=True)
+    assert lib.hswo_run(FAKE, 16, 16, 4, 0, ctypes.byref(p2), FAKE, None, None, FAKE, nb, None) == hswo.HSWO_E_INVAL
+
+
+def test_rhseg_levels_checked():
+    lib = hswo.load()
+    p = hswo.make_params(**dict(BASE, rnb_levels=3))
+    # 4 x 4 image cannot hold 4^(3-1) non-empty leaves along... it can (1x1 leaves); 3 x 3 cannot
+    assert lib.rhseg_segment(FAKE, 3, 3, 2, 0, ctypes.byref(p), 3, FAKE, None, None, FAKE, 1 << 30, None) == hswo.HSWO_E_INVAL
+    assert lib.rhseg_segment(FAKE, 8, 8, 2, 0, ctypes.byref(p), 2, FAKE, None, None, FAKE, 1 << 30, None) == hswo.HSWO_E_INVAL
+    assert "rnb_levels" in hswo.last_error()
+    p1 = hswo.make_params(**BASE)
+    assert lib.hswo_run(FAKE, 8, 8, 2, 0, ctypes.byref(p), FAKE, None, None, FAKE, 1 << 30, None) == hswo.HSWO_E_INVAL
