@@ -116,7 +116,9 @@ typedef struct hswo_stats {
     int64_t spectral_pairs;      /* unordered pairs screened in the spectral stage */
     int64_t exact_rechecks;      /* pairs re-scored in canonical FP64 */
     int64_t tile_rescans;        /* spectral tiles re-screened to collect candidates */
+    int64_t driver_launches;     /* launches of the section-driver kernel */
     double ms_total;             /* device time of the call (hipEvents), ms */
+    double ms_driver;            /* device time inside section-driver launches (hipEvents), ms */
 } hswo_stats;
 
 /* One independent section for hswo_run_batch. */

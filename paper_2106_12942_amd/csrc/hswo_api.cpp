@@ -282,11 +282,28 @@ Layout carve(const Plan& pl, int H, int W, const hswo_params* p, void* ws, const
 
 struct Timer {
     hipEvent_t a = nullptr, b = nullptr;
+    std::vector<hipEvent_t> drv;  // pairs around each section-driver launch
     ~Timer() {
         if (a) (void)hipEventDestroy(a);
         if (b) (void)hipEventDestroy(b);
+        for (hipEvent_t e : drv) (void)hipEventDestroy(e);
     }
 };
+
+// Launch the section driver, bracketed by events when timing is on.
+int timed_driver(Timer* tm, const SecDev* secs, int n, const LoopParams& lp, hipStream_t stream) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (tm) {
+        HIP_TRY(hipEventCreate(&e0));
+        tm->drv.push_back(e0);
+        HIP_TRY(hipEventCreate(&e1));
+        tm->drv.push_back(e1);
+        HIP_TRY(hipEventRecord(e0, stream));
+    }
+    HIP_TRY(launch_section_driver(secs, n, lp, stream));
+    if (tm) HIP_TRY(hipEventRecord(e1, stream));
+    return HSWO_OK;
+}
 
 int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_params* p, int L, int32_t* labels,
               hswo_merge_rec* merge_log, hswo_stats* stats, void* workspace, size_t ws_bytes,
@@ -358,7 +375,8 @@ int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_param
         int maxpix = 0;
         for (const SecPlan& s : pl.lv[d]) maxpix = std::max<int>(maxpix, (int)s.cap);
         HIP_TRY(launch_init_leaves(lay.lv[d].secs, lay.lv[d].inits, (int)pl.lv[d].size(), dtype, maxpix, stream));
-        HIP_TRY(launch_section_driver(lay.lv[d].secs, (int)pl.lv[d].size(), lp, stream));
+        rc = timed_driver(stats ? &tm : nullptr, lay.lv[d].secs, (int)pl.lv[d].size(), lp, stream);
+        if (rc) return rc;
     }
     for (int d = L - 2; d >= 0; --d) {
         const auto& secs = pl.lv[d];
@@ -372,7 +390,8 @@ int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_param
         HIP_TRY(launch_assemble(lay.lv[d].secs, lay.lv[d + 1].secs, lay.lv[d].asms, (int)secs.size(), lay.slotmap,
                                 (int)std::min<int64_t>(maxcap, 1 << 30), stream));
         HIP_TRY(launch_seam(lay.lv[d].secs, lay.lv[d].asms, (int)secs.size(), lay.slotmap, (int)maxseam, stream));
-        HIP_TRY(launch_section_driver(lay.lv[d].secs, (int)secs.size(), lp, stream));
+        rc = timed_driver(stats ? &tm : nullptr, lay.lv[d].secs, (int)secs.size(), lp, stream);
+        if (rc) return rc;
     }
     HIP_TRY(launch_snapshot(lay.snap, 1, lay.counts, p->n_levels, (int)P, stream));
 
@@ -390,6 +409,14 @@ int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_param
         stats->exact_rechecks = (int64_t)c[C_RECHECKS];
         stats->tile_rescans = (int64_t)c[C_RESCANS];
         stats->ms_total = ms;
+        double md = 0.0;
+        for (size_t k = 0; k + 1 < tm.drv.size(); k += 2) {
+            float x = 0.f;
+            HIP_TRY(hipEventElapsedTime(&x, tm.drv[k], tm.drv[k + 1]));
+            md += x;
+        }
+        stats->ms_driver = md;
+        stats->driver_launches = (int64_t)(tm.drv.size() / 2);
     }
     return HSWO_OK;
 }

@@ -59,7 +59,9 @@ class Stats(ctypes.Structure):
         ("spectral_pairs", ctypes.c_int64),
         ("exact_rechecks", ctypes.c_int64),
         ("tile_rescans", ctypes.c_int64),
+        ("driver_launches", ctypes.c_int64),
         ("ms_total", ctypes.c_double),
+        ("ms_driver", ctypes.c_double),
     ]
 
     def as_dict(self):
