@@ -61,7 +61,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rhseg512", choices=sorted(WORKLOAD_DESC))
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
+    ap.add_argument("--precision", default="fp16", choices=["fp32", "bf16", "fp16"],
+                    help="screen of the spectral stage for the timed steps (fp32 = plain path)")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -124,7 +126,17 @@ def main():
                 "avg_launch_ms": round(avg_launch_ms, 4),
                 "algorithmic_flops_per_launch": flops_per_launch}
 
+    stage_ms = {k: round(st[k], 2) for k in ("ms_adjacent", "ms_mfma_screen", "ms_fp32_spectral", "ms_merge")}
     labels = res.labels.cpu().numpy()
+    plain = None
+    if args.precision != "fp32" and not args.no_plain:
+        # the plain FP32 path on the same input, for the precision form's speed-up
+        ts = time.perf_counter()
+        rp = hswo.rhseg_segment(cube, rnb_levels=L, precision="fp32", stats=True, **kw)
+        plain_ms = (time.perf_counter() - ts) * 1e3
+        plain = {"ms_per_step": plain_ms, "speedup_of_timed_form": plain_ms / ms_per_step,
+                 "labels_identical_to_timed_form": bool(np.array_equal(rp.labels.cpu().numpy(), labels)),
+                 "stage_ms": {k: round(rp.stats[k], 2) for k in stage_ms}}
     out = {
         "metric": "RHSEG wall time + dissimilarity pairs/s, MFMA+batched vs plain, same labels",
         "value": value,
@@ -142,11 +154,17 @@ def main():
         "dtype": "f32 screen + f64 decisions",
         "data": "synthetic",
         "config": {"workload": args.workload, "desc": WORKLOAD_DESC[args.workload], "H": H, "W": W, "B": B,
-                   "precision": args.precision, "form": "plain per-level section driver"},
+                   "precision": args.precision,
+                   "form": "per-level section driver, " + ("plain FP32 screen" if args.precision == "fp32" else
+                                                           f"{args.precision} matrix-core spectral screen")},
         "pairs_per_step": pairs,
         "merges_per_step": st["merges"],
         "exact_rechecks_per_step": st["exact_rechecks"],
         "roofline": roofline,
+        "stage_ms_summed_over_sections": stage_ms,
+        "fp32_tiles_per_step": st["fp32_tiles"],
+        "mfma_super_tiles_per_step": st["mfma_tiles"],
+        "plain_fp32": plain,
     }
 
     if not args.no_cpu_baseline:

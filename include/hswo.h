@@ -116,9 +116,15 @@ typedef struct hswo_stats {
     int64_t spectral_pairs;      /* unordered pairs screened in the spectral stage */
     int64_t exact_rechecks;      /* pairs re-scored in canonical FP64 */
     int64_t tile_rescans;        /* spectral tiles re-screened to collect candidates */
+    int64_t fp32_tiles;          /* 64 x 64 spectral tiles screened in FP32 */
+    int64_t mfma_tiles;          /* 128 x 128 super tiles screened on matrix cores (16-bit forms) */
     int64_t driver_launches;     /* launches of the section-driver kernel */
     double ms_total;             /* device time of the call (hipEvents), ms */
     double ms_driver;            /* device time inside section-driver launches (hipEvents), ms */
+    /* per-stage time inside the merge loop, summed over sections (device
+       constant clock), ms: adjacent stage, matrix-core screen, FP32
+       spectral tiles with the exact re-check, merge */
+    double ms_adjacent, ms_mfma_screen, ms_fp32_spectral, ms_merge;
 } hswo_stats;
 
 /* One independent section for hswo_run_batch. */

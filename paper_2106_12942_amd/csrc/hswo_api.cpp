@@ -246,7 +246,18 @@ Layout carve(const Plan& pl, int H, int W, const hswo_params* p, void* ws, const
             s.edges = bp.take<int2>(sp.ecap);
             s.escr = bp.take<float2>(sp.ecap);
             s.tstat = bp.take<float2>(sp.tiles);
-            s.st = bp.take<int32_t>(4);
+            s.tflag = bp.take<int32_t>(sp.tiles);
+            if (p->precision != HSWO_PREC_FP32 && p->spclust_wght > 0.0f && p->spclust_max > 0) {
+                const int64_t kc = std::min<int64_t>(sp.cap, p->spclust_max);
+                s.kcap = (int32_t)kc;
+                s.g16 = bp.take<uint16_t>(kc * pl.Bp);
+                s.gn = bp.take<float>(kc);
+                s.geta = bp.take<float>(kc);
+                s.galpha = bp.take<float>(kc);
+                s.gP = bp.take<float>(kc);
+                s.cvec = bp.take<float>(pl.Bp);
+            }
+            s.st = bp.take<int32_t>(ST_WORDS);
             s.parent = lay.parent;
             s.mtime = lay.mtime;
             s.log = log ? log + log_base : nullptr;
@@ -317,8 +328,6 @@ int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_param
     if ((H >> (L - 1)) < 1 || (W >> (L - 1)) < 1)
         return fail(HSWO_E_INVAL, "rnb_levels=%d leaves empty sections for %dx%d", L, H, W);
     if ((p->flags & HSWO_FLAG_MERGE_LOG) && !merge_log) return fail(HSWO_E_INVAL, "MERGE_LOG flag needs merge_log");
-    if (p->precision != HSWO_PREC_FP32)
-        return fail(HSWO_E_UNSUPPORTED, "precision %d is not available in this build", p->precision);
     if (!workspace) return fail(HSWO_E_INVAL, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(HSWO_E_INVAL, "workspace must be 256-byte aligned");
 
@@ -408,6 +417,8 @@ int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_param
         stats->spectral_pairs = (int64_t)c[C_SPEC_PAIRS];
         stats->exact_rechecks = (int64_t)c[C_RECHECKS];
         stats->tile_rescans = (int64_t)c[C_RESCANS];
+        stats->fp32_tiles = (int64_t)c[C_FP32_TILES];
+        stats->mfma_tiles = (int64_t)c[C_MFMA_TILES];
         stats->ms_total = ms;
         double md = 0.0;
         for (size_t k = 0; k + 1 < tm.drv.size(); k += 2) {
@@ -416,6 +427,14 @@ int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_param
             md += x;
         }
         stats->ms_driver = md;
+        int dev = 0, khz = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+        const double tick_ms = khz > 0 ? 1.0 / (double)khz : 1e-5;  // device constant clock
+        stats->ms_adjacent = (double)c[C_T_ADJ] * tick_ms;
+        stats->ms_mfma_screen = (double)c[C_T_MFMA] * tick_ms;
+        stats->ms_fp32_spectral = (double)c[C_T_SPEC32] * tick_ms;
+        stats->ms_merge = (double)c[C_T_MERGE] * tick_ms;
         stats->driver_launches = (int64_t)(tm.drv.size() / 2);
     }
     return HSWO_OK;

@@ -26,8 +26,17 @@ enum Counter {
     C_SPEC_PAIRS,
     C_RECHECKS,
     C_RESCANS,
+    C_FP32_TILES,   // spectral tiles screened in FP32 (all of them on the plain path)
+    C_MFMA_TILES,   // 128 x 128 super tiles screened on matrix cores
+    C_T_ADJ,        // 100 MHz ticks in the adjacent stage (screen + exact), summed over sections
+    C_T_MFMA,       // ... matrix-core screen (row build, row terms, tiles)
+    C_T_SPEC32,     // ... FP32 spectral tiles + exact re-check
+    C_T_MERGE,      // ... merge
     C_COUNT
 };
+
+constexpr int ST_WORDS = 8;   // per-section state words
+constexpr int STILE = 128;    // matrix-core super tile edge (4 spectral tiles)
 
 // One section of one recursion level (or one independent batch section).
 struct SecDev {
@@ -48,7 +57,17 @@ struct SecDev {
     int2* edges;     // [Ecap] adjacent slot pairs
     float2* escr;    // [Ecap] per-edge screen bounds (lower, upper)
     float2* tstat;   // [tiles] per-tile bounds (min lower, min upper)
-    int32_t* st;     // state: [0] R, [1] E, [2] R at pass start, [3] merges done
+    int32_t* tflag;  // [tiles] matrix-core screen: tile may hold a pair below the threshold
+    // 16-bit screen rows (precision forms only), slots [0, kcap):
+    uint16_t* g16;   // [kcap][Bp] round16(mean - c), zero padded
+    float* gn;       // [kcap] sum of squares of the 16-bit row (FP32, from an FP64 sum)
+    float* geta;     // [kcap] bound on || g16 row - (true mean - c) ||_2
+    float* galpha;   // [kcap] per-iteration sqrt(T / n) + eta
+    float* gP;       // [kcap] per-iteration (1 - kappa) * gn - alpha^2
+    float* cvec;     // [Bp] centring spectrum, fixed when the spectral stage starts
+    int32_t kcap;    // rows available for the 16-bit screen (0 on the plain path)
+    int32_t pad1;
+    int32_t* st;     // state: [0] R, [1] E, [2] R at pass start, [3] merges done, [4] 16-bit rows ready
     int32_t* parent; // label-indexed union-find parent (image or batch section)
     int32_t* mtime;  // label-indexed merge time: -1 non-top merge, k top merge, INT_MAX alive
     hswo_merge_rec* log;  // section merge log base (may be null)

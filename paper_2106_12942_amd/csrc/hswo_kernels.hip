@@ -44,6 +44,38 @@ namespace {
 
 constexpr float U32 = 5.9604645e-08f;  // 2^-24, unit roundoff of FP32
 
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+// 16-bit screen formats: PREC 1 = bfloat16, PREC 2 = float16 (round to nearest even)
+template <int PREC>
+struct Fmt16;
+template <>
+struct Fmt16<1> {
+    typedef bf16x8 V;
+    static constexpr double U = 0x1p-8;     // unit roundoff
+    static constexpr double SUB = 0x1p-133; // largest rounding error below the normal range
+    static __device__ __forceinline__ uint16_t enc(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+    static __device__ __forceinline__ float dec(uint16_t h) { return (float)__builtin_bit_cast(__bf16, h); }
+    static __device__ __forceinline__ f32x16 mfma(V a, V b, f32x16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct Fmt16<2> {
+    typedef f16x8 V;
+    static constexpr double U = 0x1p-11;
+    static constexpr double SUB = 0x1p-25;
+    static __device__ __forceinline__ uint16_t enc(float x) { return __builtin_bit_cast(uint16_t, (_Float16)x); }
+    static __device__ __forceinline__ float dec(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
+    static __device__ __forceinline__ f32x16 mfma(V a, V b, f32x16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+constexpr int G16_LD = 40;  // LDS row stride (elements) of the 16-bit operand tiles
+
 struct KeyD {
     double d2;
     int lo, hi;  // labels, lo < hi
@@ -69,8 +101,17 @@ __device__ __forceinline__ bool key_less(const KeyD& a, const KeyD& b) {
 __device__ __forceinline__ bool key_exists(const KeyD& k) { return k.lo != INT_MAX; }
 
 struct Smem {
-    float As[BK][TILE + 4];
-    float Cs[BK][TILE + 4];
+    union {
+        struct {
+            float As[BK][TILE + 4];
+            float Cs[BK][TILE + 4];
+        } f;
+        struct {
+            uint16_t A[STILE][G16_LD];
+            uint16_t C[STILE][G16_LD];
+            float Prow[STILE], Arow[STILE], Pcol[STILE], Acol[STILE];
+        } g;
+    } u;
     int cand[CAND_CAP];
     float redf[2][NWAVE];
     int redi[NWAVE];
@@ -300,19 +341,19 @@ __device__ void tile_sums_fp32(Smem& sh, const SecDev& s, int ib, int jb, int R,
         float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vc = va;
         if (ia < R) va = *reinterpret_cast<const float4*>(s.mean + (size_t)ia * s.Bp + k0 + lb);
         if (ic < R) vc = *reinterpret_cast<const float4*>(s.mean + (size_t)ic * s.Bp + k0 + lb);
-        sh.As[lb + 0][lrow] = va.x;
-        sh.As[lb + 1][lrow] = va.y;
-        sh.As[lb + 2][lrow] = va.z;
-        sh.As[lb + 3][lrow] = va.w;
-        sh.Cs[lb + 0][lrow] = vc.x;
-        sh.Cs[lb + 1][lrow] = vc.y;
-        sh.Cs[lb + 2][lrow] = vc.z;
-        sh.Cs[lb + 3][lrow] = vc.w;
+        sh.u.f.As[lb + 0][lrow] = va.x;
+        sh.u.f.As[lb + 1][lrow] = va.y;
+        sh.u.f.As[lb + 2][lrow] = va.z;
+        sh.u.f.As[lb + 3][lrow] = va.w;
+        sh.u.f.Cs[lb + 0][lrow] = vc.x;
+        sh.u.f.Cs[lb + 1][lrow] = vc.y;
+        sh.u.f.Cs[lb + 2][lrow] = vc.z;
+        sh.u.f.Cs[lb + 3][lrow] = vc.w;
         __syncthreads();
 #pragma unroll 8
         for (int kk = 0; kk < BK; ++kk) {
-            const float4 a = *reinterpret_cast<const float4*>(&sh.As[kk][ty * 4]);
-            const float2 c = *reinterpret_cast<const float2*>(&sh.Cs[kk][tx * 2]);
+            const float4 a = *reinterpret_cast<const float4*>(&sh.u.f.As[kk][ty * 4]);
+            const float2 c = *reinterpret_cast<const float2*>(&sh.u.f.Cs[kk][tx * 2]);
             float d;
             d = a.x - c.x; acc[0][0] = fmaf(d, d, acc[0][0]);
             d = a.x - c.y; acc[0][1] = fmaf(d, d, acc[0][1]);
@@ -327,10 +368,166 @@ __device__ void tile_sums_fp32(Smem& sh, const SecDev& s, int ib, int jb, int R,
     }
 }
 
+// ---------------------------------------------------------------------------
+// 16-bit matrix-core screen of the spectral stage (precision forms).
+//
+// Rows are centred by a section-wide spectrum c and rounded to 16 bits:
+// g_i = round16(fl32(m_i - c)). With N_i = ||g_i||^2 and G_ij = g_i . g_j,
+// ||g_i - g_j||^2 = N_i + N_j - 2 G_ij, and the true mean difference d_ij
+// satisfies | ||d_ij|| - ||g_i - g_j|| | <= eta_i + eta_j, where eta_i bounds
+// ||g_i - (mu_i - c)||: 16-bit rounding u16 ||m_i - c||, the FP32 centring
+// rounding, the FP32 mean rounding ~u32 ||m_i||, and sub-normal spacing.
+//
+// D2 = n_i n_j/(n_i+n_j) ||d||^2 < T implies ||d|| < sqrt(T/n_i + T/n_j)
+// <= sqrt(T/n_i) + sqrt(T/n_j), hence ||g_i - g_j|| < alpha_i + alpha_j with
+// alpha_i = sqrt(T/n_i) + eta_i. With the FP32 accumulation error of the
+// matrix core and of the combination bounded by kappa (N_i + N_j), every pair
+// with D2 < T satisfies
+//     (1-kappa)(N_i + N_j) - (alpha_i + alpha_j)^2 < 2 G_ij,
+// i.e. P_i + P_j - 2 alpha_i alpha_j < 2 G_ij with P_i = (1-kappa) N_i - alpha_i^2
+// (rounded down) and alpha rounded up. A 64 x 64 tile in which no pair passes
+// this test holds no pair that can beat T, so only the tiles that pass go on
+// to the FP32 screen and the FP64 re-check: the merge chosen is unchanged.
+// ---------------------------------------------------------------------------
+
+// One wavefront rebuilds the 16-bit row of slot i and its N and eta.
+template <int PREC>
+__device__ void row16(const SecDev& s, int i) {
+    typedef Fmt16<PREC> F;
+    const int lane = lane_id();
+    const float* m = s.mean + (size_t)i * s.Bp;
+    uint16_t* g = s.g16 + (size_t)i * s.Bp;
+    double sq = 0.0, an = 0.0, mn = 0.0;
+    for (int b = lane; b < s.Bp; b += 64) {
+        const float mv = m[b];
+        const float ac = mv - s.cvec[b];
+        const uint16_t hv = F::enc(ac);
+        const double gv = (double)F::dec(hv);
+        g[b] = hv;
+        sq += gv * gv;
+        an += (double)ac * (double)ac;
+        mn += (double)mv * (double)mv;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        sq += __shfl_xor(sq, o);
+        an += __shfl_xor(an, o);
+        mn += __shfl_xor(mn, o);
+    }
+    if (lane == 0) {
+        s.gn[i] = (float)sq;
+        const double eta = (F::U + 0x1p-23) * sqrt(an) + 0x1.02p-24 * sqrt(mn) + F::SUB * sqrt((double)s.Bp);
+        s.geta[i] = (float)(eta * (1.0 + 0x1p-20));
+    }
+}
+
+// When the spectral stage starts: fix the centring spectrum (band means of
+// the live rows) and build every live row.
+template <int PREC>
+__device__ void build16_all(const SecDev& s, int R) {
+    const int tid = threadIdx.x;
+    for (int b = tid; b < s.Bp; b += NT) {
+        double acc = 0.0;
+        for (int i = 0; i < R; ++i) acc += (double)s.mean[(size_t)i * s.Bp + b];
+        s.cvec[b] = b < s.B ? (float)(acc / (double)R) : 0.0f;
+    }
+    __syncthreads();
+    for (int i = wave_id(); i < R; i += NWAVE) row16<PREC>(s, i);
+    __syncthreads();
+}
+
+// Per-iteration row terms of the tile test for threshold T.
+__device__ void prep_alpha_p(const SecDev& s, int R, double T) {
+    const double kappa = (2.0 * s.Bp + 64.0) * 0x1p-24;
+    for (int i = threadIdx.x; i < R; i += NT) {
+        const double a = (sqrt(T / (double)s.npix[i]) + (double)s.geta[i]) * (1.0 + 0x1p-20);
+        const float af = (float)(a * (1.0 + 0x1p-22));
+        const double P = (1.0 - kappa) * (double)s.gn[i] - (double)af * (double)af * (1.0 + 0x1p-20);
+        s.galpha[i] = af;
+        s.gP[i] = (float)(P - fabs(P) * 0x1p-21);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int tile_index(int ib, int jb, int nT) { return ib * nT - ib * (ib - 1) / 2 + (jb - ib); }
+
+// Matrix-core pass over all 128 x 128 super tiles of pairs i < j < R: sets
+// tflag of every 64 x 64 tile holding a pair that passes the test above.
+// Wave w computes rows 32*(w>>1) .. +31 and columns 64*(w&1) .. +63 of the
+// super tile, which lie in exactly one 64 x 64 tile.
+template <int PREC>
+__device__ int mfma_screen(Smem& sh, const SecDev& s, int R) {
+    typedef Fmt16<PREC> F;
+    typedef typename F::V V;
+    const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
+    const int wi = w >> 1, wj = w & 1;
+    const int nT = (R + TILE - 1) / TILE, nS = (R + STILE - 1) / STILE;
+    const int ntiles = nT * (nT + 1) / 2;
+    for (int t = tid; t < ntiles; t += NT) s.tflag[t] = 0;
+    const int lrow = tid >> 2, lseg = (tid & 3) * 8;
+    int nsup = 0;
+    for (int IB = 0; IB < nS; ++IB)
+        for (int JB = IB; JB < nS; ++JB) {
+            ++nsup;
+            __syncthreads();  // previous tile's LDS reads are done
+            if (tid < STILE) {
+                const int r = IB * STILE + tid;
+                sh.u.g.Prow[tid] = r < R ? s.gP[r] : 0.0f;
+                sh.u.g.Arow[tid] = r < R ? s.galpha[r] : 0.0f;
+            } else if (tid < 2 * STILE) {
+                const int c = JB * STILE + tid - STILE;
+                sh.u.g.Pcol[tid - STILE] = c < R ? s.gP[c] : 0.0f;
+                sh.u.g.Acol[tid - STILE] = c < R ? s.galpha[c] : 0.0f;
+            }
+            f32x16 acc0 = {}, acc1 = {};
+            const int ra = IB * STILE + lrow, rc = JB * STILE + lrow;
+            for (int k0 = 0; k0 < s.Bp; k0 += 32) {
+                uint4 va = make_uint4(0u, 0u, 0u, 0u), vc = va;
+                if (ra < R) va = *reinterpret_cast<const uint4*>(s.g16 + (size_t)ra * s.Bp + k0 + lseg);
+                if (rc < R) vc = *reinterpret_cast<const uint4*>(s.g16 + (size_t)rc * s.Bp + k0 + lseg);
+                *reinterpret_cast<uint4*>(&sh.u.g.A[lrow][lseg]) = va;
+                *reinterpret_cast<uint4*>(&sh.u.g.C[lrow][lseg]) = vc;
+                __syncthreads();
+#pragma unroll
+                for (int kk = 0; kk < 2; ++kk) {
+                    const int kc = kk * 16 + 8 * (lane >> 5);
+                    const V a = *reinterpret_cast<const V*>(&sh.u.g.A[32 * wi + (lane & 31)][kc]);
+                    const V b0 = *reinterpret_cast<const V*>(&sh.u.g.C[64 * wj + (lane & 31)][kc]);
+                    const V b1 = *reinterpret_cast<const V*>(&sh.u.g.C[64 * wj + 32 + (lane & 31)][kc]);
+                    acc0 = F::mfma(a, b0, acc0);
+                    acc1 = F::mfma(a, b1, acc1);
+                }
+                __syncthreads();
+            }
+            bool any = false;
+#pragma unroll
+            for (int sb = 0; sb < 2; ++sb) {
+                const int jl = 64 * wj + 32 * sb + (lane & 31);
+                const int gj = JB * STILE + jl;
+                const float Pj = sh.u.g.Pcol[jl], Aj = sh.u.g.Acol[jl];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int il = 32 * wi + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    const int gi = IB * STILE + il;
+                    const float g2 = 2.0f * (sb ? acc1[r] : acc0[r]);
+                    const float t = fmaf(-2.0f * sh.u.g.Arow[il], Aj, sh.u.g.Prow[il] + Pj);
+                    any = any || (gi < gj && gj < R && t < g2);
+                }
+            }
+            const unsigned long long ball = __ballot(any);
+            if (lane == 0 && ball) {
+                const int ti = 2 * IB + (wi >> 1), tj = 2 * JB + wj;
+                if (ti <= tj && tj < nT) s.tflag[tile_index(ti, tj, nT)] = 1;
+            }
+        }
+    __syncthreads();
+    return nsup;
+}
+
 // One merge (Section 4.1: the merged region replaces both). lo_s keeps the
 // region; the slot hi_s is freed and the last live slot R-1 moves into it.
 __device__ void merge_pair(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int& E, int stamp,
-                           int kind, double d2) {
+                           int kind, double d2, int g_ready, int prec) {
     const int tid = threadIdx.x;
     const int B = s.B, Bp = s.Bp;
     const int lo_l = s.label[lo_s], hi_l = s.label[hi_s];
@@ -348,6 +545,12 @@ __device__ void merge_pair(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R,
         nrm += (double)m * (double)m;
     }
     nrm = block_sum_d(sh, nrm);  // contains barriers: all reads of s.npix done
+    if (g_ready && wave_id() == 0) {  // keep the survivor's 16-bit screen row current
+        if (prec == 1)
+            row16<1>(s, lo_s);
+        else
+            row16<2>(s, lo_s);
+    }
     if (tid == 0) {
         s.npix[lo_s] = n_new;
         s.norm[lo_s] = (float)(sqrt(nrm) * (1.0 + 0x1p-20));
@@ -416,6 +619,15 @@ __device__ void merge_pair(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R,
             s.norm[hi_s] = s.norm[last];
             s.mark[hi_s] = s.mark[last];
         }
+        if (g_ready) {
+            const uint16_t* Gsrc = s.g16 + (size_t)last * Bp;
+            uint16_t* Gdst = s.g16 + (size_t)hi_s * Bp;
+            for (int b = tid; b < Bp; b += NT) Gdst[b] = Gsrc[b];
+            if (tid == 0) {
+                s.gn[hi_s] = s.gn[last];
+                s.geta[hi_s] = s.geta[last];
+            }
+        }
     }
     __syncthreads();
 }
@@ -433,13 +645,17 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
     const int tid = threadIdx.x;
     int R = s.st[0];
     int E = s.st[1];
+    int g_ready = s.st[4];
+    const int prec = s.kcap > 0 ? lp.precision : 0;
     const float gam = (float)(2 * s.B + 32) * U32;
-    unsigned long long c_adj = 0, c_spec = 0, c_chk = 0, c_resc = 0, c_it = 0;
+    unsigned long long c_adj = 0, c_spec = 0, c_chk = 0, c_resc = 0, c_it = 0, c_f32 = 0, c_mf = 0;
+    unsigned long long t_adj = 0, t_mf = 0, t_s32 = 0, t_mrg = 0;  // constant-clock ticks (thread 0)
     int stamp = 0;
     if (tid == 0) sh.ncand = 0;
     __syncthreads();
 
     while (R > s.stop) {
+        unsigned long long tk0 = wall_clock64();
         // ------------------------------------------------ adjacent stage
         float myU = __builtin_huge_valf();
         {
@@ -488,6 +704,9 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
         }
         flush_candidates(sh, s, A, nchk, true, CAND_CAP);
         c_adj += (unsigned long long)E;
+        unsigned long long tk1 = wall_clock64();
+        t_adj += tk1 - tk0;
+        tk0 = tk1;
 
         // ------------------------------------------------ spectral stage
         KeyD M = key_none();
@@ -496,10 +715,37 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
         if (spectral) {
             const int nT = (R + TILE - 1) / TILE;
             const int ty = tid >> 5, tx = tid & 31;
+            if (prec && !g_ready) {
+                if (prec == 1)
+                    build16_all<1>(s, R);
+                else
+                    build16_all<2>(s, R);
+                g_ready = 1;
+            }
+            // matrix-core pass: flags the tiles that may hold a pair below T
+            const bool use16 = prec && T < __builtin_huge_val();
+            if (use16) {
+                prep_alpha_p(s, R, T);
+                c_mf += (unsigned long long)(prec == 1 ? mfma_screen<1>(sh, s, R) : mfma_screen<2>(sh, s, R));
+            }
+            tk1 = wall_clock64();
+            t_mf += tk1 - tk0;
+            tk0 = tk1;
             float Us = __builtin_huge_valf();
             int t = 0;
             for (int ib = 0; ib < nT; ++ib)
                 for (int jb = ib; jb < nT; ++jb, ++t) {
+                    if (use16) {
+                        if (tid == 0) sh.bcast_i[1] = s.tflag[t];
+                        __syncthreads();
+                        const int fl = sh.bcast_i[1];
+                        __syncthreads();
+                        if (!fl) {
+                            if (tid == 0) s.tstat[t] = make_float2(__builtin_huge_valf(), __builtin_huge_valf());
+                            continue;  // block-uniform via LDS
+                        }
+                    }
+                    ++c_f32;
                     float acc[4][2];
                     tile_sums_fp32(sh, s, ib, jb, R, acc);
                     float mL = __builtin_huge_valf(), mU = __builtin_huge_valf();
@@ -554,6 +800,9 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
             flush_candidates(sh, s, M, nchk, false, CAND_CAP);
             c_spec += (unsigned long long)R * (unsigned long long)(R - 1) / 2ull;
             c_resc += (unsigned long long)nresc;
+            tk1 = wall_clock64();
+            t_s32 += tk1 - tk0;
+            tk0 = tk1;
         }
 
         // ------------------------------------------------ decision
@@ -572,14 +821,22 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
         c_it += 1ull;
 
         // ------------------------------------------------ merge
-        merge_pair(sh, s, win.si, win.sj, R, E, stamp, kind, win.d2);
+        merge_pair(sh, s, win.si, win.sj, R, E, stamp, kind, win.d2, g_ready, prec);
         ++stamp;
         --R;
+        t_mrg += wall_clock64() - tk0;
     }
     if (tid == 0) {
         s.st[0] = R;
         s.st[1] = E;
+        s.st[4] = g_ready;
         if (lp.counters) {
+            atomicAdd(&lp.counters[C_FP32_TILES], c_f32);
+            atomicAdd(&lp.counters[C_MFMA_TILES], c_mf);
+            atomicAdd(&lp.counters[C_T_ADJ], t_adj);
+            atomicAdd(&lp.counters[C_T_MFMA], t_mf);
+            atomicAdd(&lp.counters[C_T_SPEC32], t_s32);
+            atomicAdd(&lp.counters[C_T_MERGE], t_mrg);
             atomicAdd(&lp.counters[C_ITERS], c_it);
             atomicAdd(&lp.counters[C_MERGES], c_it);
             atomicAdd(&lp.counters[C_ADJ_PAIRS], c_adj);
@@ -678,6 +935,7 @@ __global__ void k_init_leaves(const SecDev* __restrict__ secs, const InitDev* __
         s.st[1] = (int)E0;
         s.st[2] = P;
         s.st[3] = 0;
+        s.st[4] = 0;
     }
 }
 
@@ -723,6 +981,7 @@ __global__ void k_assemble(const SecDev* __restrict__ parents, const SecDev* __r
             p.st[1] = 0;
             p.st[2] = 0;
             p.st[3] = 0;
+            p.st[4] = 0;
         }
         return;
     }
@@ -755,6 +1014,7 @@ __global__ void k_assemble(const SecDev* __restrict__ parents, const SecDev* __r
         p.st[1] = eoff[4];
         p.st[2] = off[4];
         p.st[3] = 0;
+        p.st[4] = 0;
     }
 }
 

@@ -59,9 +59,15 @@ class Stats(ctypes.Structure):
         ("spectral_pairs", ctypes.c_int64),
         ("exact_rechecks", ctypes.c_int64),
         ("tile_rescans", ctypes.c_int64),
+        ("fp32_tiles", ctypes.c_int64),
+        ("mfma_tiles", ctypes.c_int64),
         ("driver_launches", ctypes.c_int64),
         ("ms_total", ctypes.c_double),
         ("ms_driver", ctypes.c_double),
+        ("ms_adjacent", ctypes.c_double),
+        ("ms_mfma_screen", ctypes.c_double),
+        ("ms_fp32_spectral", ctypes.c_double),
+        ("ms_merge", ctypes.c_double),
     ]
 
     def as_dict(self):

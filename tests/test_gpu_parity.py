@@ -61,9 +61,13 @@ TINY = [
 ]
 
 
+PRECS = ["fp32", "bf16", "fp16"]
+
+
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("pi", range(len(TINY)))
 @pytest.mark.parametrize("kind", ["continuous", "integer"])
-def test_tiny_random_cubes(pi, kind):
+def test_tiny_random_cubes(pi, kind, prec):
     rng = np.random.default_rng(10 + pi)
     for trial in range(4):
         H, W = int(rng.integers(4, 14)), int(rng.integers(4, 14))
@@ -73,7 +77,7 @@ def test_tiny_random_cubes(pi, kind):
         p["target_regions"] = target
         p["level_counts"] = sorted({target, max(target, H * W // 2), max(target, H * W // 5)}, reverse=True)
         cube = synth.random_cube(H, W, B, seed=100 * pi + trial, kind=kind)
-        assert_parity(cube, p, tag=f"tiny pi={pi} kind={kind} trial={trial}")
+        assert_parity(cube, p, precision=prec, tag=f"tiny pi={pi} kind={kind} trial={trial}")
 
 
 def test_hswo_entry_point_matches():
@@ -82,28 +86,31 @@ def test_hswo_entry_point_matches():
     assert_parity(cube, p, entry="hswo", tag="hswo entry")
 
 
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("H,W,B,kmax", [(40, 37, 7, 600), (33, 65, 3, 1500), (70, 70, 16, 300)])
-def test_multi_tile_ragged(H, W, B, kmax):
+def test_multi_tile_ragged(H, W, B, kmax, prec):
     """Spectral stage over several 64-wide tiles with a ragged tail."""
     sc = synth.voronoi_scene(H, W, B, K=12, sigma=25.0, seed=H * W + B)
     p = dict(connectivity=4, seam_connectivity=8, spclust_wght=0.5, spclust_max=kmax, rnb_levels=1,
              target_regions=3, level_counts=[kmax, 64, 3])
-    assert_parity(sc.cube, p, tag=f"multi-tile {H}x{W}x{B} kmax={kmax}")
+    assert_parity(sc.cube, p, precision=prec, tag=f"multi-tile {H}x{W}x{B} kmax={kmax}")
 
 
-def test_float16_cube():
+@pytest.mark.parametrize("prec", PRECS)
+def test_float16_cube(prec):
     sc = synth.mixer_scene(48, 40, 24, K=10, sigma=25.0, seed=5, dtype="f16")
     p = dict(connectivity=4, seam_connectivity=8, spclust_wght=0.5, spclust_max=200, rnb_levels=2,
              section_regions=64, target_regions=4, level_counts=[200, 50, 4])
-    assert_parity(sc.cube, p, tag="f16 mixer")
+    assert_parity(sc.cube, p, precision=prec, tag="f16 mixer")
 
 
-def test_salt_ties():
+@pytest.mark.parametrize("prec", PRECS)
+def test_salt_ties(prec):
     """Identical salt spectra: exact zero-D2 ties decided by (lo, hi)."""
     sc = synth.mixer_scene(40, 40, 12, K=8, sigma=25.0, seed=7, salt=0.05)
     p = dict(connectivity=4, seam_connectivity=8, spclust_wght=0.5, spclust_max=400, rnb_levels=2,
              section_regions=100, target_regions=5, level_counts=[300, 40, 5])
-    assert_parity(sc.cube, p, tag="salt ties")
+    assert_parity(sc.cube, p, precision=prec, tag="salt ties")
 
 
 @pytest.mark.parametrize("H,W", [(1, 1), (1, 9), (7, 1), (2, 2)])
@@ -129,13 +136,18 @@ def test_deterministic_repeat():
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
-def test_workload_hswo64_full_parity():
+@pytest.mark.parametrize("prec", PRECS)
+def test_workload_hswo64_full_parity(prec):
     sc, p = synth.workload("hswo64")
-    stats = assert_parity(sc.cube, p, entry="hswo", tag="hswo64 full")
+    stats = assert_parity(sc.cube, p, entry="hswo", precision=prec, tag="hswo64 full")
     assert stats["merges"] == 64 * 64 - 2
+    if prec != "fp32":
+        assert stats["mfma_tiles"] > 0
 
 
-def test_workload_rhseg512_full_parity():
+@pytest.mark.parametrize("prec", PRECS)
+def test_workload_rhseg512_full_parity(prec):
     sc, p = synth.workload("rhseg512")
-    stats = assert_parity(sc.cube, p, tag="rhseg512 full")
+    stats = assert_parity(sc.cube, p, precision=prec, tag="rhseg512 full")
     assert stats["merges"] == 512 * 512 - 8
+    _say(f"[gpu] rhseg512 {prec}: {stats}")
