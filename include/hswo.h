@@ -43,10 +43,11 @@
  *
  * Conventions for every entry point:
  *   - Device pointers are HIP device memory of the current device. The cube
- *     and every output are owned by the caller. The library keeps no state
- *     between calls and allocates no device memory: the scratch it needs is
- *     the caller's `workspace`, at least hswo_workspace_bytes() bytes, 256-byte
- *     aligned.
+ *     and every output are owned by the caller. The library allocates no
+ *     device memory: the scratch it needs is the caller's `workspace`, at
+ *     least hswo_workspace_bytes() bytes, 256-byte aligned. Between calls it
+ *     keeps only the autotuner's choices and, with HSWO_FLAG_GRAPH, captured
+ *     graphs.
  *   - Work is enqueued on `hip_stream` (a hipStream_t; NULL = the null
  *     stream). Outputs are valid once that stream has completed. When `stats`
  *     is non-NULL the call synchronises the stream before returning to fill
@@ -86,6 +87,14 @@ extern "C" {
 
 /* flags */
 #define HSWO_FLAG_MERGE_LOG 1 /* fill merge_log (must be non-NULL) */
+#define HSWO_FLAG_GRAPH 2     /* capture the call's kernel sequence into a hipGraph on first use and
+                                 replay it on later calls with the same pointers, shapes and
+                                 parameters (needs a non-null stream); graphs are cached per
+                                 process (up to 16, oldest evicted) */
+#define HSWO_FLAG_AUTOTUNE 4  /* on the first call for a shape bucket, time every section-driver
+                                 variant on the call itself (all give identical results) and keep
+                                 the fastest; the choice is cached per process and appended to the
+                                 file named by the environment variable HSWO_TUNE_CACHE if set */
 
 typedef struct hswo_params {
     int32_t connectivity;       /* 4 or 8: pixel links inside a leaf section */
@@ -119,6 +128,7 @@ typedef struct hswo_stats {
     int64_t fp32_tiles;          /* 64 x 64 spectral tiles screened in FP32 */
     int64_t mfma_tiles;          /* 128 x 128 super tiles screened on matrix cores (16-bit forms) */
     int64_t driver_launches;     /* launches of the section-driver kernel */
+    int64_t driver_variant;      /* section-driver variant used (adjacent-stage edges in flight) */
     double ms_total;             /* device time of the call (hipEvents), ms */
     double ms_driver;            /* device time inside section-driver launches (hipEvents), ms */
     /* per-stage time inside the merge loop, summed over sections (device

@@ -8,7 +8,11 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -291,18 +295,43 @@ Layout carve(const Plan& pl, int H, int W, const hswo_params* p, void* ws, const
     return lay;
 }
 
+// ---------------------------------------------------------------------------
+// Execution. Every call is a set of descriptor uploads (always eager) and a
+// kernel sequence. The sequence runs eagerly, or is captured once into a
+// hipGraph and replayed (HSWO_FLAG_GRAPH); the section-driver variant is
+// chosen by the autotuner (HSWO_FLAG_AUTOTUNE) or from its cache.
+// ---------------------------------------------------------------------------
+struct Upload {
+    void* dst;
+    std::vector<char> bytes;
+};
+
+template <class T>
+void add_upload(std::vector<Upload>& ups, void* dst, const T* src, size_t n) {
+    Upload u;
+    u.dst = dst;
+    u.bytes.resize(sizeof(T) * n);
+    std::memcpy(u.bytes.data(), src, sizeof(T) * n);
+    ups.push_back(std::move(u));
+}
+
 struct Timer {
-    hipEvent_t a = nullptr, b = nullptr;
     std::vector<hipEvent_t> drv;  // pairs around each section-driver launch
     ~Timer() {
-        if (a) (void)hipEventDestroy(a);
-        if (b) (void)hipEventDestroy(b);
         for (hipEvent_t e : drv) (void)hipEventDestroy(e);
     }
 };
 
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
 // Launch the section driver, bracketed by events when timing is on.
-int timed_driver(Timer* tm, const SecDev* secs, int n, const LoopParams& lp, hipStream_t stream) {
+int timed_driver(Timer* tm, const SecDev* secs, int n, const LoopParams& lp, int variant, hipStream_t stream) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (tm) {
         HIP_TRY(hipEventCreate(&e0));
@@ -311,8 +340,227 @@ int timed_driver(Timer* tm, const SecDev* secs, int n, const LoopParams& lp, hip
         tm->drv.push_back(e1);
         HIP_TRY(hipEventRecord(e0, stream));
     }
-    HIP_TRY(launch_section_driver(secs, n, lp, stream));
+    HIP_TRY(launch_section_driver(secs, n, lp, variant, stream));
     if (tm) HIP_TRY(hipEventRecord(e1, stream));
+    return HSWO_OK;
+}
+
+using Seq = std::function<int(hipStream_t, Timer*, int)>;
+
+std::mutex g_mu;
+std::map<std::string, int> g_tune;
+bool g_tune_loaded = false;
+struct GraphEntry {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+};
+std::map<std::string, GraphEntry> g_graphs;
+std::vector<std::string> g_graph_fifo;
+constexpr size_t MAX_GRAPHS = 16;
+
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = getenv("HSWO_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char key[512];
+    int v;
+    while (fscanf(f, "%511s %d", key, &v) == 2) g_tune[key] = v;
+    fclose(f);
+}
+
+void tune_store_locked(const std::string& k, int v) {
+    g_tune[k] = v;
+    const char* path = getenv("HSWO_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s %d\n", k.c_str(), v);
+    fclose(f);
+}
+
+int bucket(int64_t x) {
+    int b = 0;
+    while ((int64_t)1 << b < x) ++b;
+    return b;
+}
+
+struct ExecOut {
+    unsigned long long counters[C_COUNT];
+    double ms_total = 0.0, ms_driver = 0.0;
+    int64_t driver_launches = 0;
+    int variant = 6;
+};
+
+int execute(const std::vector<Upload>& ups, const Seq& seq, const std::string& key, const std::string& tune_key,
+            int flags, hipStream_t stream, unsigned long long* d_counters, bool want_stats, ExecOut& out) {
+    if ((flags & HSWO_FLAG_GRAPH) && stream == nullptr)
+        return fail(HSWO_E_INVAL, "HSWO_FLAG_GRAPH needs a non-null stream (the null stream cannot be captured)");
+    for (const Upload& u : ups)
+        HIP_TRY(hipMemcpyAsync(u.dst, u.bytes.data(), u.bytes.size(), hipMemcpyHostToDevice, stream));
+
+    // driver variant: environment override, tuned value, tuning run, or default
+    int variant = 6;
+    bool have = false;
+    if (const char* ev = getenv("HSWO_DRIVER_VARIANT")) {
+        variant = atoi(ev);
+        have = true;
+    }
+    if (!have) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        tune_load_locked();
+        auto it = g_tune.find(tune_key);
+        if (it != g_tune.end()) {
+            variant = it->second;
+            have = true;
+        }
+    }
+    if (!have && (flags & HSWO_FLAG_AUTOTUNE)) {
+        // time every variant on this very problem; all write identical outputs
+        float best = 0.0f;
+        for (int v : DRIVER_VARIANTS) {
+            EventPair ev;
+            HIP_TRY(hipEventCreate(&ev.a));
+            HIP_TRY(hipEventCreate(&ev.b));
+            HIP_TRY(hipEventRecord(ev.a, stream));
+            int rc = seq(stream, nullptr, v);
+            if (rc) return rc;
+            HIP_TRY(hipEventRecord(ev.b, stream));
+            HIP_TRY(hipEventSynchronize(ev.b));
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
+            if (v == DRIVER_VARIANTS[0] || ms < best) {
+                best = ms;
+                variant = v;
+            }
+        }
+        std::lock_guard<std::mutex> lk(g_mu);
+        tune_store_locked(tune_key, variant);
+    }
+    out.variant = variant;
+
+    Timer tm;
+    EventPair tot;
+    if (want_stats) {
+        HIP_TRY(hipEventCreate(&tot.a));
+        HIP_TRY(hipEventCreate(&tot.b));
+        HIP_TRY(hipEventRecord(tot.a, stream));
+    }
+    if (flags & HSWO_FLAG_GRAPH) {
+        const std::string gk = key + "|v" + std::to_string(variant);
+        hipGraphExec_t exec = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            auto it = g_graphs.find(gk);
+            if (it != g_graphs.end()) exec = it->second.x;
+        }
+        if (!exec) {
+            GraphEntry ge;
+            HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+            const int rc = seq(stream, nullptr, variant);
+            const hipError_t ec = hipStreamEndCapture(stream, &ge.g);
+            if (rc) {
+                if (ge.g) (void)hipGraphDestroy(ge.g);
+                return rc;
+            }
+            if (ec != hipSuccess) return fail(HSWO_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+            HIP_TRY(hipGraphInstantiate(&ge.x, ge.g, nullptr, nullptr, 0));
+            exec = ge.x;
+            std::lock_guard<std::mutex> lk(g_mu);
+            if (g_graph_fifo.size() >= MAX_GRAPHS) {
+                GraphEntry old = g_graphs[g_graph_fifo.front()];
+                g_graphs.erase(g_graph_fifo.front());
+                g_graph_fifo.erase(g_graph_fifo.begin());
+                (void)hipGraphExecDestroy(old.x);
+                (void)hipGraphDestroy(old.g);
+            }
+            g_graphs[gk] = ge;
+            g_graph_fifo.push_back(gk);
+        }
+        HIP_TRY(hipGraphLaunch(exec, stream));
+    } else {
+        const int rc = seq(stream, want_stats ? &tm : nullptr, variant);
+        if (rc) return rc;
+    }
+    if (want_stats) {
+        HIP_TRY(hipEventRecord(tot.b, stream));
+        HIP_TRY(hipMemcpyAsync(out.counters, d_counters, sizeof(out.counters), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, tot.a, tot.b));
+        out.ms_total = ms;
+        double md = 0.0;
+        for (size_t k = 0; k + 1 < tm.drv.size(); k += 2) {
+            float x = 0.f;
+            HIP_TRY(hipEventElapsedTime(&x, tm.drv[k], tm.drv[k + 1]));
+            md += x;
+        }
+        out.driver_launches = (int64_t)(tm.drv.size() / 2);
+        // under a graph the launches are not bracketed individually
+        out.ms_driver = tm.drv.empty() ? ms : md;
+    }
+    return HSWO_OK;
+}
+
+int fill_stats(hswo_stats* st, const ExecOut& o, int64_t launches_if_graph) {
+    int dev = 0, khz = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    const double tick_ms = khz > 0 ? 1.0 / (double)khz : 1e-5;  // device constant clock
+    const unsigned long long* c = o.counters;
+    st->merges = (int64_t)c[C_MERGES];
+    st->iterations = (int64_t)c[C_ITERS];
+    st->adjacent_pairs = (int64_t)c[C_ADJ_PAIRS];
+    st->spectral_pairs = (int64_t)c[C_SPEC_PAIRS];
+    st->exact_rechecks = (int64_t)c[C_RECHECKS];
+    st->tile_rescans = (int64_t)c[C_RESCANS];
+    st->fp32_tiles = (int64_t)c[C_FP32_TILES];
+    st->mfma_tiles = (int64_t)c[C_MFMA_TILES];
+    st->driver_launches = o.driver_launches ? o.driver_launches : launches_if_graph;
+    st->driver_variant = o.variant;
+    st->ms_total = o.ms_total;
+    st->ms_driver = o.ms_driver;
+    st->ms_adjacent = (double)c[C_T_ADJ] * tick_ms;
+    st->ms_mfma_screen = (double)c[C_T_MFMA] * tick_ms;
+    st->ms_fp32_spectral = (double)c[C_T_SPEC32] * tick_ms;
+    st->ms_merge = (double)c[C_T_MERGE] * tick_ms;
+    return HSWO_OK;
+}
+
+std::string params_key(const hswo_params* p) {
+    std::string k = "c" + std::to_string(p->connectivity) + "s" + std::to_string(p->seam_connectivity) + "w" +
+                    std::to_string(p->spclust_wght) + "k" + std::to_string(p->spclust_max) + "t" +
+                    std::to_string(p->target_regions) + "S" + std::to_string(p->section_regions) + "L" +
+                    std::to_string(p->rnb_levels) + "P" + std::to_string(p->precision) + "F" +
+                    std::to_string(p->flags) + "l";
+    for (int l = 0; l < p->n_levels; ++l) k += std::to_string(p->level_counts[l]) + ",";
+    return k;
+}
+
+std::string ptr_key(const void* x) {
+    char b[32];
+    snprintf(b, sizeof(b), "%p", x);
+    return b;
+}
+
+LoopParams loop_params(const hswo_params* p, unsigned long long* counters) {
+    LoopParams lp;
+    lp.w2 = (double)p->spclust_wght * (double)p->spclust_wght;
+    lp.spectral = p->spclust_wght > 0.0f && p->spclust_max > 0 ? 1 : 0;
+    lp.kmax = p->spclust_max;
+    lp.precision = p->precision;
+    lp.pad = 0;
+    lp.counters = counters;
+    return lp;
+}
+
+int check_common(const hswo_params* p, void* workspace) {
+    if (!workspace) return fail(HSWO_E_INVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(HSWO_E_INVAL, "workspace must be 256-byte aligned");
+    if (p->flags & ~(HSWO_FLAG_MERGE_LOG | HSWO_FLAG_GRAPH | HSWO_FLAG_AUTOTUNE))
+        return fail(HSWO_E_INVAL, "unknown flags 0x%x", p->flags);
     return HSWO_OK;
 }
 
@@ -328,33 +576,23 @@ int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_param
     if ((H >> (L - 1)) < 1 || (W >> (L - 1)) < 1)
         return fail(HSWO_E_INVAL, "rnb_levels=%d leaves empty sections for %dx%d", L, H, W);
     if ((p->flags & HSWO_FLAG_MERGE_LOG) && !merge_log) return fail(HSWO_E_INVAL, "MERGE_LOG flag needs merge_log");
-    if (!workspace) return fail(HSWO_E_INVAL, "workspace is NULL");
-    if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(HSWO_E_INVAL, "workspace must be 256-byte aligned");
+    rc = check_common(p, workspace);
+    if (rc) return rc;
+    if (!(p->flags & HSWO_FLAG_MERGE_LOG)) merge_log = nullptr;
 
     const Plan pl = make_plan(H, W, B, p, L);
     Layout lay = carve(pl, H, W, p, workspace, cube, labels, merge_log);
     if (ws_bytes < lay.bytes)
         return fail(HSWO_E_NOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes, lay.bytes);
 
-    Timer tm;
-    if (stats) {
-        HIP_TRY(hipEventCreate(&tm.a));
-        HIP_TRY(hipEventCreate(&tm.b));
-        HIP_TRY(hipEventRecord(tm.a, stream));
-    }
     const int64_t P = (int64_t)H * W;
-    // descriptors
-    HIP_TRY(hipMemcpyAsync(lay.counts, p->level_counts, sizeof(int32_t) * p->n_levels, hipMemcpyHostToDevice, stream));
+    std::vector<Upload> ups;
+    add_upload(ups, lay.counts, p->level_counts, p->n_levels);
     for (int d = 0; d < L; ++d) {
-        LevelDev& lv = lay.lv[d];
-        HIP_TRY(hipMemcpyAsync(lv.secs, lv.h_secs.data(), sizeof(SecDev) * lv.h_secs.size(), hipMemcpyHostToDevice,
-                               stream));
-        if (!lv.h_asms.empty())
-            HIP_TRY(hipMemcpyAsync(lv.asms, lv.h_asms.data(), sizeof(AsmDev) * lv.h_asms.size(),
-                                   hipMemcpyHostToDevice, stream));
-        if (!lv.h_inits.empty())
-            HIP_TRY(hipMemcpyAsync(lv.inits, lv.h_inits.data(), sizeof(InitDev) * lv.h_inits.size(),
-                                   hipMemcpyHostToDevice, stream));
+        const LevelDev& lv = lay.lv[d];
+        add_upload(ups, lv.secs, lv.h_secs.data(), lv.h_secs.size());
+        if (!lv.h_asms.empty()) add_upload(ups, lv.asms, lv.h_asms.data(), lv.h_asms.size());
+        if (!lv.h_inits.empty()) add_upload(ups, lv.inits, lv.h_inits.data(), lv.h_inits.size());
     }
     SnapDev sd;
     sd.st = lay.lv[0].h_secs[0].st;
@@ -367,76 +605,218 @@ int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_param
     sd.h = H;
     sd.w = W;
     sd.label_w = W;
-    HIP_TRY(hipMemcpyAsync(lay.snap, &sd, sizeof(SnapDev), hipMemcpyHostToDevice, stream));
-    HIP_TRY(launch_fill_u64(lay.counters, C_COUNT, 0ull, stream));
+    add_upload(ups, lay.snap, &sd, 1);
+    const LoopParams lp = loop_params(p, lay.counters);
 
-    LoopParams lp;
-    lp.w2 = (double)p->spclust_wght * (double)p->spclust_wght;
-    lp.spectral = p->spclust_wght > 0.0f && p->spclust_max > 0 ? 1 : 0;
-    lp.kmax = p->spclust_max;
-    lp.precision = p->precision;
-    lp.pad = 0;
-    lp.counters = lay.counters;
-
-    HIP_TRY(launch_init_pixels(lay.parent, lay.mtime, P, stream));
-    {
-        const int d = L - 1;
-        int maxpix = 0;
-        for (const SecPlan& s : pl.lv[d]) maxpix = std::max<int>(maxpix, (int)s.cap);
-        HIP_TRY(launch_init_leaves(lay.lv[d].secs, lay.lv[d].inits, (int)pl.lv[d].size(), dtype, maxpix, stream));
-        rc = timed_driver(stats ? &tm : nullptr, lay.lv[d].secs, (int)pl.lv[d].size(), lp, stream);
-        if (rc) return rc;
-    }
-    for (int d = L - 2; d >= 0; --d) {
-        const auto& secs = pl.lv[d];
-        int64_t maxcap = 0, maxseam = 0;
-        for (const SecPlan& s : secs) {
-            maxcap = std::max(maxcap, std::max(s.cap, s.ecap));
-            maxseam = std::max(maxseam, (int64_t)(s.rect.w + 2 * s.rect.h));
-            HIP_TRY(launch_fill_u64(lay.lv[d].h_asms[&s - &secs[0]].hash, (size_t)s.hash_cap, ~0ull, stream));
+    const Seq seq = [&](hipStream_t st, Timer* tm, int variant) -> int {
+        HIP_TRY(launch_fill_u64(lay.counters, C_COUNT, 0ull, st));
+        HIP_TRY(launch_init_pixels(lay.parent, lay.mtime, P, st));
+        {
+            const int d = L - 1;
+            int maxpix = 0;
+            for (const SecPlan& s : pl.lv[d]) maxpix = std::max<int>(maxpix, (int)s.cap);
+            HIP_TRY(launch_init_leaves(lay.lv[d].secs, lay.lv[d].inits, (int)pl.lv[d].size(), dtype, maxpix, st));
+            const int r = timed_driver(tm, lay.lv[d].secs, (int)pl.lv[d].size(), lp, variant, st);
+            if (r) return r;
         }
-        HIP_TRY(launch_compress(lay.parent, P, stream));
-        HIP_TRY(launch_assemble(lay.lv[d].secs, lay.lv[d + 1].secs, lay.lv[d].asms, (int)secs.size(), lay.slotmap,
-                                (int)std::min<int64_t>(maxcap, 1 << 30), stream));
-        HIP_TRY(launch_seam(lay.lv[d].secs, lay.lv[d].asms, (int)secs.size(), lay.slotmap, (int)maxseam, stream));
-        rc = timed_driver(stats ? &tm : nullptr, lay.lv[d].secs, (int)secs.size(), lp, stream);
-        if (rc) return rc;
-    }
-    HIP_TRY(launch_snapshot(lay.snap, 1, lay.counts, p->n_levels, (int)P, stream));
-
-    if (stats) {
-        HIP_TRY(hipEventRecord(tm.b, stream));
-        unsigned long long c[C_COUNT];
-        HIP_TRY(hipMemcpyAsync(c, lay.counters, sizeof(c), hipMemcpyDeviceToHost, stream));
-        HIP_TRY(hipStreamSynchronize(stream));
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, tm.a, tm.b));
-        stats->merges = (int64_t)c[C_MERGES];
-        stats->iterations = (int64_t)c[C_ITERS];
-        stats->adjacent_pairs = (int64_t)c[C_ADJ_PAIRS];
-        stats->spectral_pairs = (int64_t)c[C_SPEC_PAIRS];
-        stats->exact_rechecks = (int64_t)c[C_RECHECKS];
-        stats->tile_rescans = (int64_t)c[C_RESCANS];
-        stats->fp32_tiles = (int64_t)c[C_FP32_TILES];
-        stats->mfma_tiles = (int64_t)c[C_MFMA_TILES];
-        stats->ms_total = ms;
-        double md = 0.0;
-        for (size_t k = 0; k + 1 < tm.drv.size(); k += 2) {
-            float x = 0.f;
-            HIP_TRY(hipEventElapsedTime(&x, tm.drv[k], tm.drv[k + 1]));
-            md += x;
+        for (int d = L - 2; d >= 0; --d) {
+            const auto& secs = pl.lv[d];
+            int64_t maxcap = 0, maxseam = 0;
+            for (size_t i = 0; i < secs.size(); ++i) {
+                const SecPlan& s = secs[i];
+                maxcap = std::max(maxcap, std::max(s.cap, s.ecap));
+                maxseam = std::max(maxseam, (int64_t)(s.rect.w + 2 * s.rect.h));
+                HIP_TRY(launch_fill_u64(lay.lv[d].h_asms[i].hash, (size_t)s.hash_cap, ~0ull, st));
+            }
+            HIP_TRY(launch_compress(lay.parent, P, st));
+            HIP_TRY(launch_assemble(lay.lv[d].secs, lay.lv[d + 1].secs, lay.lv[d].asms, (int)secs.size(), lay.slotmap,
+                                    (int)std::min<int64_t>(maxcap, 1 << 30), st));
+            HIP_TRY(launch_seam(lay.lv[d].secs, lay.lv[d].asms, (int)secs.size(), lay.slotmap, (int)maxseam, st));
+            const int r = timed_driver(tm, lay.lv[d].secs, (int)secs.size(), lp, variant, st);
+            if (r) return r;
         }
-        stats->ms_driver = md;
-        int dev = 0, khz = 0;
-        HIP_TRY(hipGetDevice(&dev));
-        HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
-        const double tick_ms = khz > 0 ? 1.0 / (double)khz : 1e-5;  // device constant clock
-        stats->ms_adjacent = (double)c[C_T_ADJ] * tick_ms;
-        stats->ms_mfma_screen = (double)c[C_T_MFMA] * tick_ms;
-        stats->ms_fp32_spectral = (double)c[C_T_SPEC32] * tick_ms;
-        stats->ms_merge = (double)c[C_T_MERGE] * tick_ms;
-        stats->driver_launches = (int64_t)(tm.drv.size() / 2);
+        HIP_TRY(launch_snapshot(lay.snap, 1, lay.counts, p->n_levels, (int)P, st));
+        return HSWO_OK;
+    };
+
+    const std::string key = "rhseg|" + ptr_key(cube) + ptr_key(labels) + ptr_key(merge_log) + ptr_key(workspace) +
+                            "|" + std::to_string(H) + "x" + std::to_string(W) + "x" + std::to_string(B) + "d" +
+                            std::to_string(dtype) + "|" + params_key(p);
+    int64_t maxcap = 0;
+    for (const auto& lv : pl.lv)
+        for (const SecPlan& s : lv) maxcap = std::max(maxcap, s.cap);
+    const std::string tkey = "gfx950:rhseg:B" + std::to_string(bucket(B)) + ":R" + std::to_string(bucket(maxcap)) +
+                             ":n" + std::to_string(bucket((int64_t)pl.lv[L - 1].size())) + ":P" +
+                             std::to_string(p->precision) + ":k" + std::to_string(bucket(p->spclust_max + 1));
+    ExecOut eo;
+    rc = execute(ups, seq, key, tkey, p->flags, stream, lay.counters, stats != nullptr, eo);
+    if (rc) return rc;
+    if (stats) return fill_stats(stats, eo, L);
+    return HSWO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batch of independent sections (each its own top pass), one persistent launch.
+// ---------------------------------------------------------------------------
+struct BatchLayout {
+    unsigned long long* counters = nullptr;
+    int32_t* counts = nullptr;
+    SecDev* secs = nullptr;      // section order
+    SecDev* secs_lpt = nullptr;  // longest-first order for the driver
+    InitDev* inits = nullptr;
+    SnapDev* snaps = nullptr;
+    std::vector<SecDev> h_secs, h_lpt;
+    std::vector<InitDev> h_inits;
+    std::vector<SnapDev> h_snaps;
+    int max_pixels = 0;
+    int64_t max_cap = 0;
+    int max_B = 0;
+    size_t bytes = 0;
+};
+
+BatchLayout carve_batch(int n, const hswo_section* sec, const hswo_params* p, void* ws) {
+    BatchLayout lay;
+    Bump bp;
+    bp.base = reinterpret_cast<char*>(ws);
+    lay.counters = bp.take<unsigned long long>(C_COUNT);
+    lay.counts = bp.take<int32_t>(p->n_levels);
+    lay.secs = bp.take<SecDev>(n);
+    lay.secs_lpt = bp.take<SecDev>(n);
+    lay.inits = bp.take<InitDev>(n);
+    lay.snaps = bp.take<SnapDev>(n);
+    lay.h_secs.resize(n);
+    lay.h_inits.resize(n);
+    lay.h_snaps.resize(n);
+    std::vector<double> work(n);
+    for (int i = 0; i < n; ++i) {
+        const hswo_section& q = sec[i];
+        const int64_t cap = (int64_t)q.H * q.W;
+        const int Bp = round_up(q.B, BK);
+        const int64_t ecap = std::max<int64_t>(1, grid_edges(q.H, q.W, p->connectivity));
+        const int64_t tiles = tiles_for(cap, p);
+        SecDev& s = lay.h_secs[i];
+        std::memset(&s, 0, sizeof(s));
+        s.R0 = (int32_t)cap;
+        s.B = q.B;
+        s.Bp = Bp;
+        s.Ecap = (int32_t)ecap;
+        s.stop = p->target_regions;
+        s.top = 1;
+        s.log_base = 0;
+        s.tiles = (int32_t)tiles;
+        s.label = bp.take<int32_t>(cap);
+        s.npix = bp.take<int32_t>(cap);
+        s.mark = bp.take<int32_t>(cap);
+        s.norm = bp.take<float>(cap);
+        s.sums = bp.take<double>(cap * q.B);
+        s.mean = bp.take<float>(cap * Bp);
+        s.edges = bp.take<int2>(ecap);
+        s.escr = bp.take<float2>(ecap);
+        s.tstat = bp.take<float2>(tiles);
+        s.tflag = bp.take<int32_t>(tiles);
+        if (p->precision != HSWO_PREC_FP32 && p->spclust_wght > 0.0f && p->spclust_max > 0) {
+            const int64_t kc = std::min<int64_t>(cap, p->spclust_max);
+            s.kcap = (int32_t)kc;
+            s.g16 = bp.take<uint16_t>(kc * Bp);
+            s.gn = bp.take<float>(kc);
+            s.geta = bp.take<float>(kc);
+            s.galpha = bp.take<float>(kc);
+            s.gP = bp.take<float>(kc);
+            s.cvec = bp.take<float>(Bp);
+        }
+        s.st = bp.take<int32_t>(ST_WORDS);
+        s.parent = bp.take<int32_t>(cap);
+        s.mtime = bp.take<int32_t>(cap);
+        s.log = (p->flags & HSWO_FLAG_MERGE_LOG) ? q.merge_log : nullptr;
+        InitDev& in = lay.h_inits[i];
+        in.cube = q.cube;
+        in.img_w = q.W;
+        in.r0 = 0;
+        in.c0 = 0;
+        in.h = q.H;
+        in.w = q.W;
+        in.label_w = q.W;
+        in.conn = p->connectivity;
+        SnapDev& sd = lay.h_snaps[i];
+        sd.st = s.st;
+        sd.parent = s.parent;
+        sd.mtime = s.mtime;
+        sd.labels = q.labels;
+        sd.img_w = q.W;
+        sd.r0 = 0;
+        sd.c0 = 0;
+        sd.h = q.H;
+        sd.w = q.W;
+        sd.label_w = q.W;
+        lay.max_pixels = std::max<int>(lay.max_pixels, (int)cap);
+        lay.max_cap = std::max(lay.max_cap, cap);
+        lay.max_B = std::max(lay.max_B, q.B);
+        // expected work: the adjacent sweep over the whole pass (~ cap^2 / 2 rows)
+        work[i] = (double)cap * (double)cap * (double)Bp;
     }
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+    lay.h_lpt.resize(n);
+    for (int i = 0; i < n; ++i) lay.h_lpt[i] = lay.h_secs[order[i]];
+    lay.bytes = bp.off + 256;
+    return lay;
+}
+
+int validate_batch(int n, const hswo_section* sec, int dtype, const hswo_params* p) {
+    if (n < 1 || !sec) return fail(HSWO_E_INVAL, "need n_sections >= 1 and a sections array");
+    int rc = validate_params(p, 1);
+    if (rc) return rc;
+    if (dtype != HSWO_F32 && dtype != HSWO_F16) return fail(HSWO_E_INVAL, "dtype must be HSWO_F32 or HSWO_F16");
+    for (int i = 0; i < n; ++i) {
+        const hswo_section& q = sec[i];
+        rc = validate_shape(q.H, q.W, q.B, dtype);
+        if (rc) return fail(rc, "section %d: %s", i, g_err.c_str());
+        if (!q.cube || !q.labels) return fail(HSWO_E_INVAL, "section %d: cube and labels must be device pointers", i);
+        if (reinterpret_cast<uintptr_t>(q.cube) % 16) return fail(HSWO_E_INVAL, "section %d: cube not 16-byte aligned", i);
+        if ((p->flags & HSWO_FLAG_MERGE_LOG) && !q.merge_log)
+            return fail(HSWO_E_INVAL, "section %d: MERGE_LOG flag needs merge_log", i);
+    }
+    return HSWO_OK;
+}
+
+int run_batch(int n, const hswo_section* sec, int dtype, const hswo_params* p, hswo_stats* stats, void* workspace,
+              size_t ws_bytes, hipStream_t stream) {
+    int rc = validate_batch(n, sec, dtype, p);
+    if (rc) return rc;
+    rc = check_common(p, workspace);
+    if (rc) return rc;
+    BatchLayout lay = carve_batch(n, sec, p, workspace);
+    if (ws_bytes < lay.bytes)
+        return fail(HSWO_E_NOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes, lay.bytes);
+    std::vector<Upload> ups;
+    add_upload(ups, lay.counts, p->level_counts, p->n_levels);
+    add_upload(ups, lay.secs, lay.h_secs.data(), n);
+    add_upload(ups, lay.secs_lpt, lay.h_lpt.data(), n);
+    add_upload(ups, lay.inits, lay.h_inits.data(), n);
+    add_upload(ups, lay.snaps, lay.h_snaps.data(), n);
+    const LoopParams lp = loop_params(p, lay.counters);
+    const Seq seq = [&](hipStream_t st, Timer* tm, int variant) -> int {
+        HIP_TRY(launch_fill_u64(lay.counters, C_COUNT, 0ull, st));
+        HIP_TRY(launch_init_pixels_secs(lay.secs, n, lay.max_pixels, st));
+        HIP_TRY(launch_init_leaves(lay.secs, lay.inits, n, dtype, lay.max_pixels, st));
+        const int r = timed_driver(tm, lay.secs_lpt, n, lp, variant, st);
+        if (r) return r;
+        HIP_TRY(launch_snapshot(lay.snaps, n, lay.counts, p->n_levels, lay.max_pixels, st));
+        return HSWO_OK;
+    };
+    std::string key = "batch|" + std::to_string(n) + "|" + ptr_key(workspace) + "d" + std::to_string(dtype) + "|" +
+                      params_key(p) + "|";
+    for (int i = 0; i < n; ++i)
+        key += ptr_key(sec[i].cube) + ptr_key(sec[i].labels) + ptr_key(sec[i].merge_log) + std::to_string(sec[i].H) +
+               "x" + std::to_string(sec[i].W) + "x" + std::to_string(sec[i].B) + ";";
+    const std::string tkey = "gfx950:batch:B" + std::to_string(bucket(lay.max_B)) + ":R" +
+                             std::to_string(bucket(lay.max_cap)) + ":n" + std::to_string(bucket(n)) + ":P" +
+                             std::to_string(p->precision) + ":k" + std::to_string(bucket(p->spclust_max + 1));
+    ExecOut eo;
+    rc = execute(ups, seq, key, tkey, p->flags, stream, lay.counters, stats != nullptr, eo);
+    if (rc) return rc;
+    if (stats) return fill_stats(stats, eo, 1);
     return HSWO_OK;
 }
 
@@ -476,25 +856,15 @@ int rhseg_segment(const void* cube, int32_t H, int32_t W, int32_t B, int32_t dty
 
 size_t hswo_batch_workspace_bytes(int32_t n_sections, const hswo_section* sections, int32_t dtype,
                                   const hswo_params* p) {
-    (void)n_sections;
-    (void)sections;
-    (void)dtype;
-    (void)p;
-    return 0;
+    if (validate_batch(n_sections, sections, dtype, p)) return 0;
+    return carve_batch(n_sections, sections, p, nullptr).bytes;
 }
 
 int hswo_run_batch(int32_t n_sections, const hswo_section* sections, int32_t dtype, const hswo_params* p,
                    hswo_stats* stats, void* workspace, size_t ws_bytes, void* hip_stream) {
-    (void)n_sections;
-    (void)sections;
-    (void)dtype;
-    (void)p;
-    (void)stats;
-    (void)workspace;
-    (void)ws_bytes;
-    (void)hip_stream;
     g_err.clear();
-    return fail(HSWO_E_UNSUPPORTED, "hswo_run_batch is not available in this build");
+    return run_batch(n_sections, sections, dtype, p, stats, workspace, ws_bytes,
+                     reinterpret_cast<hipStream_t>(hip_stream));
 }
 
 }  // extern "C"

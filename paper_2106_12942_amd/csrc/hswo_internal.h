@@ -114,9 +114,11 @@ struct LoopParams {
 
 // kernel launchers (hswo_kernels.hip)
 hipError_t launch_init_pixels(int32_t* parent, int32_t* mtime, int64_t n, hipStream_t s);
+hipError_t launch_init_pixels_secs(const SecDev* secs, int n, int max_pixels, hipStream_t s);
 hipError_t launch_init_leaves(const SecDev* secs, const InitDev* init, int n, int dtype, int max_pixels,
                               hipStream_t s);
-hipError_t launch_section_driver(const SecDev* secs, int n, const LoopParams& lp, hipStream_t s);
+hipError_t launch_section_driver(const SecDev* secs, int n, const LoopParams& lp, int variant, hipStream_t s);
+constexpr int DRIVER_VARIANTS[3] = {2, 4, 6};  // adjacent-stage edges in flight per lane group
 hipError_t launch_compress(int32_t* parent, int64_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_assemble(const SecDev* parents, const SecDev* children, const AsmDev* asm_, int n,

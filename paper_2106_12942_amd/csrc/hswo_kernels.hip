@@ -637,6 +637,7 @@ __device__ void merge_pair(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R,
 // ---------------------------------------------------------------------------
 // The section driver: one workgroup runs the whole HSEG loop of one section.
 // ---------------------------------------------------------------------------
+template <int EPG>
 __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict__ secs, int n_sec,
                                                        LoopParams lp) {
     __shared__ Smem sh;
@@ -657,35 +658,68 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
     while (R > s.stop) {
         unsigned long long tk0 = wall_clock64();
         // ------------------------------------------------ adjacent stage
+        // 16 lanes per edge, EPG edges per lane group in flight: each lane
+        // streams 4 consecutive bands of both rows of EPG edges per 64-band
+        // chunk (2*EPG float4 loads outstanding per lane).
         float myU = __builtin_huge_valf();
         {
             const int g = tid >> 4, gl = tid & 15;
-            const int nf4 = s.Bp >> 2;
-            for (int e0 = 0; e0 < E; e0 += NT / 16) {
-                const int e = e0 + g;
-                float acc = 0.0f;
-                int a = 0, b = 0;
-                if (e < E) {
-                    const int2 ed = s.edges[e];
-                    a = ed.x;
-                    b = ed.y;
-                    const float4* ra = reinterpret_cast<const float4*>(s.mean + (size_t)a * s.Bp);
-                    const float4* rb = reinterpret_cast<const float4*>(s.mean + (size_t)b * s.Bp);
-                    for (int c = gl; c < nf4; c += 16) {
-                        const float4 x = ra[c], y = rb[c];
-                        float d;
-                        d = x.x - y.x; acc = fmaf(d, d, acc);
-                        d = x.y - y.y; acc = fmaf(d, d, acc);
-                        d = x.z - y.z; acc = fmaf(d, d, acc);
-                        d = x.w - y.w; acc = fmaf(d, d, acc);
+            for (int e0 = 0; e0 < E; e0 += (NT / 16) * EPG) {
+                int ea[EPG], eb[EPG];
+                float acc[EPG];
+#pragma unroll
+                for (int k = 0; k < EPG; ++k) {
+                    const int e = e0 + g * EPG + k;
+                    ea[k] = -1;
+                    eb[k] = -1;
+                    if (e < E) {
+                        const int2 ed = s.edges[e];
+                        ea[k] = ed.x;
+                        eb[k] = ed.y;
+                    }
+                    acc[k] = 0.0f;
+                }
+                for (int c = 0; c < s.Bp; c += 64) {
+                    const int b = c + gl * 4;
+                    if (b < s.Bp) {
+                        float4 x[EPG], y[EPG];
+#pragma unroll
+                        for (int k = 0; k < EPG; ++k) {
+                            x[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+                            y[k] = x[k];
+                            if (ea[k] >= 0) {
+                                x[k] = *reinterpret_cast<const float4*>(s.mean + (size_t)ea[k] * s.Bp + b);
+                                y[k] = *reinterpret_cast<const float4*>(s.mean + (size_t)eb[k] * s.Bp + b);
+                            }
+                        }
+#pragma unroll
+                        for (int k = 0; k < EPG; ++k) {
+                            float d;
+                            d = x[k].x - y[k].x; acc[k] = fmaf(d, d, acc[k]);
+                            d = x[k].y - y[k].y; acc[k] = fmaf(d, d, acc[k]);
+                            d = x[k].z - y[k].z; acc[k] = fmaf(d, d, acc[k]);
+                            d = x[k].w - y[k].w; acc[k] = fmaf(d, d, acc[k]);
+                        }
                     }
                 }
-                acc += __shfl_xor(acc, 8);
-                acc += __shfl_xor(acc, 4);
-                acc += __shfl_xor(acc, 2);
-                acc += __shfl_xor(acc, 1);
-                if (e < E && gl == 0) {
-                    const float2 lu = screen_bounds(acc, s.npix[a], s.npix[b], s.norm[a], s.norm[b], gam);
+                float mine = 0.0f;
+                int ma = -1, mb = -1;
+#pragma unroll
+                for (int k = 0; k < EPG; ++k) {
+                    float v = acc[k];
+                    v += __shfl_xor(v, 8);
+                    v += __shfl_xor(v, 4);
+                    v += __shfl_xor(v, 2);
+                    v += __shfl_xor(v, 1);
+                    if (gl == k) {
+                        mine = v;
+                        ma = ea[k];
+                        mb = eb[k];
+                    }
+                }
+                if (gl < EPG && ma >= 0) {
+                    const int e = e0 + g * EPG + gl;
+                    const float2 lu = screen_bounds(mine, s.npix[ma], s.npix[mb], s.norm[ma], s.norm[mb], gam);
                     s.escr[e] = lu;
                     myU = fminf(myU, lu.y);
                 }
@@ -854,6 +888,15 @@ __global__ void k_init_pixels(int32_t* parent, int32_t* mtime, int64_t n) {
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
         parent[p] = (int32_t)p;
         mtime[p] = INT_MAX;
+    }
+}
+
+// Batch sections: labels are local pixel indices of each section.
+__global__ void k_init_pixels_secs(const SecDev* __restrict__ secs) {
+    const SecDev s = secs[blockIdx.y];
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < s.R0; p += gridDim.x * blockDim.x) {
+        s.parent[p] = p;
+        s.mtime[p] = INT_MAX;
     }
 }
 
@@ -1118,6 +1161,11 @@ hipError_t launch_init_pixels(int32_t* parent, int32_t* mtime, int64_t n, hipStr
     return hipGetLastError();
 }
 
+hipError_t launch_init_pixels_secs(const SecDev* secs, int n, int max_pixels, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_pixels_secs, dim3(grid_for(max_pixels, 256, 256), n), dim3(256), 0, s, secs);
+    return hipGetLastError();
+}
+
 hipError_t launch_init_leaves(const SecDev* secs, const InitDev* init, int n, int dtype, int max_pixels,
                               hipStream_t s) {
     const dim3 grid(grid_for((int64_t)max_pixels * 8, 256, 1024), n);
@@ -1128,8 +1176,14 @@ hipError_t launch_init_leaves(const SecDev* secs, const InitDev* init, int n, in
     return hipGetLastError();
 }
 
-hipError_t launch_section_driver(const SecDev* secs, int n, const LoopParams& lp, hipStream_t s) {
-    hipLaunchKernelGGL(k_section_driver, dim3(n), dim3(NT), 0, s, secs, n, lp);
+hipError_t launch_section_driver(const SecDev* secs, int n, const LoopParams& lp, int variant, hipStream_t s) {
+    // variant = edges in flight per 16-lane group in the adjacent stage (tunable, result-neutral)
+    if (variant == 2)
+        hipLaunchKernelGGL(k_section_driver<2>, dim3(n), dim3(NT), 0, s, secs, n, lp);
+    else if (variant == 4)
+        hipLaunchKernelGGL(k_section_driver<4>, dim3(n), dim3(NT), 0, s, secs, n, lp);
+    else
+        hipLaunchKernelGGL(k_section_driver<6>, dim3(n), dim3(NT), 0, s, secs, n, lp);
     return hipGetLastError();
 }
 

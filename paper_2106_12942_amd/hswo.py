@@ -28,6 +28,8 @@ HSWO_F16 = 1
 
 PREC = {"fp32": 0, "bf16": 1, "fp16": 2}
 HSWO_FLAG_MERGE_LOG = 1
+HSWO_FLAG_GRAPH = 2
+HSWO_FLAG_AUTOTUNE = 4
 
 MERGE_DTYPE = np.dtype([("lo", "<i4"), ("hi", "<i4"), ("kind", "<i4"), ("r_after", "<i4"), ("d2", "<f8")])
 
@@ -62,6 +64,7 @@ class Stats(ctypes.Structure):
         ("fp32_tiles", ctypes.c_int64),
         ("mfma_tiles", ctypes.c_int64),
         ("driver_launches", ctypes.c_int64),
+        ("driver_variant", ctypes.c_int64),
         ("ms_total", ctypes.c_double),
         ("ms_driver", ctypes.c_double),
         ("ms_adjacent", ctypes.c_double),
@@ -128,13 +131,14 @@ def last_error() -> str:
 
 def make_params(*, connectivity=4, seam_connectivity=8, spclust_wght=0.0, spclust_max=0, target_regions=1,
                 section_regions=0, rnb_levels=1, level_counts: Optional[Sequence[int]] = None,
-                precision="fp32", merge_log=False, **_ignored):
+                precision="fp32", merge_log=False, graph=False, autotune=False, **_ignored):
     counts = list(level_counts) if level_counts is not None else [target_regions]
     arr = (ctypes.c_int32 * len(counts))(*counts)
     p = Params(connectivity, seam_connectivity, spclust_wght, spclust_max, target_regions, section_regions,
                rnb_levels, len(counts), ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32)),
                PREC[precision] if isinstance(precision, str) else int(precision),
-               HSWO_FLAG_MERGE_LOG if merge_log else 0)
+               (HSWO_FLAG_MERGE_LOG if merge_log else 0) | (HSWO_FLAG_GRAPH if graph else 0) |
+               (HSWO_FLAG_AUTOTUNE if autotune else 0))
     p._counts_keepalive = arr  # the struct holds a raw pointer into arr
     return p
 
@@ -171,7 +175,8 @@ def _aligned_workspace(nbytes: int, device):
     return buf, buf.data_ptr() + off
 
 
-def _segment(entry: str, cube, rnb_levels: int, merge_log: bool, stats: bool, stream, params) -> Result:
+def _segment(entry: str, cube, rnb_levels: int, merge_log: bool, stats: bool, stream, params,
+             workspace=None, labels_out=None) -> Result:
     import torch
     if not cube.is_cuda:
         raise ValueError("cube must be a device tensor")
@@ -195,8 +200,15 @@ def _segment(entry: str, cube, rnb_levels: int, merge_log: bool, stats: bool, st
     if nb == 0:
         _check(call(None, None, None, None, 0))  # the entry point reports why
         raise HswoError(HSWO_E_INVAL, "workspace query failed")
-    ws, ws_ptr = _aligned_workspace(nb, cube.device)
-    labels = torch.empty((p.n_levels, H, W), dtype=torch.int32, device=cube.device)
+    if workspace is not None:
+        # caller-kept workspace (graph replays need the same pointers every call)
+        ws, ws_ptr = workspace.get(nb, cube.device)
+    else:
+        ws, ws_ptr = _aligned_workspace(nb, cube.device)
+    labels = labels_out if labels_out is not None else \
+        torch.empty((p.n_levels, H, W), dtype=torch.int32, device=cube.device)
+    if tuple(labels.shape) != (p.n_levels, H, W) or labels.dtype != torch.int32 or not labels.is_contiguous():
+        raise ValueError("labels_out must be a contiguous int32 [n_levels, H, W] device tensor")
     n_merges = H * W - params.get("target_regions", 1)
     log_t = torch.empty((max(n_merges, 1) * MERGE_DTYPE.itemsize,), dtype=torch.uint8, device=cube.device) \
         if merge_log else None
@@ -212,13 +224,87 @@ def _segment(entry: str, cube, rnb_levels: int, merge_log: bool, stats: bool, st
     return Result(labels=labels, log=log, stats=st.as_dict() if st is not None else None)
 
 
+class Workspace:
+    """A device scratch buffer kept across calls (grows when needed)."""
+
+    def __init__(self):
+        self.buf = None
+        self.ptr = 0
+        self.nbytes = 0
+
+    def get(self, nbytes, device):
+        if self.buf is None or self.nbytes < nbytes:
+            self.buf, self.ptr = _aligned_workspace(nbytes, device)
+            self.nbytes = nbytes
+        return self.buf, self.ptr
+
+
 def rhseg_segment(cube, *, rnb_levels: int = 1, merge_log: bool = False, stats: bool = False, stream=None,
-                  **params) -> Result:
+                  workspace: Optional[Workspace] = None, labels_out=None, **params) -> Result:
     """RHSEG of a device cube H x W x B (C entry point rhseg_segment)."""
-    return _segment("rhseg_segment", cube, rnb_levels, merge_log, stats, stream, params)
+    return _segment("rhseg_segment", cube, rnb_levels, merge_log, stats, stream, params, workspace, labels_out)
 
 
-def hswo_run(cube, *, merge_log: bool = False, stats: bool = False, stream=None, **params) -> Result:
+def hswo_run(cube, *, merge_log: bool = False, stats: bool = False, stream=None,
+             workspace: Optional[Workspace] = None, **params) -> Result:
     """HSEG on the whole image as one section (C entry point hswo_run)."""
     params.pop("rnb_levels", None)
-    return _segment("hswo_run", cube, 1, merge_log, stats, stream, params)
+    return _segment("hswo_run", cube, 1, merge_log, stats, stream, params, workspace)
+
+
+@dataclasses.dataclass
+class BatchResult:
+    labels: list               # per section: torch int32 [n_levels, H, W]
+    logs: Optional[list]       # per section: MERGE_DTYPE records, or None
+    stats: Optional[dict]
+
+
+def hswo_run_batch(cubes, *, merge_log: bool = False, stats: bool = False, stream=None,
+                   workspace: Optional[Workspace] = None, labels_out: Optional[list] = None,
+                   **params) -> BatchResult:
+    """Independent sections (device cubes H_s x W_s x B_s of one dtype), each
+    segmented as its own top pass, all in one persistent launch."""
+    import torch
+    if len(cubes) == 0:
+        raise ValueError("no sections")
+    cubes = [c.contiguous() for c in cubes]
+    code = _dtype_code(cubes[0])
+    for c in cubes:
+        if not c.is_cuda or _dtype_code(c) != code:
+            raise ValueError("all sections must be device tensors of one dtype")
+    params = dict(params)
+    params["rnb_levels"] = 1
+    p = make_params(**params, merge_log=merge_log)
+    dev = cubes[0].device
+    n = len(cubes)
+    target = params.get("target_regions", 1)
+    labs = labels_out if labels_out is not None else \
+        [torch.empty((p.n_levels, c.shape[0], c.shape[1]), dtype=torch.int32, device=dev) for c in cubes]
+    logs_t = [torch.empty((max(c.shape[0] * c.shape[1] - target, 1) * MERGE_DTYPE.itemsize,), dtype=torch.uint8,
+                          device=dev) for c in cubes] if merge_log else None
+    secs = (Section * n)()
+    for i, c in enumerate(cubes):
+        H, W, B = c.shape
+        secs[i] = Section(c.data_ptr(), H, W, B, labs[i].data_ptr(), logs_t[i].data_ptr() if logs_t else None)
+    lib = load()
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    nb = int(lib.hswo_batch_workspace_bytes(n, secs, code, ctypes.byref(p)))
+    if nb == 0:
+        _check(lib.hswo_run_batch(n, secs, code, ctypes.byref(p), None, None, 0, s.cuda_stream))
+        raise HswoError(HSWO_E_INVAL, "workspace query failed")
+    if workspace is not None:
+        ws, ws_ptr = workspace.get(nb, dev)
+    else:
+        ws, ws_ptr = _aligned_workspace(nb, dev)
+    st = Stats() if stats else None
+    _check(lib.hswo_run_batch(n, secs, code, ctypes.byref(p), ctypes.byref(st) if st is not None else None, ws_ptr,
+                              nb, s.cuda_stream))
+    ws.record_stream(s)
+    logs = None
+    if logs_t is not None:
+        s.synchronize()
+        logs = []
+        for c, t in zip(cubes, logs_t):
+            m = c.shape[0] * c.shape[1] - target
+            logs.append(np.frombuffer(t.cpu().numpy().tobytes(), dtype=MERGE_DTYPE)[:max(m, 0)])
+    return BatchResult(labels=labs, logs=logs, stats=st.as_dict() if st is not None else None)

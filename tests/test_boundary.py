@@ -38,7 +38,7 @@ def test_version_and_empty_error():
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(hswo.Params) == 48
     assert hswo.MERGE_DTYPE.itemsize == 24
-    assert ctypes.sizeof(hswo.Stats) == 120
+    assert ctypes.sizeof(hswo.Stats) == 128
 
 
 BASE = dict(connectivity=4, seam_connectivity=8, spclust_wght=0.5, spclust_max=256, target_regions=2,
@@ -117,3 +117,30 @@ def test_rhseg_levels_checked():
     assert "rnb_levels" in hswo.last_error()
     p1 = hswo.make_params(**BASE)
     assert lib.hswo_run(FAKE, 8, 8, 2, 0, ctypes.byref(p), FAKE, None, None, FAKE, 1 << 30, None) == hswo.HSWO_E_INVAL
+
+
+def test_batch_validation():
+    lib = hswo.load()
+    p = hswo.make_params(**BASE)
+    secs = (hswo.Section * 2)(hswo.Section(FAKE, 8, 8, 4, FAKE, None), hswo.Section(FAKE, 16, 9, 7, FAKE, None))
+    nb = lib.hswo_batch_workspace_bytes(2, secs, 0, ctypes.byref(p))
+    assert nb > 0
+    assert lib.hswo_run_batch(0, secs, 0, ctypes.byref(p), None, FAKE, nb, None) == hswo.HSWO_E_INVAL
+    assert lib.hswo_run_batch(2, secs, 0, ctypes.byref(p), None, FAKE, nb - 1, None) == hswo.HSWO_E_NOMEM
+    bad = (hswo.Section * 2)(hswo.Section(FAKE, 8, 8, 4, FAKE, None), hswo.Section(FAKE, 0, 9, 7, FAKE, None))
+    assert lib.hswo_run_batch(2, bad, 0, ctypes.byref(p), None, FAKE, nb, None) == hswo.HSWO_E_INVAL
+    assert "section 1" in hswo.last_error()
+    p3 = hswo.make_params(**dict(BASE, rnb_levels=2))
+    assert lib.hswo_run_batch(2, secs, 0, ctypes.byref(p3), None, FAKE, nb, None) == hswo.HSWO_E_INVAL
+
+
+def test_graph_flag_needs_a_stream_and_unknown_flags_rejected():
+    lib = hswo.load()
+    p = hswo.make_params(**BASE, graph=True)
+    nb = hswo.workspace_bytes(16, 16, 4, 0, p)
+    # validation passes, then the null stream is refused before any device work
+    assert lib.hswo_run(FAKE, 16, 16, 4, 0, ctypes.byref(p), FAKE, None, None, FAKE, nb, None) == hswo.HSWO_E_INVAL
+    assert "non-null stream" in hswo.last_error()
+    q = hswo.make_params(**BASE)
+    q.flags = 64
+    assert lib.hswo_run(FAKE, 16, 16, 4, 0, ctypes.byref(q), FAKE, None, None, FAKE, nb, None) == hswo.HSWO_E_INVAL
