@@ -262,6 +262,9 @@ Layout carve(const Plan& pl, int H, int W, const hswo_params* p, void* ws, const
                 s.cvec = bp.take<float>(pl.Bp);
             }
             s.st = bp.take<int32_t>(ST_WORDS);
+            s.wi = bp.take<int32_t>(8);
+            s.wd = bp.take<double>(2);
+            s.wpart = bp.take<float>(2 * GMAX);
             s.parent = lay.parent;
             s.mtime = lay.mtime;
             s.log = log ? log + log_base : nullptr;
@@ -341,6 +344,55 @@ int timed_driver(Timer* tm, const SecDev* secs, int n, const LoopParams& lp, int
         HIP_TRY(hipEventRecord(e0, stream));
     }
     HIP_TRY(launch_section_driver(secs, n, lp, variant, stream));
+    if (tm) HIP_TRY(hipEventRecord(e1, stream));
+    return HSWO_OK;
+}
+
+// How a level's merge loops run: persistent (one workgroup per section, one
+// launch) or wide (G workgroups per section, one launch sequence per iteration).
+int wide_max_sections() {
+    if (const char* e = getenv("HSWO_WIDE_MAX_SECTIONS")) return atoi(e);
+    return 32;
+}
+
+int device_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
+// One level: secs[0..n) with per-section (cap, stop). In wide mode the host
+// knows R at iteration t exactly (cap - t, until the stop count), so the
+// spectral kernels are launched only for iterations where some section can be
+// in its spectral stage.
+int run_level(Timer* tm, const SecDev* secs, int n, const std::vector<int64_t>& cap, const std::vector<int64_t>& stop,
+              const LoopParams& lp, int variant, hipStream_t stream) {
+    if (n > wide_max_sections()) return timed_driver(tm, secs, n, lp, variant, stream);
+    const int G = std::max(1, std::min(GMAX, device_cus() / n));
+    int64_t iters = 0;
+    for (int i = 0; i < n; ++i) iters = std::max(iters, cap[i] - std::min(cap[i], stop[i]));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (tm) {
+        HIP_TRY(hipEventCreate(&e0));
+        tm->drv.push_back(e0);
+        HIP_TRY(hipEventCreate(&e1));
+        tm->drv.push_back(e1);
+        HIP_TRY(hipEventRecord(e0, stream));
+    }
+    for (int64_t t = 0; t < iters; ++t) {
+        bool spec = false;
+        if (lp.spectral)
+            for (int i = 0; i < n && !spec; ++i) {
+                const int64_t R = cap[i] - t;
+                spec = R > stop[i] && R <= lp.kmax;
+            }
+        HIP_TRY(launch_wide_iteration(secs, n, G, lp, variant, spec, stream));
+    }
     if (tm) HIP_TRY(hipEventRecord(e1, stream));
     return HSWO_OK;
 }
@@ -607,6 +659,12 @@ int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_param
     sd.label_w = W;
     add_upload(ups, lay.snap, &sd, 1);
     const LoopParams lp = loop_params(p, lay.counters);
+    std::vector<std::vector<int64_t>> caps(L), stops(L);
+    for (int d = 0; d < L; ++d)
+        for (const SecPlan& s : pl.lv[d]) {
+            caps[d].push_back(s.cap);
+            stops[d].push_back(s.stop);
+        }
 
     const Seq seq = [&](hipStream_t st, Timer* tm, int variant) -> int {
         HIP_TRY(launch_fill_u64(lay.counters, C_COUNT, 0ull, st));
@@ -616,7 +674,7 @@ int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_param
             int maxpix = 0;
             for (const SecPlan& s : pl.lv[d]) maxpix = std::max<int>(maxpix, (int)s.cap);
             HIP_TRY(launch_init_leaves(lay.lv[d].secs, lay.lv[d].inits, (int)pl.lv[d].size(), dtype, maxpix, st));
-            const int r = timed_driver(tm, lay.lv[d].secs, (int)pl.lv[d].size(), lp, variant, st);
+            const int r = run_level(tm, lay.lv[d].secs, (int)pl.lv[d].size(), caps[d], stops[d], lp, variant, st);
             if (r) return r;
         }
         for (int d = L - 2; d >= 0; --d) {
@@ -632,7 +690,7 @@ int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_param
             HIP_TRY(launch_assemble(lay.lv[d].secs, lay.lv[d + 1].secs, lay.lv[d].asms, (int)secs.size(), lay.slotmap,
                                     (int)std::min<int64_t>(maxcap, 1 << 30), st));
             HIP_TRY(launch_seam(lay.lv[d].secs, lay.lv[d].asms, (int)secs.size(), lay.slotmap, (int)maxseam, st));
-            const int r = timed_driver(tm, lay.lv[d].secs, (int)secs.size(), lp, variant, st);
+            const int r = run_level(tm, lay.lv[d].secs, (int)secs.size(), caps[d], stops[d], lp, variant, st);
             if (r) return r;
         }
         HIP_TRY(launch_snapshot(lay.snap, 1, lay.counts, p->n_levels, (int)P, st));
@@ -725,6 +783,9 @@ BatchLayout carve_batch(int n, const hswo_section* sec, const hswo_params* p, vo
             s.cvec = bp.take<float>(Bp);
         }
         s.st = bp.take<int32_t>(ST_WORDS);
+        s.wi = bp.take<int32_t>(8);
+        s.wd = bp.take<double>(2);
+        s.wpart = bp.take<float>(2 * GMAX);
         s.parent = bp.take<int32_t>(cap);
         s.mtime = bp.take<int32_t>(cap);
         s.log = (p->flags & HSWO_FLAG_MERGE_LOG) ? q.merge_log : nullptr;

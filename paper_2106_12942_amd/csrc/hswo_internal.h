@@ -36,6 +36,7 @@ enum Counter {
 };
 
 constexpr int ST_WORDS = 8;   // per-section state words
+constexpr int GMAX = 256;     // wide mode: most workgroups per section
 constexpr int STILE = 128;    // matrix-core super tile edge (4 spectral tiles)
 
 // One section of one recursion level (or one independent batch section).
@@ -67,6 +68,10 @@ struct SecDev {
     float* cvec;     // [Bp] centring spectrum, fixed when the spectral stage starts
     int32_t kcap;    // rows available for the 16-bit screen (0 on the plain path)
     int32_t pad1;
+    // wide mode iteration scratch
+    int32_t* wi;     // [8]
+    double* wd;      // [2]
+    float* wpart;    // [2 * GMAX]
     int32_t* st;     // state: [0] R, [1] E, [2] R at pass start, [3] merges done, [4] 16-bit rows ready
     int32_t* parent; // label-indexed union-find parent (image or batch section)
     int32_t* mtime;  // label-indexed merge time: -1 non-top merge, k top merge, INT_MAX alive
@@ -119,6 +124,8 @@ hipError_t launch_init_leaves(const SecDev* secs, const InitDev* init, int n, in
                               hipStream_t s);
 hipError_t launch_section_driver(const SecDev* secs, int n, const LoopParams& lp, int variant, hipStream_t s);
 constexpr int DRIVER_VARIANTS[3] = {2, 4, 6};  // adjacent-stage edges in flight per lane group
+hipError_t launch_wide_iteration(const SecDev* secs, int n, int G, const LoopParams& lp, int variant,
+                                 bool spectral_possible, hipStream_t s);
 hipError_t launch_compress(int32_t* parent, int64_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_assemble(const SecDev* parents, const SecDev* children, const AsmDev* asm_, int n,

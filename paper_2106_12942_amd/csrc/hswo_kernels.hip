@@ -451,23 +451,23 @@ __device__ void prep_alpha_p(const SecDev& s, int R, double T) {
 
 __device__ __forceinline__ int tile_index(int ib, int jb, int nT) { return ib * nT - ib * (ib - 1) / 2 + (jb - ib); }
 
-// Matrix-core pass over all 128 x 128 super tiles of pairs i < j < R: sets
-// tflag of every 64 x 64 tile holding a pair that passes the test above.
+// Matrix-core pass over the 128 x 128 super tiles q = g0, g0 + gstride, ...
+// of pairs i < j < R: sets tflag of every 64 x 64 tile holding a pair that
+// passes the test above (flags are cleared beforehand).
 // Wave w computes rows 32*(w>>1) .. +31 and columns 64*(w&1) .. +63 of the
 // super tile, which lie in exactly one 64 x 64 tile.
 template <int PREC>
-__device__ int mfma_screen(Smem& sh, const SecDev& s, int R) {
+__device__ int mfma_screen(Smem& sh, const SecDev& s, int R, int g0, int gstride) {
     typedef Fmt16<PREC> F;
     typedef typename F::V V;
     const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
     const int wi = w >> 1, wj = w & 1;
     const int nT = (R + TILE - 1) / TILE, nS = (R + STILE - 1) / STILE;
-    const int ntiles = nT * (nT + 1) / 2;
-    for (int t = tid; t < ntiles; t += NT) s.tflag[t] = 0;
     const int lrow = tid >> 2, lseg = (tid & 3) * 8;
-    int nsup = 0;
+    int nsup = 0, q = 0;
     for (int IB = 0; IB < nS; ++IB)
-        for (int JB = IB; JB < nS; ++JB) {
+        for (int JB = IB; JB < nS; ++JB, ++q) {
+            if (q < g0 || (q - g0) % gstride != 0) continue;  // block-uniform
             ++nsup;
             __syncthreads();  // previous tile's LDS reads are done
             if (tid < STILE) {
@@ -635,7 +635,213 @@ __device__ void merge_pair(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R,
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// The section driver: one workgroup runs the whole HSEG loop of one section.
+// Stages of one merge-loop iteration, as block-level functions over a range
+// of the work, shared by the persistent driver (one workgroup does all of a
+// section's work) and the wide kernels (G workgroups share the sweeps).
+// ---------------------------------------------------------------------------
+
+// Adjacent screen of edges [e_begin, e_end): 16 lanes per edge, EPG edges per
+// lane group in flight; each lane streams 4 consecutive bands of both rows of
+// EPG edges per 64-band chunk (2*EPG float4 loads outstanding per lane).
+// Writes each edge's bounds to escr; returns this thread's least upper bound.
+template <int EPG>
+__device__ float adj_screen_range(const SecDev& s, int e_begin, int e_end, float gam) {
+    const int tid = threadIdx.x;
+    const int g = tid >> 4, gl = tid & 15;
+    float myU = __builtin_huge_valf();
+    for (int e0 = e_begin; e0 < e_end; e0 += (NT / 16) * EPG) {
+        int ea[EPG], eb[EPG];
+        float acc[EPG];
+#pragma unroll
+        for (int k = 0; k < EPG; ++k) {
+            const int e = e0 + g * EPG + k;
+            ea[k] = -1;
+            eb[k] = -1;
+            if (e < e_end) {
+                const int2 ed = s.edges[e];
+                ea[k] = ed.x;
+                eb[k] = ed.y;
+            }
+            acc[k] = 0.0f;
+        }
+        for (int c = 0; c < s.Bp; c += 64) {
+            const int b = c + gl * 4;
+            if (b < s.Bp) {
+                float4 x[EPG], y[EPG];
+#pragma unroll
+                for (int k = 0; k < EPG; ++k) {
+                    x[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    y[k] = x[k];
+                    if (ea[k] >= 0) {
+                        x[k] = *reinterpret_cast<const float4*>(s.mean + (size_t)ea[k] * s.Bp + b);
+                        y[k] = *reinterpret_cast<const float4*>(s.mean + (size_t)eb[k] * s.Bp + b);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < EPG; ++k) {
+                    float d;
+                    d = x[k].x - y[k].x; acc[k] = fmaf(d, d, acc[k]);
+                    d = x[k].y - y[k].y; acc[k] = fmaf(d, d, acc[k]);
+                    d = x[k].z - y[k].z; acc[k] = fmaf(d, d, acc[k]);
+                    d = x[k].w - y[k].w; acc[k] = fmaf(d, d, acc[k]);
+                }
+            }
+        }
+        float mine = 0.0f;
+        int ma = -1, mb = -1;
+#pragma unroll
+        for (int k = 0; k < EPG; ++k) {
+            float v = acc[k];
+            v += __shfl_xor(v, 8);
+            v += __shfl_xor(v, 4);
+            v += __shfl_xor(v, 2);
+            v += __shfl_xor(v, 1);
+            if (gl == k) {
+                mine = v;
+                ma = ea[k];
+                mb = eb[k];
+            }
+        }
+        if (gl < EPG && ma >= 0) {
+            const int e = e0 + g * EPG + gl;
+            const float2 lu = screen_bounds(mine, s.npix[ma], s.npix[mb], s.norm[ma], s.norm[mb], gam);
+            s.escr[e] = lu;
+            myU = fminf(myU, lu.y);
+        }
+    }
+    return myU;
+}
+
+// Exact best adjacent pair: every edge whose lower bound reaches Ua is
+// re-scored in FP64.
+__device__ KeyD adj_collect(Smem& sh, const SecDev& s, int E, float Ua, int& nchk) {
+    const int tid = threadIdx.x;
+    KeyD A = key_none();
+    for (int e0 = 0; e0 < E; e0 += NT) {
+        const int e = e0 + tid;
+        if (e < E && s.escr[e].x <= Ua) {
+            const int k = atomicAdd(&sh.ncand, 1);
+            if (k < CAND_CAP) sh.cand[k] = e;
+        }
+        flush_candidates(sh, s, A, nchk, true, NT);
+    }
+    flush_candidates(sh, s, A, nchk, true, CAND_CAP);
+    return A;
+}
+
+// FP32 spectral tiles t = t0, t0 + stride, ...: per-tile (min lower, min
+// upper) to tstat. With use16 only the tiles the matrix-core screen flagged
+// are screened (the others get +inf). Returns the least upper bound seen
+// (block-uniform) and counts the tiles screened.
+__device__ float fp32_tiles(Smem& sh, const SecDev& s, int R, bool use16, float gam, int t0, int stride,
+                            int& nproc) {
+    const int tid = threadIdx.x;
+    const int ty = tid >> 5, tx = tid & 31;
+    const int nT = (R + TILE - 1) / TILE;
+    float Us = __builtin_huge_valf();
+    int t = 0;
+    for (int ib = 0; ib < nT; ++ib)
+        for (int jb = ib; jb < nT; ++jb, ++t) {
+            if ((t - t0) % stride != 0 || t < t0) continue;  // block-uniform
+            if (use16) {
+                if (tid == 0) sh.bcast_i[1] = s.tflag[t];
+                __syncthreads();
+                const int fl = sh.bcast_i[1];
+                __syncthreads();
+                if (!fl) {
+                    if (tid == 0) s.tstat[t] = make_float2(__builtin_huge_valf(), __builtin_huge_valf());
+                    continue;  // block-uniform via LDS
+                }
+            }
+            ++nproc;
+            float acc[4][2];
+            tile_sums_fp32(sh, s, ib, jb, R, acc);
+            float mL = __builtin_huge_valf(), mU = __builtin_huge_valf();
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const int i = ib * TILE + ty * 4 + a, j = jb * TILE + tx * 2 + c;
+                    if (i < j && j < R) {
+                        const float2 lu = screen_bounds(acc[a][c], s.npix[i], s.npix[j], s.norm[i], s.norm[j], gam);
+                        mL = fminf(mL, lu.x);
+                        mU = fminf(mU, lu.y);
+                    }
+                }
+            const float2 lu = block_min_f2(sh, mL, mU);
+            if (tid == 0) s.tstat[t] = lu;
+            Us = fminf(Us, lu.y);
+        }
+    return Us;
+}
+
+// Exact best non-adjacent candidate: re-screen every tile whose least lower
+// bound reaches theta (and is below T), collect its pairs with lower <= theta
+// and < T, re-score them in FP64.
+__device__ KeyD spectral_collect(Smem& sh, const SecDev& s, int R, double T, double theta, float gam, int& nchk,
+                                 int& nresc) {
+    const int tid = threadIdx.x;
+    const int ty = tid >> 5, tx = tid & 31;
+    const int nT = (R + TILE - 1) / TILE;
+    KeyD M = key_none();
+    int t = 0;
+    for (int ib = 0; ib < nT; ++ib)
+        for (int jb = ib; jb < nT; ++jb, ++t) {
+            if (tid == 0) {
+                const float tl = s.tstat[t].x;
+                sh.bcast_i[0] = ((double)tl <= theta && (double)tl < T) ? 1 : 0;
+            }
+            __syncthreads();
+            const int flagged = sh.bcast_i[0];
+            __syncthreads();
+            if (!flagged) continue;  // block-uniform via LDS
+            ++nresc;
+            float acc[4][2];
+            tile_sums_fp32(sh, s, ib, jb, R, acc);
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const int i = ib * TILE + ty * 4 + a, j = jb * TILE + tx * 2 + c;
+                    if (i < j && j < R) {
+                        const float lo = screen_bounds(acc[a][c], s.npix[i], s.npix[j], s.norm[i], s.norm[j], gam).x;
+                        if ((double)lo <= theta && (double)lo < T) {
+                            const int k = atomicAdd(&sh.ncand, 1);
+                            if (k < CAND_CAP) sh.cand[k] = (int)(((unsigned)i << 16) | (unsigned)j);
+                        }
+                    }
+                }
+            flush_candidates(sh, s, M, nchk, false, TILE * TILE);
+        }
+    flush_candidates(sh, s, M, nchk, false, CAND_CAP);
+    return M;
+}
+
+__device__ void clear_tile_flags(const SecDev& s, int R) {
+    const int nT = (R + TILE - 1) / TILE;
+    const int ntiles = nT * (nT + 1) / 2;
+    for (int t = threadIdx.x; t < ntiles; t += NT) s.tflag[t] = 0;
+}
+
+// The merge decision (one merge per iteration; the non-adjacent minimum wins
+// only below w^2 times the adjacent minimum).
+__device__ __forceinline__ bool decide(bool spectral, const KeyD& A, const KeyD& M, double T, KeyD& win, int& kind) {
+    if (spectral && key_exists(M) && M.d2 < T) {
+        win = M;
+        kind = 1;
+        return true;
+    }
+    if (key_exists(A)) {
+        win = A;
+        kind = 0;
+        return true;
+    }
+    return false;
+}
+
+// ---------------------------------------------------------------------------
+// The persistent section driver: one workgroup runs the whole HSEG loop of
+// one section; one launch covers every section of a recursion level.
 // ---------------------------------------------------------------------------
 template <int EPG>
 __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict__ secs, int n_sec,
@@ -651,104 +857,26 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
     const float gam = (float)(2 * s.B + 32) * U32;
     unsigned long long c_adj = 0, c_spec = 0, c_chk = 0, c_resc = 0, c_it = 0, c_f32 = 0, c_mf = 0;
     unsigned long long t_adj = 0, t_mf = 0, t_s32 = 0, t_mrg = 0;  // constant-clock ticks (thread 0)
-    int stamp = 0;
     if (tid == 0) sh.ncand = 0;
     __syncthreads();
 
     while (R > s.stop) {
         unsigned long long tk0 = wall_clock64();
-        // ------------------------------------------------ adjacent stage
-        // 16 lanes per edge, EPG edges per lane group in flight: each lane
-        // streams 4 consecutive bands of both rows of EPG edges per 64-band
-        // chunk (2*EPG float4 loads outstanding per lane).
-        float myU = __builtin_huge_valf();
-        {
-            const int g = tid >> 4, gl = tid & 15;
-            for (int e0 = 0; e0 < E; e0 += (NT / 16) * EPG) {
-                int ea[EPG], eb[EPG];
-                float acc[EPG];
-#pragma unroll
-                for (int k = 0; k < EPG; ++k) {
-                    const int e = e0 + g * EPG + k;
-                    ea[k] = -1;
-                    eb[k] = -1;
-                    if (e < E) {
-                        const int2 ed = s.edges[e];
-                        ea[k] = ed.x;
-                        eb[k] = ed.y;
-                    }
-                    acc[k] = 0.0f;
-                }
-                for (int c = 0; c < s.Bp; c += 64) {
-                    const int b = c + gl * 4;
-                    if (b < s.Bp) {
-                        float4 x[EPG], y[EPG];
-#pragma unroll
-                        for (int k = 0; k < EPG; ++k) {
-                            x[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-                            y[k] = x[k];
-                            if (ea[k] >= 0) {
-                                x[k] = *reinterpret_cast<const float4*>(s.mean + (size_t)ea[k] * s.Bp + b);
-                                y[k] = *reinterpret_cast<const float4*>(s.mean + (size_t)eb[k] * s.Bp + b);
-                            }
-                        }
-#pragma unroll
-                        for (int k = 0; k < EPG; ++k) {
-                            float d;
-                            d = x[k].x - y[k].x; acc[k] = fmaf(d, d, acc[k]);
-                            d = x[k].y - y[k].y; acc[k] = fmaf(d, d, acc[k]);
-                            d = x[k].z - y[k].z; acc[k] = fmaf(d, d, acc[k]);
-                            d = x[k].w - y[k].w; acc[k] = fmaf(d, d, acc[k]);
-                        }
-                    }
-                }
-                float mine = 0.0f;
-                int ma = -1, mb = -1;
-#pragma unroll
-                for (int k = 0; k < EPG; ++k) {
-                    float v = acc[k];
-                    v += __shfl_xor(v, 8);
-                    v += __shfl_xor(v, 4);
-                    v += __shfl_xor(v, 2);
-                    v += __shfl_xor(v, 1);
-                    if (gl == k) {
-                        mine = v;
-                        ma = ea[k];
-                        mb = eb[k];
-                    }
-                }
-                if (gl < EPG && ma >= 0) {
-                    const int e = e0 + g * EPG + gl;
-                    const float2 lu = screen_bounds(mine, s.npix[ma], s.npix[mb], s.norm[ma], s.norm[mb], gam);
-                    s.escr[e] = lu;
-                    myU = fminf(myU, lu.y);
-                }
-            }
-        }
+        // adjacent stage
+        const float myU = adj_screen_range<EPG>(s, 0, E, gam);
         const float Ua = block_min_f2(sh, myU, myU).x;
-        KeyD A = key_none();
         int nchk = 0;
-        for (int e0 = 0; e0 < E; e0 += NT) {
-            const int e = e0 + tid;
-            if (e < E && s.escr[e].x <= Ua) {
-                const int k = atomicAdd(&sh.ncand, 1);
-                if (k < CAND_CAP) sh.cand[k] = e;
-            }
-            flush_candidates(sh, s, A, nchk, true, NT);
-        }
-        flush_candidates(sh, s, A, nchk, true, CAND_CAP);
+        const KeyD A = adj_collect(sh, s, E, Ua, nchk);
         c_adj += (unsigned long long)E;
         unsigned long long tk1 = wall_clock64();
         t_adj += tk1 - tk0;
         tk0 = tk1;
 
-        // ------------------------------------------------ spectral stage
+        // spectral stage
         KeyD M = key_none();
         const bool spectral = lp.spectral && R <= lp.kmax;
         const double T = key_exists(A) ? lp.w2 * A.d2 : __builtin_huge_val();
         if (spectral) {
-            const int nT = (R + TILE - 1) / TILE;
-            const int ty = tid >> 5, tx = tid & 31;
             if (prec && !g_ready) {
                 if (prec == 1)
                     build16_all<1>(s, R);
@@ -760,78 +888,17 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
             const bool use16 = prec && T < __builtin_huge_val();
             if (use16) {
                 prep_alpha_p(s, R, T);
-                c_mf += (unsigned long long)(prec == 1 ? mfma_screen<1>(sh, s, R) : mfma_screen<2>(sh, s, R));
+                clear_tile_flags(s, R);
+                c_mf += (unsigned long long)(prec == 1 ? mfma_screen<1>(sh, s, R, 0, 1) : mfma_screen<2>(sh, s, R, 0, 1));
             }
             tk1 = wall_clock64();
             t_mf += tk1 - tk0;
             tk0 = tk1;
-            float Us = __builtin_huge_valf();
-            int t = 0;
-            for (int ib = 0; ib < nT; ++ib)
-                for (int jb = ib; jb < nT; ++jb, ++t) {
-                    if (use16) {
-                        if (tid == 0) sh.bcast_i[1] = s.tflag[t];
-                        __syncthreads();
-                        const int fl = sh.bcast_i[1];
-                        __syncthreads();
-                        if (!fl) {
-                            if (tid == 0) s.tstat[t] = make_float2(__builtin_huge_valf(), __builtin_huge_valf());
-                            continue;  // block-uniform via LDS
-                        }
-                    }
-                    ++c_f32;
-                    float acc[4][2];
-                    tile_sums_fp32(sh, s, ib, jb, R, acc);
-                    float mL = __builtin_huge_valf(), mU = __builtin_huge_valf();
-#pragma unroll
-                    for (int a = 0; a < 4; ++a)
-#pragma unroll
-                        for (int c = 0; c < 2; ++c) {
-                            const int i = ib * TILE + ty * 4 + a, j = jb * TILE + tx * 2 + c;
-                            if (i < j && j < R) {
-                                const float2 lu = screen_bounds(acc[a][c], s.npix[i], s.npix[j], s.norm[i],
-                                                                s.norm[j], gam);
-                                mL = fminf(mL, lu.x);
-                                mU = fminf(mU, lu.y);
-                            }
-                        }
-                    const float2 lu = block_min_f2(sh, mL, mU);
-                    if (tid == 0) s.tstat[t] = lu;
-                    Us = fminf(Us, lu.y);
-                }
+            int nf = 0, nresc = 0;
+            const float Us = fp32_tiles(sh, s, R, use16, gam, 0, 1, nf);
             const double theta = fmin((double)Us, T);
-            int nresc = 0;
-            t = 0;
-            for (int ib = 0; ib < nT; ++ib)
-                for (int jb = ib; jb < nT; ++jb, ++t) {
-                    if (tid == 0) {
-                        const float tl = s.tstat[t].x;
-                        sh.bcast_i[0] = ((double)tl <= theta && (double)tl < T) ? 1 : 0;
-                    }
-                    __syncthreads();
-                    const int flagged = sh.bcast_i[0];
-                    __syncthreads();
-                    if (!flagged) continue;  // block-uniform via LDS
-                    ++nresc;
-                    float acc[4][2];
-                    tile_sums_fp32(sh, s, ib, jb, R, acc);
-#pragma unroll
-                    for (int a = 0; a < 4; ++a)
-#pragma unroll
-                        for (int c = 0; c < 2; ++c) {
-                            const int i = ib * TILE + ty * 4 + a, j = jb * TILE + tx * 2 + c;
-                            if (i < j && j < R) {
-                                const float lo = screen_bounds(acc[a][c], s.npix[i], s.npix[j], s.norm[i],
-                                                               s.norm[j], gam).x;
-                                if ((double)lo <= theta && (double)lo < T) {
-                                    const int k = atomicAdd(&sh.ncand, 1);
-                                    if (k < CAND_CAP) sh.cand[k] = (int)(((unsigned)i << 16) | (unsigned)j);
-                                }
-                            }
-                        }
-                    flush_candidates(sh, s, M, nchk, false, TILE * TILE);
-                }
-            flush_candidates(sh, s, M, nchk, false, CAND_CAP);
+            M = spectral_collect(sh, s, R, T, theta, gam, nchk, nresc);
+            c_f32 += (unsigned long long)nf;
             c_spec += (unsigned long long)R * (unsigned long long)(R - 1) / 2ull;
             c_resc += (unsigned long long)nresc;
             tk1 = wall_clock64();
@@ -839,24 +906,12 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
             tk0 = tk1;
         }
 
-        // ------------------------------------------------ decision
         KeyD win;
         int kind;
-        if (spectral && key_exists(M) && M.d2 < T) {
-            win = M;
-            kind = 1;
-        } else if (key_exists(A)) {
-            win = A;
-            kind = 0;
-        } else {
-            break;  // no pair left (cannot happen in a connected section)
-        }
+        if (!decide(spectral, A, M, T, win, kind)) break;  // no pair left (not in a connected section)
         c_chk += (unsigned long long)nchk;
         c_it += 1ull;
-
-        // ------------------------------------------------ merge
-        merge_pair(sh, s, win.si, win.sj, R, E, stamp, kind, win.d2, g_ready, prec);
-        ++stamp;
+        merge_pair(sh, s, win.si, win.sj, R, E, s.st[3], kind, win.d2, g_ready, prec);
         --R;
         t_mrg += wall_clock64() - tk0;
     }
@@ -878,6 +933,165 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
             atomicAdd(&lp.counters[C_RECHECKS], c_chk);
             atomicAdd(&lp.counters[C_RESCANS], c_resc);
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Wide mode: one merge-loop iteration of every section of a level as five
+// launches, G workgroups per section sharing the sweeps. Launch boundaries
+// order the phases; a section that has reached its stop count does nothing.
+//   1 k_wide_adj       adjacent screen, edges split over G workgroups
+//   2 k_wide_decide    adjacent decision; merge now if the spectral stage is off
+//   3 k_wide_mfma      matrix-core tile screen, super tiles split over G
+//   4 k_wide_fp32      FP32 tile screen, tiles split over G
+//   5 k_wide_finish    spectral decision and merge
+// Per-section iteration scratch: wi[0] phase (0 idle, 1 adjacent merged,
+// 2 spectral pending), wi[1..4] A's lo, hi, si, sj, wi[5] use16, wi[6] checks;
+// wd[0] A's D2, wd[1] T; wpart[g] adjacent and wpart[GMAX + g] spectral
+// partial least upper bounds.
+// ---------------------------------------------------------------------------
+template <int EPG>
+__global__ void __launch_bounds__(NT) k_wide_adj(const SecDev* __restrict__ secs, int G) {
+    __shared__ Smem sh;
+    const SecDev s = secs[blockIdx.y];
+    const int R = s.st[0], E = s.st[1];
+    if (R <= s.stop) return;
+    const float gam = (float)(2 * s.B + 32) * U32;
+    const int per = (E + G - 1) / G;
+    const int e0 = blockIdx.x * per, e1 = min(E, e0 + per);
+    const float myU = adj_screen_range<EPG>(s, e0, e1, gam);
+    const float U = block_min_f2(sh, myU, myU).x;
+    if (threadIdx.x == 0) s.wpart[blockIdx.x] = U;
+}
+
+__global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ secs, int G, LoopParams lp) {
+    __shared__ Smem sh;
+    const SecDev s = secs[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int R = s.st[0];
+    int E = s.st[1];
+    if (R <= s.stop) {
+        if (tid == 0) s.wi[0] = 0;
+        return;
+    }
+    const int prec = s.kcap > 0 ? lp.precision : 0;
+    if (tid == 0) sh.ncand = 0;
+    __syncthreads();
+    float Ua = __builtin_huge_valf();
+    for (int g = 0; g < G; ++g) Ua = fminf(Ua, s.wpart[g]);
+    int nchk = 0;
+    const KeyD A = adj_collect(sh, s, E, Ua, nchk);
+    const bool spectral = lp.spectral && R <= lp.kmax;
+    const double T = key_exists(A) ? lp.w2 * A.d2 : __builtin_huge_val();
+    if (!spectral) {
+        KeyD win;
+        int kind;
+        if (decide(false, A, A, T, win, kind)) {
+            merge_pair(sh, s, win.si, win.sj, R, E, s.st[3], kind, win.d2, s.st[4], prec);
+            if (tid == 0) {
+                s.st[0] = R - 1;
+                s.st[1] = E;
+            }
+        }
+        if (tid == 0) {
+            s.wi[0] = 1;
+            if (lp.counters) {
+                atomicAdd(&lp.counters[C_ITERS], 1ull);
+                atomicAdd(&lp.counters[C_MERGES], 1ull);
+                atomicAdd(&lp.counters[C_ADJ_PAIRS], (unsigned long long)E);
+                atomicAdd(&lp.counters[C_RECHECKS], (unsigned long long)nchk);
+            }
+        }
+        return;
+    }
+    int g_ready = s.st[4];
+    if (prec && !g_ready) {
+        if (prec == 1)
+            build16_all<1>(s, R);
+        else
+            build16_all<2>(s, R);
+        g_ready = 1;
+    }
+    const bool use16 = prec && T < __builtin_huge_val();
+    if (use16) {
+        prep_alpha_p(s, R, T);
+        clear_tile_flags(s, R);
+    }
+    if (tid == 0) {
+        s.st[4] = g_ready;
+        s.wi[0] = 2;
+        s.wi[1] = A.lo;
+        s.wi[2] = A.hi;
+        s.wi[3] = A.si;
+        s.wi[4] = A.sj;
+        s.wi[5] = use16 ? 1 : 0;
+        s.wi[6] = nchk;
+        s.wd[0] = A.d2;
+        s.wd[1] = T;
+        if (lp.counters) atomicAdd(&lp.counters[C_ADJ_PAIRS], (unsigned long long)E);
+    }
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(NT) k_wide_mfma(const SecDev* __restrict__ secs, int G, LoopParams lp) {
+    __shared__ Smem sh;
+    const SecDev s = secs[blockIdx.y];
+    if (s.wi[0] != 2 || !s.wi[5]) return;
+    const int n = mfma_screen<PREC>(sh, s, s.st[0], blockIdx.x, G);
+    if (threadIdx.x == 0 && lp.counters) atomicAdd(&lp.counters[C_MFMA_TILES], (unsigned long long)n);
+}
+
+__global__ void __launch_bounds__(NT) k_wide_fp32(const SecDev* __restrict__ secs, int G, LoopParams lp) {
+    __shared__ Smem sh;
+    const SecDev s = secs[blockIdx.y];
+    if (s.wi[0] != 2) return;
+    const float gam = (float)(2 * s.B + 32) * U32;
+    int nf = 0;
+    const float Us = fp32_tiles(sh, s, s.st[0], s.wi[5] != 0, gam, blockIdx.x, G, nf);
+    if (threadIdx.x == 0) {
+        s.wpart[GMAX + blockIdx.x] = Us;
+        if (lp.counters) atomicAdd(&lp.counters[C_FP32_TILES], (unsigned long long)nf);
+    }
+}
+
+__global__ void __launch_bounds__(NT) k_wide_finish(const SecDev* __restrict__ secs, int G, LoopParams lp) {
+    __shared__ Smem sh;
+    const SecDev s = secs[blockIdx.x];
+    const int tid = threadIdx.x;
+    if (s.wi[0] != 2) return;
+    const int R = s.st[0];
+    int E = s.st[1];
+    const int prec = s.kcap > 0 ? lp.precision : 0;
+    if (tid == 0) sh.ncand = 0;
+    __syncthreads();
+    KeyD A;
+    A.d2 = s.wd[0];
+    A.lo = s.wi[1];
+    A.hi = s.wi[2];
+    A.si = s.wi[3];
+    A.sj = s.wi[4];
+    const double T = s.wd[1];
+    int nchk = s.wi[6], nresc = 0;
+    float Us = __builtin_huge_valf();
+    for (int g = 0; g < G; ++g) Us = fminf(Us, s.wpart[GMAX + g]);
+    const double theta = fmin((double)Us, T);
+    const float gam = (float)(2 * s.B + 32) * U32;
+    const KeyD M = spectral_collect(sh, s, R, T, theta, gam, nchk, nresc);
+    KeyD win;
+    int kind;
+    if (decide(true, A, M, T, win, kind)) {
+        merge_pair(sh, s, win.si, win.sj, R, E, s.st[3], kind, win.d2, s.st[4], prec);
+        if (tid == 0) {
+            s.st[0] = R - 1;
+            s.st[1] = E;
+        }
+    }
+    if (tid == 0 && lp.counters) {
+        atomicAdd(&lp.counters[C_ITERS], 1ull);
+        atomicAdd(&lp.counters[C_MERGES], 1ull);
+        atomicAdd(&lp.counters[C_SPEC_PAIRS], (unsigned long long)R * (unsigned long long)(R - 1) / 2ull);
+        atomicAdd(&lp.counters[C_RECHECKS], (unsigned long long)nchk);
+        atomicAdd(&lp.counters[C_RESCANS], (unsigned long long)nresc);
     }
 }
 
@@ -1184,6 +1398,27 @@ hipError_t launch_section_driver(const SecDev* secs, int n, const LoopParams& lp
         hipLaunchKernelGGL(k_section_driver<4>, dim3(n), dim3(NT), 0, s, secs, n, lp);
     else
         hipLaunchKernelGGL(k_section_driver<6>, dim3(n), dim3(NT), 0, s, secs, n, lp);
+    return hipGetLastError();
+}
+
+hipError_t launch_wide_iteration(const SecDev* secs, int n, int G, const LoopParams& lp, int variant,
+                                 bool spectral_possible, hipStream_t s) {
+    const dim3 grid(G, n);
+    if (variant == 2)
+        hipLaunchKernelGGL(k_wide_adj<2>, grid, dim3(NT), 0, s, secs, G);
+    else if (variant == 4)
+        hipLaunchKernelGGL(k_wide_adj<4>, grid, dim3(NT), 0, s, secs, G);
+    else
+        hipLaunchKernelGGL(k_wide_adj<6>, grid, dim3(NT), 0, s, secs, G);
+    hipLaunchKernelGGL(k_wide_decide, dim3(n), dim3(NT), 0, s, secs, G, lp);
+    if (spectral_possible) {
+        if (lp.precision == 1)
+            hipLaunchKernelGGL(k_wide_mfma<1>, grid, dim3(NT), 0, s, secs, G, lp);
+        else if (lp.precision == 2)
+            hipLaunchKernelGGL(k_wide_mfma<2>, grid, dim3(NT), 0, s, secs, G, lp);
+        hipLaunchKernelGGL(k_wide_fp32, grid, dim3(NT), 0, s, secs, G, lp);
+        hipLaunchKernelGGL(k_wide_finish, dim3(n), dim3(NT), 0, s, secs, G, lp);
+    }
     return hipGetLastError();
 }
 

@@ -149,3 +149,18 @@ def test_graph_batch_replays():
             stream.synchronize()
             for a, b in zip(eager.labels, outs):
                 assert torch.equal(a, b), f"batch replay {k} differs"
+
+
+@pytest.mark.parametrize("mode", ["persistent", "wide"])
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_level_modes_identical(mode, prec, monkeypatch):
+    """Every level run by the persistent driver, or every level in wide mode
+    (G workgroups per section, one launch sequence per iteration)."""
+    monkeypatch.setenv("HSWO_WIDE_MAX_SECTIONS", "0" if mode == "persistent" else "100000")
+    sc = synth.voronoi_scene(96, 80, 20, 14, 25.0, 55)
+    p = dict(connectivity=4, seam_connectivity=8, spclust_wght=0.5, spclust_max=300, target_regions=5,
+             section_regions=80, level_counts=[300, 64, 5])
+    _say(f"[gpu] level mode {mode} prec={prec}")
+    res = hswo.rhseg_segment(torch.from_numpy(sc.cube).cuda(), rnb_levels=3, precision=prec, merge_log=True,
+                             stats=True, **p)
+    check_against_oracle(sc.cube, res.labels.cpu().numpy(), res.log, dict(p, rnb_levels=3), f"{mode}/{prec}")
