@@ -91,6 +91,9 @@ extern "C" {
                                  replay it on later calls with the same pointers, shapes and
                                  parameters (needs a non-null stream); graphs are cached per
                                  process (up to 16, oldest evicted) */
+#define HSWO_FLAG_INCREMENTAL 8 /* keep each adjacent pair's exact D2 and re-score only the pairs a merge
+                                   changed (the adjacent minimum is then a reduction over the cached
+                                   values); same merges and labels as the full per-iteration sweep */
 #define HSWO_FLAG_AUTOTUNE 4  /* on the first call for a shape bucket, time every section-driver
                                  variant on the call itself (all give identical results) and keep
                                  the fastest; the choice is cached per process and appended to the

@@ -53,11 +53,10 @@ void split4(const Rect& r, Rect q[4]) {
     q[3] = {r.r0 + h0, r.c0 + w0, r.h - h0, r.w - w0};
 }
 
-int64_t grid_edges(int h, int w, int conn) {
-    int64_t e = (int64_t)h * (w - 1) + (int64_t)(h - 1) * w;
-    if (conn == 8) e += 2 * (int64_t)(h - 1) * (w - 1);
-    return e;
-}
+// Edge slots of a leaf: one per pixel and forward neighbour direction (the
+// boundary's missing neighbours are empty slots until the first merge).
+int64_t grid_edges(int h, int w, int conn) { return (int64_t)h * w * (conn == 8 ? 4 : 2); }
+
 
 int64_t seam_bound(const Rect& r, int seam_conn) { return (int64_t)(r.w + 2 * r.h) * (seam_conn == 8 ? 4 : 2); }
 
@@ -168,7 +167,9 @@ Plan make_plan(int H, int W, int B, const hswo_params* p, int L) {
                 for (int k = 0; k < 4; ++k) {
                     const SecPlan& c = pl.lv[d + 1][4 * i + k];
                     s.cap += c.fin;
-                    s.ecap += std::min<int64_t>(c.ecap, c.fin * (c.fin - 1) / 2);
+                    // a child that merges ends with distinct real edges only; one that
+                    // makes no merge hands over its slots as they are
+                    s.ecap += c.cap > c.stop ? std::min<int64_t>(c.ecap, c.fin * (c.fin - 1) / 2) : c.ecap;
                 }
                 s.seam = seam_bound(s.rect, p->seam_connectivity);
                 s.ecap += s.seam;
@@ -249,6 +250,10 @@ Layout carve(const Plan& pl, int H, int W, const hswo_params* p, void* ws, const
             s.mean = bp.take<float>(sp.cap * pl.Bp);
             s.edges = bp.take<int2>(sp.ecap);
             s.escr = bp.take<float2>(sp.ecap);
+            if (p->flags & HSWO_FLAG_INCREMENTAL) {
+                s.ed2 = bp.take<double>(sp.ecap);
+                s.edirty = bp.take<int32_t>(sp.ecap);
+            }
             s.tstat = bp.take<float2>(sp.tiles);
             s.tflag = bp.take<int32_t>(sp.tiles);
             if (p->precision != HSWO_PREC_FP32 && p->spclust_wght > 0.0f && p->spclust_max > 0) {
@@ -603,7 +608,7 @@ LoopParams loop_params(const hswo_params* p, unsigned long long* counters) {
     lp.spectral = p->spclust_wght > 0.0f && p->spclust_max > 0 ? 1 : 0;
     lp.kmax = p->spclust_max;
     lp.precision = p->precision;
-    lp.pad = 0;
+    lp.incremental = (p->flags & HSWO_FLAG_INCREMENTAL) ? 1 : 0;
     lp.counters = counters;
     return lp;
 }
@@ -611,7 +616,7 @@ LoopParams loop_params(const hswo_params* p, unsigned long long* counters) {
 int check_common(const hswo_params* p, void* workspace) {
     if (!workspace) return fail(HSWO_E_INVAL, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(HSWO_E_INVAL, "workspace must be 256-byte aligned");
-    if (p->flags & ~(HSWO_FLAG_MERGE_LOG | HSWO_FLAG_GRAPH | HSWO_FLAG_AUTOTUNE))
+    if (p->flags & ~(HSWO_FLAG_MERGE_LOG | HSWO_FLAG_GRAPH | HSWO_FLAG_AUTOTUNE | HSWO_FLAG_INCREMENTAL))
         return fail(HSWO_E_INVAL, "unknown flags 0x%x", p->flags);
     return HSWO_OK;
 }
@@ -770,6 +775,10 @@ BatchLayout carve_batch(int n, const hswo_section* sec, const hswo_params* p, vo
         s.mean = bp.take<float>(cap * Bp);
         s.edges = bp.take<int2>(ecap);
         s.escr = bp.take<float2>(ecap);
+        if (p->flags & HSWO_FLAG_INCREMENTAL) {
+            s.ed2 = bp.take<double>(ecap);
+            s.edirty = bp.take<int32_t>(ecap);
+        }
         s.tstat = bp.take<float2>(tiles);
         s.tflag = bp.take<int32_t>(tiles);
         if (p->precision != HSWO_PREC_FP32 && p->spclust_wght > 0.0f && p->spclust_max > 0) {

@@ -68,11 +68,15 @@ struct SecDev {
     float* cvec;     // [Bp] centring spectrum, fixed when the spectral stage starts
     int32_t kcap;    // rows available for the 16-bit screen (0 on the plain path)
     int32_t pad1;
+    // incremental adjacent stage: exact D2 per edge slot and the edges to refresh
+    double* ed2;     // [Ecap]
+    int32_t* edirty; // [Ecap]
     // wide mode iteration scratch
     int32_t* wi;     // [8]
     double* wd;      // [2]
     float* wpart;    // [2 * GMAX]
-    int32_t* st;     // state: [0] R, [1] E, [2] R at pass start, [3] merges done, [4] 16-bit rows ready
+    int32_t* st;     // state: [0] R, [1] E, [2] R at pass start, [3] merges done, [4] 16-bit rows ready,
+                     //        [5] per-edge exact D2 cache valid
     int32_t* parent; // label-indexed union-find parent (image or batch section)
     int32_t* mtime;  // label-indexed merge time: -1 non-top merge, k top merge, INT_MAX alive
     hswo_merge_rec* log;  // section merge log base (may be null)
@@ -113,7 +117,7 @@ struct LoopParams {
     int32_t spectral; // w > 0
     int32_t kmax;     // spectral stage iff R <= kmax
     int32_t precision;
-    int32_t pad;
+    int32_t incremental;  // adjacent minimum from cached exact per-edge D2 (only changed edges re-scored)
     unsigned long long* counters;  // [C_COUNT]
 };
 

@@ -74,7 +74,8 @@ struct Fmt16<2> {
     }
 };
 
-constexpr int G16_LD = 40;  // LDS row stride (elements) of the 16-bit operand tiles
+constexpr int KSLAB = 256;           // bands of the 16-bit operands staged in LDS at a time
+constexpr int G16_LD = KSLAB + 8;    // LDS row stride (elements) of the 16-bit operand tiles
 
 struct KeyD {
     double d2;
@@ -105,6 +106,7 @@ struct Smem {
         struct {
             float As[BK][TILE + 4];
             float Cs[BK][TILE + 4];
+            int cand[CAND_CAP];
         } f;
         struct {
             uint16_t A[STILE][G16_LD];
@@ -112,7 +114,6 @@ struct Smem {
             float Prow[STILE], Arow[STILE], Pcol[STILE], Acol[STILE];
         } g;
     } u;
-    int cand[CAND_CAP];
     float redf[2][NWAVE];
     int redi[NWAVE];
     double redd[NWAVE];
@@ -120,6 +121,7 @@ struct Smem {
     double csum[NWAVE][16];
     int ncand;
     int bcast_i[4];
+    unsigned long long cnt[C_COUNT];  // per-block counters and stage clocks (thread 0 only)
 };
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
@@ -279,12 +281,27 @@ __device__ double exact_d2_wave(Smem& sh, const SecDev& s, int si, int sj) {
     return fac * acc;
 }
 
+// Exact score of edge e into the per-edge cache (one wavefront; +inf for an
+// empty slot).
+__device__ __forceinline__ void score_edge_exact(Smem& sh, const SecDev& s, int e) {
+    const int2 ed = s.edges[e];
+    double v = __builtin_huge_val();
+    if (ed.x >= 0) {
+        int a = ed.x, b = ed.y;
+        if (s.label[a] > s.label[b]) {
+            const int t = a; a = b; b = t;
+        }
+        v = exact_d2_wave(sh, s, a, b);
+    }
+    if (lane_id() == 0) s.ed2[e] = v;
+}
+
 // Exact lexicographic minimum over the first n entries of the LDS candidate
 // list. Adjacent mode: entries are edge indices; spectral mode: (i<<16)|j.
 __device__ KeyD exact_best_of_list(Smem& sh, const SecDev& s, int n, bool edge_mode) {
     KeyD best = key_none();
     for (int c = wave_id(); c < n; c += NWAVE) {
-        const int ent = sh.cand[c];
+        const int ent = sh.u.f.cand[c];
         int a, b;
         if (edge_mode) {
             const int2 e = s.edges[ent];
@@ -463,41 +480,56 @@ __device__ int mfma_screen(Smem& sh, const SecDev& s, int R, int g0, int gstride
     const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
     const int wi = w >> 1, wj = w & 1;
     const int nT = (R + TILE - 1) / TILE, nS = (R + STILE - 1) / STILE;
-    const int lrow = tid >> 2, lseg = (tid & 3) * 8;
+    const int Bp = s.Bp;
+    const int nslab = (Bp + KSLAB - 1) / KSLAB;
     int nsup = 0, q = 0;
-    for (int IB = 0; IB < nS; ++IB)
+    for (int IB = 0; IB < nS; ++IB) {
+        bool a_ready = false;  // the row block stays in LDS across this row of super tiles
         for (int JB = IB; JB < nS; ++JB, ++q) {
             if (q < g0 || (q - g0) % gstride != 0) continue;  // block-uniform
             ++nsup;
-            __syncthreads();  // previous tile's LDS reads are done
-            if (tid < STILE) {
-                const int r = IB * STILE + tid;
-                sh.u.g.Prow[tid] = r < R ? s.gP[r] : 0.0f;
-                sh.u.g.Arow[tid] = r < R ? s.galpha[r] : 0.0f;
-            } else if (tid < 2 * STILE) {
-                const int c = JB * STILE + tid - STILE;
-                sh.u.g.Pcol[tid - STILE] = c < R ? s.gP[c] : 0.0f;
-                sh.u.g.Acol[tid - STILE] = c < R ? s.galpha[c] : 0.0f;
-            }
             f32x16 acc0 = {}, acc1 = {};
-            const int ra = IB * STILE + lrow, rc = JB * STILE + lrow;
-            for (int k0 = 0; k0 < s.Bp; k0 += 32) {
-                uint4 va = make_uint4(0u, 0u, 0u, 0u), vc = va;
-                if (ra < R) va = *reinterpret_cast<const uint4*>(s.g16 + (size_t)ra * s.Bp + k0 + lseg);
-                if (rc < R) vc = *reinterpret_cast<const uint4*>(s.g16 + (size_t)rc * s.Bp + k0 + lseg);
-                *reinterpret_cast<uint4*>(&sh.u.g.A[lrow][lseg]) = va;
-                *reinterpret_cast<uint4*>(&sh.u.g.C[lrow][lseg]) = vc;
+            for (int sl = 0; sl < nslab; ++sl) {
+                const int k0 = sl * KSLAB;
+                const int kw = min(KSLAB, Bp - k0);  // a multiple of 32
+                const int segs = kw >> 3;           // 16-byte segments per row
+                __syncthreads();  // previous reads of the LDS tiles are done
+                if (!a_ready) {
+                    for (int idx = tid; idx < STILE * segs; idx += NT) {
+                        const int r = idx / segs, sg = idx % segs;
+                        const int gr = IB * STILE + r;
+                        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                        if (gr < R) v = *reinterpret_cast<const uint4*>(s.g16 + (size_t)gr * Bp + k0 + sg * 8);
+                        *reinterpret_cast<uint4*>(&sh.u.g.A[r][sg * 8]) = v;
+                    }
+                    if (tid < STILE) {
+                        const int r = IB * STILE + tid;
+                        sh.u.g.Prow[tid] = r < R ? s.gP[r] : 0.0f;
+                        sh.u.g.Arow[tid] = r < R ? s.galpha[r] : 0.0f;
+                    }
+                }
+                for (int idx = tid; idx < STILE * segs; idx += NT) {
+                    const int r = idx / segs, sg = idx % segs;
+                    const int gc = JB * STILE + r;
+                    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                    if (gc < R) v = *reinterpret_cast<const uint4*>(s.g16 + (size_t)gc * Bp + k0 + sg * 8);
+                    *reinterpret_cast<uint4*>(&sh.u.g.C[r][sg * 8]) = v;
+                }
+                if (sl == 0 && tid >= STILE && tid < 2 * STILE) {
+                    const int c = JB * STILE + tid - STILE;
+                    sh.u.g.Pcol[tid - STILE] = c < R ? s.gP[c] : 0.0f;
+                    sh.u.g.Acol[tid - STILE] = c < R ? s.galpha[c] : 0.0f;
+                }
                 __syncthreads();
-#pragma unroll
-                for (int kk = 0; kk < 2; ++kk) {
-                    const int kc = kk * 16 + 8 * (lane >> 5);
+                for (int kk = 0; kk < kw; kk += 16) {
+                    const int kc = kk + 8 * (lane >> 5);
                     const V a = *reinterpret_cast<const V*>(&sh.u.g.A[32 * wi + (lane & 31)][kc]);
                     const V b0 = *reinterpret_cast<const V*>(&sh.u.g.C[64 * wj + (lane & 31)][kc]);
                     const V b1 = *reinterpret_cast<const V*>(&sh.u.g.C[64 * wj + 32 + (lane & 31)][kc]);
                     acc0 = F::mfma(a, b0, acc0);
                     acc1 = F::mfma(a, b1, acc1);
                 }
-                __syncthreads();
+                a_ready = (nslab == 1);
             }
             bool any = false;
 #pragma unroll
@@ -520,6 +552,7 @@ __device__ int mfma_screen(Smem& sh, const SecDev& s, int R, int g0, int gstride
                 if (ti <= tj && tj < nT) s.tflag[tile_index(ti, tj, nT)] = 1;
             }
         }
+    }
     __syncthreads();
     return nsup;
 }
@@ -578,12 +611,17 @@ __device__ void merge_pair(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R,
     // relabel hi -> lo, drop the merged pair and duplicate (lo, x) edges,
     // rename the moved slot, compact in place (writes never pass reads)
     const int last = R - 1;
+    const bool inc = s.ed2 != nullptr && s.st[5] != 0;
+    const int surv = (lo_s == last) ? hi_s : lo_s;  // the survivor's slot after the swap-remove
+    if (tid == 0) sh.bcast_i[2] = 0;
     int newE = 0;
     for (int e0 = 0; e0 < E; e0 += NT) {
         const int e = e0 + tid;
         bool keep = false;
         int a = 0, b = 0;
+        double v = 0.0;
         if (e < E) {
+            if (inc) v = s.ed2[e];
             const int2 ed = s.edges[e];
             a = ed.x;
             b = ed.y;
@@ -600,7 +638,13 @@ __device__ void merge_pair(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R,
         }
         int tot;
         const int pos = block_scan_flag(sh, keep, &tot);  // barrier: chunk fully read
-        if (keep) s.edges[newE + pos] = make_int2(a, b);
+        if (keep) {
+            s.edges[newE + pos] = make_int2(a, b);
+            if (inc) {
+                s.ed2[newE + pos] = v;
+                if (a == surv || b == surv) s.edirty[atomicAdd(&sh.bcast_i[2], 1)] = newE + pos;
+            }
+        }
         newE += tot;
     }
     E = newE;
@@ -630,6 +674,11 @@ __device__ void merge_pair(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R,
         }
     }
     __syncthreads();
+    if (inc) {  // re-score the survivor's edges; every other edge keeps its cached value
+        const int nd = sh.bcast_i[2];
+        for (int i = wave_id(); i < nd; i += NWAVE) score_edge_exact(sh, s, s.edirty[i]);
+        __syncthreads();
+    }
 }
 
 }  // namespace
@@ -702,11 +751,15 @@ __device__ float adj_screen_range(const SecDev& s, int e_begin, int e_end, float
                 mb = eb[k];
             }
         }
-        if (gl < EPG && ma >= 0) {
+        if (gl < EPG) {
             const int e = e0 + g * EPG + gl;
-            const float2 lu = screen_bounds(mine, s.npix[ma], s.npix[mb], s.norm[ma], s.norm[mb], gam);
-            s.escr[e] = lu;
-            myU = fminf(myU, lu.y);
+            if (ma >= 0) {
+                const float2 lu = screen_bounds(mine, s.npix[ma], s.npix[mb], s.norm[ma], s.norm[mb], gam);
+                s.escr[e] = lu;
+                myU = fminf(myU, lu.y);
+            } else if (e < e_end) {
+                s.escr[e] = make_float2(__builtin_huge_valf(), __builtin_huge_valf());  // empty slot
+            }
         }
     }
     return myU;
@@ -719,14 +772,47 @@ __device__ KeyD adj_collect(Smem& sh, const SecDev& s, int E, float Ua, int& nch
     KeyD A = key_none();
     for (int e0 = 0; e0 < E; e0 += NT) {
         const int e = e0 + tid;
-        if (e < E && s.escr[e].x <= Ua) {
+        const float lo = e < E ? s.escr[e].x : __builtin_huge_valf();
+        if (lo <= Ua && lo < __builtin_huge_valf()) {  // empty slots have +inf bounds
             const int k = atomicAdd(&sh.ncand, 1);
-            if (k < CAND_CAP) sh.cand[k] = e;
+            if (k < CAND_CAP) sh.u.f.cand[k] = e;
         }
         flush_candidates(sh, s, A, nchk, true, NT);
     }
     flush_candidates(sh, s, A, nchk, true, CAND_CAP);
     return A;
+}
+
+// Incremental adjacent stage: the exact lexicographic minimum over the cached
+// per-edge D2 (scoring every edge first when the cache is not yet valid).
+// Labels are read only for values that can still win.
+__device__ KeyD adj_incremental(Smem& sh, const SecDev& s, int E, bool init, int& nchk) {
+    if (init) {
+        for (int e = wave_id(); e < E; e += NWAVE) score_edge_exact(sh, s, e);
+        nchk += E;
+        __syncthreads();
+    }
+    KeyD best = key_none();
+    for (int e = threadIdx.x; e < E; e += NT) {
+        const double v = s.ed2[e];
+        if (v <= best.d2 && v < __builtin_huge_val()) {
+            const int2 ed = s.edges[e];
+            int a = ed.x, b = ed.y;
+            int la = s.label[a], lb = s.label[b];
+            if (la > lb) {
+                const int t = a; a = b; b = t;
+                const int u = la; la = lb; lb = u;
+            }
+            KeyD k;
+            k.d2 = v;
+            k.lo = la;
+            k.hi = lb;
+            k.si = a;
+            k.sj = b;
+            if (key_less(k, best)) best = k;
+        }
+    }
+    return block_min_key(sh, best);
 }
 
 // FP32 spectral tiles t = t0, t0 + stride, ...: per-tile (min lower, min
@@ -807,7 +893,7 @@ __device__ KeyD spectral_collect(Smem& sh, const SecDev& s, int R, double T, dou
                         const float lo = screen_bounds(acc[a][c], s.npix[i], s.npix[j], s.norm[i], s.norm[j], gam).x;
                         if ((double)lo <= theta && (double)lo < T) {
                             const int k = atomicAdd(&sh.ncand, 1);
-                            if (k < CAND_CAP) sh.cand[k] = (int)(((unsigned)i << 16) | (unsigned)j);
+                            if (k < CAND_CAP) sh.u.f.cand[k] = (int)(((unsigned)i << 16) | (unsigned)j);
                         }
                     }
                 }
@@ -855,21 +941,32 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
     int g_ready = s.st[4];
     const int prec = s.kcap > 0 ? lp.precision : 0;
     const float gam = (float)(2 * s.B + 32) * U32;
-    unsigned long long c_adj = 0, c_spec = 0, c_chk = 0, c_resc = 0, c_it = 0, c_f32 = 0, c_mf = 0;
-    unsigned long long t_adj = 0, t_mf = 0, t_s32 = 0, t_mrg = 0;  // constant-clock ticks (thread 0)
-    if (tid == 0) sh.ncand = 0;
+    if (tid == 0) {
+        sh.ncand = 0;
+        for (int c = 0; c < C_COUNT; ++c) sh.cnt[c] = 0ull;
+    }
     __syncthreads();
+#define CNT_ADD(k, v)                             \
+    do {                                          \
+        if (tid == 0) sh.cnt[k] += (unsigned long long)(v); \
+    } while (0)
 
     while (R > s.stop) {
         unsigned long long tk0 = wall_clock64();
-        // adjacent stage
-        const float myU = adj_screen_range<EPG>(s, 0, E, gam);
-        const float Ua = block_min_f2(sh, myU, myU).x;
+        // adjacent stage: full screen of every edge, or the cached exact values
         int nchk = 0;
-        const KeyD A = adj_collect(sh, s, E, Ua, nchk);
-        c_adj += (unsigned long long)E;
+        KeyD A;
+        if (lp.incremental) {
+            A = adj_incremental(sh, s, E, s.st[5] == 0, nchk);
+            if (tid == 0) s.st[5] = 1;
+        } else {
+            const float myU = adj_screen_range<EPG>(s, 0, E, gam);
+            const float Ua = block_min_f2(sh, myU, myU).x;
+            A = adj_collect(sh, s, E, Ua, nchk);
+        }
+        CNT_ADD(C_ADJ_PAIRS, E);
         unsigned long long tk1 = wall_clock64();
-        t_adj += tk1 - tk0;
+        CNT_ADD(C_T_ADJ, tk1 - tk0);
         tk0 = tk1;
 
         // spectral stage
@@ -889,50 +986,41 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
             if (use16) {
                 prep_alpha_p(s, R, T);
                 clear_tile_flags(s, R);
-                c_mf += (unsigned long long)(prec == 1 ? mfma_screen<1>(sh, s, R, 0, 1) : mfma_screen<2>(sh, s, R, 0, 1));
+                CNT_ADD(C_MFMA_TILES, prec == 1 ? mfma_screen<1>(sh, s, R, 0, 1) : mfma_screen<2>(sh, s, R, 0, 1));
             }
             tk1 = wall_clock64();
-            t_mf += tk1 - tk0;
+            CNT_ADD(C_T_MFMA, tk1 - tk0);
             tk0 = tk1;
             int nf = 0, nresc = 0;
             const float Us = fp32_tiles(sh, s, R, use16, gam, 0, 1, nf);
             const double theta = fmin((double)Us, T);
             M = spectral_collect(sh, s, R, T, theta, gam, nchk, nresc);
-            c_f32 += (unsigned long long)nf;
-            c_spec += (unsigned long long)R * (unsigned long long)(R - 1) / 2ull;
-            c_resc += (unsigned long long)nresc;
+            CNT_ADD(C_FP32_TILES, nf);
+            CNT_ADD(C_SPEC_PAIRS, (unsigned long long)R * (unsigned long long)(R - 1) / 2ull);
+            CNT_ADD(C_RESCANS, nresc);
             tk1 = wall_clock64();
-            t_s32 += tk1 - tk0;
+            CNT_ADD(C_T_SPEC32, tk1 - tk0);
             tk0 = tk1;
         }
 
         KeyD win;
         int kind;
         if (!decide(spectral, A, M, T, win, kind)) break;  // no pair left (not in a connected section)
-        c_chk += (unsigned long long)nchk;
-        c_it += 1ull;
+        CNT_ADD(C_RECHECKS, nchk);
+        CNT_ADD(C_ITERS, 1);
+        CNT_ADD(C_MERGES, 1);
         merge_pair(sh, s, win.si, win.sj, R, E, s.st[3], kind, win.d2, g_ready, prec);
         --R;
-        t_mrg += wall_clock64() - tk0;
+        CNT_ADD(C_T_MERGE, wall_clock64() - tk0);
     }
+#undef CNT_ADD
     if (tid == 0) {
         s.st[0] = R;
         s.st[1] = E;
         s.st[4] = g_ready;
-        if (lp.counters) {
-            atomicAdd(&lp.counters[C_FP32_TILES], c_f32);
-            atomicAdd(&lp.counters[C_MFMA_TILES], c_mf);
-            atomicAdd(&lp.counters[C_T_ADJ], t_adj);
-            atomicAdd(&lp.counters[C_T_MFMA], t_mf);
-            atomicAdd(&lp.counters[C_T_SPEC32], t_s32);
-            atomicAdd(&lp.counters[C_T_MERGE], t_mrg);
-            atomicAdd(&lp.counters[C_ITERS], c_it);
-            atomicAdd(&lp.counters[C_MERGES], c_it);
-            atomicAdd(&lp.counters[C_ADJ_PAIRS], c_adj);
-            atomicAdd(&lp.counters[C_SPEC_PAIRS], c_spec);
-            atomicAdd(&lp.counters[C_RECHECKS], c_chk);
-            atomicAdd(&lp.counters[C_RESCANS], c_resc);
-        }
+        if (lp.counters)
+            for (int c = 0; c < C_COUNT; ++c)
+                if (sh.cnt[c]) atomicAdd(&lp.counters[c], sh.cnt[c]);
     }
 }
 
@@ -977,10 +1065,17 @@ __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ s
     const int prec = s.kcap > 0 ? lp.precision : 0;
     if (tid == 0) sh.ncand = 0;
     __syncthreads();
-    float Ua = __builtin_huge_valf();
-    for (int g = 0; g < G; ++g) Ua = fminf(Ua, s.wpart[g]);
     int nchk = 0;
-    const KeyD A = adj_collect(sh, s, E, Ua, nchk);
+    KeyD A;
+    if (lp.incremental) {
+        A = adj_incremental(sh, s, E, s.st[5] == 0, nchk);
+        if (tid == 0) s.st[5] = 1;
+        __syncthreads();
+    } else {
+        float Ua = __builtin_huge_valf();
+        for (int g = 0; g < G; ++g) Ua = fminf(Ua, s.wpart[g]);
+        A = adj_collect(sh, s, E, Ua, nchk);
+    }
     const bool spectral = lp.spectral && R <= lp.kmax;
     const double T = key_exists(A) ? lp.w2 * A.d2 : __builtin_huge_val();
     if (!spectral) {
@@ -1160,30 +1255,29 @@ __global__ void k_init_leaves(const SecDev* __restrict__ secs, const InitDev* __
         }
         s.norm[k] = (float)(sqrt(nrm) * (1.0 + 0x1p-20));
     }
-    // grid edges: horizontal, vertical, then (8-connectivity) both diagonals
-    const int64_t nh = (int64_t)h * (w - 1), nv = (int64_t)(h - 1) * w, nd = (int64_t)(h - 1) * (w - 1);
-    const int64_t E0 = nh + nv + (in.conn == 8 ? 2 * nd : 0);
+    // grid edges in pixel order: pixel k owns slots k*nf .. k*nf+nf-1 for its
+    // right, down (and, under 8-connectivity, down-right, down-left)
+    // neighbours, so the two rows of consecutive edges stay close. Slots
+    // without a neighbour hold (-1,-1): the screen gives them +inf bounds and
+    // the first merge's order-preserving compaction removes them.
+    const int nf = in.conn == 8 ? 4 : 2;
+    const int64_t E0 = (int64_t)P * nf;
     for (int64_t e = t0; e < E0; e += stride) {
-        int a, b;
-        if (e < nh) {
-            const int r = (int)(e / (w - 1)), c = (int)(e % (w - 1));
-            a = r * w + c;
-            b = a + 1;
-        } else if (e < nh + nv) {
-            const int64_t f = e - nh;
-            const int r = (int)(f / w), c = (int)(f % w);
-            a = r * w + c;
-            b = a + w;
-        } else if (e < nh + nv + nd) {
-            const int64_t f = e - nh - nv;
-            const int r = (int)(f / (w - 1)), c = (int)(f % (w - 1));
-            a = r * w + c;
-            b = a + w + 1;
-        } else {
-            const int64_t f = e - nh - nv - nd;
-            const int r = (int)(f / (w - 1)), c = (int)(f % (w - 1)) + 1;
-            a = r * w + c;
-            b = a + w - 1;
+        const int k = (int)(e / nf), f = (int)(e % nf);
+        const int r = k / w, c = k % w;
+        int a = -1, b = -1;
+        if (f == 0 && c + 1 < w) {
+            a = k;
+            b = k + 1;
+        } else if (f == 1 && r + 1 < h) {
+            a = k;
+            b = k + w;
+        } else if (f == 2 && r + 1 < h && c + 1 < w) {
+            a = k;
+            b = k + w + 1;
+        } else if (f == 3 && r + 1 < h && c >= 1) {
+            a = k;
+            b = k + w - 1;
         }
         s.edges[e] = make_int2(a, b);
     }
@@ -1193,6 +1287,7 @@ __global__ void k_init_leaves(const SecDev* __restrict__ secs, const InitDev* __
         s.st[2] = P;
         s.st[3] = 0;
         s.st[4] = 0;
+        s.st[5] = 0;
     }
 }
 
@@ -1239,6 +1334,7 @@ __global__ void k_assemble(const SecDev* __restrict__ parents, const SecDev* __r
             p.st[2] = 0;
             p.st[3] = 0;
             p.st[4] = 0;
+            p.st[5] = 0;
         }
         return;
     }
@@ -1263,7 +1359,8 @@ __global__ void k_assemble(const SecDev* __restrict__ parents, const SecDev* __r
             p.mean[(size_t)off[c] * Bp + idx] = ch.mean[idx];
         for (int64_t e = t0; e < Ec; e += stride) {
             const int2 ed = ch.edges[e];
-            p.edges[eoff[c] + e] = make_int2(ed.x + off[c], ed.y + off[c]);
+            // empty slots (a child that made no merge still has them) stay empty
+            p.edges[eoff[c] + e] = ed.x < 0 ? make_int2(-1, -1) : make_int2(ed.x + off[c], ed.y + off[c]);
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1272,6 +1369,7 @@ __global__ void k_assemble(const SecDev* __restrict__ parents, const SecDev* __r
         p.st[2] = off[4];
         p.st[3] = 0;
         p.st[4] = 0;
+        p.st[5] = 0;
     }
 }
 
@@ -1404,12 +1502,14 @@ hipError_t launch_section_driver(const SecDev* secs, int n, const LoopParams& lp
 hipError_t launch_wide_iteration(const SecDev* secs, int n, int G, const LoopParams& lp, int variant,
                                  bool spectral_possible, hipStream_t s) {
     const dim3 grid(G, n);
-    if (variant == 2)
-        hipLaunchKernelGGL(k_wide_adj<2>, grid, dim3(NT), 0, s, secs, G);
-    else if (variant == 4)
-        hipLaunchKernelGGL(k_wide_adj<4>, grid, dim3(NT), 0, s, secs, G);
-    else
-        hipLaunchKernelGGL(k_wide_adj<6>, grid, dim3(NT), 0, s, secs, G);
+    if (!lp.incremental) {
+        if (variant == 2)
+            hipLaunchKernelGGL(k_wide_adj<2>, grid, dim3(NT), 0, s, secs, G);
+        else if (variant == 4)
+            hipLaunchKernelGGL(k_wide_adj<4>, grid, dim3(NT), 0, s, secs, G);
+        else
+            hipLaunchKernelGGL(k_wide_adj<6>, grid, dim3(NT), 0, s, secs, G);
+    }
     hipLaunchKernelGGL(k_wide_decide, dim3(n), dim3(NT), 0, s, secs, G, lp);
     if (spectral_possible) {
         if (lp.precision == 1)

@@ -30,6 +30,7 @@ PREC = {"fp32": 0, "bf16": 1, "fp16": 2}
 HSWO_FLAG_MERGE_LOG = 1
 HSWO_FLAG_GRAPH = 2
 HSWO_FLAG_AUTOTUNE = 4
+HSWO_FLAG_INCREMENTAL = 8
 
 MERGE_DTYPE = np.dtype([("lo", "<i4"), ("hi", "<i4"), ("kind", "<i4"), ("r_after", "<i4"), ("d2", "<f8")])
 
@@ -131,14 +132,14 @@ def last_error() -> str:
 
 def make_params(*, connectivity=4, seam_connectivity=8, spclust_wght=0.0, spclust_max=0, target_regions=1,
                 section_regions=0, rnb_levels=1, level_counts: Optional[Sequence[int]] = None,
-                precision="fp32", merge_log=False, graph=False, autotune=False, **_ignored):
+                precision="fp32", merge_log=False, graph=False, autotune=False, incremental=False, **_ignored):
     counts = list(level_counts) if level_counts is not None else [target_regions]
     arr = (ctypes.c_int32 * len(counts))(*counts)
     p = Params(connectivity, seam_connectivity, spclust_wght, spclust_max, target_regions, section_regions,
                rnb_levels, len(counts), ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32)),
                PREC[precision] if isinstance(precision, str) else int(precision),
                (HSWO_FLAG_MERGE_LOG if merge_log else 0) | (HSWO_FLAG_GRAPH if graph else 0) |
-               (HSWO_FLAG_AUTOTUNE if autotune else 0))
+               (HSWO_FLAG_AUTOTUNE if autotune else 0) | (HSWO_FLAG_INCREMENTAL if incremental else 0))
     p._counts_keepalive = arr  # the struct holds a raw pointer into arr
     return p
 

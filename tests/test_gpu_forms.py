@@ -164,3 +164,35 @@ def test_level_modes_identical(mode, prec, monkeypatch):
     res = hswo.rhseg_segment(torch.from_numpy(sc.cube).cuda(), rnb_levels=3, precision=prec, merge_log=True,
                              stats=True, **p)
     check_against_oracle(sc.cube, res.labels.cpu().numpy(), res.log, dict(p, rnb_levels=3), f"{mode}/{prec}")
+
+
+@pytest.mark.parametrize("mode", ["persistent", "wide"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_incremental_adjacent_identical(mode, prec, monkeypatch):
+    """Cached exact per-edge D2, re-scoring only what a merge changed: the
+    same merges and labels as the full sweep (and the oracle)."""
+    monkeypatch.setenv("HSWO_WIDE_MAX_SECTIONS", "0" if mode == "persistent" else "100000")
+    sc = synth.voronoi_scene(96, 80, 20, 14, 25.0, 56)
+    p = dict(connectivity=4, seam_connectivity=8, spclust_wght=0.5, spclust_max=300, target_regions=5,
+             section_regions=80, level_counts=[300, 64, 5])
+    _say(f"[gpu] incremental {mode} prec={prec}")
+    res = hswo.rhseg_segment(torch.from_numpy(sc.cube).cuda(), rnb_levels=3, precision=prec, merge_log=True,
+                             incremental=True, stats=True, **p)
+    check_against_oracle(sc.cube, res.labels.cpu().numpy(), res.log, dict(p, rnb_levels=3), f"inc {mode}/{prec}")
+
+
+def test_incremental_batch_and_salt():
+    cubes = uneven_sections(6, seed0=4321)
+    _say("[gpu] incremental batch")
+    res = hswo.hswo_run_batch([torch.from_numpy(c).cuda() for c in cubes], precision="fp16", merge_log=True,
+                              incremental=True, **BATCH_P)
+    torch.cuda.synchronize()
+    for i, c in enumerate(cubes):
+        check_against_oracle(c, res.labels[i].cpu().numpy(), res.logs[i], BATCH_P, f"inc section {i}")
+    sc = synth.mixer_scene(40, 40, 12, K=8, sigma=25.0, seed=7, salt=0.05)
+    p = dict(connectivity=8, seam_connectivity=8, spclust_wght=0.5, spclust_max=400, rnb_levels=2,
+             section_regions=100, target_regions=5, level_counts=[300, 40, 5])
+    _say("[gpu] incremental salt ties")
+    r = hswo.rhseg_segment(torch.from_numpy(sc.cube).cuda(), rnb_levels=2, precision="fp16", merge_log=True,
+                           incremental=True, **{k: v for k, v in p.items() if k != "rnb_levels"})
+    check_against_oracle(sc.cube, r.labels.cpu().numpy(), r.log, p, "inc salt")
