@@ -946,6 +946,7 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
         for (int c = 0; c < C_COUNT; ++c) sh.cnt[c] = 0ull;
     }
     __syncthreads();
+// thread 0 adds a plain value (never pass a call: the argument is evaluated by thread 0 only)
 #define CNT_ADD(k, v)                             \
     do {                                          \
         if (tid == 0) sh.cnt[k] += (unsigned long long)(v); \
@@ -986,7 +987,9 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
             if (use16) {
                 prep_alpha_p(s, R, T);
                 clear_tile_flags(s, R);
-                CNT_ADD(C_MFMA_TILES, prec == 1 ? mfma_screen<1>(sh, s, R, 0, 1) : mfma_screen<2>(sh, s, R, 0, 1));
+                // the screen is a block-level function: the whole block calls it, then thread 0 counts
+                const int nsup = prec == 1 ? mfma_screen<1>(sh, s, R, 0, 1) : mfma_screen<2>(sh, s, R, 0, 1);
+                CNT_ADD(C_MFMA_TILES, nsup);
             }
             tk1 = wall_clock64();
             CNT_ADD(C_T_MFMA, tk1 - tk0);
