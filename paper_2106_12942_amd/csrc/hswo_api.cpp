@@ -139,6 +139,12 @@ int64_t tiles_for(int64_t cap, const hswo_params* p) {
     return std::max<int64_t>(1, nT * (nT + 1) / 2);
 }
 
+// The incremental form keeps exact spectral rows instead of screening every
+// pair each iteration (the 16-bit screen rows are then not needed).
+bool row_cache_on(const hswo_params* p) {
+    return (p->flags & HSWO_FLAG_INCREMENTAL) && p->spclust_wght > 0.0f && p->spclust_max > 0;
+}
+
 Plan make_plan(int H, int W, int B, const hswo_params* p, int L) {
     Plan pl;
     pl.L = L;
@@ -256,7 +262,17 @@ Layout carve(const Plan& pl, int H, int W, const hswo_params* p, void* ws, const
             }
             s.tstat = bp.take<float2>(sp.tiles);
             s.tflag = bp.take<int32_t>(sp.tiles);
-            if (p->precision != HSWO_PREC_FP32 && p->spclust_wght > 0.0f && p->spclust_max > 0) {
+            if (row_cache_on(p)) {
+                const int64_t rc = std::min<int64_t>(sp.cap, p->spclust_max);
+                s.rcap = (int32_t)rc;
+                s.m64 = bp.take<double>(rc * pl.B);
+            s.m64r = bp.take<double>(rc * (((int64_t)pl.B + 7) / 8 * 8));
+                s.rbd = bp.take<double>(rc);
+                s.rbp = bp.take<int32_t>(rc);
+                s.rpend = bp.take<int32_t>(rc);
+        s.rpart = bp.take<RowPart>(rc * ((rc + 63) / 64));
+            s.rpart = bp.take<RowPart>(rc * ((rc + 63) / 64));
+                } else if (p->precision != HSWO_PREC_FP32 && p->spclust_wght > 0.0f && p->spclust_max > 0) {
                 const int64_t kc = std::min<int64_t>(sp.cap, p->spclust_max);
                 s.kcap = (int32_t)kc;
                 s.g16 = bp.take<uint16_t>(kc * pl.Bp);
@@ -357,7 +373,7 @@ int timed_driver(Timer* tm, const SecDev* secs, int n, const LoopParams& lp, int
 // launch) or wide (G workgroups per section, one launch sequence per iteration).
 int wide_max_sections() {
     if (const char* e = getenv("HSWO_WIDE_MAX_SECTIONS")) return atoi(e);
-    return 32;
+    return 64;  // measured on the 512x512 workload: its 64 leaves run faster wide (G = 4)
 }
 
 int device_cus() {
@@ -376,8 +392,9 @@ int device_cus() {
 // spectral kernels are launched only for iterations where some section can be
 // in its spectral stage.
 int run_level(Timer* tm, const SecDev* secs, int n, const std::vector<int64_t>& cap, const std::vector<int64_t>& stop,
-              const LoopParams& lp, int variant, hipStream_t stream) {
-    if (n > wide_max_sections()) return timed_driver(tm, secs, n, lp, variant, stream);
+              const LoopParams& lp, bool row_cache, int variant, hipStream_t stream) {
+    if (n > wide_max_sections() || (row_cache && n > ROWS_MAX_SECTIONS))
+        return timed_driver(tm, secs, n, lp, variant, stream);
     const int G = std::max(1, std::min(GMAX, device_cus() / n));
     int64_t iters = 0;
     for (int i = 0; i < n; ++i) iters = std::max(iters, cap[i] - std::min(cap[i], stop[i]));
@@ -389,6 +406,7 @@ int run_level(Timer* tm, const SecDev* secs, int n, const std::vector<int64_t>& 
         tm->drv.push_back(e1);
         HIP_TRY(hipEventRecord(e0, stream));
     }
+    if (row_cache) HIP_TRY(launch_rowcache_prep(secs, n, lp, stream));
     for (int64_t t = 0; t < iters; ++t) {
         bool spec = false;
         if (lp.spectral)
@@ -396,7 +414,7 @@ int run_level(Timer* tm, const SecDev* secs, int n, const std::vector<int64_t>& 
                 const int64_t R = cap[i] - t;
                 spec = R > stop[i] && R <= lp.kmax;
             }
-        HIP_TRY(launch_wide_iteration(secs, n, G, lp, variant, spec, stream));
+        HIP_TRY(launch_wide_iteration(secs, n, G, lp, variant, spec, row_cache, stream));
     }
     if (tm) HIP_TRY(hipEventRecord(e1, stream));
     return HSWO_OK;
@@ -664,6 +682,7 @@ int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_param
     sd.label_w = W;
     add_upload(ups, lay.snap, &sd, 1);
     const LoopParams lp = loop_params(p, lay.counters);
+    const bool row_cache = row_cache_on(p);
     std::vector<std::vector<int64_t>> caps(L), stops(L);
     for (int d = 0; d < L; ++d)
         for (const SecPlan& s : pl.lv[d]) {
@@ -679,7 +698,7 @@ int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_param
             int maxpix = 0;
             for (const SecPlan& s : pl.lv[d]) maxpix = std::max<int>(maxpix, (int)s.cap);
             HIP_TRY(launch_init_leaves(lay.lv[d].secs, lay.lv[d].inits, (int)pl.lv[d].size(), dtype, maxpix, st));
-            const int r = run_level(tm, lay.lv[d].secs, (int)pl.lv[d].size(), caps[d], stops[d], lp, variant, st);
+            const int r = run_level(tm, lay.lv[d].secs, (int)pl.lv[d].size(), caps[d], stops[d], lp, row_cache, variant, st);
             if (r) return r;
         }
         for (int d = L - 2; d >= 0; --d) {
@@ -695,7 +714,7 @@ int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_param
             HIP_TRY(launch_assemble(lay.lv[d].secs, lay.lv[d + 1].secs, lay.lv[d].asms, (int)secs.size(), lay.slotmap,
                                     (int)std::min<int64_t>(maxcap, 1 << 30), st));
             HIP_TRY(launch_seam(lay.lv[d].secs, lay.lv[d].asms, (int)secs.size(), lay.slotmap, (int)maxseam, st));
-            const int r = run_level(tm, lay.lv[d].secs, (int)secs.size(), caps[d], stops[d], lp, variant, st);
+            const int r = run_level(tm, lay.lv[d].secs, (int)secs.size(), caps[d], stops[d], lp, row_cache, variant, st);
             if (r) return r;
         }
         HIP_TRY(launch_snapshot(lay.snap, 1, lay.counts, p->n_levels, (int)P, st));
@@ -781,7 +800,17 @@ BatchLayout carve_batch(int n, const hswo_section* sec, const hswo_params* p, vo
         }
         s.tstat = bp.take<float2>(tiles);
         s.tflag = bp.take<int32_t>(tiles);
-        if (p->precision != HSWO_PREC_FP32 && p->spclust_wght > 0.0f && p->spclust_max > 0) {
+        if (row_cache_on(p)) {
+            const int64_t rc = std::min<int64_t>(cap, p->spclust_max);
+            s.rcap = (int32_t)rc;
+            s.m64 = bp.take<double>(rc * q.B);
+        s.m64r = bp.take<double>(rc * (((int64_t)q.B + 7) / 8 * 8));
+            s.rbd = bp.take<double>(rc);
+            s.rbp = bp.take<int32_t>(rc);
+            s.rpend = bp.take<int32_t>(rc);
+        s.rpart = bp.take<RowPart>(rc * ((rc + 63) / 64));
+            s.rpart = bp.take<RowPart>(rc * ((rc + 63) / 64));
+        } else if (p->precision != HSWO_PREC_FP32 && p->spclust_wght > 0.0f && p->spclust_max > 0) {
             const int64_t kc = std::min<int64_t>(cap, p->spclust_max);
             s.kcap = (int32_t)kc;
             s.g16 = bp.take<uint16_t>(kc * Bp);

@@ -40,6 +40,13 @@ constexpr int GMAX = 256;     // wide mode: most workgroups per section
 constexpr int STILE = 128;    // matrix-core super tile edge (4 spectral tiles)
 
 // One section of one recursion level (or one independent batch section).
+// Partial result of a row-cache task: a row's best candidate among 64 columns.
+struct RowPart {
+    double d2;
+    int32_t lab;   // partner label (orders equal D2 for a fixed row)
+    int32_t slot;  // partner slot (-1: none)
+};
+
 struct SecDev {
     int32_t R0;      // slot capacity (regions at the start of the pass, upper bound)
     int32_t B;       // bands
@@ -67,16 +74,25 @@ struct SecDev {
     float* gP;       // [kcap] per-iteration (1 - kappa) * gn - alpha^2
     float* cvec;     // [Bp] centring spectrum, fixed when the spectral stage starts
     int32_t kcap;    // rows available for the 16-bit screen (0 on the plain path)
-    int32_t pad1;
+    int32_t rcap;    // rows of the spectral row cache (0 when it is off)
     // incremental adjacent stage: exact D2 per edge slot and the edges to refresh
     double* ed2;     // [Ecap]
     int32_t* edirty; // [Ecap]
+    // spectral row cache (incremental form), slots [0, rcap):
+    double* m64;     // [B][rcap] FP64 mean spectra S/n, band-major (column j = slot j)
+    double* m64r;    // [rcap][B8] the same means slot-major, B8 = B rounded up to 8
+    double* rbd;     // [rcap] exact D2 of the row's cached pair
+    int32_t* rbp;    // [rcap] partner slot of that pair (-1: none)
+    int32_t* rpend;  // [rcap] rows to re-evaluate: [0] the last merge's survivor, then stale rows
+    RowPart* rpart;  // [rcap][ceil(rcap / 64)] per-row, per-64-column partial minima
     // wide mode iteration scratch
     int32_t* wi;     // [8]
     double* wd;      // [2]
     float* wpart;    // [2 * GMAX]
     int32_t* st;     // state: [0] R, [1] E, [2] R at pass start, [3] merges done, [4] 16-bit rows ready,
-                     //        [5] per-edge exact D2 cache valid
+                     //        [5] per-edge exact D2 cache valid,
+                     //        [6] row cache: 0 off, 1 means ready (every row pending), 2 valid,
+                     //        [7] pending rows of the row cache
     int32_t* parent; // label-indexed union-find parent (image or batch section)
     int32_t* mtime;  // label-indexed merge time: -1 non-top merge, k top merge, INT_MAX alive
     hswo_merge_rec* log;  // section merge log base (may be null)
@@ -129,7 +145,9 @@ hipError_t launch_init_leaves(const SecDev* secs, const InitDev* init, int n, in
 hipError_t launch_section_driver(const SecDev* secs, int n, const LoopParams& lp, int variant, hipStream_t s);
 constexpr int DRIVER_VARIANTS[3] = {2, 4, 6};  // adjacent-stage edges in flight per lane group
 hipError_t launch_wide_iteration(const SecDev* secs, int n, int G, const LoopParams& lp, int variant,
-                                 bool spectral_possible, hipStream_t s);
+                                 bool spectral_possible, bool row_cache, hipStream_t s);
+constexpr int ROWS_MAX_SECTIONS = 1024;  // sections a row-cache task pool launch can cover
+hipError_t launch_rowcache_prep(const SecDev* secs, int n, const LoopParams& lp, hipStream_t s);
 hipError_t launch_compress(int32_t* parent, int64_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_assemble(const SecDev* parents, const SecDev* children, const AsmDev* asm_, int n,

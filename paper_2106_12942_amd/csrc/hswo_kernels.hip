@@ -74,6 +74,7 @@ struct Fmt16<2> {
     }
 };
 
+constexpr int TLIST = 1024;          // tile list chunk (LDS)
 constexpr int KSLAB = 256;           // bands of the 16-bit operands staged in LDS at a time
 constexpr int G16_LD = KSLAB + 8;    // LDS row stride (elements) of the 16-bit operand tiles
 
@@ -113,6 +114,7 @@ struct Smem {
             uint16_t C[STILE][G16_LD];
             float Prow[STILE], Arow[STILE], Pcol[STILE], Acol[STILE];
         } g;
+        double rsum[NWAVE][4][64];  // row cache: per-wave band-chunk sums of a task
     } u;
     float redf[2][NWAVE];
     int redi[NWAVE];
@@ -120,6 +122,9 @@ struct Smem {
     KeyD redk[NWAVE];
     double csum[NWAVE][16];
     int ncand;
+    int ntl;                 // entries of tlist
+    int npend;               // rows appended to the row cache's pending list
+    int tlist[TLIST];        // tiles gathered for a pass (one barrier instead of one per tile)
     int bcast_i[4];
     unsigned long long cnt[C_COUNT];  // per-block counters and stage clocks (thread 0 only)
 };
@@ -468,6 +473,17 @@ __device__ void prep_alpha_p(const SecDev& s, int R, double T) {
 
 __device__ __forceinline__ int tile_index(int ib, int jb, int nT) { return ib * nT - ib * (ib - 1) / 2 + (jb - ib); }
 
+__device__ __forceinline__ void tile_coords(int t, int nT, int& ib, int& jb) {
+    ib = 0;
+    int len = nT;
+    while (t >= len) {
+        t -= len;
+        ++ib;
+        --len;
+    }
+    jb = ib + t;
+}
+
 // Matrix-core pass over the 128 x 128 super tiles q = g0, g0 + gstride, ...
 // of pairs i < j < R: sets tflag of every 64 x 64 tile holding a pair that
 // passes the test above (flags are cleared beforehand).
@@ -559,8 +575,250 @@ __device__ int mfma_screen(Smem& sh, const SecDev& s, int R, int g0, int gstride
 
 // One merge (Section 4.1: the merged region replaces both). lo_s keeps the
 // region; the slot hi_s is freed and the last live slot R-1 moves into it.
+// ---------------------------------------------------------------------------
+// Spectral row cache (incremental form). Every live slot i keeps a pair
+// (i, p_i) with its exact D2. Invariant: every pair (a, b) of live slots has
+// key(a, b) >= the key cached in row a or in row b, and every cached key is
+// the key of a live pair. The least cached key is then the exact spectral
+// minimum. A merge changes only the survivor's statistics and removes a slot,
+// so re-evaluating the survivor's row in full, and every row whose cached
+// partner was one of the merged pair, restores the invariant; all other rows
+// keep their (still valid) pairs.
+// ---------------------------------------------------------------------------
+
+
+// Binary counter of finished subtrees for the band sum of one pair: group
+// sum v (a subtree of GB bands, group index g) joins the counter; level l
+// holds a finished subtree of GB * 2^l bands.
+template <int LV>
+__device__ __forceinline__ void counter_push(double (&part)[LV], double v, int g) {
+    bool carry = true;
+#pragma unroll
+    for (int l = 0; l < LV; ++l) {
+        if (carry) {
+            if ((g >> l) & 1) {
+                v = part[l] + v;
+            } else {
+                part[l] = v;
+                carry = false;
+            }
+        }
+    }
+}
+
+// Sum of the unfinished subtrees after ng groups: they sit at the set bits of
+// ng, and the lower ones are the right-hand operands (the zero padding in
+// between adds nothing).
+template <int LV>
+__device__ __forceinline__ double counter_total(const double (&part)[LV], int ng) {
+    double acc = 0.0;
+    bool have = false;
+#pragma unroll
+    for (int l = 0; l < LV; ++l)
+        if ((ng >> l) & 1) {
+            acc = have ? part[l] + acc : part[l];
+            have = true;
+        }
+    return acc;
+}
+
+// Start the row cache of a section at R live slots: FP64 means of every slot;
+// every row is then pending (state 1).
+__device__ void rowcache_begin(Smem& sh, const SecDev& s, int R) {
+    const int B = s.B;
+    const size_t kc = (size_t)s.rcap;
+    const int tot = R * B;
+    const int B8 = (B + 7) & ~7;
+    for (int x = threadIdx.x; x < tot; x += NT) {
+        const int b = x / R, i = x - b * R;
+        const double m = s.sums[(size_t)i * B + b] / (double)s.npix[i];
+        s.m64[(size_t)b * kc + i] = m;
+        s.m64r[(size_t)i * B8 + b] = m;
+    }
+    for (int i = threadIdx.x; i < R; i += NT) {
+        s.rbp[i] = -1;
+        s.rbd[i] = __builtin_huge_val();
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s.st[6] = 1;
+        s.st[7] = 0;
+    }
+    __syncthreads();
+}
+
+// Exact D2 of KR pending rows against 64 columns (one block task; a pair per
+// lane and wave). The bands are added in the perfect binary tree over the
+// zero-padded bands (P = next power of two >= B) that exact_d2_wave uses:
+// wave w < nbc takes the aligned subtree of bands [w cs, (w + 1) cs), in
+// groups of 8 bands (fixed subtrees) combined through a binary counter; the
+// nbc chunk sums are then added in tree order from LDS. Column means come from
+// the band-major copy (coalesced over the lanes), row means from the
+// slot-major copy (the same for the whole wavefront). Each row's best
+// candidate among the 64 columns goes to rpart. Pending rows: the first np
+// slots (all) or rpend[0, np). Called by the whole block.
+template <int KR>
+__device__ void row_block_task(double (*rsum)[4][64], const SecDev& s, int R, int np, bool all, int bq, int c) {
+    constexpr int GB = 8;
+    constexpr int LV = 7;  // up to 64 groups of 8 bands per wave (4096 bands over 8 waves)
+    const int lane = lane_id(), w = wave_id();
+    const int B = s.B, B8 = (B + 7) & ~7;
+    const size_t kc = (size_t)s.rcap;
+    int P = 1;
+    while (P < B) P <<= 1;
+    const int nbc = min(NWAVE, max(1, P / GB));
+    const int cs = P / nbc;
+    const int j = (c << 6) + lane;
+    const bool jv = j < R;
+    int ir[KR];
+#pragma unroll
+    for (int r = 0; r < KR; ++r) {
+        const int q = bq * KR + r;
+        int v = -1;
+        if (q < np) v = all ? q : s.rpend[q];
+        ir[r] = __builtin_amdgcn_readfirstlane(v);
+    }
+    if (w < nbc) {  // wavefront-uniform
+        const int b_lo = w * cs;
+        const int ngw = (cs + GB - 1) / GB;
+        double part[KR][LV];
+#pragma unroll
+        for (int r = 0; r < KR; ++r)
+#pragma unroll
+            for (int l = 0; l < LV; ++l) part[r][l] = 0.0;
+        const double* mj = s.m64 + (jv ? j : 0);
+        int gd = 0;
+        for (int g = 0; g < ngw; ++g) {
+            const int b0 = b_lo + g * GB;
+            if (b0 >= B) break;  // the rest of the chunk is zero padding
+            double cv[GB];
+#pragma unroll
+            for (int k = 0; k < GB; ++k) cv[k] = (b0 + k < B) ? mj[(size_t)(b0 + k) * kc] : 0.0;
+#pragma unroll
+            for (int r = 0; r < KR; ++r) {
+                if (ir[r] < 0) continue;  // wavefront-uniform
+                const double* mi = s.m64r + (size_t)ir[r] * B8 + b0;
+                double qv[GB];
+#pragma unroll
+                for (int k = 0; k < GB; ++k) {
+                    const double d = (b0 + k < B) ? mi[k] - cv[k] : 0.0;
+                    qv[k] = d * d;
+                }
+#pragma unroll
+                for (int h = 1; h < GB; h <<= 1)
+#pragma unroll
+                    for (int k = 0; k < GB; k += 2 * h) qv[k] = qv[k] + qv[k + h];
+                counter_push<LV>(part[r], qv[0], g);
+            }
+            gd = g + 1;
+        }
+#pragma unroll
+        for (int r = 0; r < KR; ++r) rsum[w][r][lane] = counter_total<LV>(part[r], gd);
+    }
+    __syncthreads();
+    if (w < KR) {  // wavefront r finishes row r of the batch
+        const int q = bq * KR + w;
+        if (q < np) {  // wavefront-uniform
+            const int i = all ? q : s.rpend[q];
+            double v[NWAVE];
+#pragma unroll
+            for (int k = 0; k < NWAVE; ++k) v[k] = (k < nbc) ? rsum[k][w][lane] : 0.0;
+#pragma unroll
+            for (int h = 1; h < NWAVE; h <<= 1)
+#pragma unroll
+                for (int k = 0; k < NWAVE; k += 2 * h) v[k] = v[k] + v[k + h];
+            const int n_i = s.npix[i];
+            const int n_j = jv ? s.npix[j] : 1;
+            const double dni = (double)n_i, dnj = (double)n_j;
+            const double fac = (dni * dnj) / (double)(n_i + n_j);
+            double d2 = fac * v[0];
+            int lab = jv ? s.label[j] : INT_MAX, slot = j;
+            if (!jv || j == i) {
+                d2 = __builtin_huge_val();
+                lab = INT_MAX;
+                slot = -1;
+            }
+            // for a fixed row the pair order (D2, lo, hi) is the order of (D2, partner label)
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+                const double d2o = __shfl_xor(d2, o);
+                const int labo = __shfl_xor(lab, o);
+                const int sloto = __shfl_xor(slot, o);
+                if (d2o < d2 || (d2o == d2 && labo < lab)) {
+                    d2 = d2o;
+                    lab = labo;
+                    slot = sloto;
+                }
+            }
+            if (lane == 0) {
+                RowPart rp;
+                rp.d2 = d2;
+                rp.lab = lab;
+                rp.slot = slot;
+                s.rpart[(size_t)q * ((R + 63) >> 6) + c] = rp;
+            }
+        }
+    }
+    __syncthreads();  // rsum is reused by the next task
+}
+
+// Number of block tasks of a section's row cache stage this iteration.
+__device__ __forceinline__ int row_task_count(int R, int np) { return ((np + 3) / 4) * ((R + 63) >> 6); }
+
+// Each pending row's best pair from its column-chunk partials.
+__device__ void rows_finish(const SecDev& s, int R, int np, bool all) {
+    const int nch = (R + 63) >> 6;
+    for (int q = threadIdx.x; q < np; q += NT) {
+        const int i = all ? q : s.rpend[q];
+        double bd = __builtin_huge_val();
+        int bl = INT_MAX, bs = -1;
+        for (int c = 0; c < nch; ++c) {
+            const RowPart rp = s.rpart[(size_t)q * nch + c];
+            if (rp.d2 < bd || (rp.d2 == bd && rp.lab < bl)) {
+                bd = rp.d2;
+                bl = rp.lab;
+                bs = rp.slot;
+            }
+        }
+        s.rbd[i] = bd;
+        s.rbp[i] = bs;
+    }
+}
+
+__device__ __forceinline__ KeyD pair_key(const SecDev& s, double d2, int a, int b) {
+    const int la = s.label[a], lb = s.label[b];
+    KeyD k;
+    k.d2 = d2;
+    if (la < lb) {
+        k.lo = la;
+        k.hi = lb;
+        k.si = a;
+        k.sj = b;
+    } else {
+        k.lo = lb;
+        k.hi = la;
+        k.si = b;
+        k.sj = a;
+    }
+    return k;
+}
+
+// Least pair over all live slots, from the cached rows.
+__device__ KeyD cached_min(Smem& sh, const SecDev& s, int R) {
+    KeyD best = key_none();
+    for (int i = threadIdx.x; i < R; i += NT) {
+        const int p = s.rbp[i];
+        if (p < 0) continue;
+        const KeyD k = pair_key(s, s.rbd[i], i, p);
+        if (key_less(k, best)) best = k;
+    }
+    return block_min_key(sh, best);
+}
+
+// rc: row cache state of the section (0 off, 1 means maintained, 2 rows
+// maintained: the stale rows are listed for re-evaluation).
 __device__ void merge_pair(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int& E, int stamp,
-                           int kind, double d2, int g_ready, int prec) {
+                           int kind, double d2, int g_ready, int prec, int rc) {
     const int tid = threadIdx.x;
     const int B = s.B, Bp = s.Bp;
     const int lo_l = s.label[lo_s], hi_l = s.label[hi_s];
@@ -573,6 +831,11 @@ __device__ void merge_pair(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R,
     for (int b = tid; b < B; b += NT) {
         const double v = Slo[b] + Shi[b];
         Slo[b] = v;
+        if (rc) {
+            const double m = v / dn;
+            s.m64[(size_t)b * s.rcap + lo_s] = m;
+            s.m64r[(size_t)lo_s * ((B + 7) & ~7) + b] = m;
+        }
         const float m = (float)(v / dn);
         Mlo[b] = m;
         nrm += (double)m * (double)m;
@@ -663,6 +926,13 @@ __device__ void merge_pair(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R,
             s.norm[hi_s] = s.norm[last];
             s.mark[hi_s] = s.mark[last];
         }
+        if (rc) {
+            const size_t kc = (size_t)s.rcap, B8 = (size_t)((B + 7) & ~7);
+            for (int b = tid; b < B; b += NT) {
+                s.m64[(size_t)b * kc + hi_s] = s.m64[(size_t)b * kc + last];
+                s.m64r[(size_t)hi_s * B8 + b] = s.m64r[(size_t)last * B8 + b];
+            }
+        }
         if (g_ready) {
             const uint16_t* Gsrc = s.g16 + (size_t)last * Bp;
             uint16_t* Gdst = s.g16 + (size_t)hi_s * Bp;
@@ -672,6 +942,32 @@ __device__ void merge_pair(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R,
                 s.geta[hi_s] = s.geta[last];
             }
         }
+    }
+    if (rc == 2) {
+        // row cache: move the last row's entry into the freed slot, rename
+        // partners that moved, list the survivor and every row whose cached
+        // partner was one of the merged pair
+        if (tid == 0) sh.npend = 1;
+        __syncthreads();
+        for (int i = tid; i < R; i += NT) {
+            if (i == lo_s || i == hi_s) continue;
+            const int ni = (i == last) ? hi_s : i;
+            const int p = s.rbp[i];
+            const double v = s.rbd[i];
+            if (p == lo_s || p == hi_s) {
+                s.rbp[ni] = -1;
+                s.rpend[atomicAdd(&sh.npend, 1)] = ni;
+            } else {
+                s.rbp[ni] = (p == last) ? hi_s : p;
+                s.rbd[ni] = v;
+            }
+        }
+        if (tid == 0) {
+            s.rpend[0] = surv;
+            s.rbp[surv] = -1;
+        }
+        __syncthreads();
+        if (tid == 0) s.st[7] = sh.npend;
     }
     __syncthreads();
     if (inc) {  // re-score the survivor's edges; every other edge keeps its cached value
@@ -768,16 +1064,19 @@ __device__ float adj_screen_range(const SecDev& s, int e_begin, int e_end, float
 // Exact best adjacent pair: every edge whose lower bound reaches Ua is
 // re-scored in FP64.
 __device__ KeyD adj_collect(Smem& sh, const SecDev& s, int E, float Ua, int& nchk) {
+    constexpr int SPAN = NT * 16;  // edges appended between two fullness checks (<= CAND_CAP)
     const int tid = threadIdx.x;
     KeyD A = key_none();
-    for (int e0 = 0; e0 < E; e0 += NT) {
-        const int e = e0 + tid;
-        const float lo = e < E ? s.escr[e].x : __builtin_huge_valf();
-        if (lo <= Ua && lo < __builtin_huge_valf()) {  // empty slots have +inf bounds
-            const int k = atomicAdd(&sh.ncand, 1);
-            if (k < CAND_CAP) sh.u.f.cand[k] = e;
+    for (int e0 = 0; e0 < E; e0 += SPAN) {
+        const int e1 = min(E, e0 + SPAN);
+        for (int e = e0 + tid; e < e1; e += NT) {
+            const float lo = s.escr[e].x;
+            if (lo <= Ua && lo < __builtin_huge_valf()) {  // empty slots have +inf bounds
+                const int k = atomicAdd(&sh.ncand, 1);
+                if (k < CAND_CAP) sh.u.f.cand[k] = e;
+            }
         }
-        flush_candidates(sh, s, A, nchk, true, NT);
+        flush_candidates(sh, s, A, nchk, true, SPAN);
     }
     flush_candidates(sh, s, A, nchk, true, CAND_CAP);
     return A;
@@ -824,21 +1123,27 @@ __device__ float fp32_tiles(Smem& sh, const SecDev& s, int R, bool use16, float 
     const int tid = threadIdx.x;
     const int ty = tid >> 5, tx = tid & 31;
     const int nT = (R + TILE - 1) / TILE;
+    const int ntiles = nT * (nT + 1) / 2;
     float Us = __builtin_huge_valf();
-    int t = 0;
-    for (int ib = 0; ib < nT; ++ib)
-        for (int jb = ib; jb < nT; ++jb, ++t) {
-            if ((t - t0) % stride != 0 || t < t0) continue;  // block-uniform
-            if (use16) {
-                if (tid == 0) sh.bcast_i[1] = s.tflag[t];
-                __syncthreads();
-                const int fl = sh.bcast_i[1];
-                __syncthreads();
-                if (!fl) {
-                    if (tid == 0) s.tstat[t] = make_float2(__builtin_huge_valf(), __builtin_huge_valf());
-                    continue;  // block-uniform via LDS
-                }
+    for (int c0 = t0; c0 < ntiles; c0 += stride * TLIST) {
+        // gather this workgroup's tiles t = c0, c0 + stride, ... (flagged ones with use16)
+        if (tid == 0) sh.ntl = 0;
+        __syncthreads();
+        for (int k = tid; k < TLIST; k += NT) {
+            const int t = c0 + k * stride;
+            if (t >= ntiles) break;
+            if (!use16 || s.tflag[t]) {
+                sh.tlist[atomicAdd(&sh.ntl, 1)] = t;
+            } else {
+                s.tstat[t] = make_float2(__builtin_huge_valf(), __builtin_huge_valf());
             }
+        }
+        __syncthreads();
+        const int nt = sh.ntl;
+        for (int q = 0; q < nt; ++q) {
+            const int t = sh.tlist[q];
+            int ib, jb;
+            tile_coords(t, nT, ib, jb);
             ++nproc;
             float acc[4][2];
             tile_sums_fp32(sh, s, ib, jb, R, acc);
@@ -858,6 +1163,8 @@ __device__ float fp32_tiles(Smem& sh, const SecDev& s, int R, bool use16, float 
             if (tid == 0) s.tstat[t] = lu;
             Us = fminf(Us, lu.y);
         }
+        __syncthreads();  // tlist is rewritten by the next chunk
+    }
     return Us;
 }
 
@@ -869,18 +1176,21 @@ __device__ KeyD spectral_collect(Smem& sh, const SecDev& s, int R, double T, dou
     const int tid = threadIdx.x;
     const int ty = tid >> 5, tx = tid & 31;
     const int nT = (R + TILE - 1) / TILE;
+    const int ntiles = nT * (nT + 1) / 2;
     KeyD M = key_none();
-    int t = 0;
-    for (int ib = 0; ib < nT; ++ib)
-        for (int jb = ib; jb < nT; ++jb, ++t) {
-            if (tid == 0) {
-                const float tl = s.tstat[t].x;
-                sh.bcast_i[0] = ((double)tl <= theta && (double)tl < T) ? 1 : 0;
-            }
-            __syncthreads();
-            const int flagged = sh.bcast_i[0];
-            __syncthreads();
-            if (!flagged) continue;  // block-uniform via LDS
+    for (int c0 = 0; c0 < ntiles; c0 += TLIST) {
+        if (tid == 0) sh.ntl = 0;
+        __syncthreads();
+        for (int t = c0 + tid; t < min(ntiles, c0 + TLIST); t += NT) {
+            const float tl = s.tstat[t].x;
+            if ((double)tl <= theta && (double)tl < T) sh.tlist[atomicAdd(&sh.ntl, 1)] = t;
+        }
+        __syncthreads();
+        const int nt = sh.ntl;
+        for (int q = 0; q < nt; ++q) {
+            const int t = sh.tlist[q];
+            int ib, jb;
+            tile_coords(t, nT, ib, jb);
             ++nresc;
             float acc[4][2];
             tile_sums_fp32(sh, s, ib, jb, R, acc);
@@ -899,6 +1209,8 @@ __device__ KeyD spectral_collect(Smem& sh, const SecDev& s, int R, double T, dou
                 }
             flush_candidates(sh, s, M, nchk, false, TILE * TILE);
         }
+        __syncthreads();  // tlist is rewritten by the next chunk
+    }
     flush_candidates(sh, s, M, nchk, false, CAND_CAP);
     return M;
 }
@@ -941,6 +1253,10 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
     int g_ready = s.st[4];
     const int prec = s.kcap > 0 ? lp.precision : 0;
     const float gam = (float)(2 * s.B + 32) * U32;
+    const bool row_cache = lp.incremental && s.rcap > 0;
+    int rcs = row_cache ? s.st[6] : 0;   // row cache state, block-uniform
+    int npend = row_cache ? s.st[7] : 0; // pending rows (state 2)
+    int merges = s.st[3];
     if (tid == 0) {
         sh.ncand = 0;
         for (int c = 0; c < C_COUNT; ++c) sh.cnt[c] = 0ull;
@@ -974,7 +1290,27 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
         KeyD M = key_none();
         const bool spectral = lp.spectral && R <= lp.kmax;
         const double T = key_exists(A) ? lp.w2 * A.d2 : __builtin_huge_val();
-        if (spectral) {
+        if (spectral && row_cache) {
+            // exact rows: all of them when the cache starts, else the pending ones
+            if (rcs == 0) {
+                rowcache_begin(sh, s, R);
+                rcs = 1;
+            }
+            const bool all = rcs == 1;
+            const int rows = all ? R : npend;
+            const int nch = (R + 63) >> 6;
+            const int ntask = row_task_count(R, rows);
+            for (int t = 0; t < ntask; ++t) row_block_task<4>(sh.u.rsum, s, R, rows, all, t / nch, t % nch);
+            rows_finish(s, R, rows, all);
+            __syncthreads();
+            rcs = 2;
+            npend = 0;
+            M = cached_min(sh, s, R);
+            CNT_ADD(C_SPEC_PAIRS, (unsigned long long)rows * (unsigned long long)(R - 1));
+            tk1 = wall_clock64();
+            CNT_ADD(C_T_SPEC32, tk1 - tk0);
+            tk0 = tk1;
+        } else if (spectral) {
             if (prec && !g_ready) {
                 if (prec == 1)
                     build16_all<1>(s, R);
@@ -1012,8 +1348,14 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
         CNT_ADD(C_RECHECKS, nchk);
         CNT_ADD(C_ITERS, 1);
         CNT_ADD(C_MERGES, 1);
-        merge_pair(sh, s, win.si, win.sj, R, E, s.st[3], kind, win.d2, g_ready, prec);
+        merge_pair(sh, s, win.si, win.sj, R, E, merges, kind, win.d2, g_ready, prec, rcs);
+        ++merges;
         --R;
+        if (rcs == 2) npend = sh.npend;
+        if (row_cache && rcs == 0 && lp.spectral && R <= lp.kmax && R > s.stop) {
+            rowcache_begin(sh, s, R);  // the spectral stage starts with the next iteration
+            rcs = 1;
+        }
         CNT_ADD(C_T_MERGE, wall_clock64() - tk0);
     }
 #undef CNT_ADD
@@ -1021,6 +1363,10 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
         s.st[0] = R;
         s.st[1] = E;
         s.st[4] = g_ready;
+        if (row_cache) {
+            s.st[6] = rcs;
+            s.st[7] = npend;
+        }
         if (lp.counters)
             for (int c = 0; c < C_COUNT; ++c)
                 if (sh.cnt[c]) atomicAdd(&lp.counters[c], sh.cnt[c]);
@@ -1043,16 +1389,73 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
 // ---------------------------------------------------------------------------
 template <int EPG>
 __global__ void __launch_bounds__(NT) k_wide_adj(const SecDev* __restrict__ secs, int G) {
-    __shared__ Smem sh;
+    __shared__ float red[NWAVE];  // only a block minimum: keep LDS small so several blocks fit a CU
     const SecDev s = secs[blockIdx.y];
     const int R = s.st[0], E = s.st[1];
     if (R <= s.stop) return;
     const float gam = (float)(2 * s.B + 32) * U32;
     const int per = (E + G - 1) / G;
     const int e0 = blockIdx.x * per, e1 = min(E, e0 + per);
-    const float myU = adj_screen_range<EPG>(s, e0, e1, gam);
-    const float U = block_min_f2(sh, myU, myU).x;
-    if (threadIdx.x == 0) s.wpart[blockIdx.x] = U;
+    float U = wave_min_f(adj_screen_range<EPG>(s, e0, e1, gam));
+    if (lane_id() == 0) red[wave_id()] = U;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < NWAVE; ++w) U = fminf(U, red[w]);
+        s.wpart[blockIdx.x] = U;
+    }
+}
+
+// Row cache stage of one iteration (incremental form): G workgroups per
+// section share the rows to re-evaluate (every row when the cache starts).
+__global__ void __launch_bounds__(NT) k_wide_rows(const SecDev* __restrict__ secs, int n, LoopParams lp) {
+    __shared__ double rsum[NWAVE][4][64];
+    __shared__ int pre[ROWS_MAX_SECTIONS + 1];
+    // tasks of every section of the level in one pool: section k owns tasks
+    // [pre[k], pre[k + 1])
+    for (int k = threadIdx.x; k < n; k += NT) {
+        const SecDev& s = secs[k];
+        const int R = s.st[0], mode = s.st[6];
+        int cnt = 0;
+        if (s.rcap > 0 && R > s.stop && R <= lp.kmax && (mode == 1 || mode == 2)) {
+            const int np = mode == 1 ? R : s.st[7];
+            cnt = row_task_count(R, np);
+            if (blockIdx.x == 0 && lp.counters)
+                atomicAdd(&lp.counters[C_SPEC_PAIRS], (unsigned long long)np * (unsigned long long)(R - 1));
+        }
+        pre[k + 1] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        pre[0] = 0;
+        for (int k = 0; k < n; ++k) pre[k + 1] += pre[k];
+    }
+    __syncthreads();
+    const int total = pre[n];
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        int lo = 0, hi = n - 1;  // section k with pre[k] <= t < pre[k + 1]
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (pre[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const SecDev s = secs[lo];
+        const int R = s.st[0];
+        const bool all = s.st[6] == 1;
+        const int np = all ? R : s.st[7];
+        const int nch = (R + 63) >> 6;
+        const int lt = t - pre[lo];
+        row_block_task<4>(rsum, s, R, np, all, lt / nch, lt % nch);
+    }
+}
+
+// Start the row caches of the sections whose pass begins inside the spectral
+// stage (one workgroup per section).
+__global__ void __launch_bounds__(NT) k_rowcache_prep(const SecDev* __restrict__ secs, LoopParams lp) {
+    __shared__ Smem sh;
+    const SecDev s = secs[blockIdx.x];
+    const int R = s.st[0];
+    if (s.rcap == 0 || R <= s.stop || R > lp.kmax || s.st[6] != 0) return;
+    rowcache_begin(sh, s, R);
 }
 
 __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ secs, int G, LoopParams lp) {
@@ -1081,15 +1484,31 @@ __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ s
     }
     const bool spectral = lp.spectral && R <= lp.kmax;
     const double T = key_exists(A) ? lp.w2 * A.d2 : __builtin_huge_val();
-    if (!spectral) {
+    const bool row_cache = lp.incremental && s.rcap > 0;
+    if (!spectral || row_cache) {
+        // the adjacent stage alone, or the spectral minimum from the row cache
+        // (its pending rows were re-evaluated by k_wide_rows)
+        int rcs = row_cache ? s.st[6] : 0;
+        KeyD M = key_none();
+        if (spectral) {
+            const bool all = rcs == 1;
+            rows_finish(s, R, all ? R : s.st[7], all);
+            __syncthreads();
+            rcs = 2;
+            M = cached_min(sh, s, R);
+        }
         KeyD win;
         int kind;
-        if (decide(false, A, A, T, win, kind)) {
-            merge_pair(sh, s, win.si, win.sj, R, E, s.st[3], kind, win.d2, s.st[4], prec);
+        if (decide(spectral, A, M, T, win, kind)) {
+            const int stamp = s.st[3];
+            merge_pair(sh, s, win.si, win.sj, R, E, stamp, kind, win.d2, s.st[4], prec, rcs);
             if (tid == 0) {
                 s.st[0] = R - 1;
                 s.st[1] = E;
+                if (row_cache) s.st[6] = rcs;
             }
+            if (row_cache && rcs == 0 && lp.spectral && R - 1 <= lp.kmax && R - 1 > s.stop)
+                rowcache_begin(sh, s, R - 1);
         }
         if (tid == 0) {
             s.wi[0] = 1;
@@ -1178,7 +1597,7 @@ __global__ void __launch_bounds__(NT) k_wide_finish(const SecDev* __restrict__ s
     KeyD win;
     int kind;
     if (decide(true, A, M, T, win, kind)) {
-        merge_pair(sh, s, win.si, win.sj, R, E, s.st[3], kind, win.d2, s.st[4], prec);
+        merge_pair(sh, s, win.si, win.sj, R, E, s.st[3], kind, win.d2, s.st[4], prec, 0);
         if (tid == 0) {
             s.st[0] = R - 1;
             s.st[1] = E;
@@ -1291,6 +1710,8 @@ __global__ void k_init_leaves(const SecDev* __restrict__ secs, const InitDev* __
         s.st[3] = 0;
         s.st[4] = 0;
         s.st[5] = 0;
+        s.st[6] = 0;
+        s.st[7] = 0;
     }
 }
 
@@ -1338,6 +1759,10 @@ __global__ void k_assemble(const SecDev* __restrict__ parents, const SecDev* __r
             p.st[3] = 0;
             p.st[4] = 0;
             p.st[5] = 0;
+        p.st[6] = 0;
+        p.st[7] = 0;
+            p.st[6] = 0;
+            p.st[7] = 0;
         }
         return;
     }
@@ -1373,6 +1798,8 @@ __global__ void k_assemble(const SecDev* __restrict__ parents, const SecDev* __r
         p.st[3] = 0;
         p.st[4] = 0;
         p.st[5] = 0;
+        p.st[6] = 0;
+        p.st[7] = 0;
     }
 }
 
@@ -1502,9 +1929,31 @@ hipError_t launch_section_driver(const SecDev* secs, int n, const LoopParams& lp
     return hipGetLastError();
 }
 
+int rows_grid() {
+    static int g = 0;
+    if (!g) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        g = 2 * cus;
+    }
+    return g;
+}
+
+hipError_t launch_rowcache_prep(const SecDev* secs, int n, const LoopParams& lp, hipStream_t s) {
+    hipLaunchKernelGGL(k_rowcache_prep, dim3(n), dim3(NT), 0, s, secs, lp);
+    return hipGetLastError();
+}
+
 hipError_t launch_wide_iteration(const SecDev* secs, int n, int G, const LoopParams& lp, int variant,
-                                 bool spectral_possible, hipStream_t s) {
+                                 bool spectral_possible, bool row_cache, hipStream_t s) {
     const dim3 grid(G, n);
+    if (row_cache) {  // incremental form: cached adjacent values and spectral rows
+        if (spectral_possible) hipLaunchKernelGGL(k_wide_rows, dim3(rows_grid()), dim3(NT), 0, s, secs, n, lp);
+        hipLaunchKernelGGL(k_wide_decide, dim3(n), dim3(NT), 0, s, secs, G, lp);
+        return hipGetLastError();
+    }
     if (!lp.incremental) {
         if (variant == 2)
             hipLaunchKernelGGL(k_wide_adj<2>, grid, dim3(NT), 0, s, secs, G);

@@ -23,21 +23,23 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def gpu_run(cube, params, entry="rhseg", precision="fp32"):
+def gpu_run(cube, params, entry="rhseg", precision="fp32", incremental=False):
     t = torch.from_numpy(np.ascontiguousarray(cube)).cuda()
     p = dict(params)
     L = p.pop("rnb_levels", 1)
     if entry == "hswo":
-        res = hswo.hswo_run(t, **p, precision=precision, merge_log=True, stats=True)
+        res = hswo.hswo_run(t, **p, precision=precision, merge_log=True, stats=True, incremental=incremental)
     else:
-        res = hswo.rhseg_segment(t, rnb_levels=L, **p, precision=precision, merge_log=True, stats=True)
+        res = hswo.rhseg_segment(t, rnb_levels=L, **p, precision=precision, merge_log=True, stats=True,
+                                 incremental=incremental)
     torch.cuda.synchronize()
     return res.labels.cpu().numpy(), res.log, res.stats
 
 
-def assert_parity(cube, params, entry="rhseg", precision="fp32", tag=""):
-    _say(f"[gpu] {tag} shape={cube.shape} dtype={cube.dtype} entry={entry} prec={precision} params={params}")
-    lab, log, stats = gpu_run(cube, params, entry, precision)
+def assert_parity(cube, params, entry="rhseg", precision="fp32", tag="", incremental=False):
+    _say(f"[gpu] {tag} shape={cube.shape} dtype={cube.dtype} entry={entry} prec={precision} inc={incremental} "
+         f"params={params}")
+    lab, log, stats = gpu_run(cube, params, entry, precision, incremental)
     ref = oracle.rhseg(cube, **params)
     n = len(ref.log)
     assert stats["merges"] == n

@@ -1,0 +1,188 @@
+"""CPU emulation of the spectral row cache's bookkeeping and of its band-sum
+order (no GPU).
+
+The row cache keeps, per live slot i, a pair (i, p_i) with its exact D2,
+such that every pair of live slots is bounded below by the key cached in one
+of its two rows. After a merge only the survivor's row and the rows whose
+cached partner was one of the merged pair are re-evaluated. The model below
+does exactly what the kernels do with the slot arrays (swap-remove of the
+freed slot, partner renaming, pending list) and checks, every iteration of a
+real merge sequence (taken from the oracle), the invariant and that the
+cached minimum equals a brute-force minimum over all pairs.
+
+The second part checks that the per-thread band sum used by the row cache
+(fixed subtrees of GB bands combined through a binary counter) adds in the
+same perfect binary tree as the wavefront evaluator (4 bands per lane, lane
+butterflies, then a 16-leaf tree over 256-band chunks), bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2106_12942_amd import synth
+
+
+def _d2(m, n, i, j):
+    d = m[i] - m[j]
+    return (n[i] * n[j] / (n[i] + n[j])) * float(np.sum(d * d))
+
+
+def _key(lab, d2, a, b):
+    la, lb = lab[a], lab[b]
+    return (d2, la, lb) if la < lb else (d2, lb, la)
+
+
+class RowCache:
+    def __init__(self, S, n, lab):
+        self.S, self.n, self.lab = S, n, lab
+        self.R = len(lab)
+        self.m = S / n[:, None]
+        self.rbd = np.full(self.R, np.inf)
+        self.rbp = np.full(self.R, -1)
+        self.pending = list(range(self.R))
+
+    def row(self, i):
+        best = None
+        for j in range(self.R):
+            if j == i:
+                continue
+            k = _key(self.lab, _d2(self.m, self.n, i, j), i, j)
+            if best is None or k < best[0]:
+                best = (k, j)
+        self.rbd[i], self.rbp[i] = (best[0][0], best[1]) if best else (np.inf, -1)
+
+    def evaluate(self):
+        for i in self.pending:
+            self.row(i)
+        self.pending = []
+
+    def minimum(self):
+        ks = [(_key(self.lab, self.rbd[i], i, self.rbp[i]), i) for i in range(self.R) if self.rbp[i] >= 0]
+        return min(ks)[0] if ks else None
+
+    def merge(self, lo_s, hi_s):
+        R, last = self.R, self.R - 1
+        surv = hi_s if lo_s == last else lo_s
+        self.S[lo_s] += self.S[hi_s]
+        self.n[lo_s] += self.n[hi_s]
+        self.m[lo_s] = self.S[lo_s] / self.n[lo_s]
+        rbp, rbd = self.rbp.copy(), self.rbd.copy()
+        pend = [surv]
+        for i in range(R):
+            if i in (lo_s, hi_s):
+                continue
+            ni = hi_s if i == last else i
+            p = self.rbp[i]
+            if p in (lo_s, hi_s):
+                rbp[ni] = -1
+                pend.append(ni)
+            else:
+                rbp[ni] = hi_s if p == last else p
+                rbd[ni] = self.rbd[i]
+        rbp[surv] = -1
+        if hi_s != last:  # swap-remove
+            for a in (self.S, self.m):
+                a[hi_s] = a[last]
+            self.n[hi_s], self.lab[hi_s] = self.n[last], self.lab[last]
+        self.R -= 1
+        self.rbp, self.rbd = rbp[: self.R], rbd[: self.R]
+        self.S, self.m, self.n, self.lab = self.S[: self.R], self.m[: self.R], self.n[: self.R], self.lab[: self.R]
+        self.pending = pend
+
+
+def _brute_min(rc):
+    """Least pair key, and a check of the invariant: every cached key is the key
+    of a live pair, and every pair is bounded below by one of its rows."""
+    cached = [_key(rc.lab, rc.rbd[i], i, rc.rbp[i]) if rc.rbp[i] >= 0 else None for i in range(rc.R)]
+    best = None
+    for i in range(rc.R):
+        if cached[i] is not None:
+            p = rc.rbp[i]
+            assert cached[i] == _key(rc.lab, _d2(rc.m, rc.n, i, p), i, p), f"row {i} holds a stale pair"
+        for j in range(i + 1, rc.R):
+            k = _key(rc.lab, _d2(rc.m, rc.n, i, j), i, j)
+            assert min(c for c in (cached[i], cached[j]) if c is not None) <= k, f"pair ({i},{j}) unwitnessed"
+            best = k if best is None or k < best else best
+    return best
+
+
+@pytest.mark.parametrize("salt", [0.0, 0.3])
+def test_row_cache_tracks_brute_minimum(salt):
+    # a small section whose whole merge sequence runs in the spectral stage;
+    # salt gives many identical pixels (exact ties, stale rows in bulk)
+    if salt:
+        cube = synth.mixer_scene(10, 10, 12, 6, 25.0, 17, salt=salt).cube
+    else:
+        cube = synth.voronoi_scene(10, 10, 12, 8, 30.0, 19).cube
+    H, W, B = cube.shape
+    ref = oracle.rhseg(cube, connectivity=4, seam_connectivity=8, spclust_wght=0.5, spclust_max=1000,
+                       target_regions=2, section_regions=0, rnb_levels=1, level_counts=[2])
+    S = cube.reshape(-1, B).astype(np.float64).copy()
+    n = np.ones(H * W)
+    lab = np.arange(H * W)
+    rc = RowCache(S, n, lab)
+    stale_rows = 0
+    for k, rec in enumerate(ref.log):
+        rc.evaluate()
+        got, want = rc.minimum(), _brute_min(rc)
+        assert got == want, (k, got, want)
+        if rec["kind"] == 1:  # a spectral merge is the global minimum pair
+            assert (got[1], got[2]) == (rec["lo"], rec["hi"])
+        lo_s = int(np.nonzero(rc.lab == rec["lo"])[0][0])
+        hi_s = int(np.nonzero(rc.lab == rec["hi"])[0][0])
+        rc.merge(lo_s, hi_s)
+        stale_rows += len(rc.pending) - 1
+    assert stale_rows > 0
+
+
+def _wave_order_sum(q):
+    """Sum of q (len B) in the wavefront evaluator's order."""
+    B = len(q)
+    nch = (B + 255) // 256
+    cs = np.zeros(16)
+    for c in range(nch):
+        lanes = np.zeros(64)
+        for l in range(64):
+            v = [q[b] if b < B else 0.0 for b in range(256 * c + 4 * l, 256 * c + 4 * l + 4)]
+            lanes[l] = (v[0] + v[1]) + (v[2] + v[3])
+        for o in (1, 2, 4, 8, 16, 32):
+            lanes = np.array([lanes[l] + lanes[l ^ o] for l in range(64)])
+        cs[c] = lanes[0]
+    for o in (1, 2, 4, 8):
+        cs = np.array([cs[l] + cs[l ^ o] for l in range(16)])
+    return cs[0]
+
+
+def _counter_order_sum(q, GB):
+    """Sum of q in the row cache's order: GB-band subtrees through a binary counter."""
+    B = len(q)
+    ng = (B + GB - 1) // GB
+    part = {}
+    for g in range(ng):
+        t = [q[b] if b < B else 0.0 for b in range(g * GB, g * GB + GB)]
+        w = 1
+        while w < GB:
+            t = [t[k] + t[k + w] if k % (2 * w) == 0 else t[k] for k in range(GB)]
+            w *= 2
+        v = t[0]
+        lv = 0
+        while (g >> lv) & 1:
+            v = part[lv] + v
+            lv += 1
+        part[lv] = v
+    acc = None
+    for lv in range(16):
+        if (ng >> lv) & 1:
+            acc = part[lv] if acc is None else part[lv] + acc
+    return acc
+
+
+@pytest.mark.parametrize("B", [1, 3, 4, 15, 16, 17, 32, 100, 128, 220, 224, 255, 256, 257, 600, 1000])
+@pytest.mark.parametrize("GB", [4, 8, 16])
+def test_counter_order_equals_wave_order(B, GB):
+    rng = np.random.default_rng(1000 + B)
+    # magnitudes spread over many binades so a different association shows
+    q = rng.random(B) * np.exp2(rng.integers(-30, 30, B))
+    a = _wave_order_sum(q)
+    b = _counter_order_sum(q, GB)
+    assert a.tobytes() == np.float64(b).tobytes()
