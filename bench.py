@@ -16,14 +16,20 @@ Workloads
       10..120 Voronoi classes, sigma 30 (seed 404000+s), each merged down to
       256 regions (w 0.5, spectral at <= 1024) -- one hswo_run_batch call.
 
-Forms: the timed steps use the matrix-core screened form (fp16 by default)
-with levels batched into one launch (persistent) or one launch sequence
-(wide), replayed from a hipGraph; the plain FP32 path is run on the same
-input for the comparison.
+Forms (--form): "incremental" (default): cached exact per-edge D2 and the
+spectral row cache; "screened": every pair screened each iteration, the
+spectral stage on matrix cores (--precision fp16 or bf16); "plain": every
+pair screened each iteration in FP32. Levels run batched into one launch
+(persistent) or one launch sequence per iteration (wide), replayed from a
+hipGraph. The other forms run once on the same input for the comparison, and
+must give the same labels.
 
-Output: one JSON line. `value` is dissimilarity pairs per second (adjacent
-pairs screened + non-adjacent pairs screened, from the kernels' counters,
-over the wall time of a step).
+Output: one JSON line. `value` is dissimilarity pairs per second: the
+method's pairs (live adjacent pairs, plus R(R-1)/2 per iteration of the
+spectral stage, counted by the kernels) over the wall time of a step. The
+roofline object is for the kernel with the largest device time in one extra
+eager step of the timed form with every launch bracketed by hipEvents
+(HSWO_FLAG_KERNEL_TIMES).
 """
 from __future__ import annotations
 
@@ -43,6 +49,7 @@ PEAK_HBM_GBS = 8000.0
 # generated code): 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 PEAK_FP32_VALU_TFLOPS = 78.6
 PEAK_MFMA_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0}
+PEAK_FP64_VALU_TFLOPS = 78.6
 
 WORKLOAD_DESC = {
     "rhseg512": "512x512x128 f32 Voronoi (200 classes, sigma 30, seed 202); rnb_levels 4 (64x64 leaves); "
@@ -66,23 +73,82 @@ def traffic_from_profiles(tag: str):
     return None
 
 
-def stage_dict(st):
-    return {k: round(st[k], 2) for k in ("ms_adjacent", "ms_mfma_screen", "ms_fp32_spectral", "ms_merge")}
+KIND_DESC = {
+    "section_driver": "k_section_driver (one workgroup runs a section's whole pass)",
+    "wide_adj": "k_wide_adj (adjacent screen, edges over G workgroups)",
+    "wide_decide": "k_wide_decide (decision, merge and edge/row-cache upkeep, one workgroup per section)",
+    "wide_mfma": "k_wide_mfma (matrix-core tile screen)",
+    "wide_fp32": "k_wide_fp32 (FP32 tile screen)",
+    "wide_finish": "k_wide_finish (spectral decision and merge)",
+    "wide_rows": "k_wide_rows (row-cache re-evaluation, exact FP64)",
+    "rowcache_prep": "k_rowcache_prep",
+}
 
 
-def roofline_of(st, B, steps_ms, launches, tag):
-    """Roofline of the section-driver launches: algorithmic work = 3 flops
-    per band (difference, square, accumulate) per screened pair, over the
-    live-timed driver time; screened pairs are dominated by the spectral
-    all-pairs stage, so the bound is FP32 vector arithmetic."""
-    pairs = st["adjacent_pairs"] + st["spectral_pairs"]
-    flops = 3.0 * B * pairs
-    achieved = flops / (st["ms_driver"] / 1e3) / 1e12
-    return {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 5), "traffic": traffic_from_profiles(tag),
-            "kernel": "section driver launches (persistent driver + wide-mode kernels)",
-            "launches_per_step": launches, "avg_launch_ms": round(st["ms_driver"] / max(launches, 1), 4),
-            "algorithmic_flops_per_launch": flops / max(launches, 1)}
+def kernel_roofline(st, B, tag):
+    """Roofline of the kernel kind with the largest device time (from a
+    HSWO_FLAG_KERNEL_TIMES step). Algorithmic work, summed over the step and
+    divided by the kind's launches:
+      wide_decide: 16 B per live adjacent pair (endpoints and cached D2 read
+        for the minimum) + 24 B per band per merge (two FP64 sum rows read,
+        one written) -> HBM bound;
+      wide_rows: 3 FP64 flops per band per exactly evaluated pair -> FP64
+        vector bound (78.6 TFLOP/s);
+      wide_adj / section_driver / wide_fp32: 3 FP32 flops per band per
+        screened pair -> FP32 vector bound;
+      wide_mfma: 2 flops per band per unique spectral pair -> matrix cores."""
+    from paper_2106_12942_amd.hswo import KERNEL_KINDS
+    ms = st["ms_kernel"]
+    n = st["kernel_launches"]
+    k = max(range(len(ms)), key=lambda i: ms[i])
+    kind = KERNEL_KINDS[k]
+    avg_ms = ms[k] / max(n[k], 1)
+    if kind == "wide_decide":
+        work = 16.0 * st["adjacent_pairs"] + 24.0 * B * st["merges"]
+        bound, peak, unit, scale = "hbm", PEAK_HBM_GBS, "GB/s", 1e9
+    elif kind == "wide_rows":
+        work = 3.0 * B * st["exact_rechecks"]
+        bound, peak, unit, scale = "alu", PEAK_FP64_VALU_TFLOPS, "TFLOP/s", 1e12
+    elif kind == "wide_mfma":
+        work = 2.0 * B * st["spectral_pairs"]
+        bound, peak, unit, scale = "mfma", PEAK_MFMA_TFLOPS["fp16"], "TFLOP/s", 1e12
+    else:
+        work = 3.0 * B * (st["adjacent_pairs"] + st["spectral_pairs"])
+        bound, peak, unit, scale = "alu", PEAK_FP32_VALU_TFLOPS, "TFLOP/s", 1e12
+    per_launch = work / max(n[k], 1)
+    achieved = per_launch / (avg_ms / 1e3) / scale
+    return {"bound": bound, "achieved": round(achieved, 4), "peak": peak, "unit": unit,
+            "frac": round(achieved / peak, 5), "traffic": traffic_from_profiles(f"{kind}_{tag}"),
+            "kernel": KIND_DESC[kind], "launches_per_step": n[k], "avg_launch_us": round(avg_ms * 1e3, 3),
+            "algorithmic_work_per_launch": per_launch,
+            "kernel_ms_per_step": {KERNEL_KINDS[i]: round(ms[i], 3) for i in range(len(ms)) if n[i]},
+            "kernel_launches_per_step": {KERNEL_KINDS[i]: n[i] for i in range(len(ms)) if n[i]}}
+
+
+def form_kwargs(form, precision):
+    if form == "plain":
+        return dict(precision="fp32", incremental=False)
+    if form == "screened":
+        return dict(precision=precision, incremental=False)
+    return dict(precision=precision, incremental=True)
+
+
+def timed_steps(step, stream, torch, steps, warmup):
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            step()
+        stream.synchronize()
+        torch.cuda.synchronize()
+        walls, res = [], None
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ts = time.perf_counter()
+            res = step()  # stats=True: the call synchronises its stream before returning
+            walls.append((time.perf_counter() - ts) * 1e3)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+    return elapsed * 1e3 / steps, walls, res
 
 
 def bench_rhseg(args, np, torch, hswo, synth):
@@ -95,61 +161,49 @@ def bench_rhseg(args, np, torch, hswo, synth):
     kw = {k: v for k, v in params.items() if k != "rnb_levels"}
     stream = torch.cuda.Stream(dev)
     ws = hswo.Workspace()
-    labels = torch.empty((len(params["level_counts"]), H, W), dtype=torch.int32, device=dev)
+    nl = len(params["level_counts"])
+    labels = torch.empty((nl, H, W), dtype=torch.int32, device=dev)
 
-    def step(stats=True):
-        return hswo.rhseg_segment(cube, rnb_levels=L, precision=args.precision, stats=stats, stream=stream,
-                                  workspace=ws, labels_out=labels, graph=args.graph, autotune=args.autotune, **kw)
+    def runner(form, out, graph, kernel_times=False):
+        fk = form_kwargs(form, args.precision)
 
-    with torch.cuda.stream(stream):
-        for _ in range(args.warmup):
-            step()
-        stream.synchronize()
-        torch.cuda.synchronize()
-        walls, res = [], None
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            ts = time.perf_counter()
-            res = step()  # stats=True: the call synchronises its stream before returning
-            walls.append((time.perf_counter() - ts) * 1e3)
-        stream.synchronize()
-        torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t0
-    ms_per_step = elapsed * 1e3 / args.steps
+        def step():
+            return hswo.rhseg_segment(cube, rnb_levels=L, stats=True, stream=stream, workspace=ws, labels_out=out,
+                                      graph=graph, autotune=args.autotune, kernel_times=kernel_times, **fk, **kw)
+        return step
+
+    ms_per_step, walls, res = timed_steps(runner(args.form, labels, args.graph), stream, torch, args.steps,
+                                          args.warmup)
     st = res.stats
     pairs = st["adjacent_pairs"] + st["spectral_pairs"]
+    fk = form_kwargs(args.form, args.precision)
     out = {
         "value": pairs / (ms_per_step / 1e3), "unit": "pairs/s", "ms_per_step": ms_per_step,
         "wall_ms_median": statistics.median(walls), "wall_ms_min": min(walls), "wall_ms_max": max(walls),
         "config": {"workload": args.workload, "desc": WORKLOAD_DESC[args.workload], "H": H, "W": W, "B": B,
-                   "precision": args.precision, "graph": args.graph, "autotune": args.autotune,
-                   "driver_variant": st["driver_variant"]},
-        "pairs_per_step": pairs, "merges_per_step": st["merges"], "exact_rechecks_per_step": st["exact_rechecks"],
+                   "form": args.form, "precision": fk["precision"], "graph": args.graph,
+                   "autotune": args.autotune, "driver_variant": st["driver_variant"]},
+        "pairs_per_step": pairs, "merges_per_step": st["merges"], "exact_evaluations_per_step": st["exact_rechecks"],
         "fp32_tiles_per_step": st["fp32_tiles"], "mfma_super_tiles_per_step": st["mfma_tiles"],
-        "stage_ms_persistent_levels_summed_over_sections": stage_dict(st),
-        "roofline": roofline_of(st, B, ms_per_step, st["driver_launches"], f"{args.workload}_{args.precision}"),
     }
+    # per-kernel device times: one more step of the timed form, eager, every launch bracketed by hipEvents
+    kt = torch.empty_like(labels)
+    _, _, rk = timed_steps(runner(args.form, kt, False, kernel_times=True), stream, torch, 1, 0)
+    out["kernel_times_step_ms"] = rk.stats["ms_total"]
+    out["roofline"] = kernel_roofline(rk.stats, B, f"{args.workload}_{args.form}")
     lab = labels.cpu().numpy()
-    if not args.no_plain and args.precision != "fp32":
-        ts = time.perf_counter()
-        rp = hswo.rhseg_segment(cube, rnb_levels=L, precision="fp32", stats=True, **kw)
-        plain_ms = (time.perf_counter() - ts) * 1e3
-        out["plain_fp32"] = {"ms_per_step": plain_ms, "speedup_of_timed_form": plain_ms / ms_per_step,
-                             "labels_identical_to_timed_form": bool(np.array_equal(rp.labels.cpu().numpy(), lab))}
-    if not args.no_incremental:
-        # the incremental adjacent stage (cached exact per-edge D2): same merges, fewer pairs scored
-        with torch.cuda.stream(stream):
-            inc_lab = torch.empty_like(labels)
-            hswo.rhseg_segment(cube, rnb_levels=L, precision=args.precision, stream=stream, labels_out=inc_lab,
-                               incremental=True, **kw)
-            stream.synchronize()
-            ts = time.perf_counter()
-            ri = hswo.rhseg_segment(cube, rnb_levels=L, precision=args.precision, stats=True, stream=stream,
-                                    labels_out=inc_lab, incremental=True, **kw)
-            inc_ms = (time.perf_counter() - ts) * 1e3
-        out["incremental_form"] = {"ms_per_step": inc_ms, "speedup_vs_timed_form": ms_per_step / inc_ms,
-                                   "labels_identical_to_timed_form": bool(torch.equal(inc_lab, labels)),
-                                   "exact_rechecks": ri.stats["exact_rechecks"]}
+    same_kt = bool(torch.equal(kt, labels))
+    comparisons = {}
+    for form in ("plain", "screened", "incremental"):
+        if form == args.form or (form == "plain" and args.no_plain):
+            continue
+        o = torch.empty_like(labels)
+        ms, _, r = timed_steps(runner(form, o, args.graph), stream, torch, 1, 1)
+        comparisons[form] = {"ms_per_step": ms, "speedup_of_timed_form": ms / ms_per_step,
+                             "labels_identical_to_timed_form": bool(torch.equal(o, labels)),
+                             "precision": form_kwargs(form, args.precision)["precision"]}
+    out["forms"] = comparisons
+    out["labels_identical_kernel_times_step"] = same_kt
     if not args.no_cpu_baseline:
         import oracle
         threads = os.cpu_count() or 1
@@ -158,8 +212,8 @@ def bench_rhseg(args, np, torch, hswo, synth):
         cpu_s = time.perf_counter() - tc
         out["cpu_baseline"] = {"value": pairs / cpu_s, "unit": "pairs/s", "cores": threads, "kind": "oracle",
                                "sample": f"the full {args.workload} workload, FP64 oracle (cached mode, sections of "
-                                         f"a level on {threads} threads), {cpu_s:.2f} s; pairs counted as the GPU "
-                                         "path screens them"}
+                                         f"a level on {threads} threads), {cpu_s:.2f} s; the method's pairs "
+                                         "counted as for the GPU value"}
         out["labels_identical_to_oracle"] = bool(np.array_equal(lab, ref.labels))
         out["gpu_vs_oracle_speedup"] = cpu_s * 1e3 / ms_per_step
     return out, B
@@ -173,73 +227,81 @@ def bench_batch(args, np, torch, hswo, synth):
     dc = [torch.from_numpy(c).to(dev) for c, _ in secs]
     stream = torch.cuda.Stream(dev)
     ws = hswo.Workspace()
-    outs = [torch.empty((len(params["level_counts"]), c.shape[0], c.shape[1]), dtype=torch.int32, device=dev)
-            for c in dc]
 
-    def step():
-        return hswo.hswo_run_batch(dc, precision=args.precision, stats=True, stream=stream, workspace=ws,
-                                   labels_out=outs, graph=args.graph, autotune=args.autotune, **params)
+    def new_outs():
+        return [torch.empty((len(params["level_counts"]), c.shape[0], c.shape[1]), dtype=torch.int32, device=dev)
+                for c in dc]
 
-    with torch.cuda.stream(stream):
-        for _ in range(args.warmup):
-            step()
-        stream.synchronize()
-        walls, res = [], None
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            ts = time.perf_counter()
-            res = step()
-            walls.append((time.perf_counter() - ts) * 1e3)
-        stream.synchronize()
-        elapsed = time.perf_counter() - t0
-    ms_per_step = elapsed * 1e3 / args.steps
+    def runner(form, outs, graph, kernel_times=False):
+        fk = form_kwargs(form, args.precision)
+
+        def step():
+            return hswo.hswo_run_batch(dc, stats=True, stream=stream, workspace=ws, labels_out=outs, graph=graph,
+                                       autotune=args.autotune, kernel_times=kernel_times, **fk, **params)
+        return step
+
+    outs = new_outs()
+    ms_per_step, walls, res = timed_steps(runner(args.form, outs, args.graph), stream, torch, args.steps,
+                                          args.warmup)
     st = res.stats
     pairs = st["adjacent_pairs"] + st["spectral_pairs"]
     Bmean = float(np.mean([c.shape[2] for c, _ in secs]))
+    fk = form_kwargs(args.form, args.precision)
     out = {
         "value": pairs / (ms_per_step / 1e3), "unit": "pairs/s", "ms_per_step": ms_per_step,
         "wall_ms_median": statistics.median(walls), "wall_ms_min": min(walls), "wall_ms_max": max(walls),
         "config": {"workload": "batch256", "desc": WORKLOAD_DESC["batch256"], "sections": len(secs),
-                   "precision": args.precision, "graph": args.graph, "autotune": args.autotune,
-                   "driver_variant": st["driver_variant"]},
-        "pairs_per_step": pairs, "merges_per_step": st["merges"],
-        "stage_ms_persistent_levels_summed_over_sections": stage_dict(st),
+                   "form": args.form, "precision": fk["precision"], "graph": args.graph,
+                   "autotune": args.autotune, "driver_variant": st["driver_variant"]},
+        "pairs_per_step": pairs, "merges_per_step": st["merges"], "exact_evaluations_per_step": st["exact_rechecks"],
     }
-    # roofline with the mean band count (the pair counts mix sections)
-    out["roofline"] = roofline_of(st, Bmean, ms_per_step, st["driver_launches"], f"batch256_{args.precision}")
-    per_pairs = []
+    ko = new_outs()
+    _, _, rk = timed_steps(runner(args.form, ko, False, kernel_times=True), stream, torch, 1, 0)
+    out["kernel_times_step_ms"] = rk.stats["ms_total"]
+    # the band count varies by section: the roofline uses the mean
+    out["roofline"] = kernel_roofline(rk.stats, Bmean, f"batch256_{args.form}")
+    comparisons = {}
     if not args.no_plain:
-        # the plain path: 256 sequential hswo_run calls, FP32 screen
+        # the plain path: 256 sequential hswo_run calls, FP32 screen, every pair each iteration
         torch.cuda.synchronize()
         ts = time.perf_counter()
         same = True
         for i, c in enumerate(dc):
-            r = hswo.hswo_run(c, precision="fp32", stats=True, **params)
-            per_pairs.append(r.stats["adjacent_pairs"] + r.stats["spectral_pairs"])
+            r = hswo.hswo_run(c, precision="fp32", **params)
             same = same and bool(torch.equal(r.labels, outs[i]))
         torch.cuda.synchronize()
         plain_ms = (time.perf_counter() - ts) * 1e3
-        out["plain_fp32"] = {"form": "256 sequential hswo_run calls", "ms_per_step": plain_ms,
-                             "speedup_of_timed_form": plain_ms / ms_per_step, "labels_identical_to_timed_form": same}
+        comparisons["plain_sequential"] = {"form": "256 sequential hswo_run calls, plain FP32", "ms_per_step": plain_ms,
+                                           "speedup_of_timed_form": plain_ms / ms_per_step,
+                                           "labels_identical_to_timed_form": same}
+    if args.form != "screened":
+        so = new_outs()
+        ms, _, _ = timed_steps(runner("screened", so, args.graph), stream, torch, 1, 1)
+        comparisons["screened_batched"] = {"ms_per_step": ms, "speedup_of_timed_form": ms / ms_per_step,
+                                           "precision": args.precision,
+                                           "labels_identical_to_timed_form":
+                                               all(bool(torch.equal(a, b)) for a, b in zip(so, outs))}
+    out["forms"] = comparisons
     if not args.no_cpu_baseline:
+        import concurrent.futures as cf
+
         import oracle
         threads = os.cpu_count() or 1
         tc = time.perf_counter()
-        done, same, cpu_pairs = 0, True, 0
+        done, same = 0, True
         # a bounded sample of whole sections (in index order) for ~15 s
         while done < len(secs) and time.perf_counter() - tc < 15.0:
             batch = list(range(done, min(len(secs), done + threads)))
-            import concurrent.futures as cf
             with cf.ThreadPoolExecutor(threads) as ex:
                 refs = list(ex.map(lambda i: oracle.rhseg(secs[i][0], **params, n_threads=1), batch))
             for i, ref in zip(batch, refs):
                 same = same and bool(np.array_equal(outs[i].cpu().numpy(), ref.labels))
-                if per_pairs:
-                    cpu_pairs += per_pairs[i]
             done += len(batch)
         cpu_s = time.perf_counter() - tc
-        out["cpu_baseline"] = {"value": (cpu_pairs / cpu_s) if cpu_pairs else None, "unit": "pairs/s",
-                               "cores": threads, "kind": "oracle",
+        # the method's pairs of the sampled sections, counted by the kernels of a batch over them
+        rs = hswo.hswo_run_batch(dc[:done], stats=True, **form_kwargs("incremental", args.precision), **params)
+        cpu_pairs = rs.stats["adjacent_pairs"] + rs.stats["spectral_pairs"]
+        out["cpu_baseline"] = {"value": cpu_pairs / cpu_s, "unit": "pairs/s", "cores": threads, "kind": "oracle",
                                "sample": f"sections 0..{done - 1} of 256, one oracle run per section on {threads} "
                                          f"threads, {cpu_s:.2f} s"}
         out["labels_identical_to_oracle_on_sample"] = same
@@ -252,19 +314,20 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rhseg512", choices=sorted(WORKLOAD_DESC))
+    ap.add_argument("--form", default="incremental", choices=["incremental", "screened", "plain"],
+                    help="form of the timed steps (the others run once for the comparison)")
     ap.add_argument("--precision", default="fp16", choices=["fp32", "bf16", "fp16"],
-                    help="screen of the spectral stage for the timed steps (fp32 = plain path)")
+                    help="matrix-core screen precision of the screened form")
     ap.add_argument("--no-graph", dest="graph", action="store_false", help="launch eagerly instead of a hipGraph")
     ap.add_argument("--autotune", action="store_true", help="autotune the section-driver variant first")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 comparison run")
-    ap.add_argument("--no-incremental", action="store_true", help="skip the incremental-adjacent run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the sections of a recursion level would be "
-                                   "sharded across GPUs (see DESIGN.md), which is not implemented",
+        print(json.dumps({"error": "one GPU only: sharding the sections of a recursion level across GPUs is not "
+                                   "implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
@@ -280,7 +343,9 @@ def main():
     out = {"metric": "RHSEG wall time + dissimilarity pairs/s, MFMA+batched vs plain, same labels",
            "value": body.pop("value"), "unit": body.pop("unit"), "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": body.pop("ms_per_step"), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f32+f16 screens, f64 decisions",
+           "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if args.form == "incremental" else ("f32+f16 screens, f64 decisions"
+                                                              if args.precision != "fp32" else "f32 screen, f64 decisions"),
            "data": "synthetic"}
     out.update(body)
     print(json.dumps(out))

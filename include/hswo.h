@@ -74,7 +74,7 @@ extern "C" {
 #define HSWO_E_NOMEM (-2)       /* workspace too small (see hswo_workspace_bytes) */
 #define HSWO_E_DEVICE (-3)      /* a HIP call failed */
 #define HSWO_E_NONFINITE (-4)   /* reserved: non-finite input found by a caller-side check */
-#define HSWO_E_UNSUPPORTED (-5) /* valid request this build does not implement */
+#define HSWO_E_UNSUPPORTED (-5) /* valid request this library version does not implement */
 
 /* cube element types */
 #define HSWO_F32 0
@@ -94,6 +94,10 @@ extern "C" {
 #define HSWO_FLAG_INCREMENTAL 8 /* keep each adjacent pair's exact D2 and re-score only the pairs a merge
                                    changed (the adjacent minimum is then a reduction over the cached
                                    values); same merges and labels as the full per-iteration sweep */
+#define HSWO_FLAG_KERNEL_TIMES 16 /* bracket every merge-loop kernel launch with hipEvents on the call's
+                                     stream and report per-kernel device time in hswo_stats
+                                     (ms_kernel, kernel_launches); needs stats, not with
+                                     HSWO_FLAG_GRAPH */
 #define HSWO_FLAG_AUTOTUNE 4  /* on the first call for a shape bucket, time every section-driver
                                  variant on the call itself (all give identical results) and keep
                                  the fastest; the choice is cached per process and appended to the
@@ -121,12 +125,26 @@ typedef struct hswo_merge_rec {
     double d2;        /* the canonical FP64 squared criterion of the merge */
 } hswo_merge_rec;     /* 24 bytes */
 
+/* kernel kinds of hswo_stats.ms_kernel / kernel_launches */
+#define HSWO_K_SECTION_DRIVER 0 /* one workgroup per section runs a whole pass */
+#define HSWO_K_WIDE_ADJ 1       /* wide mode: adjacent screen, edges split over G workgroups */
+#define HSWO_K_WIDE_DECIDE 2    /* wide mode: decision and merge, one workgroup per section */
+#define HSWO_K_WIDE_MFMA 3      /* wide mode: matrix-core tile screen of the spectral stage */
+#define HSWO_K_WIDE_FP32 4      /* wide mode: FP32 tile screen of the spectral stage */
+#define HSWO_K_WIDE_FINISH 5    /* wide mode: spectral decision and merge */
+#define HSWO_K_WIDE_ROWS 6      /* wide mode, incremental form: row-cache re-evaluation */
+#define HSWO_K_ROWCACHE_PREP 7  /* incremental form: row cache start at a pass start */
+#define HSWO_NK 8
+
 typedef struct hswo_stats {
     int64_t merges;              /* merges performed */
     int64_t iterations;          /* merge-loop iterations over all sections */
-    int64_t adjacent_pairs;      /* adjacent pairs screened (summed over iterations) */
-    int64_t spectral_pairs;      /* unordered pairs screened in the spectral stage */
-    int64_t exact_rechecks;      /* pairs re-scored in canonical FP64 */
+    int64_t adjacent_pairs;      /* adjacent pairs of the method, summed over iterations (live edges
+                                    per iteration, whether screened or read from the cache) */
+    int64_t spectral_pairs;      /* unordered pairs of the method's spectral stage, summed over the
+                                    iterations where it is active (R (R - 1) / 2 each) */
+    int64_t exact_rechecks;      /* pairs evaluated in canonical FP64 (screen re-checks, cache
+                                    re-scoring and row-cache rows) */
     int64_t tile_rescans;        /* spectral tiles re-screened to collect candidates */
     int64_t fp32_tiles;          /* 64 x 64 spectral tiles screened in FP32 */
     int64_t mfma_tiles;          /* 128 x 128 super tiles screened on matrix cores (16-bit forms) */
@@ -138,7 +156,11 @@ typedef struct hswo_stats {
        constant clock), ms: adjacent stage, matrix-core screen, FP32
        spectral tiles with the exact re-check, merge */
     double ms_adjacent, ms_mfma_screen, ms_fp32_spectral, ms_merge;
-} hswo_stats;
+    /* with HSWO_FLAG_KERNEL_TIMES: device time (hipEvents around each launch)
+       and launches per kernel kind HSWO_K_*; zero otherwise */
+    double ms_kernel[HSWO_NK];
+    int64_t kernel_launches[HSWO_NK];
+} hswo_stats;   /* 256 bytes */
 
 /* One independent section for hswo_run_batch. */
 typedef struct hswo_section {

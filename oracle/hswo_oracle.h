@@ -19,7 +19,7 @@
  *   Criterion (Equation 1): sqrt( n_i n_j / (n_i + n_j) * sum_b (mu_ib - mu_jb)^2 ).
  *   The oracle ranks on the squared value D2 (sqrt is monotone).
  *
- * Readings taken where the paper is silent (listed in the design doc):
+ * Readings taken where the paper is silent:
  *   one merge per iteration; the non-adjacent pair wins iff
  *   D2_na < w^2 * D2_adj (strict); spectral stage active iff w > 0 and
  *   R <= spclust_max; ties broken lexicographically on (D2, lo, hi) where

@@ -251,6 +251,7 @@ Layout carve(const Plan& pl, int H, int W, const hswo_params* p, void* ws, const
             s.label = bp.take<int32_t>(sp.cap);
             s.npix = bp.take<int32_t>(sp.cap);
             s.mark = bp.take<int32_t>(sp.cap);
+            s.dmark = bp.take<int32_t>(sp.cap);
             s.norm = bp.take<float>(sp.cap);
             s.sums = bp.take<double>(sp.cap * pl.B);
             s.mean = bp.take<float>(sp.cap * pl.Bp);
@@ -283,8 +284,8 @@ Layout carve(const Plan& pl, int H, int W, const hswo_params* p, void* ws, const
                 s.cvec = bp.take<float>(pl.Bp);
             }
             s.st = bp.take<int32_t>(ST_WORDS);
-            s.wi = bp.take<int32_t>(8);
-            s.wd = bp.take<double>(2);
+            s.wi = bp.take<int32_t>(16);
+            s.wd = bp.take<double>(4);
             s.wpart = bp.take<float>(2 * GMAX);
             s.parent = lay.parent;
             s.mtime = lay.mtime;
@@ -340,7 +341,10 @@ void add_upload(std::vector<Upload>& ups, void* dst, const T* src, size_t n) {
 }
 
 struct Timer {
-    std::vector<hipEvent_t> drv;  // pairs around each section-driver launch
+    std::vector<hipEvent_t> drv;  // pairs around each level's merge-loop launches
+    bool kernels = false;         // HSWO_FLAG_KERNEL_TIMES: also bracket every launch by kind
+    KTimer kt;
+    KTimer* per_kernel() { return kernels ? &kt : nullptr; }
     ~Timer() {
         for (hipEvent_t e : drv) (void)hipEventDestroy(e);
     }
@@ -364,7 +368,10 @@ int timed_driver(Timer* tm, const SecDev* secs, int n, const LoopParams& lp, int
         tm->drv.push_back(e1);
         HIP_TRY(hipEventRecord(e0, stream));
     }
+    KTimer* kt = tm ? tm->per_kernel() : nullptr;
+    if (kt) HIP_TRY(kt->mark(HSWO_K_SECTION_DRIVER, stream));
     HIP_TRY(launch_section_driver(secs, n, lp, variant, stream));
+    if (kt) HIP_TRY(kt->mark(HSWO_K_SECTION_DRIVER, stream));
     if (tm) HIP_TRY(hipEventRecord(e1, stream));
     return HSWO_OK;
 }
@@ -391,13 +398,42 @@ int device_cus() {
 // knows R at iteration t exactly (cap - t, until the stop count), so the
 // spectral kernels are launched only for iterations where some section can be
 // in its spectral stage.
+// In the incremental form the iterations of a pass before its spectral stage
+// (R > spclust_max) need no work spread over workgroups: they run in the
+// section driver (one launch, state kept on chip) up to R = spclust_max, and
+// wide mode takes the rest. HSWO_HYBRID=0 turns this off.
+bool hybrid_on() {
+    const char* e = getenv("HSWO_HYBRID");
+    return !(e && atoi(e) == 0);
+}
+
 int run_level(Timer* tm, const SecDev* secs, int n, const std::vector<int64_t>& cap, const std::vector<int64_t>& stop,
               const LoopParams& lp, bool row_cache, int variant, hipStream_t stream) {
     if (n > wide_max_sections() || (row_cache && n > ROWS_MAX_SECTIONS))
         return timed_driver(tm, secs, n, lp, variant, stream);
     const int G = std::max(1, std::min(GMAX, device_cus() / n));
+    // R of each section when the wide iterations start
+    std::vector<int64_t> r0(cap);
+    if (lp.incremental && lp.spectral && hybrid_on()) {
+        int64_t pre = 0;
+        for (int i = 0; i < n; ++i) {
+            const int64_t p = std::max<int64_t>(lp.kmax, stop[i]);
+            if (cap[i] > p) {
+                pre = std::max(pre, cap[i] - p);
+                r0[i] = p;
+            }
+        }
+        if (pre > 0) {
+            LoopParams lpp = lp;
+            lpp.phase_stop = lp.kmax;
+            const int rc = timed_driver(tm, secs, n, lpp, variant, stream);
+            if (rc) return rc;
+        } else {
+            r0 = cap;
+        }
+    }
     int64_t iters = 0;
-    for (int i = 0; i < n; ++i) iters = std::max(iters, cap[i] - std::min(cap[i], stop[i]));
+    for (int i = 0; i < n; ++i) iters = std::max(iters, r0[i] - std::min(r0[i], stop[i]));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (tm) {
         HIP_TRY(hipEventCreate(&e0));
@@ -406,15 +442,16 @@ int run_level(Timer* tm, const SecDev* secs, int n, const std::vector<int64_t>& 
         tm->drv.push_back(e1);
         HIP_TRY(hipEventRecord(e0, stream));
     }
-    if (row_cache) HIP_TRY(launch_rowcache_prep(secs, n, lp, stream));
+    KTimer* kt = tm ? tm->per_kernel() : nullptr;
+    if (row_cache) HIP_TRY(launch_rowcache_prep(secs, n, lp, stream, kt));
     for (int64_t t = 0; t < iters; ++t) {
         bool spec = false;
         if (lp.spectral)
             for (int i = 0; i < n && !spec; ++i) {
-                const int64_t R = cap[i] - t;
+                const int64_t R = r0[i] - t;
                 spec = R > stop[i] && R <= lp.kmax;
             }
-        HIP_TRY(launch_wide_iteration(secs, n, G, lp, variant, spec, row_cache, stream));
+        HIP_TRY(launch_wide_iteration(secs, n, G, lp, variant, spec, row_cache, stream, kt));
     }
     if (tm) HIP_TRY(hipEventRecord(e1, stream));
     return HSWO_OK;
@@ -467,12 +504,16 @@ struct ExecOut {
     double ms_total = 0.0, ms_driver = 0.0;
     int64_t driver_launches = 0;
     int variant = 6;
+    double ms_kernel[HSWO_NK] = {};
+    int64_t kernel_launches[HSWO_NK] = {};
 };
 
 int execute(const std::vector<Upload>& ups, const Seq& seq, const std::string& key, const std::string& tune_key,
             int flags, hipStream_t stream, unsigned long long* d_counters, bool want_stats, ExecOut& out) {
     if ((flags & HSWO_FLAG_GRAPH) && stream == nullptr)
         return fail(HSWO_E_INVAL, "HSWO_FLAG_GRAPH needs a non-null stream (the null stream cannot be captured)");
+    if ((flags & HSWO_FLAG_KERNEL_TIMES) && ((flags & HSWO_FLAG_GRAPH) || !want_stats))
+        return fail(HSWO_E_INVAL, "HSWO_FLAG_KERNEL_TIMES needs stats and cannot be combined with HSWO_FLAG_GRAPH");
     for (const Upload& u : ups)
         HIP_TRY(hipMemcpyAsync(u.dst, u.bytes.data(), u.bytes.size(), hipMemcpyHostToDevice, stream));
 
@@ -517,6 +558,7 @@ int execute(const std::vector<Upload>& ups, const Seq& seq, const std::string& k
     out.variant = variant;
 
     Timer tm;
+    tm.kernels = (flags & HSWO_FLAG_KERNEL_TIMES) != 0;
     EventPair tot;
     if (want_stats) {
         HIP_TRY(hipEventCreate(&tot.a));
@@ -573,6 +615,17 @@ int execute(const std::vector<Upload>& ups, const Seq& seq, const std::string& k
             md += x;
         }
         out.driver_launches = (int64_t)(tm.drv.size() / 2);
+        for (int k = 0; k < HSWO_NK; ++k) {
+            const std::vector<hipEvent_t>& v = tm.kt.ev[k];
+            double t = 0.0;
+            for (size_t i = 0; i + 1 < v.size(); i += 2) {
+                float x = 0.f;
+                HIP_TRY(hipEventElapsedTime(&x, v[i], v[i + 1]));
+                t += x;
+            }
+            out.ms_kernel[k] = t;
+            out.kernel_launches[k] = (int64_t)(v.size() / 2);
+        }
         // under a graph the launches are not bracketed individually
         out.ms_driver = tm.drv.empty() ? ms : md;
     }
@@ -601,6 +654,10 @@ int fill_stats(hswo_stats* st, const ExecOut& o, int64_t launches_if_graph) {
     st->ms_mfma_screen = (double)c[C_T_MFMA] * tick_ms;
     st->ms_fp32_spectral = (double)c[C_T_SPEC32] * tick_ms;
     st->ms_merge = (double)c[C_T_MERGE] * tick_ms;
+    for (int k = 0; k < HSWO_NK; ++k) {
+        st->ms_kernel[k] = o.ms_kernel[k];
+        st->kernel_launches[k] = o.kernel_launches[k];
+    }
     return HSWO_OK;
 }
 
@@ -627,6 +684,7 @@ LoopParams loop_params(const hswo_params* p, unsigned long long* counters) {
     lp.kmax = p->spclust_max;
     lp.precision = p->precision;
     lp.incremental = (p->flags & HSWO_FLAG_INCREMENTAL) ? 1 : 0;
+    lp.phase_stop = 0;
     lp.counters = counters;
     return lp;
 }
@@ -634,7 +692,8 @@ LoopParams loop_params(const hswo_params* p, unsigned long long* counters) {
 int check_common(const hswo_params* p, void* workspace) {
     if (!workspace) return fail(HSWO_E_INVAL, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(HSWO_E_INVAL, "workspace must be 256-byte aligned");
-    if (p->flags & ~(HSWO_FLAG_MERGE_LOG | HSWO_FLAG_GRAPH | HSWO_FLAG_AUTOTUNE | HSWO_FLAG_INCREMENTAL))
+    if (p->flags & ~(HSWO_FLAG_MERGE_LOG | HSWO_FLAG_GRAPH | HSWO_FLAG_AUTOTUNE | HSWO_FLAG_INCREMENTAL |
+                     HSWO_FLAG_KERNEL_TIMES))
         return fail(HSWO_E_INVAL, "unknown flags 0x%x", p->flags);
     return HSWO_OK;
 }
@@ -789,6 +848,7 @@ BatchLayout carve_batch(int n, const hswo_section* sec, const hswo_params* p, vo
         s.label = bp.take<int32_t>(cap);
         s.npix = bp.take<int32_t>(cap);
         s.mark = bp.take<int32_t>(cap);
+        s.dmark = bp.take<int32_t>(cap);
         s.norm = bp.take<float>(cap);
         s.sums = bp.take<double>(cap * q.B);
         s.mean = bp.take<float>(cap * Bp);
@@ -821,8 +881,8 @@ BatchLayout carve_batch(int n, const hswo_section* sec, const hswo_params* p, vo
             s.cvec = bp.take<float>(Bp);
         }
         s.st = bp.take<int32_t>(ST_WORDS);
-        s.wi = bp.take<int32_t>(8);
-        s.wd = bp.take<double>(2);
+        s.wi = bp.take<int32_t>(16);
+        s.wd = bp.take<double>(4);
         s.wpart = bp.take<float>(2 * GMAX);
         s.parent = bp.take<int32_t>(cap);
         s.mtime = bp.take<int32_t>(cap);

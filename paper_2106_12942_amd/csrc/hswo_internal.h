@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include <cstddef>
 #include <cstdint>
 
@@ -35,7 +37,7 @@ enum Counter {
     C_COUNT
 };
 
-constexpr int ST_WORDS = 8;   // per-section state words
+constexpr int ST_WORDS = 16;  // per-section state words
 constexpr int GMAX = 256;     // wide mode: most workgroups per section
 constexpr int STILE = 128;    // matrix-core super tile edge (4 spectral tiles)
 
@@ -62,6 +64,7 @@ struct SecDev {
     float* mean;     // [R0][Bp] FP32 mean spectrum (screen copy), zero padded
     float* norm;     // [R0] upper bound of the L2 norm of the FP32 mean row
     int32_t* mark;   // [R0] per-iteration marks for edge de-duplication
+    int32_t* dmark;  // [R0] incremental merge: least edge slot per neighbour of the merged pair
     int2* edges;     // [Ecap] adjacent slot pairs
     float2* escr;    // [Ecap] per-edge screen bounds (lower, upper)
     float2* tstat;   // [tiles] per-tile bounds (min lower, min upper)
@@ -86,13 +89,15 @@ struct SecDev {
     int32_t* rpend;  // [rcap] rows to re-evaluate: [0] the last merge's survivor, then stale rows
     RowPart* rpart;  // [rcap][ceil(rcap / 64)] per-row, per-64-column partial minima
     // wide mode iteration scratch
-    int32_t* wi;     // [8]
-    double* wd;      // [2]
+    int32_t* wi;     // [16]
+    double* wd;      // [4]
     float* wpart;    // [2 * GMAX]
     int32_t* st;     // state: [0] R, [1] E, [2] R at pass start, [3] merges done, [4] 16-bit rows ready,
                      //        [5] per-edge exact D2 cache valid,
                      //        [6] row cache: 0 off, 1 means ready (every row pending), 2 valid,
-                     //        [7] pending rows of the row cache
+                     //        [7] pending rows of the row cache,
+                     //        [8] incremental form: next adjacent minimum cached (wd[2], wi[8..11]),
+                     //        [9] empty edge slots left by incremental merges
     int32_t* parent; // label-indexed union-find parent (image or batch section)
     int32_t* mtime;  // label-indexed merge time: -1 non-top merge, k top merge, INT_MAX alive
     hswo_merge_rec* log;  // section merge log base (may be null)
@@ -134,7 +139,24 @@ struct LoopParams {
     int32_t kmax;     // spectral stage iff R <= kmax
     int32_t precision;
     int32_t incremental;  // adjacent minimum from cached exact per-edge D2 (only changed edges re-scored)
+    int32_t phase_stop;   // section driver: also stop at this region count (0: the pass's stop only)
     unsigned long long* counters;  // [C_COUNT]
+};
+
+// Per-kernel-kind event pairs (HSWO_FLAG_KERNEL_TIMES), host side.
+struct KTimer {
+    std::vector<hipEvent_t> ev[HSWO_NK];  // pairs around each launch of a kind
+    hipError_t mark(int kind, hipStream_t s) {
+        hipEvent_t e = nullptr;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        ev[kind].push_back(e);
+        return hipEventRecord(e, s);
+    }
+    ~KTimer() {
+        for (auto& v : ev)
+            for (hipEvent_t e : v) (void)hipEventDestroy(e);
+    }
 };
 
 // kernel launchers (hswo_kernels.hip)
@@ -145,9 +167,9 @@ hipError_t launch_init_leaves(const SecDev* secs, const InitDev* init, int n, in
 hipError_t launch_section_driver(const SecDev* secs, int n, const LoopParams& lp, int variant, hipStream_t s);
 constexpr int DRIVER_VARIANTS[3] = {2, 4, 6};  // adjacent-stage edges in flight per lane group
 hipError_t launch_wide_iteration(const SecDev* secs, int n, int G, const LoopParams& lp, int variant,
-                                 bool spectral_possible, bool row_cache, hipStream_t s);
+                                 bool spectral_possible, bool row_cache, hipStream_t s, KTimer* kt);
 constexpr int ROWS_MAX_SECTIONS = 1024;  // sections a row-cache task pool launch can cover
-hipError_t launch_rowcache_prep(const SecDev* secs, int n, const LoopParams& lp, hipStream_t s);
+hipError_t launch_rowcache_prep(const SecDev* secs, int n, const LoopParams& lp, hipStream_t s, KTimer* kt);
 hipError_t launch_compress(int32_t* parent, int64_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_assemble(const SecDev* parents, const SecDev* children, const AsmDev* asm_, int n,

@@ -815,10 +815,12 @@ __device__ KeyD cached_min(Smem& sh, const SecDev& s, int R) {
     return block_min_key(sh, best);
 }
 
-// rc: row cache state of the section (0 off, 1 means maintained, 2 rows
-// maintained: the stale rows are listed for re-evaluation).
-__device__ void merge_pair(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int& E, int stamp,
-                           int kind, double d2, int g_ready, int prec, int rc) {
+// Statistics part of a merge (HSEG step 4): the survivor lo takes hi's band
+// sums and pixel count; its FP32 screen row (and 16-bit row, FP64 mean
+// copies) are refreshed; union-find parent, merge time and log record.
+// rc: row cache state of the section (0 off, 1 or 2 means maintained).
+__device__ void merge_stats(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int kind, double d2, int g_ready,
+                            int prec, int rc) {
     const int tid = threadIdx.x;
     const int B = s.B, Bp = s.Bp;
     const int lo_l = s.label[lo_s], hi_l = s.label[hi_s];
@@ -864,6 +866,15 @@ __device__ void merge_pair(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R,
         }
         s.st[3] = k + 1;
     }
+}
+
+// Edge list part of a merge, by a full pass: relabel hi -> lo, drop the
+// merged pair and duplicate (lo, x) edges, rename the moved slot, compact in
+// place (writes never pass reads). With inc the cached D2 moves along, and
+// the edges that touch the survivor are listed in edirty (count in
+// sh.bcast_i[2]) for re-scoring.
+__device__ void merge_edges_full(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int& E, int stamp, bool inc) {
+    const int tid = threadIdx.x;
     // mark the neighbours of the survivor
     for (int e = tid; e < E; e += NT) {
         const int2 ed = s.edges[e];
@@ -871,10 +882,7 @@ __device__ void merge_pair(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R,
         if (ed.y == lo_s) s.mark[ed.x] = stamp;
     }
     __syncthreads();
-    // relabel hi -> lo, drop the merged pair and duplicate (lo, x) edges,
-    // rename the moved slot, compact in place (writes never pass reads)
     const int last = R - 1;
-    const bool inc = s.ed2 != nullptr && s.st[5] != 0;
     const int surv = (lo_s == last) ? hi_s : lo_s;  // the survivor's slot after the swap-remove
     if (tid == 0) sh.bcast_i[2] = 0;
     int newE = 0;
@@ -912,7 +920,18 @@ __device__ void merge_pair(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R,
     }
     E = newE;
     __syncthreads();
-    // swap-remove: move the last live slot into the freed one
+}
+
+// Slot part of a merge: swap-remove (the last live slot moves into the freed
+// one) and, with the row cache (rc == 2), the row entries: the moved row's
+// entry follows it, partners that moved are renamed, and the survivor and
+// every row whose cached partner was one of the merged pair are listed for
+// re-evaluation (count in st[7] and sh.npend).
+__device__ void merge_slots(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int g_ready, int rc) {
+    const int tid = threadIdx.x;
+    const int B = s.B, Bp = s.Bp;
+    const int last = R - 1;
+    const int surv = (lo_s == last) ? hi_s : lo_s;
     if (hi_s != last) {
         const double* Ssrc = s.sums + (size_t)last * B;
         double* Sdst = s.sums + (size_t)hi_s * B;
@@ -944,9 +963,6 @@ __device__ void merge_pair(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R,
         }
     }
     if (rc == 2) {
-        // row cache: move the last row's entry into the freed slot, rename
-        // partners that moved, list the survivor and every row whose cached
-        // partner was one of the merged pair
         if (tid == 0) sh.npend = 1;
         __syncthreads();
         for (int i = tid; i < R; i += NT) {
@@ -970,11 +986,201 @@ __device__ void merge_pair(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R,
         if (tid == 0) s.st[7] = sh.npend;
     }
     __syncthreads();
+}
+
+// Merge of (lo_s, hi_s) (HSEG step 4). rc: row cache state (0 off, 1 means
+// maintained, 2 rows maintained).
+__device__ void merge_pair(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int& E, int stamp,
+                           int kind, double d2, int g_ready, int prec, int rc) {
+    merge_stats(sh, s, lo_s, hi_s, R, kind, d2, g_ready, prec, rc);
+    const bool inc = s.ed2 != nullptr && s.st[5] != 0;
+    merge_edges_full(sh, s, lo_s, hi_s, R, E, stamp, inc);
+    merge_slots(sh, s, lo_s, hi_s, R, g_ready, rc);
     if (inc) {  // re-score the survivor's edges; every other edge keeps its cached value
         const int nd = sh.bcast_i[2];
         for (int i = wave_id(); i < nd; i += NWAVE) score_edge_exact(sh, s, s.edirty[i]);
         __syncthreads();
     }
+}
+
+// Remove the empty slots (-1, -1) of the edge list, keeping order, with the
+// cached D2 moving along.
+__device__ void compact_edges(Smem& sh, const SecDev& s, int& E) {
+    int newE = 0;
+    for (int e0 = 0; e0 < E; e0 += NT) {
+        const int e = e0 + threadIdx.x;
+        bool keep = false;
+        int2 ed = make_int2(-1, -1);
+        double v = 0.0;
+        if (e < E) {
+            ed = s.edges[e];
+            v = s.ed2[e];
+            keep = ed.x >= 0;
+        }
+        int tot;
+        const int pos = block_scan_flag(sh, keep, &tot);  // barrier: chunk fully read
+        if (keep) {
+            s.edges[newE + pos] = ed;
+            s.ed2[newE + pos] = v;
+        }
+        newE += tot;
+    }
+    E = newE;
+    __syncthreads();
+}
+
+constexpr int LCAP = CAND_CAP / 2;  // edges listed per merge by the incremental form
+
+// Merge in the incremental form (every edge slot holds its exact D2). One
+// pass over the edge slots lists the edges that touch the merged pair (L)
+// and those that touch the slot that will move (L2), and takes the least key
+// over every edge not in L, whose D2 cannot change. Only the listed edges are
+// then rewritten: one edge per neighbour x of the merged pair becomes
+// (survivor, x) and is re-scored, the others become empty slots; the edge
+// list is compacted when a quarter of it is empty, and at the last merge of a
+// pass. Returns true with the least adjacent key after the merge in anext;
+// false (full pass taken) when a list would overflow.
+__device__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int& E, int stamp, int kind,
+                               double d2, int rc, KeyD& anext, int& nchk) {
+    const int tid = threadIdx.x;
+    merge_stats(sh, s, lo_s, hi_s, R, kind, d2, 0, 0, rc);
+    const int last = R - 1;
+    const int surv = (lo_s == last) ? hi_s : lo_s;
+    int* L = sh.u.f.cand;
+    int* L2 = sh.u.f.cand + LCAP;
+    if (tid == 0) {
+        sh.bcast_i[0] = 0;  // |L|
+        sh.bcast_i[1] = 0;  // |L2|
+        sh.bcast_i[2] = 0;  // kept edges
+        sh.bcast_i[3] = 0;  // emptied slots
+    }
+    __syncthreads();
+    KeyD best = key_none();
+    constexpr int U = 4;  // edge slots per thread with loads in flight together
+    for (int e0 = tid; e0 < E; e0 += NT * U) {
+        int2 ed[U];
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * NT;
+            ed[u] = e < E ? s.edges[e] : make_int2(-1, -1);
+            v[u] = e < E ? s.ed2[e] : __builtin_huge_val();
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * NT;
+            const int a = ed[u].x, b = ed[u].y;
+            const bool touch = a == lo_s || a == hi_s || b == lo_s || b == hi_s;
+            if (a >= 0 && touch) {
+                const int k = atomicAdd(&sh.bcast_i[0], 1);
+                if (k < LCAP) L[k] = e;
+            }
+            const int na = (a == last) ? hi_s : a, nb = (b == last) ? hi_s : b;
+            if (a >= 0 && !touch && (na != a || nb != b)) {
+                const int k = atomicAdd(&sh.bcast_i[1], 1);
+                if (k < LCAP) L2[k] = e;
+            }
+            if (a >= 0 && !touch && v[u] <= best.d2) {
+                const int la = s.label[a], lb = s.label[b];
+                KeyD k;
+                k.d2 = v[u];
+                if (la < lb) {
+                    k.lo = la;
+                    k.hi = lb;
+                    k.si = na;
+                    k.sj = nb;
+                } else {
+                    k.lo = lb;
+                    k.hi = la;
+                    k.si = nb;
+                    k.sj = na;
+                }
+                if (key_less(k, best)) best = k;
+            }
+        }
+    }
+    __syncthreads();
+    const int n1 = sh.bcast_i[0], n2 = sh.bcast_i[1];
+    if (n1 > LCAP || n2 > LCAP) {
+        // a very high degree at the merged pair: the full pass
+        merge_edges_full(sh, s, lo_s, hi_s, R, E, stamp, true);
+        merge_slots(sh, s, lo_s, hi_s, R, 0, rc);
+        const int nd = sh.bcast_i[2];
+        for (int i = wave_id(); i < nd; i += NWAVE) score_edge_exact(sh, s, s.edirty[i]);
+        nchk += nd;
+        __syncthreads();
+        if (tid == 0) s.st[9] = 0;
+        return false;
+    }
+    // rename the moved slot in L2; reset the marks of the neighbours in L
+    for (int k = tid; k < n2; k += NT) {
+        const int e = L2[k];
+        int2 ed = s.edges[e];
+        if (ed.x == last) ed.x = hi_s;
+        if (ed.y == last) ed.y = hi_s;
+        s.edges[e] = ed;
+    }
+    for (int k = tid; k < n1; k += NT) {
+        const int2 ed = s.edges[L[k]];
+        const bool ax = ed.x == lo_s || ed.x == hi_s, bx = ed.y == lo_s || ed.y == hi_s;
+        if (!(ax && bx)) s.dmark[ax ? ed.y : ed.x] = INT_MAX;
+    }
+    __syncthreads();
+    for (int k = tid; k < n1; k += NT) {
+        const int e = L[k];
+        const int2 ed = s.edges[e];
+        const bool ax = ed.x == lo_s || ed.x == hi_s, bx = ed.y == lo_s || ed.y == hi_s;
+        if (!(ax && bx)) atomicMin(&s.dmark[ax ? ed.y : ed.x], e);
+    }
+    __syncthreads();
+    int* K = L2;  // L2 is consumed
+    for (int k = tid; k < n1; k += NT) {
+        const int e = L[k];
+        const int2 ed = s.edges[e];
+        const bool ax = ed.x == lo_s || ed.x == hi_s, bx = ed.y == lo_s || ed.y == hi_s;
+        const int x = (ax && bx) ? -1 : (ax ? ed.y : ed.x);
+        if (x >= 0 && s.dmark[x] == e) {
+            s.edges[e] = make_int2(surv, x == last ? hi_s : x);
+            K[atomicAdd(&sh.bcast_i[2], 1)] = e;
+        } else {
+            s.edges[e] = make_int2(-1, -1);
+            s.ed2[e] = __builtin_huge_val();
+            atomicAdd(&sh.bcast_i[3], 1);
+        }
+    }
+    __syncthreads();
+    merge_slots(sh, s, lo_s, hi_s, R, 0, rc);  // ends with a barrier
+    const int nk = sh.bcast_i[2];
+    const int emptied = sh.bcast_i[3];
+    for (int k = wave_id(); k < nk; k += NWAVE) {
+        const int e = K[k];
+        const int2 ed = s.edges[e];
+        int a = ed.x, b = ed.y;
+        int la = s.label[a], lb = s.label[b];
+        if (la > lb) {
+            const int t = a; a = b; b = t;
+            const int u = la; la = lb; lb = u;
+        }
+        KeyD kk;
+        kk.d2 = exact_d2_wave(sh, s, a, b);
+        kk.lo = la;
+        kk.hi = lb;
+        kk.si = a;
+        kk.sj = b;
+        if (lane_id() == 0) s.ed2[e] = kk.d2;
+        if (key_less(kk, best)) best = kk;
+    }
+    nchk += nk;
+    anext = block_min_key(sh, best);
+    const int empty = s.st[9] + emptied;
+    __syncthreads();  // every thread has read st[9]
+    if (4 * empty > E || R - 1 <= s.stop) {
+        compact_edges(sh, s, E);
+        if (tid == 0) s.st[9] = 0;
+    } else if (tid == 0) {
+        s.st[9] = empty;
+    }
+    return true;
 }
 
 }  // namespace
@@ -1092,23 +1298,33 @@ __device__ KeyD adj_incremental(Smem& sh, const SecDev& s, int E, bool init, int
         __syncthreads();
     }
     KeyD best = key_none();
-    for (int e = threadIdx.x; e < E; e += NT) {
-        const double v = s.ed2[e];
-        if (v <= best.d2 && v < __builtin_huge_val()) {
-            const int2 ed = s.edges[e];
-            int a = ed.x, b = ed.y;
-            int la = s.label[a], lb = s.label[b];
-            if (la > lb) {
-                const int t = a; a = b; b = t;
-                const int u = la; la = lb; lb = u;
+    constexpr int U = 4;  // cached values per thread with loads in flight together
+    for (int e0 = threadIdx.x; e0 < E; e0 += NT * U) {
+        double vv[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int e = e0 + q * NT;
+            vv[q] = e < E ? s.ed2[e] : __builtin_huge_val();
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const double v = vv[q];
+            if (v <= best.d2 && v < __builtin_huge_val()) {
+                const int2 ed = s.edges[e0 + q * NT];
+                int a = ed.x, b = ed.y;
+                int la = s.label[a], lb = s.label[b];
+                if (la > lb) {
+                    const int t = a; a = b; b = t;
+                    const int w = la; la = lb; lb = w;
+                }
+                KeyD k;
+                k.d2 = v;
+                k.lo = la;
+                k.hi = lb;
+                k.si = a;
+                k.sj = b;
+                if (key_less(k, best)) best = k;
             }
-            KeyD k;
-            k.d2 = v;
-            k.lo = la;
-            k.hi = lb;
-            k.si = a;
-            k.sj = b;
-            if (key_less(k, best)) best = k;
         }
     }
     return block_min_key(sh, best);
@@ -1257,6 +1473,8 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
     int rcs = row_cache ? s.st[6] : 0;   // row cache state, block-uniform
     int npend = row_cache ? s.st[7] : 0; // pending rows (state 2)
     int merges = s.st[3];
+    bool avalid = false;  // incremental form: the least adjacent key after the last merge is known
+    KeyD anext = key_none();
     if (tid == 0) {
         sh.ncand = 0;
         for (int c = 0; c < C_COUNT; ++c) sh.cnt[c] = 0ull;
@@ -1268,20 +1486,25 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
         if (tid == 0) sh.cnt[k] += (unsigned long long)(v); \
     } while (0)
 
-    while (R > s.stop) {
+    const int stop_here = max(s.stop, lp.phase_stop);
+    while (R > stop_here) {
         unsigned long long tk0 = wall_clock64();
         // adjacent stage: full screen of every edge, or the cached exact values
         int nchk = 0;
         KeyD A;
         if (lp.incremental) {
-            A = adj_incremental(sh, s, E, s.st[5] == 0, nchk);
-            if (tid == 0) s.st[5] = 1;
+            if (avalid) {
+                A = anext;
+            } else {
+                A = adj_incremental(sh, s, E, s.st[5] == 0, nchk);
+                if (tid == 0) s.st[5] = 1;
+            }
         } else {
             const float myU = adj_screen_range<EPG>(s, 0, E, gam);
             const float Ua = block_min_f2(sh, myU, myU).x;
             A = adj_collect(sh, s, E, Ua, nchk);
         }
-        CNT_ADD(C_ADJ_PAIRS, E);
+        CNT_ADD(C_ADJ_PAIRS, E - s.st[9]);
         unsigned long long tk1 = wall_clock64();
         CNT_ADD(C_T_ADJ, tk1 - tk0);
         tk0 = tk1;
@@ -1306,7 +1529,8 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
             rcs = 2;
             npend = 0;
             M = cached_min(sh, s, R);
-            CNT_ADD(C_SPEC_PAIRS, (unsigned long long)rows * (unsigned long long)(R - 1));
+            CNT_ADD(C_SPEC_PAIRS, (unsigned long long)R * (unsigned long long)(R - 1) / 2ull);
+            CNT_ADD(C_RECHECKS, (unsigned long long)rows * (unsigned long long)(R - 1));
             tk1 = wall_clock64();
             CNT_ADD(C_T_SPEC32, tk1 - tk0);
             tk0 = tk1;
@@ -1348,7 +1572,13 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
         CNT_ADD(C_RECHECKS, nchk);
         CNT_ADD(C_ITERS, 1);
         CNT_ADD(C_MERGES, 1);
-        merge_pair(sh, s, win.si, win.sj, R, E, merges, kind, win.d2, g_ready, prec, rcs);
+        if (lp.incremental) {
+            int nre = 0;
+            avalid = merge_pair_inc(sh, s, win.si, win.sj, R, E, merges, kind, win.d2, rcs, anext, nre);
+            CNT_ADD(C_RECHECKS, nre);
+        } else {
+            merge_pair(sh, s, win.si, win.sj, R, E, merges, kind, win.d2, g_ready, prec, rcs);
+        }
         ++merges;
         --R;
         if (rcs == 2) npend = sh.npend;
@@ -1367,6 +1597,7 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
             s.st[6] = rcs;
             s.st[7] = npend;
         }
+        s.st[8] = 0;  // the driver keeps its adjacent minimum in registers
         if (lp.counters)
             for (int c = 0; c < C_COUNT; ++c)
                 if (sh.cnt[c]) atomicAdd(&lp.counters[c], sh.cnt[c]);
@@ -1420,7 +1651,7 @@ __global__ void __launch_bounds__(NT) k_wide_rows(const SecDev* __restrict__ sec
             const int np = mode == 1 ? R : s.st[7];
             cnt = row_task_count(R, np);
             if (blockIdx.x == 0 && lp.counters)
-                atomicAdd(&lp.counters[C_SPEC_PAIRS], (unsigned long long)np * (unsigned long long)(R - 1));
+                atomicAdd(&lp.counters[C_RECHECKS], (unsigned long long)np * (unsigned long long)(R - 1));
         }
         pre[k + 1] = cnt;
     }
@@ -1474,14 +1705,23 @@ __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ s
     int nchk = 0;
     KeyD A;
     if (lp.incremental) {
-        A = adj_incremental(sh, s, E, s.st[5] == 0, nchk);
-        if (tid == 0) s.st[5] = 1;
+        if (s.st[8]) {  // cached by the last merge
+            A.d2 = s.wd[2];
+            A.lo = s.wi[8];
+            A.hi = s.wi[9];
+            A.si = s.wi[10];
+            A.sj = s.wi[11];
+        } else {
+            A = adj_incremental(sh, s, E, s.st[5] == 0, nchk);
+            if (tid == 0) s.st[5] = 1;
+        }
         __syncthreads();
     } else {
         float Ua = __builtin_huge_valf();
         for (int g = 0; g < G; ++g) Ua = fminf(Ua, s.wpart[g]);
         A = adj_collect(sh, s, E, Ua, nchk);
     }
+    const int Elive = E - s.st[9];
     const bool spectral = lp.spectral && R <= lp.kmax;
     const double T = key_exists(A) ? lp.w2 * A.d2 : __builtin_huge_val();
     const bool row_cache = lp.incremental && s.rcap > 0;
@@ -1501,7 +1741,20 @@ __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ s
         int kind;
         if (decide(spectral, A, M, T, win, kind)) {
             const int stamp = s.st[3];
-            merge_pair(sh, s, win.si, win.sj, R, E, stamp, kind, win.d2, s.st[4], prec, rcs);
+            if (lp.incremental) {
+                KeyD an;
+                const bool av = merge_pair_inc(sh, s, win.si, win.sj, R, E, stamp, kind, win.d2, rcs, an, nchk);
+                if (tid == 0) {
+                    s.st[8] = av ? 1 : 0;
+                    s.wd[2] = an.d2;
+                    s.wi[8] = an.lo;
+                    s.wi[9] = an.hi;
+                    s.wi[10] = an.si;
+                    s.wi[11] = an.sj;
+                }
+            } else {
+                merge_pair(sh, s, win.si, win.sj, R, E, stamp, kind, win.d2, s.st[4], prec, rcs);
+            }
             if (tid == 0) {
                 s.st[0] = R - 1;
                 s.st[1] = E;
@@ -1515,8 +1768,10 @@ __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ s
             if (lp.counters) {
                 atomicAdd(&lp.counters[C_ITERS], 1ull);
                 atomicAdd(&lp.counters[C_MERGES], 1ull);
-                atomicAdd(&lp.counters[C_ADJ_PAIRS], (unsigned long long)E);
+                atomicAdd(&lp.counters[C_ADJ_PAIRS], (unsigned long long)Elive);
                 atomicAdd(&lp.counters[C_RECHECKS], (unsigned long long)nchk);
+                if (spectral)
+                    atomicAdd(&lp.counters[C_SPEC_PAIRS], (unsigned long long)R * (unsigned long long)(R - 1) / 2ull);
             }
         }
         return;
@@ -1712,6 +1967,8 @@ __global__ void k_init_leaves(const SecDev* __restrict__ secs, const InitDev* __
         s.st[5] = 0;
         s.st[6] = 0;
         s.st[7] = 0;
+        s.st[8] = 0;
+        s.st[9] = 0;
     }
 }
 
@@ -1759,10 +2016,10 @@ __global__ void k_assemble(const SecDev* __restrict__ parents, const SecDev* __r
             p.st[3] = 0;
             p.st[4] = 0;
             p.st[5] = 0;
-        p.st[6] = 0;
-        p.st[7] = 0;
             p.st[6] = 0;
             p.st[7] = 0;
+            p.st[8] = 0;
+            p.st[9] = 0;
         }
         return;
     }
@@ -1800,6 +2057,8 @@ __global__ void k_assemble(const SecDev* __restrict__ parents, const SecDev* __r
         p.st[5] = 0;
         p.st[6] = 0;
         p.st[7] = 0;
+        p.st[8] = 0;
+        p.st[9] = 0;
     }
 }
 
@@ -1941,35 +2200,63 @@ int rows_grid() {
     return g;
 }
 
-hipError_t launch_rowcache_prep(const SecDev* secs, int n, const LoopParams& lp, hipStream_t s) {
+#define KT_MARK(kind)                                          \
+    do {                                                       \
+        if (kt) {                                              \
+            const hipError_t r_ = kt->mark((kind), s);         \
+            if (r_ != hipSuccess) return r_;                   \
+        }                                                      \
+    } while (0)
+
+hipError_t launch_rowcache_prep(const SecDev* secs, int n, const LoopParams& lp, hipStream_t s, KTimer* kt) {
+    KT_MARK(HSWO_K_ROWCACHE_PREP);
     hipLaunchKernelGGL(k_rowcache_prep, dim3(n), dim3(NT), 0, s, secs, lp);
+    KT_MARK(HSWO_K_ROWCACHE_PREP);
     return hipGetLastError();
 }
 
 hipError_t launch_wide_iteration(const SecDev* secs, int n, int G, const LoopParams& lp, int variant,
-                                 bool spectral_possible, bool row_cache, hipStream_t s) {
+                                 bool spectral_possible, bool row_cache, hipStream_t s, KTimer* kt) {
     const dim3 grid(G, n);
     if (row_cache) {  // incremental form: cached adjacent values and spectral rows
-        if (spectral_possible) hipLaunchKernelGGL(k_wide_rows, dim3(rows_grid()), dim3(NT), 0, s, secs, n, lp);
+        if (spectral_possible) {
+            KT_MARK(HSWO_K_WIDE_ROWS);
+            hipLaunchKernelGGL(k_wide_rows, dim3(rows_grid()), dim3(NT), 0, s, secs, n, lp);
+            KT_MARK(HSWO_K_WIDE_ROWS);
+        }
+        KT_MARK(HSWO_K_WIDE_DECIDE);
         hipLaunchKernelGGL(k_wide_decide, dim3(n), dim3(NT), 0, s, secs, G, lp);
+        KT_MARK(HSWO_K_WIDE_DECIDE);
         return hipGetLastError();
     }
     if (!lp.incremental) {
+        KT_MARK(HSWO_K_WIDE_ADJ);
         if (variant == 2)
             hipLaunchKernelGGL(k_wide_adj<2>, grid, dim3(NT), 0, s, secs, G);
         else if (variant == 4)
             hipLaunchKernelGGL(k_wide_adj<4>, grid, dim3(NT), 0, s, secs, G);
         else
             hipLaunchKernelGGL(k_wide_adj<6>, grid, dim3(NT), 0, s, secs, G);
+        KT_MARK(HSWO_K_WIDE_ADJ);
     }
+    KT_MARK(HSWO_K_WIDE_DECIDE);
     hipLaunchKernelGGL(k_wide_decide, dim3(n), dim3(NT), 0, s, secs, G, lp);
+    KT_MARK(HSWO_K_WIDE_DECIDE);
     if (spectral_possible) {
-        if (lp.precision == 1)
-            hipLaunchKernelGGL(k_wide_mfma<1>, grid, dim3(NT), 0, s, secs, G, lp);
-        else if (lp.precision == 2)
-            hipLaunchKernelGGL(k_wide_mfma<2>, grid, dim3(NT), 0, s, secs, G, lp);
+        if (lp.precision == 1 || lp.precision == 2) {
+            KT_MARK(HSWO_K_WIDE_MFMA);
+            if (lp.precision == 1)
+                hipLaunchKernelGGL(k_wide_mfma<1>, grid, dim3(NT), 0, s, secs, G, lp);
+            else
+                hipLaunchKernelGGL(k_wide_mfma<2>, grid, dim3(NT), 0, s, secs, G, lp);
+            KT_MARK(HSWO_K_WIDE_MFMA);
+        }
+        KT_MARK(HSWO_K_WIDE_FP32);
         hipLaunchKernelGGL(k_wide_fp32, grid, dim3(NT), 0, s, secs, G, lp);
+        KT_MARK(HSWO_K_WIDE_FP32);
+        KT_MARK(HSWO_K_WIDE_FINISH);
         hipLaunchKernelGGL(k_wide_finish, dim3(n), dim3(NT), 0, s, secs, G, lp);
+        KT_MARK(HSWO_K_WIDE_FINISH);
     }
     return hipGetLastError();
 }

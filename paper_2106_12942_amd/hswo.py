@@ -31,6 +31,9 @@ HSWO_FLAG_MERGE_LOG = 1
 HSWO_FLAG_GRAPH = 2
 HSWO_FLAG_AUTOTUNE = 4
 HSWO_FLAG_INCREMENTAL = 8
+HSWO_FLAG_KERNEL_TIMES = 16
+KERNEL_KINDS = ["section_driver", "wide_adj", "wide_decide", "wide_mfma", "wide_fp32", "wide_finish", "wide_rows",
+                "rowcache_prep"]
 
 MERGE_DTYPE = np.dtype([("lo", "<i4"), ("hi", "<i4"), ("kind", "<i4"), ("r_after", "<i4"), ("d2", "<f8")])
 
@@ -72,10 +75,16 @@ class Stats(ctypes.Structure):
         ("ms_mfma_screen", ctypes.c_double),
         ("ms_fp32_spectral", ctypes.c_double),
         ("ms_merge", ctypes.c_double),
+        ("ms_kernel", ctypes.c_double * 8),
+        ("kernel_launches", ctypes.c_int64 * 8),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            d[k] = list(v) if k in ("ms_kernel", "kernel_launches") else v
+        return d
 
 
 class Section(ctypes.Structure):
@@ -132,14 +141,16 @@ def last_error() -> str:
 
 def make_params(*, connectivity=4, seam_connectivity=8, spclust_wght=0.0, spclust_max=0, target_regions=1,
                 section_regions=0, rnb_levels=1, level_counts: Optional[Sequence[int]] = None,
-                precision="fp32", merge_log=False, graph=False, autotune=False, incremental=False, **_ignored):
+                precision="fp32", merge_log=False, graph=False, autotune=False, incremental=False,
+                kernel_times=False, **_ignored):
     counts = list(level_counts) if level_counts is not None else [target_regions]
     arr = (ctypes.c_int32 * len(counts))(*counts)
     p = Params(connectivity, seam_connectivity, spclust_wght, spclust_max, target_regions, section_regions,
                rnb_levels, len(counts), ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32)),
                PREC[precision] if isinstance(precision, str) else int(precision),
                (HSWO_FLAG_MERGE_LOG if merge_log else 0) | (HSWO_FLAG_GRAPH if graph else 0) |
-               (HSWO_FLAG_AUTOTUNE if autotune else 0) | (HSWO_FLAG_INCREMENTAL if incremental else 0))
+               (HSWO_FLAG_AUTOTUNE if autotune else 0) | (HSWO_FLAG_INCREMENTAL if incremental else 0) |
+               (HSWO_FLAG_KERNEL_TIMES if kernel_times else 0))
     p._counts_keepalive = arr  # the struct holds a raw pointer into arr
     return p
 

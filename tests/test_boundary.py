@@ -38,7 +38,7 @@ def test_version_and_empty_error():
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(hswo.Params) == 48
     assert hswo.MERGE_DTYPE.itemsize == 24
-    assert ctypes.sizeof(hswo.Stats) == 128
+    assert ctypes.sizeof(hswo.Stats) == 256
 
 
 BASE = dict(connectivity=4, seam_connectivity=8, spclust_wght=0.5, spclust_max=256, target_regions=2,
@@ -144,3 +144,28 @@ def test_graph_flag_needs_a_stream_and_unknown_flags_rejected():
     q = hswo.make_params(**BASE)
     q.flags = 64
     assert lib.hswo_run(FAKE, 16, 16, 4, 0, ctypes.byref(q), FAKE, None, None, FAKE, nb, None) == hswo.HSWO_E_INVAL
+
+
+def test_kernel_times_flag_needs_stats_and_no_graph():
+    lib = hswo.load()
+    st = hswo.Stats()
+    p = hswo.make_params(**BASE, graph=True, kernel_times=True)
+    nb = hswo.workspace_bytes(16, 16, 4, 0, p)
+    # a non-null (never used) stream passes the graph check; the flag check refuses before device work
+    assert lib.hswo_run(FAKE, 16, 16, 4, 0, ctypes.byref(p), FAKE, None, ctypes.byref(st), FAKE, nb,
+                        ctypes.c_void_p(FAKE)) == hswo.HSWO_E_INVAL
+    assert "KERNEL_TIMES" in hswo.last_error()
+    q = hswo.make_params(**BASE, kernel_times=True)
+    assert lib.hswo_run(FAKE, 16, 16, 4, 0, ctypes.byref(q), FAKE, None, None, FAKE, nb, None) == hswo.HSWO_E_INVAL
+    assert "KERNEL_TIMES" in hswo.last_error()
+
+
+def test_python_constants_match_header():
+    src = open(HEADER).read()
+    defs = dict(re.findall(r"#define\s+(HSWO_\w+)\s+\(?(-?\d+)\)?", src))
+    for name in ("HSWO_FLAG_MERGE_LOG", "HSWO_FLAG_GRAPH", "HSWO_FLAG_AUTOTUNE", "HSWO_FLAG_INCREMENTAL",
+                 "HSWO_FLAG_KERNEL_TIMES", "HSWO_F32", "HSWO_F16", "HSWO_E_INVAL", "HSWO_E_NOMEM"):
+        assert int(defs[name]) == getattr(hswo, name), name
+    kinds = sorted((int(v), k) for k, v in defs.items() if k.startswith("HSWO_K_"))
+    assert [k for _, k in kinds] == ["HSWO_K_" + n.upper() for n in hswo.KERNEL_KINDS]
+    assert int(defs["HSWO_NK"]) == len(hswo.KERNEL_KINDS)
