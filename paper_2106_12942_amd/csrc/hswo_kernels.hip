@@ -157,6 +157,19 @@ __device__ __forceinline__ float2 block_min_f2(Smem& sh, float a, float b) {
     return make_float2(ra, rb);
 }
 
+// minimum of a double over the block; every thread gets the result
+__device__ double block_min_d(Smem& sh, double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    if (lane_id() == 0) sh.redd[wave_id()] = v;
+    __syncthreads();
+    double r = sh.redd[0];
+#pragma unroll
+    for (int w = 1; w < NWAVE; ++w) r = fmin(r, sh.redd[w]);
+    __syncthreads();
+    return r;
+}
+
 __device__ __forceinline__ double block_sum_d(Smem& sh, double v) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
@@ -990,7 +1003,7 @@ __device__ void merge_slots(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R
 
 // Merge of (lo_s, hi_s) (HSEG step 4). rc: row cache state (0 off, 1 means
 // maintained, 2 rows maintained).
-__device__ void merge_pair(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int& E, int stamp,
+__device__ __forceinline__ void merge_pair(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int& E, int stamp,
                            int kind, double d2, int g_ready, int prec, int rc) {
     merge_stats(sh, s, lo_s, hi_s, R, kind, d2, g_ready, prec, rc);
     const bool inc = s.ed2 != nullptr && s.st[5] != 0;
@@ -1040,7 +1053,7 @@ constexpr int LCAP = CAND_CAP / 2;  // edges listed per merge by the incremental
 // list is compacted when a quarter of it is empty, and at the last merge of a
 // pass. Returns true with the least adjacent key after the merge in anext;
 // false (full pass taken) when a list would overflow.
-__device__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int& E, int stamp, int kind,
+__device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int& E, int stamp, int kind,
                                double d2, int rc, KeyD& anext, int& nchk) {
     const int tid = threadIdx.x;
     merge_stats(sh, s, lo_s, hi_s, R, kind, d2, 0, 0, rc);
@@ -1055,51 +1068,89 @@ __device__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo_s, int hi_s, in
         sh.bcast_i[3] = 0;  // emptied slots
     }
     __syncthreads();
-    KeyD best = key_none();
-    constexpr int U = 4;  // edge slots per thread with loads in flight together
-    for (int e0 = tid; e0 < E; e0 += NT * U) {
-        int2 ed[U];
-        double v[U];
+    // least cached D2 of this thread's edges that do not touch the merged pair
+    // (labels are read only to order exact ties inside the thread)
+    double bv = __builtin_huge_val();
+    int be = -1, bla = 0, blb = 0;
+    constexpr int U = 4;  // pairs of edge slots per thread with loads in flight together
+    for (int e0 = 2 * tid; e0 < E; e0 += 2 * NT * U) {
+        int4 ed[U];
+        double2 v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int e = e0 + u * NT;
-            ed[u] = e < E ? s.edges[e] : make_int2(-1, -1);
-            v[u] = e < E ? s.ed2[e] : __builtin_huge_val();
+            const int e = e0 + u * 2 * NT;
+            ed[u] = make_int4(-1, -1, -1, -1);
+            v[u] = make_double2(__builtin_huge_val(), __builtin_huge_val());
+            if (e + 1 < E) {
+                ed[u] = *reinterpret_cast<const int4*>(s.edges + e);
+                v[u] = *reinterpret_cast<const double2*>(s.ed2 + e);
+            } else if (e < E) {
+                const int2 x = s.edges[e];
+                ed[u] = make_int4(x.x, x.y, -1, -1);
+                v[u].x = s.ed2[e];
+            }
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = e0 + u * NT;
-            const int a = ed[u].x, b = ed[u].y;
-            const bool touch = a == lo_s || a == hi_s || b == lo_s || b == hi_s;
-            if (a >= 0 && touch) {
-                const int k = atomicAdd(&sh.bcast_i[0], 1);
-                if (k < LCAP) L[k] = e;
-            }
-            const int na = (a == last) ? hi_s : a, nb = (b == last) ? hi_s : b;
-            if (a >= 0 && !touch && (na != a || nb != b)) {
-                const int k = atomicAdd(&sh.bcast_i[1], 1);
-                if (k < LCAP) L2[k] = e;
-            }
-            if (a >= 0 && !touch && v[u] <= best.d2) {
-                const int la = s.label[a], lb = s.label[b];
-                KeyD k;
-                k.d2 = v[u];
-                if (la < lb) {
-                    k.lo = la;
-                    k.hi = lb;
-                    k.si = na;
-                    k.sj = nb;
-                } else {
-                    k.lo = lb;
-                    k.hi = la;
-                    k.si = nb;
-                    k.sj = na;
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int e = e0 + u * 2 * NT + h;
+                const int a = h ? ed[u].z : ed[u].x, b = h ? ed[u].w : ed[u].y;
+                const double vv = h ? v[u].y : v[u].x;
+                const bool touch = a == lo_s || a == hi_s || b == lo_s || b == hi_s;
+                if (a >= 0 && touch) {
+                    const int k = atomicAdd(&sh.bcast_i[0], 1);
+                    if (k < LCAP) L[k] = e;
                 }
-                if (key_less(k, best)) best = k;
+                if (a >= 0 && !touch && (a == last || b == last)) {
+                    const int k = atomicAdd(&sh.bcast_i[1], 1);
+                    if (k < LCAP) L2[k] = e;
+                }
+                if (a >= 0 && !touch) {
+                    if (vv < bv) {
+                        bv = vv;
+                        be = e;
+                        bla = -1;  // labels not loaded
+                    } else if (vv == bv && vv < __builtin_huge_val()) {
+                        // exact tie: order by (lo, hi) labels
+                        if (bla < 0) {
+                            const int2 x = s.edges[be];
+                            const int p = s.label[x.x], q = s.label[x.y];
+                            bla = min(p, q);
+                            blb = max(p, q);
+                        }
+                        const int p = s.label[a], q = s.label[b];
+                        const int lo = min(p, q), hi = max(p, q);
+                        if (lo < bla || (lo == bla && hi < blb)) {
+                            be = e;
+                            bla = lo;
+                            blb = hi;
+                        }
+                    }
+                }
             }
-        }
     }
     __syncthreads();
+    const double vmin = block_min_d(sh, bv);
+    KeyD best = key_none();
+    if (be >= 0 && bv == vmin) {
+        const int2 x = s.edges[be];
+        const int a = x.x, b = x.y;
+        const int na = (a == last) ? hi_s : a, nb = (b == last) ? hi_s : b;
+        const int la = s.label[a], lb = s.label[b];
+        best.d2 = bv;
+        if (la < lb) {
+            best.lo = la;
+            best.hi = lb;
+            best.si = na;
+            best.sj = nb;
+        } else {
+            best.lo = lb;
+            best.hi = la;
+            best.si = nb;
+            best.sj = na;
+        }
+    }
     const int n1 = sh.bcast_i[0], n2 = sh.bcast_i[1];
     if (n1 > LCAP || n2 > LCAP) {
         // a very high degree at the merged pair: the full pass
@@ -1462,7 +1513,7 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
                                                        LoopParams lp) {
     __shared__ Smem sh;
     if ((int)blockIdx.x >= n_sec) return;
-    const SecDev s = secs[blockIdx.x];
+    const SecDev& s = secs[blockIdx.x];
     const int tid = threadIdx.x;
     int R = s.st[0];
     int E = s.st[1];
@@ -1621,7 +1672,7 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
 template <int EPG>
 __global__ void __launch_bounds__(NT) k_wide_adj(const SecDev* __restrict__ secs, int G) {
     __shared__ float red[NWAVE];  // only a block minimum: keep LDS small so several blocks fit a CU
-    const SecDev s = secs[blockIdx.y];
+    const SecDev& s = secs[blockIdx.y];
     const int R = s.st[0], E = s.st[1];
     if (R <= s.stop) return;
     const float gam = (float)(2 * s.B + 32) * U32;
@@ -1683,7 +1734,7 @@ __global__ void __launch_bounds__(NT) k_wide_rows(const SecDev* __restrict__ sec
 // stage (one workgroup per section).
 __global__ void __launch_bounds__(NT) k_rowcache_prep(const SecDev* __restrict__ secs, LoopParams lp) {
     __shared__ Smem sh;
-    const SecDev s = secs[blockIdx.x];
+    const SecDev& s = secs[blockIdx.x];
     const int R = s.st[0];
     if (s.rcap == 0 || R <= s.stop || R > lp.kmax || s.st[6] != 0) return;
     rowcache_begin(sh, s, R);
@@ -1691,7 +1742,7 @@ __global__ void __launch_bounds__(NT) k_rowcache_prep(const SecDev* __restrict__
 
 __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ secs, int G, LoopParams lp) {
     __shared__ Smem sh;
-    const SecDev s = secs[blockIdx.x];
+    const SecDev& s = secs[blockIdx.x];
     const int tid = threadIdx.x;
     const int R = s.st[0];
     int E = s.st[1];
@@ -1815,7 +1866,7 @@ __global__ void __launch_bounds__(NT) k_wide_mfma(const SecDev* __restrict__ sec
 
 __global__ void __launch_bounds__(NT) k_wide_fp32(const SecDev* __restrict__ secs, int G, LoopParams lp) {
     __shared__ Smem sh;
-    const SecDev s = secs[blockIdx.y];
+    const SecDev& s = secs[blockIdx.y];
     if (s.wi[0] != 2) return;
     const float gam = (float)(2 * s.B + 32) * U32;
     int nf = 0;
@@ -1828,7 +1879,7 @@ __global__ void __launch_bounds__(NT) k_wide_fp32(const SecDev* __restrict__ sec
 
 __global__ void __launch_bounds__(NT) k_wide_finish(const SecDev* __restrict__ secs, int G, LoopParams lp) {
     __shared__ Smem sh;
-    const SecDev s = secs[blockIdx.x];
+    const SecDev& s = secs[blockIdx.x];
     const int tid = threadIdx.x;
     if (s.wi[0] != 2) return;
     const int R = s.st[0];
@@ -1879,7 +1930,7 @@ __global__ void k_init_pixels(int32_t* parent, int32_t* mtime, int64_t n) {
 
 // Batch sections: labels are local pixel indices of each section.
 __global__ void k_init_pixels_secs(const SecDev* __restrict__ secs) {
-    const SecDev s = secs[blockIdx.y];
+    const SecDev& s = secs[blockIdx.y];
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < s.R0; p += gridDim.x * blockDim.x) {
         s.parent[p] = p;
         s.mtime[p] = INT_MAX;
@@ -1901,7 +1952,7 @@ __device__ __forceinline__ float load_px<__half>(const void* cube, size_t idx) {
 // edges under 4- or 8-connectivity.
 template <typename T>
 __global__ void k_init_leaves(const SecDev* __restrict__ secs, const InitDev* __restrict__ init) {
-    const SecDev s = secs[blockIdx.y];
+    const SecDev& s = secs[blockIdx.y];
     const InitDev in = init[blockIdx.y];
     const int h = in.h, w = in.w, B = s.B, Bp = s.Bp;
     const int P = h * w;
