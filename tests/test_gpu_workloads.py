@@ -1,8 +1,9 @@
 """GPU parity at the benchmark workloads' full sizes.
 
 * rhseg1024_salt (1024 x 1024 x 220, 5% identical salt pixels, L = 5): the
-  whole merge log and every label map against the oracle.
-* rhseg2048_f16 (2048 x 2048 x 224 float16, L = 5): the GPU runs the whole
+  whole merge log and every label map against the oracle, for the
+  incremental form and the BF16 matrix-core screened form.
+* rhseg2048_f16 (2048 x 2048 x 224 float16, L = 5, incremental form): the GPU runs the whole
   image; the oracle, which would take minutes, checks a sample that is exact
   on its own: the top-left 1024 x 1024 quadrant. Below the top pass that
   quadrant's sections are independent of the rest, so the oracle run on the
@@ -31,16 +32,28 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def test_rhseg1024_salt_full_parity():
-    sc, p = synth.workload("rhseg1024_salt")
+_C3_REF = {}
+
+
+def _c3_reference():
+    if "ref" not in _C3_REF:
+        sc, p = synth.workload("rhseg1024_salt")
+        _say("[gpu] rhseg1024_salt oracle (CPU)")
+        _C3_REF["ref"] = (sc, p, oracle.rhseg(sc.cube, **p))
+    return _C3_REF["ref"]
+
+
+@pytest.mark.parametrize("form", ["incremental", "bf16"])
+def test_rhseg1024_salt_full_parity(form):
+    sc, p, ref = _c3_reference()
     L = p["rnb_levels"]
     kw = {k: v for k, v in p.items() if k != "rnb_levels"}
-    _say("[gpu] rhseg1024_salt full size, fp16 screen")
-    res = hswo.rhseg_segment(torch.from_numpy(sc.cube).cuda(), rnb_levels=L, precision="fp16", merge_log=True,
-                             stats=True, **kw)
+    _say(f"[gpu] rhseg1024_salt full size, form {form}")
+    res = hswo.rhseg_segment(torch.from_numpy(sc.cube).cuda(), rnb_levels=L, merge_log=True, stats=True,
+                             precision="fp16" if form == "incremental" else form, incremental=form == "incremental",
+                             **kw)
     torch.cuda.synchronize()
     _say(f"[gpu] rhseg1024_salt stats {res.stats}")
-    ref = oracle.rhseg(sc.cube, **p)
     assert np.array_equal(res.log[: len(ref.log)], ref.log)
     assert np.array_equal(res.labels.cpu().numpy(), ref.labels)
 
@@ -50,9 +63,9 @@ def test_rhseg2048_f16_quadrant_parity():
     L = p["rnb_levels"]
     kw = {k: v for k, v in p.items() if k != "rnb_levels"}
     H, W, _ = sc.cube.shape
-    _say("[gpu] rhseg2048_f16 full size, fp16 screen")
-    res = hswo.rhseg_segment(torch.from_numpy(sc.cube).cuda(), rnb_levels=L, precision="fp16", merge_log=True,
-                             stats=True, **kw)
+    _say("[gpu] rhseg2048_f16 full size, incremental form")
+    res = hswo.rhseg_segment(torch.from_numpy(sc.cube).cuda(), rnb_levels=L, merge_log=True, stats=True,
+                             incremental=True, **kw)
     torch.cuda.synchronize()
     _say(f"[gpu] rhseg2048_f16 stats {res.stats}")
     lab = res.labels.cpu().numpy()
@@ -74,12 +87,13 @@ def test_rhseg2048_f16_quadrant_parity():
     assert np.array_equal(got, want)
 
 
-def test_batch256_sampled_parity():
+@pytest.mark.parametrize("form", ["incremental", "fp16"])
+def test_batch256_sampled_parity(form):
     secs = synth.batch_sections(256)
     params = {k: v for k, v in synth.BATCH_PARAMS.items() if k != "rnb_levels"}
-    _say("[gpu] batch256 fp16 screen")
-    res = hswo.hswo_run_batch([torch.from_numpy(c).cuda() for c, _ in secs], precision="fp16", merge_log=True,
-                              stats=True, **params)
+    _say(f"[gpu] batch256 form {form}")
+    res = hswo.hswo_run_batch([torch.from_numpy(c).cuda() for c, _ in secs], merge_log=True, stats=True,
+                              precision="fp16", incremental=form == "incremental", **params)
     torch.cuda.synchronize()
     _say(f"[gpu] batch256 stats {res.stats}")
     for i, (c, _) in enumerate(secs):
