@@ -87,27 +87,32 @@ KIND_DESC = {
 
 def kernel_roofline(st, B, tag):
     """Roofline of the kernel kind with the largest device time (from a
-    HSWO_FLAG_KERNEL_TIMES step). Algorithmic work, summed over the step and
-    divided by the kind's launches:
-      wide_decide: 16 B per live adjacent pair (endpoints and cached D2 read
-        for the minimum) + 24 B per band per merge (two FP64 sum rows read,
-        one written) -> HBM bound;
-      wide_rows: 3 FP64 flops per band per exactly evaluated pair -> FP64
-        vector bound (78.6 TFLOP/s);
-      wide_adj / section_driver / wide_fp32: 3 FP32 flops per band per
-        screened pair -> FP32 vector bound;
-      wide_mfma: 2 flops per band per unique spectral pair -> matrix cores."""
+    HSWO_FLAG_KERNEL_TIMES step: every launch between a pair of hipEvents on
+    its stream, less what an event pair adds to a launch, which the library
+    measures in the same call on an empty kernel). Algorithmic work per launch = the kind's work over the step
+    divided by its launches:
+      wide_decide: bytes counted on the device by the kernel (16 per edge slot
+        read for the minimum, 24 per band per merge, 12 per live row and 16
+        per pending row per 64 live rows in the spectral stage) -> HBM bound;
+      wide_rows: 3 FP64 flops per band per exactly evaluated pair, counted on
+        the device -> FP64 vector bound (78.6 TFLOP/s);
+      wide_mfma: 2 flops per band per unique spectral pair -> matrix cores;
+      otherwise 3 FP32 flops per band per screened pair -> FP32 vector bound."""
     from paper_2106_12942_amd.hswo import KERNEL_KINDS
     ms = st["ms_kernel"]
     n = st["kernel_launches"]
+    kw = st["kernel_work"]
+    ov = st["ms_event_pair_overhead"]
+    # each launch's time without what its event pair adds (measured in the same call)
+    ms = [max(0.0, ms[i] - n[i] * ov) for i in range(len(ms))]
     k = max(range(len(ms)), key=lambda i: ms[i])
     kind = KERNEL_KINDS[k]
     avg_ms = ms[k] / max(n[k], 1)
-    if kind == "wide_decide":
-        work = 16.0 * st["adjacent_pairs"] + 24.0 * B * st["merges"]
+    if kind == "wide_decide" and kw[k]:
+        work = float(kw[k])
         bound, peak, unit, scale = "hbm", PEAK_HBM_GBS, "GB/s", 1e9
     elif kind == "wide_rows":
-        work = 3.0 * B * st["exact_rechecks"]
+        work = float(kw[k])
         bound, peak, unit, scale = "alu", PEAK_FP64_VALU_TFLOPS, "TFLOP/s", 1e12
     elif kind == "wide_mfma":
         work = 2.0 * B * st["spectral_pairs"]
@@ -120,9 +125,12 @@ def kernel_roofline(st, B, tag):
     return {"bound": bound, "achieved": round(achieved, 4), "peak": peak, "unit": unit,
             "frac": round(achieved / peak, 5), "traffic": traffic_from_profiles(f"{kind}_{tag}"),
             "kernel": KIND_DESC[kind], "launches_per_step": n[k], "avg_launch_us": round(avg_ms * 1e3, 3),
+            "event_pair_overhead_us": round(ov * 1e3, 3),
+            "avg_launch_us_with_event_pair": round(st["ms_kernel"][k] / max(n[k], 1) * 1e3, 3),
             "algorithmic_work_per_launch": per_launch,
             "kernel_ms_per_step": {KERNEL_KINDS[i]: round(ms[i], 3) for i in range(len(ms)) if n[i]},
-            "kernel_launches_per_step": {KERNEL_KINDS[i]: n[i] for i in range(len(ms)) if n[i]}}
+            "kernel_launches_per_step": {KERNEL_KINDS[i]: n[i] for i in range(len(ms)) if n[i]},
+            "kernel_work_per_step": {KERNEL_KINDS[i]: kw[i] for i in range(len(ms)) if kw[i]}}
 
 
 def form_kwargs(form, precision):
@@ -187,15 +195,17 @@ def bench_rhseg(args, np, torch, hswo, synth):
         "fp32_tiles_per_step": st["fp32_tiles"], "mfma_super_tiles_per_step": st["mfma_tiles"],
     }
     # per-kernel device times: one more step of the timed form, eager, every launch bracketed by hipEvents
-    kt = torch.empty_like(labels)
-    _, _, rk = timed_steps(runner(args.form, kt, False, kernel_times=True), stream, torch, 1, 0)
-    out["kernel_times_step_ms"] = rk.stats["ms_total"]
-    out["roofline"] = kernel_roofline(rk.stats, B, f"{args.workload}_{args.form}")
+    same_kt = None
+    if not args.no_kernel_times:
+        kt = torch.empty_like(labels)
+        _, _, rk = timed_steps(runner(args.form, kt, False, kernel_times=True), stream, torch, 1, 0)
+        out["kernel_times_step_ms"] = rk.stats["ms_total"]
+        out["roofline"] = kernel_roofline(rk.stats, B, f"{args.workload}_{args.form}")
+        same_kt = bool(torch.equal(kt, labels))
     lab = labels.cpu().numpy()
-    same_kt = bool(torch.equal(kt, labels))
     comparisons = {}
     for form in ("plain", "screened", "incremental"):
-        if form == args.form or (form == "plain" and args.no_plain):
+        if form == args.form or (form == "plain" and args.no_plain) or args.no_forms:
             continue
         o = torch.empty_like(labels)
         ms, _, r = timed_steps(runner(form, o, args.graph), stream, torch, 1, 1)
@@ -255,13 +265,14 @@ def bench_batch(args, np, torch, hswo, synth):
                    "autotune": args.autotune, "driver_variant": st["driver_variant"]},
         "pairs_per_step": pairs, "merges_per_step": st["merges"], "exact_evaluations_per_step": st["exact_rechecks"],
     }
-    ko = new_outs()
-    _, _, rk = timed_steps(runner(args.form, ko, False, kernel_times=True), stream, torch, 1, 0)
-    out["kernel_times_step_ms"] = rk.stats["ms_total"]
-    # the band count varies by section: the roofline uses the mean
-    out["roofline"] = kernel_roofline(rk.stats, Bmean, f"batch256_{args.form}")
+    if not args.no_kernel_times:
+        ko = new_outs()
+        _, _, rk = timed_steps(runner(args.form, ko, False, kernel_times=True), stream, torch, 1, 0)
+        out["kernel_times_step_ms"] = rk.stats["ms_total"]
+        # the band count varies by section: the roofline uses the mean
+        out["roofline"] = kernel_roofline(rk.stats, Bmean, f"batch256_{args.form}")
     comparisons = {}
-    if not args.no_plain:
+    if not args.no_plain and not args.no_forms:
         # the plain path: 256 sequential hswo_run calls, FP32 screen, every pair each iteration
         torch.cuda.synchronize()
         ts = time.perf_counter()
@@ -274,7 +285,7 @@ def bench_batch(args, np, torch, hswo, synth):
         comparisons["plain_sequential"] = {"form": "256 sequential hswo_run calls, plain FP32", "ms_per_step": plain_ms,
                                            "speedup_of_timed_form": plain_ms / ms_per_step,
                                            "labels_identical_to_timed_form": same}
-    if args.form != "screened":
+    if args.form != "screened" and not args.no_forms:
         so = new_outs()
         ms, _, _ = timed_steps(runner("screened", so, args.graph), stream, torch, 1, 1)
         comparisons["screened_batched"] = {"ms_per_step": ms, "speedup_of_timed_form": ms / ms_per_step,
@@ -322,6 +333,12 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="autotune the section-driver variant first")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the runs of the forms not timed")
+    ap.add_argument("--no-kernel-times", action="store_true",
+                    help="skip the per-kernel timing step (no roofline object)")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only copy this many bytes device to device (3 times) and exit: the known-size "
+                         "reference for the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -333,6 +350,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_bytes:
+        n = args.copy_bytes // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 4 * n, "copies": 3}))
+        return
 
     from paper_2106_12942_amd import hswo, synth
 

@@ -160,7 +160,20 @@ typedef struct hswo_stats {
        and launches per kernel kind HSWO_K_*; zero otherwise */
     double ms_kernel[HSWO_NK];
     int64_t kernel_launches[HSWO_NK];
-} hswo_stats;   /* 256 bytes */
+    /* algorithmic work of the kind's launches, counted on the device (0 where
+       not defined): HSWO_K_WIDE_DECIDE (incremental form) bytes =
+       16 per edge slot (endpoints and cached D2 read for the minimum)
+       + 24 per band per merge (two FP64 sum rows read, one written)
+       + in the spectral stage 12 per live row (cached pair) and 16 per
+       pending row per 64 live rows (partial minima);
+       HSWO_K_WIDE_ROWS flops = 3 per band per pair evaluated */
+    int64_t kernel_work[HSWO_NK];
+    /* with HSWO_FLAG_KERNEL_TIMES: what one event pair around a launch adds to
+       the launch's own time, measured in the same call on an empty kernel
+       (bracketed launches minus back-to-back launches), ms; ms_kernel[k] minus
+       kernel_launches[k] times this is the kind's launch time */
+    double ms_event_pair_overhead;
+} hswo_stats;   /* 328 bytes */
 
 /* One independent section for hswo_run_batch. */
 typedef struct hswo_section {

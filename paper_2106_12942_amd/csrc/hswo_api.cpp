@@ -270,6 +270,8 @@ Layout carve(const Plan& pl, int H, int W, const hswo_params* p, void* ws, const
             s.m64r = bp.take<double>(rc * (((int64_t)pl.B + 7) / 8 * 8));
                 s.rbd = bp.take<double>(rc);
                 s.rbp = bp.take<int32_t>(rc);
+        s.rbl = bp.take<int32_t>(rc);
+            s.rbl = bp.take<int32_t>(rc);
                 s.rpend = bp.take<int32_t>(rc);
         s.rpart = bp.take<RowPart>(rc * ((rc + 63) / 64));
             s.rpart = bp.take<RowPart>(rc * ((rc + 63) / 64));
@@ -368,10 +370,7 @@ int timed_driver(Timer* tm, const SecDev* secs, int n, const LoopParams& lp, int
         tm->drv.push_back(e1);
         HIP_TRY(hipEventRecord(e0, stream));
     }
-    KTimer* kt = tm ? tm->per_kernel() : nullptr;
-    if (kt) HIP_TRY(kt->mark(HSWO_K_SECTION_DRIVER, stream));
-    HIP_TRY(launch_section_driver(secs, n, lp, variant, stream));
-    if (kt) HIP_TRY(kt->mark(HSWO_K_SECTION_DRIVER, stream));
+    HIP_TRY(launch_section_driver(secs, n, lp, variant, stream, tm ? tm->per_kernel() : nullptr));
     if (tm) HIP_TRY(hipEventRecord(e1, stream));
     return HSWO_OK;
 }
@@ -506,7 +505,49 @@ struct ExecOut {
     int variant = 6;
     double ms_kernel[HSWO_NK] = {};
     int64_t kernel_launches[HSWO_NK] = {};
+    double ms_event_pair = 0.0;
 };
+
+// What one event pair around a launch adds to the launch's own time on this
+// stream: an empty kernel launched between its own event pair, against the
+// same kernel launched back to back under one pair.
+int event_pair_overhead(hipStream_t stream, double* ms_out) {
+    constexpr int N = 64;
+    std::vector<hipEvent_t> ev;
+    auto cleanup = [&]() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    };
+    for (int i = 0; i < 2 * N + 2; ++i) {
+        hipEvent_t e = nullptr;
+        const hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
+        if (r != hipSuccess) {
+            cleanup();
+            return fail(HSWO_E_DEVICE, "hipEventCreateWithFlags: %s", hipGetErrorString(r));
+        }
+        ev.push_back(e);
+    }
+    hipError_t r = hipSuccess;
+    for (int i = 0; i < N && r == hipSuccess; ++i) {
+        r = hipEventRecord(ev[2 * i], stream);
+        if (r == hipSuccess) r = launch_empty(stream);
+        if (r == hipSuccess) r = hipEventRecord(ev[2 * i + 1], stream);
+    }
+    if (r == hipSuccess) r = hipEventRecord(ev[2 * N], stream);
+    for (int i = 0; i < N && r == hipSuccess; ++i) r = launch_empty(stream);
+    if (r == hipSuccess) r = hipEventRecord(ev[2 * N + 1], stream);
+    if (r == hipSuccess) r = hipStreamSynchronize(stream);
+    double bracketed = 0.0;
+    float x = 0.f;
+    for (int i = 0; i < N && r == hipSuccess; ++i) {
+        r = hipEventElapsedTime(&x, ev[2 * i], ev[2 * i + 1]);
+        bracketed += x;
+    }
+    if (r == hipSuccess) r = hipEventElapsedTime(&x, ev[2 * N], ev[2 * N + 1]);
+    cleanup();
+    if (r != hipSuccess) return fail(HSWO_E_DEVICE, "event timing: %s", hipGetErrorString(r));
+    *ms_out = std::max(0.0, bracketed / N - (double)x / N);
+    return HSWO_OK;
+}
 
 int execute(const std::vector<Upload>& ups, const Seq& seq, const std::string& key, const std::string& tune_key,
             int flags, hipStream_t stream, unsigned long long* d_counters, bool want_stats, ExecOut& out) {
@@ -559,6 +600,10 @@ int execute(const std::vector<Upload>& ups, const Seq& seq, const std::string& k
 
     Timer tm;
     tm.kernels = (flags & HSWO_FLAG_KERNEL_TIMES) != 0;
+    if (tm.kernels) {
+        const int rc = event_pair_overhead(stream, &out.ms_event_pair);
+        if (rc) return rc;
+    }
     EventPair tot;
     if (want_stats) {
         HIP_TRY(hipEventCreate(&tot.a));
@@ -657,7 +702,11 @@ int fill_stats(hswo_stats* st, const ExecOut& o, int64_t launches_if_graph) {
     for (int k = 0; k < HSWO_NK; ++k) {
         st->ms_kernel[k] = o.ms_kernel[k];
         st->kernel_launches[k] = o.kernel_launches[k];
+        st->kernel_work[k] = 0;
     }
+    st->kernel_work[HSWO_K_WIDE_DECIDE] = (int64_t)c[C_W_DECIDE_BYTES];
+    st->kernel_work[HSWO_K_WIDE_ROWS] = (int64_t)c[C_W_ROWS_FLOPS];
+    st->ms_event_pair_overhead = o.ms_event_pair;
     return HSWO_OK;
 }
 
@@ -867,6 +916,8 @@ BatchLayout carve_batch(int n, const hswo_section* sec, const hswo_params* p, vo
         s.m64r = bp.take<double>(rc * (((int64_t)q.B + 7) / 8 * 8));
             s.rbd = bp.take<double>(rc);
             s.rbp = bp.take<int32_t>(rc);
+        s.rbl = bp.take<int32_t>(rc);
+            s.rbl = bp.take<int32_t>(rc);
             s.rpend = bp.take<int32_t>(rc);
         s.rpart = bp.take<RowPart>(rc * ((rc + 63) / 64));
             s.rpart = bp.take<RowPart>(rc * ((rc + 63) / 64));

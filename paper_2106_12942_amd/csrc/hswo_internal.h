@@ -34,6 +34,8 @@ enum Counter {
     C_T_MFMA,       // ... matrix-core screen (row build, row terms, tiles)
     C_T_SPEC32,     // ... FP32 spectral tiles + exact re-check
     C_T_MERGE,      // ... merge
+    C_W_DECIDE_BYTES, // k_wide_decide, incremental form: algorithmic bytes (see hswo_stats.kernel_work)
+    C_W_ROWS_FLOPS,   // k_wide_rows: 3 FP64 flops per band per evaluated pair
     C_COUNT
 };
 
@@ -85,7 +87,8 @@ struct SecDev {
     double* m64;     // [B][rcap] FP64 mean spectra S/n, band-major (column j = slot j)
     double* m64r;    // [rcap][B8] the same means slot-major, B8 = B rounded up to 8
     double* rbd;     // [rcap] exact D2 of the row's cached pair
-    int32_t* rbp;    // [rcap] partner slot of that pair (-1: none)
+    int32_t* rbp;    // [rcap] partner slot of that pair (-1: none or pending)
+    int32_t* rbl;    // [rcap] partner label of that pair
     int32_t* rpend;  // [rcap] rows to re-evaluate: [0] the last merge's survivor, then stale rows
     RowPart* rpart;  // [rcap][ceil(rcap / 64)] per-row, per-64-column partial minima
     // wide mode iteration scratch
@@ -145,13 +148,16 @@ struct LoopParams {
 
 // Per-kernel-kind event pairs (HSWO_FLAG_KERNEL_TIMES), host side.
 struct KTimer {
-    std::vector<hipEvent_t> ev[HSWO_NK];  // pairs around each launch of a kind
-    hipError_t mark(int kind, hipStream_t s) {
-        hipEvent_t e = nullptr;
-        hipError_t r = hipEventCreate(&e);
+    std::vector<hipEvent_t> ev[HSWO_NK];  // (start, end) of each launch of a kind
+    hipError_t pair(int kind, hipEvent_t* a, hipEvent_t* b) {
+        // no system-scope fence: the stamps then hold only the launch itself
+        hipError_t r = hipEventCreateWithFlags(a, hipEventDisableSystemFence);
         if (r != hipSuccess) return r;
-        ev[kind].push_back(e);
-        return hipEventRecord(e, s);
+        ev[kind].push_back(*a);
+        r = hipEventCreateWithFlags(b, hipEventDisableSystemFence);
+        if (r != hipSuccess) return r;
+        ev[kind].push_back(*b);
+        return hipSuccess;
     }
     ~KTimer() {
         for (auto& v : ev)
@@ -164,13 +170,15 @@ hipError_t launch_init_pixels(int32_t* parent, int32_t* mtime, int64_t n, hipStr
 hipError_t launch_init_pixels_secs(const SecDev* secs, int n, int max_pixels, hipStream_t s);
 hipError_t launch_init_leaves(const SecDev* secs, const InitDev* init, int n, int dtype, int max_pixels,
                               hipStream_t s);
-hipError_t launch_section_driver(const SecDev* secs, int n, const LoopParams& lp, int variant, hipStream_t s);
+hipError_t launch_section_driver(const SecDev* secs, int n, const LoopParams& lp, int variant, hipStream_t s,
+                                 KTimer* kt);
 constexpr int DRIVER_VARIANTS[3] = {2, 4, 6};  // adjacent-stage edges in flight per lane group
 hipError_t launch_wide_iteration(const SecDev* secs, int n, int G, const LoopParams& lp, int variant,
                                  bool spectral_possible, bool row_cache, hipStream_t s, KTimer* kt);
 constexpr int ROWS_MAX_SECTIONS = 1024;  // sections a row-cache task pool launch can cover
 hipError_t launch_rowcache_prep(const SecDev* secs, int n, const LoopParams& lp, hipStream_t s, KTimer* kt);
 hipError_t launch_compress(int32_t* parent, int64_t n, hipStream_t s);
+hipError_t launch_empty(hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_assemble(const SecDev* parents, const SecDev* children, const AsmDev* asm_, int n,
                            int32_t* slotmap, int max_cap, hipStream_t s);

@@ -778,26 +778,6 @@ __device__ void row_block_task(double (*rsum)[4][64], const SecDev& s, int R, in
 // Number of block tasks of a section's row cache stage this iteration.
 __device__ __forceinline__ int row_task_count(int R, int np) { return ((np + 3) / 4) * ((R + 63) >> 6); }
 
-// Each pending row's best pair from its column-chunk partials.
-__device__ void rows_finish(const SecDev& s, int R, int np, bool all) {
-    const int nch = (R + 63) >> 6;
-    for (int q = threadIdx.x; q < np; q += NT) {
-        const int i = all ? q : s.rpend[q];
-        double bd = __builtin_huge_val();
-        int bl = INT_MAX, bs = -1;
-        for (int c = 0; c < nch; ++c) {
-            const RowPart rp = s.rpart[(size_t)q * nch + c];
-            if (rp.d2 < bd || (rp.d2 == bd && rp.lab < bl)) {
-                bd = rp.d2;
-                bl = rp.lab;
-                bs = rp.slot;
-            }
-        }
-        s.rbd[i] = bd;
-        s.rbp[i] = bs;
-    }
-}
-
 __device__ __forceinline__ KeyD pair_key(const SecDev& s, double d2, int a, int b) {
     const int la = s.label[a], lb = s.label[b];
     KeyD k;
@@ -817,23 +797,119 @@ __device__ __forceinline__ KeyD pair_key(const SecDev& s, double d2, int a, int 
 }
 
 // Least pair over all live slots, from the cached rows.
-__device__ KeyD cached_min(Smem& sh, const SecDev& s, int R) {
-    KeyD best = key_none();
-    for (int i = threadIdx.x; i < R; i += NT) {
-        const int p = s.rbp[i];
-        if (p < 0) continue;
-        const KeyD k = pair_key(s, s.rbd[i], i, p);
-        if (key_less(k, best)) best = k;
+// Best pair of pending row q from its column-chunk partials.
+__device__ __forceinline__ RowPart row_from_parts(const SecDev& s, int q, int nch) {
+    RowPart b;
+    b.d2 = __builtin_huge_val();
+    b.lab = INT_MAX;
+    b.slot = -1;
+    for (int c = 0; c < nch; ++c) {
+        const RowPart rp = s.rpart[(size_t)q * nch + c];
+        if (rp.d2 < b.d2 || (rp.d2 == b.d2 && rp.lab < b.lab)) b = rp;
     }
-    return block_min_key(sh, best);
+    return b;
+}
+
+__device__ __forceinline__ KeyD row_key(double d2, int i, int li, int p, int lp) {
+    KeyD k;
+    k.d2 = d2;
+    if (li < lp) {
+        k.lo = li;
+        k.hi = lp;
+        k.si = i;
+        k.sj = p;
+    } else {
+        k.lo = lp;
+        k.hi = li;
+        k.si = p;
+        k.sj = i;
+    }
+    return k;
+}
+
+// The spectral minimum from the row cache: the pending rows (the first np
+// slots when `all`, else rpend[0, np)) are finished from their partials, the
+// other rows are read as cached (a pending row has rbp = -1), and the least
+// key of both is returned to every thread. Every read happens before the
+// block reduction and every write after it, so the cached rows are read
+// unchanged; the finished rows are held in LDS when they fit.
+__device__ KeyD spectral_min_rows(Smem& sh, const SecDev& s, int R, int np, bool all) {
+    constexpr int HOLD = (int)(sizeof(sh.u.rsum) / sizeof(RowPart));
+    RowPart* held = reinterpret_cast<RowPart*>(&sh.u.rsum[0][0][0]);
+    const int nch = (R + 63) >> 6;
+    KeyD best = key_none();
+    int c2 = 1;
+    while (c2 < nch) c2 <<= 1;
+    if (c2 <= 64) {
+        // a segment of c2 lanes per pending row, a lane per partial, reduced by butterflies
+        const int rpw = 64 / c2;
+        const int lane = lane_id(), sub = lane / c2, c = lane % c2;
+        for (int q0 = wave_id() * rpw; q0 < np; q0 += NWAVE * rpw) {
+            const int q = q0 + sub;
+            RowPart r;
+            r.d2 = __builtin_huge_val();
+            r.lab = INT_MAX;
+            r.slot = -1;
+            if (q < np && c < nch) r = s.rpart[(size_t)q * nch + c];
+            for (int o = c2 >> 1; o >= 1; o >>= 1) {
+                const double d = __shfl_xor(r.d2, o);
+                const int l = __shfl_xor(r.lab, o);
+                const int sl = __shfl_xor(r.slot, o);
+                if (d < r.d2 || (d == r.d2 && l < r.lab)) {
+                    r.d2 = d;
+                    r.lab = l;
+                    r.slot = sl;
+                }
+            }
+            if (c == 0 && q < np) {
+                const int i = all ? q : s.rpend[q];
+                if (np <= HOLD) held[q] = r;
+                if (r.slot >= 0) {
+                    const KeyD k = row_key(r.d2, i, s.label[i], r.slot, r.lab);
+                    if (key_less(k, best)) best = k;
+                }
+            }
+        }
+    } else {
+        for (int q = threadIdx.x; q < np; q += NT) {
+            const int i = all ? q : s.rpend[q];
+            const RowPart r = row_from_parts(s, q, nch);
+            if (np <= HOLD) held[q] = r;
+            if (r.slot >= 0) {
+                const KeyD k = row_key(r.d2, i, s.label[i], r.slot, r.lab);
+                if (key_less(k, best)) best = k;
+            }
+        }
+    }
+    if (!all)
+        for (int i = threadIdx.x; i < R; i += NT) {
+            const int p = s.rbp[i];
+            const double d2 = s.rbd[i];
+            const int li = s.label[i], lp = s.rbl[i];
+            if (p < 0) continue;
+            const KeyD k = row_key(d2, i, li, p, lp);
+            if (key_less(k, best)) best = k;
+        }
+    const KeyD M = block_min_key(sh, best);  // barriers: every read above is done
+    for (int q = threadIdx.x; q < np; q += NT) {
+        const int i = all ? q : s.rpend[q];
+        const RowPart r = np <= HOLD ? held[q] : row_from_parts(s, q, nch);
+        s.rbd[i] = r.d2;
+        s.rbp[i] = r.slot;
+        s.rbl[i] = r.lab;
+    }
+    __syncthreads();
+    return M;
 }
 
 // Statistics part of a merge (HSEG step 4): the survivor lo takes hi's band
 // sums and pixel count; its FP32 screen row (and 16-bit row, FP64 mean
 // copies) are refreshed; union-find parent, merge time and log record.
 // rc: row cache state of the section (0 off, 1 or 2 means maintained).
+// screens: keep the FP32 mean row and its norm bound current (the screened
+// and plain forms read them; the incremental form does not).
 __device__ void merge_stats(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int kind, double d2, int g_ready,
-                            int prec, int rc) {
+                            int prec, int rc, bool screens) {
     const int tid = threadIdx.x;
     const int B = s.B, Bp = s.Bp;
     const int lo_l = s.label[lo_s], hi_l = s.label[hi_s];
@@ -851,11 +927,16 @@ __device__ void merge_stats(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R
             s.m64[(size_t)b * s.rcap + lo_s] = m;
             s.m64r[(size_t)lo_s * ((B + 7) & ~7) + b] = m;
         }
-        const float m = (float)(v / dn);
-        Mlo[b] = m;
-        nrm += (double)m * (double)m;
+        if (screens) {
+            const float m = (float)(v / dn);
+            Mlo[b] = m;
+            nrm += (double)m * (double)m;
+        }
     }
-    nrm = block_sum_d(sh, nrm);  // contains barriers: all reads of s.npix done
+    if (screens)
+        nrm = block_sum_d(sh, nrm);  // contains barriers: all reads of s.npix done
+    else
+        __syncthreads();  // all reads of s.npix done
     if (g_ready && wave_id() == 0) {  // keep the survivor's 16-bit screen row current
         if (prec == 1)
             row16<1>(s, lo_s);
@@ -864,7 +945,7 @@ __device__ void merge_stats(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R
     }
     if (tid == 0) {
         s.npix[lo_s] = n_new;
-        s.norm[lo_s] = (float)(sqrt(nrm) * (1.0 + 0x1p-20));
+        if (screens) s.norm[lo_s] = (float)(sqrt(nrm) * (1.0 + 0x1p-20));
         s.parent[hi_l] = lo_l;
         const int k = s.st[3];
         s.mtime[hi_l] = s.top ? k : -1;
@@ -940,7 +1021,7 @@ __device__ void merge_edges_full(Smem& sh, const SecDev& s, int lo_s, int hi_s, 
 // entry follows it, partners that moved are renamed, and the survivor and
 // every row whose cached partner was one of the merged pair are listed for
 // re-evaluation (count in st[7] and sh.npend).
-__device__ void merge_slots(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int g_ready, int rc) {
+__device__ void merge_slots(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int g_ready, int rc, bool screens) {
     const int tid = threadIdx.x;
     const int B = s.B, Bp = s.Bp;
     const int last = R - 1;
@@ -949,13 +1030,15 @@ __device__ void merge_slots(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R
         const double* Ssrc = s.sums + (size_t)last * B;
         double* Sdst = s.sums + (size_t)hi_s * B;
         for (int b = tid; b < B; b += NT) Sdst[b] = Ssrc[b];
-        const float* Msrc = s.mean + (size_t)last * Bp;
-        float* Mdst = s.mean + (size_t)hi_s * Bp;
-        for (int b = tid; b < Bp; b += NT) Mdst[b] = Msrc[b];
+        if (screens) {
+            const float* Msrc = s.mean + (size_t)last * Bp;
+            float* Mdst = s.mean + (size_t)hi_s * Bp;
+            for (int b = tid; b < Bp; b += NT) Mdst[b] = Msrc[b];
+        }
         if (tid == 0) {
             s.label[hi_s] = s.label[last];
             s.npix[hi_s] = s.npix[last];
-            s.norm[hi_s] = s.norm[last];
+            if (screens) s.norm[hi_s] = s.norm[last];
             s.mark[hi_s] = s.mark[last];
         }
         if (rc) {
@@ -982,13 +1065,17 @@ __device__ void merge_slots(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R
             if (i == lo_s || i == hi_s) continue;
             const int ni = (i == last) ? hi_s : i;
             const int p = s.rbp[i];
-            const double v = s.rbd[i];
             if (p == lo_s || p == hi_s) {
                 s.rbp[ni] = -1;
                 s.rpend[atomicAdd(&sh.npend, 1)] = ni;
             } else {
-                s.rbp[ni] = (p == last) ? hi_s : p;
-                s.rbd[ni] = v;
+                // only a moved row or a moved partner changes the entry
+                const int np = (p == last) ? hi_s : p;
+                if (ni != i) {
+                    s.rbd[ni] = s.rbd[i];
+                    s.rbl[ni] = s.rbl[i];
+                }
+                if (ni != i || np != p) s.rbp[ni] = np;
             }
         }
         if (tid == 0) {
@@ -1005,10 +1092,10 @@ __device__ void merge_slots(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R
 // maintained, 2 rows maintained).
 __device__ __forceinline__ void merge_pair(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int& E, int stamp,
                            int kind, double d2, int g_ready, int prec, int rc) {
-    merge_stats(sh, s, lo_s, hi_s, R, kind, d2, g_ready, prec, rc);
+    merge_stats(sh, s, lo_s, hi_s, R, kind, d2, g_ready, prec, rc, true);
     const bool inc = s.ed2 != nullptr && s.st[5] != 0;
     merge_edges_full(sh, s, lo_s, hi_s, R, E, stamp, inc);
-    merge_slots(sh, s, lo_s, hi_s, R, g_ready, rc);
+    merge_slots(sh, s, lo_s, hi_s, R, g_ready, rc, true);
     if (inc) {  // re-score the survivor's edges; every other edge keeps its cached value
         const int nd = sh.bcast_i[2];
         for (int i = wave_id(); i < nd; i += NWAVE) score_edge_exact(sh, s, s.edirty[i]);
@@ -1042,7 +1129,7 @@ __device__ void compact_edges(Smem& sh, const SecDev& s, int& E) {
     __syncthreads();
 }
 
-constexpr int LCAP = CAND_CAP / 2;  // edges listed per merge by the incremental form
+constexpr int LCAP = CAND_CAP / 3;  // edges listed per merge by the incremental form (L, L2, neighbours)
 
 // Merge in the incremental form (every edge slot holds its exact D2). One
 // pass over the edge slots lists the edges that touch the merged pair (L)
@@ -1056,7 +1143,7 @@ constexpr int LCAP = CAND_CAP / 2;  // edges listed per merge by the incremental
 __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int& E, int stamp, int kind,
                                double d2, int rc, KeyD& anext, int& nchk) {
     const int tid = threadIdx.x;
-    merge_stats(sh, s, lo_s, hi_s, R, kind, d2, 0, 0, rc);
+    merge_stats(sh, s, lo_s, hi_s, R, kind, d2, 0, 0, rc, false);
     const int last = R - 1;
     const int surv = (lo_s == last) ? hi_s : lo_s;
     int* L = sh.u.f.cand;
@@ -1155,7 +1242,7 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
     if (n1 > LCAP || n2 > LCAP) {
         // a very high degree at the merged pair: the full pass
         merge_edges_full(sh, s, lo_s, hi_s, R, E, stamp, true);
-        merge_slots(sh, s, lo_s, hi_s, R, 0, rc);
+        merge_slots(sh, s, lo_s, hi_s, R, 0, rc, false);
         const int nd = sh.bcast_i[2];
         for (int i = wave_id(); i < nd; i += NWAVE) score_edge_exact(sh, s, s.edirty[i]);
         nchk += nd;
@@ -1163,7 +1250,9 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
         if (tid == 0) s.st[9] = 0;
         return false;
     }
-    // rename the moved slot in L2; reset the marks of the neighbours in L
+    // rename the moved slot in L2; note the neighbour x of each edge in L (-1:
+    // the merged pair itself)
+    int* XL = sh.u.f.cand + 2 * LCAP;
     for (int k = tid; k < n2; k += NT) {
         const int e = L2[k];
         int2 ed = s.edges[e];
@@ -1174,25 +1263,38 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
     for (int k = tid; k < n1; k += NT) {
         const int2 ed = s.edges[L[k]];
         const bool ax = ed.x == lo_s || ed.x == hi_s, bx = ed.y == lo_s || ed.y == hi_s;
-        if (!(ax && bx)) s.dmark[ax ? ed.y : ed.x] = INT_MAX;
+        XL[k] = (ax && bx) ? -1 : (ax ? ed.y : ed.x);
     }
     __syncthreads();
-    for (int k = tid; k < n1; k += NT) {
-        const int e = L[k];
-        const int2 ed = s.edges[e];
-        const bool ax = ed.x == lo_s || ed.x == hi_s, bx = ed.y == lo_s || ed.y == hi_s;
-        if (!(ax && bx)) atomicMin(&s.dmark[ax ? ed.y : ed.x], e);
+    // one edge per neighbour survives: the least edge slot (compared in LDS
+    // for a short list, by an atomic minimum per neighbour otherwise)
+    const bool short_list = n1 <= 64;
+    if (!short_list) {
+        for (int k = tid; k < n1; k += NT)
+            if (XL[k] >= 0) s.dmark[XL[k]] = INT_MAX;
+        __syncthreads();
+        for (int k = tid; k < n1; k += NT)
+            if (XL[k] >= 0) atomicMin(&s.dmark[XL[k]], L[k]);
+        __syncthreads();
     }
-    __syncthreads();
-    int* K = L2;  // L2 is consumed
+    int* K = L2;  // L2 is consumed: indices into L of the kept edges
     for (int k = tid; k < n1; k += NT) {
-        const int e = L[k];
-        const int2 ed = s.edges[e];
-        const bool ax = ed.x == lo_s || ed.x == hi_s, bx = ed.y == lo_s || ed.y == hi_s;
-        const int x = (ax && bx) ? -1 : (ax ? ed.y : ed.x);
-        if (x >= 0 && s.dmark[x] == e) {
+        const int e = L[k], x = XL[k];
+        bool keep = x >= 0;
+        if (keep) {
+            if (short_list) {
+                for (int q = 0; q < n1; ++q)
+                    if (XL[q] == x && L[q] < e) {
+                        keep = false;
+                        break;
+                    }
+            } else {
+                keep = s.dmark[x] == e;
+            }
+        }
+        if (keep) {
             s.edges[e] = make_int2(surv, x == last ? hi_s : x);
-            K[atomicAdd(&sh.bcast_i[2], 1)] = e;
+            K[atomicAdd(&sh.bcast_i[2], 1)] = k;
         } else {
             s.edges[e] = make_int2(-1, -1);
             s.ed2[e] = __builtin_huge_val();
@@ -1200,17 +1302,21 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
         }
     }
     __syncthreads();
-    merge_slots(sh, s, lo_s, hi_s, R, 0, rc);  // ends with a barrier
+    merge_slots(sh, s, lo_s, hi_s, R, 0, rc, false);  // ends with a barrier
     const int nk = sh.bcast_i[2];
     const int emptied = sh.bcast_i[3];
-    for (int k = wave_id(); k < nk; k += NWAVE) {
-        const int e = K[k];
-        const int2 ed = s.edges[e];
-        int a = ed.x, b = ed.y;
-        int la = s.label[a], lb = s.label[b];
+    const int l_surv = s.label[surv];
+    for (int q = wave_id(); q < nk; q += NWAVE) {
+        const int k = K[q];
+        const int e = L[k];
+        const int x = XL[k] == last ? hi_s : XL[k];
+        const int lx = s.label[x];
+        int a = surv, b = x, la = l_surv, lb = lx;
         if (la > lb) {
-            const int t = a; a = b; b = t;
-            const int u = la; la = lb; lb = u;
+            a = x;
+            b = surv;
+            la = lx;
+            lb = l_surv;
         }
         KeyD kk;
         kk.d2 = exact_d2_wave(sh, s, a, b);
@@ -1575,11 +1681,9 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
             const int nch = (R + 63) >> 6;
             const int ntask = row_task_count(R, rows);
             for (int t = 0; t < ntask; ++t) row_block_task<4>(sh.u.rsum, s, R, rows, all, t / nch, t % nch);
-            rows_finish(s, R, rows, all);
-            __syncthreads();
+            M = spectral_min_rows(sh, s, R, rows, all);
             rcs = 2;
             npend = 0;
-            M = cached_min(sh, s, R);
             CNT_ADD(C_SPEC_PAIRS, (unsigned long long)R * (unsigned long long)(R - 1) / 2ull);
             CNT_ADD(C_RECHECKS, (unsigned long long)rows * (unsigned long long)(R - 1));
             tk1 = wall_clock64();
@@ -1701,8 +1805,11 @@ __global__ void __launch_bounds__(NT) k_wide_rows(const SecDev* __restrict__ sec
         if (s.rcap > 0 && R > s.stop && R <= lp.kmax && (mode == 1 || mode == 2)) {
             const int np = mode == 1 ? R : s.st[7];
             cnt = row_task_count(R, np);
-            if (blockIdx.x == 0 && lp.counters)
-                atomicAdd(&lp.counters[C_RECHECKS], (unsigned long long)np * (unsigned long long)(R - 1));
+            if (blockIdx.x == 0 && lp.counters) {
+                const unsigned long long pairs = (unsigned long long)np * (unsigned long long)(R - 1);
+                atomicAdd(&lp.counters[C_RECHECKS], pairs);
+                atomicAdd(&lp.counters[C_W_ROWS_FLOPS], 3ull * (unsigned long long)s.B * pairs);
+            }
         }
         pre[k + 1] = cnt;
     }
@@ -1781,17 +1888,19 @@ __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ s
         // (its pending rows were re-evaluated by k_wide_rows)
         int rcs = row_cache ? s.st[6] : 0;
         KeyD M = key_none();
+        unsigned long long decide_bytes = 0;  // algorithmic bytes of this iteration (incremental form)
         if (spectral) {
             const bool all = rcs == 1;
-            rows_finish(s, R, all ? R : s.st[7], all);
-            __syncthreads();
+            const int np = all ? R : s.st[7];
+            M = spectral_min_rows(sh, s, R, np, all);
             rcs = 2;
-            M = cached_min(sh, s, R);
+            decide_bytes += 12ull * (unsigned long long)R + 16ull * (unsigned long long)np * (unsigned long long)((R + 63) >> 6);
         }
         KeyD win;
         int kind;
         if (decide(spectral, A, M, T, win, kind)) {
             const int stamp = s.st[3];
+            decide_bytes += 16ull * (unsigned long long)E + 24ull * (unsigned long long)s.B;
             if (lp.incremental) {
                 KeyD an;
                 const bool av = merge_pair_inc(sh, s, win.si, win.sj, R, E, stamp, kind, win.d2, rcs, an, nchk);
@@ -1823,6 +1932,8 @@ __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ s
                 atomicAdd(&lp.counters[C_RECHECKS], (unsigned long long)nchk);
                 if (spectral)
                     atomicAdd(&lp.counters[C_SPEC_PAIRS], (unsigned long long)R * (unsigned long long)(R - 1) / 2ull);
+                if (lp.incremental)
+                    atomicAdd(&lp.counters[C_W_DECIDE_BYTES], decide_bytes);
             }
         }
         return;
@@ -2038,6 +2149,8 @@ __global__ void k_compress(int32_t* parent, int64_t n) {
     }
 }
 
+__global__ void k_empty() {}
+
 __global__ void k_fill_u64(unsigned long long* p, size_t n, unsigned long long v) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -2228,14 +2341,33 @@ hipError_t launch_init_leaves(const SecDev* secs, const InitDev* init, int n, in
     return hipGetLastError();
 }
 
-hipError_t launch_section_driver(const SecDev* secs, int n, const LoopParams& lp, int variant, hipStream_t s) {
+// Launch, bracketed by a pair of events of the given kind (recorded on the
+// same stream right before and after it) when per-kernel timing is on.
+#define KLAUNCH(kind, kern, grid, block, ...)                                 \
+    do {                                                                   \
+        hipEvent_t a_ = nullptr, b_ = nullptr;                             \
+        if (kt) {                                                          \
+            const hipError_t r_ = kt->pair((kind), &a_, &b_);              \
+            if (r_ != hipSuccess) return r_;                               \
+            const hipError_t q_ = hipEventRecord(a_, s);                   \
+            if (q_ != hipSuccess) return q_;                               \
+        }                                                                  \
+        hipLaunchKernelGGL(kern, grid, block, 0, s, __VA_ARGS__);          \
+        if (kt) {                                                          \
+            const hipError_t q_ = hipEventRecord(b_, s);                   \
+            if (q_ != hipSuccess) return q_;                               \
+        }                                                                  \
+    } while (0)
+
+hipError_t launch_section_driver(const SecDev* secs, int n, const LoopParams& lp, int variant, hipStream_t s,
+                                 KTimer* kt) {
     // variant = edges in flight per 16-lane group in the adjacent stage (tunable, result-neutral)
     if (variant == 2)
-        hipLaunchKernelGGL(k_section_driver<2>, dim3(n), dim3(NT), 0, s, secs, n, lp);
+        KLAUNCH(HSWO_K_SECTION_DRIVER, k_section_driver<2>, dim3(n), dim3(NT), secs, n, lp);
     else if (variant == 4)
-        hipLaunchKernelGGL(k_section_driver<4>, dim3(n), dim3(NT), 0, s, secs, n, lp);
+        KLAUNCH(HSWO_K_SECTION_DRIVER, k_section_driver<4>, dim3(n), dim3(NT), secs, n, lp);
     else
-        hipLaunchKernelGGL(k_section_driver<6>, dim3(n), dim3(NT), 0, s, secs, n, lp);
+        KLAUNCH(HSWO_K_SECTION_DRIVER, k_section_driver<6>, dim3(n), dim3(NT), secs, n, lp);
     return hipGetLastError();
 }
 
@@ -2251,18 +2383,8 @@ int rows_grid() {
     return g;
 }
 
-#define KT_MARK(kind)                                          \
-    do {                                                       \
-        if (kt) {                                              \
-            const hipError_t r_ = kt->mark((kind), s);         \
-            if (r_ != hipSuccess) return r_;                   \
-        }                                                      \
-    } while (0)
-
 hipError_t launch_rowcache_prep(const SecDev* secs, int n, const LoopParams& lp, hipStream_t s, KTimer* kt) {
-    KT_MARK(HSWO_K_ROWCACHE_PREP);
-    hipLaunchKernelGGL(k_rowcache_prep, dim3(n), dim3(NT), 0, s, secs, lp);
-    KT_MARK(HSWO_K_ROWCACHE_PREP);
+    KLAUNCH(HSWO_K_ROWCACHE_PREP, k_rowcache_prep, dim3(n), dim3(NT), secs, lp);
     return hipGetLastError();
 }
 
@@ -2270,50 +2392,37 @@ hipError_t launch_wide_iteration(const SecDev* secs, int n, int G, const LoopPar
                                  bool spectral_possible, bool row_cache, hipStream_t s, KTimer* kt) {
     const dim3 grid(G, n);
     if (row_cache) {  // incremental form: cached adjacent values and spectral rows
-        if (spectral_possible) {
-            KT_MARK(HSWO_K_WIDE_ROWS);
-            hipLaunchKernelGGL(k_wide_rows, dim3(rows_grid()), dim3(NT), 0, s, secs, n, lp);
-            KT_MARK(HSWO_K_WIDE_ROWS);
-        }
-        KT_MARK(HSWO_K_WIDE_DECIDE);
-        hipLaunchKernelGGL(k_wide_decide, dim3(n), dim3(NT), 0, s, secs, G, lp);
-        KT_MARK(HSWO_K_WIDE_DECIDE);
+        if (spectral_possible) KLAUNCH(HSWO_K_WIDE_ROWS, k_wide_rows, dim3(rows_grid()), dim3(NT), secs, n, lp);
+        KLAUNCH(HSWO_K_WIDE_DECIDE, k_wide_decide, dim3(n), dim3(NT), secs, G, lp);
         return hipGetLastError();
     }
     if (!lp.incremental) {
-        KT_MARK(HSWO_K_WIDE_ADJ);
         if (variant == 2)
-            hipLaunchKernelGGL(k_wide_adj<2>, grid, dim3(NT), 0, s, secs, G);
+            KLAUNCH(HSWO_K_WIDE_ADJ, k_wide_adj<2>, grid, dim3(NT), secs, G);
         else if (variant == 4)
-            hipLaunchKernelGGL(k_wide_adj<4>, grid, dim3(NT), 0, s, secs, G);
+            KLAUNCH(HSWO_K_WIDE_ADJ, k_wide_adj<4>, grid, dim3(NT), secs, G);
         else
-            hipLaunchKernelGGL(k_wide_adj<6>, grid, dim3(NT), 0, s, secs, G);
-        KT_MARK(HSWO_K_WIDE_ADJ);
+            KLAUNCH(HSWO_K_WIDE_ADJ, k_wide_adj<6>, grid, dim3(NT), secs, G);
     }
-    KT_MARK(HSWO_K_WIDE_DECIDE);
-    hipLaunchKernelGGL(k_wide_decide, dim3(n), dim3(NT), 0, s, secs, G, lp);
-    KT_MARK(HSWO_K_WIDE_DECIDE);
+    KLAUNCH(HSWO_K_WIDE_DECIDE, k_wide_decide, dim3(n), dim3(NT), secs, G, lp);
     if (spectral_possible) {
-        if (lp.precision == 1 || lp.precision == 2) {
-            KT_MARK(HSWO_K_WIDE_MFMA);
-            if (lp.precision == 1)
-                hipLaunchKernelGGL(k_wide_mfma<1>, grid, dim3(NT), 0, s, secs, G, lp);
-            else
-                hipLaunchKernelGGL(k_wide_mfma<2>, grid, dim3(NT), 0, s, secs, G, lp);
-            KT_MARK(HSWO_K_WIDE_MFMA);
-        }
-        KT_MARK(HSWO_K_WIDE_FP32);
-        hipLaunchKernelGGL(k_wide_fp32, grid, dim3(NT), 0, s, secs, G, lp);
-        KT_MARK(HSWO_K_WIDE_FP32);
-        KT_MARK(HSWO_K_WIDE_FINISH);
-        hipLaunchKernelGGL(k_wide_finish, dim3(n), dim3(NT), 0, s, secs, G, lp);
-        KT_MARK(HSWO_K_WIDE_FINISH);
+        if (lp.precision == 1)
+            KLAUNCH(HSWO_K_WIDE_MFMA, k_wide_mfma<1>, grid, dim3(NT), secs, G, lp);
+        else if (lp.precision == 2)
+            KLAUNCH(HSWO_K_WIDE_MFMA, k_wide_mfma<2>, grid, dim3(NT), secs, G, lp);
+        KLAUNCH(HSWO_K_WIDE_FP32, k_wide_fp32, grid, dim3(NT), secs, G, lp);
+        KLAUNCH(HSWO_K_WIDE_FINISH, k_wide_finish, dim3(n), dim3(NT), secs, G, lp);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_compress(int32_t* parent, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_compress, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, parent, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_empty(hipStream_t s) {
+    hipLaunchKernelGGL(k_empty, dim3(1), dim3(64), 0, s);
     return hipGetLastError();
 }
 

@@ -77,13 +77,15 @@ class Stats(ctypes.Structure):
         ("ms_merge", ctypes.c_double),
         ("ms_kernel", ctypes.c_double * 8),
         ("kernel_launches", ctypes.c_int64 * 8),
+        ("kernel_work", ctypes.c_int64 * 8),
+        ("ms_event_pair_overhead", ctypes.c_double),
     ]
 
     def as_dict(self):
         d = {}
         for k, _ in self._fields_:
             v = getattr(self, k)
-            d[k] = list(v) if k in ("ms_kernel", "kernel_launches") else v
+            d[k] = list(v) if k in ("ms_kernel", "kernel_launches", "kernel_work") else v
         return d
 
 

@@ -38,7 +38,7 @@ def test_version_and_empty_error():
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(hswo.Params) == 48
     assert hswo.MERGE_DTYPE.itemsize == 24
-    assert ctypes.sizeof(hswo.Stats) == 256
+    assert ctypes.sizeof(hswo.Stats) == 328
 
 
 BASE = dict(connectivity=4, seam_connectivity=8, spclust_wght=0.5, spclust_max=256, target_regions=2,
