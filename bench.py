@@ -85,7 +85,7 @@ KIND_DESC = {
 }
 
 
-def kernel_roofline(st, B, tag):
+def kernel_roofline(st, B, tag, kind=None):
     """Roofline of the kernel kind with the largest device time (from a
     HSWO_FLAG_KERNEL_TIMES step: every launch between a pair of hipEvents on
     its stream, less what an event pair adds to a launch, which the library
@@ -96,7 +96,10 @@ def kernel_roofline(st, B, tag):
         per pending row per 64 live rows in the spectral stage) -> HBM bound;
       wide_rows: 3 FP64 flops per band per exactly evaluated pair, counted on
         the device -> FP64 vector bound (78.6 TFLOP/s);
-      wide_mfma: 2 flops per band per unique spectral pair -> matrix cores;
+      wide_mfma: 2 flops per band per unique pair of each screened section,
+        counted on the device -> matrix cores;
+      wide_adj: FP32 mean rows read once + 8 B per edge slot + 8 B per
+        region, counted on the device -> HBM bound;
       otherwise 3 FP32 flops per band per screened pair -> FP32 vector bound."""
     from paper_2106_12942_amd.hswo import KERNEL_KINDS
     ms = st["ms_kernel"]
@@ -105,7 +108,7 @@ def kernel_roofline(st, B, tag):
     ov = st["ms_event_pair_overhead"]
     # each launch's time without what its event pair adds (measured in the same call)
     ms = [max(0.0, ms[i] - n[i] * ov) for i in range(len(ms))]
-    k = max(range(len(ms)), key=lambda i: ms[i])
+    k = max(range(len(ms)), key=lambda i: ms[i]) if kind is None else KERNEL_KINDS.index(kind)
     kind = KERNEL_KINDS[k]
     avg_ms = ms[k] / max(n[k], 1)
     if kind == "wide_decide" and kw[k]:
@@ -115,8 +118,11 @@ def kernel_roofline(st, B, tag):
         work = float(kw[k])
         bound, peak, unit, scale = "alu", PEAK_FP64_VALU_TFLOPS, "TFLOP/s", 1e12
     elif kind == "wide_mfma":
-        work = 2.0 * B * st["spectral_pairs"]
+        work = float(kw[k])
         bound, peak, unit, scale = "mfma", PEAK_MFMA_TFLOPS["fp16"], "TFLOP/s", 1e12
+    elif kind == "wide_adj":
+        work = float(kw[k])
+        bound, peak, unit, scale = "hbm", PEAK_HBM_GBS, "GB/s", 1e9
     else:
         work = 3.0 * B * (st["adjacent_pairs"] + st["spectral_pairs"])
         bound, peak, unit, scale = "alu", PEAK_FP32_VALU_TFLOPS, "TFLOP/s", 1e12
@@ -212,6 +218,12 @@ def bench_rhseg(args, np, torch, hswo, synth):
         comparisons[form] = {"ms_per_step": ms, "speedup_of_timed_form": ms / ms_per_step,
                              "labels_identical_to_timed_form": bool(torch.equal(o, labels)),
                              "precision": form_kwargs(form, args.precision)["precision"]}
+        if form == "screened" and not args.no_kernel_times:
+            # the screened form's own sweeps: adjacent screen against HBM, matrix-core screen against MFMA peak
+            _, _, rs = timed_steps(runner(form, o, False, kernel_times=True), stream, torch, 1, 0)
+            comparisons[form]["rooflines"] = {
+                kd: kernel_roofline(rs.stats, B, f"{args.workload}_{form}", kind=kd)
+                for kd in ("wide_adj", "wide_mfma") if rs.stats["kernel_launches"][hswo.KERNEL_KINDS.index(kd)]}
     out["forms"] = comparisons
     out["labels_identical_kernel_times_step"] = same_kt
     if not args.no_cpu_baseline:

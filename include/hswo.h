@@ -166,7 +166,11 @@ typedef struct hswo_stats {
        + 24 per band per merge (two FP64 sum rows read, one written)
        + in the spectral stage 12 per live row (cached pair) and 16 per
        pending row per 64 live rows (partial minima);
-       HSWO_K_WIDE_ROWS flops = 3 per band per pair evaluated */
+       HSWO_K_WIDE_ROWS flops = 3 per band per pair evaluated;
+       HSWO_K_WIDE_ADJ bytes = per section and iteration, the FP32 mean rows
+       read once (4 per band per live region) + 8 per edge slot + 8 per region;
+       HSWO_K_WIDE_MFMA flops = 2 per band per unique pair of every section
+       screened on matrix cores */
     int64_t kernel_work[HSWO_NK];
     /* with HSWO_FLAG_KERNEL_TIMES: what one event pair around a launch adds to
        the launch's own time, measured in the same call on an empty kernel

@@ -1774,7 +1774,8 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
 // partial least upper bounds.
 // ---------------------------------------------------------------------------
 template <int EPG>
-__global__ void __launch_bounds__(NT) k_wide_adj(const SecDev* __restrict__ secs, int G) {
+__global__ void __launch_bounds__(NT) k_wide_adj(const SecDev* __restrict__ secs, int G,
+                                                 unsigned long long* counters) {
     __shared__ float red[NWAVE];  // only a block minimum: keep LDS small so several blocks fit a CU
     const SecDev& s = secs[blockIdx.y];
     const int R = s.st[0], E = s.st[1];
@@ -1788,6 +1789,9 @@ __global__ void __launch_bounds__(NT) k_wide_adj(const SecDev* __restrict__ secs
     if (threadIdx.x == 0) {
         for (int w = 1; w < NWAVE; ++w) U = fminf(U, red[w]);
         s.wpart[blockIdx.x] = U;
+        if (blockIdx.x == 0 && counters)
+            atomicAdd(&counters[C_W_ADJ_BYTES],
+                      4ull * (unsigned long long)R * (unsigned long long)s.B + 8ull * (unsigned long long)E + 8ull * R);
     }
 }
 
@@ -1971,8 +1975,14 @@ __global__ void __launch_bounds__(NT) k_wide_mfma(const SecDev* __restrict__ sec
     __shared__ Smem sh;
     const SecDev s = secs[blockIdx.y];
     if (s.wi[0] != 2 || !s.wi[5]) return;
-    const int n = mfma_screen<PREC>(sh, s, s.st[0], blockIdx.x, G);
-    if (threadIdx.x == 0 && lp.counters) atomicAdd(&lp.counters[C_MFMA_TILES], (unsigned long long)n);
+    const int R = s.st[0];
+    const int n = mfma_screen<PREC>(sh, s, R, blockIdx.x, G);
+    if (threadIdx.x == 0 && lp.counters) {
+        atomicAdd(&lp.counters[C_MFMA_TILES], (unsigned long long)n);
+        if (blockIdx.x == 0)
+            atomicAdd(&lp.counters[C_W_MFMA_FLOPS],
+                      (unsigned long long)s.B * (unsigned long long)R * (unsigned long long)(R - 1));
+    }
 }
 
 __global__ void __launch_bounds__(NT) k_wide_fp32(const SecDev* __restrict__ secs, int G, LoopParams lp) {
@@ -2398,11 +2408,11 @@ hipError_t launch_wide_iteration(const SecDev* secs, int n, int G, const LoopPar
     }
     if (!lp.incremental) {
         if (variant == 2)
-            KLAUNCH(HSWO_K_WIDE_ADJ, k_wide_adj<2>, grid, dim3(NT), secs, G);
+            KLAUNCH(HSWO_K_WIDE_ADJ, k_wide_adj<2>, grid, dim3(NT), secs, G, lp.counters);
         else if (variant == 4)
-            KLAUNCH(HSWO_K_WIDE_ADJ, k_wide_adj<4>, grid, dim3(NT), secs, G);
+            KLAUNCH(HSWO_K_WIDE_ADJ, k_wide_adj<4>, grid, dim3(NT), secs, G, lp.counters);
         else
-            KLAUNCH(HSWO_K_WIDE_ADJ, k_wide_adj<6>, grid, dim3(NT), secs, G);
+            KLAUNCH(HSWO_K_WIDE_ADJ, k_wide_adj<6>, grid, dim3(NT), secs, G, lp.counters);
     }
     KLAUNCH(HSWO_K_WIDE_DECIDE, k_wide_decide, dim3(n), dim3(NT), secs, G, lp);
     if (spectral_possible) {
