@@ -331,6 +331,69 @@ def bench_batch(args, np, torch, hswo, synth):
     return out, Bmean
 
 
+SWEEPS = {
+    # image side at 220 bands (the paper's image-size table): leaves of 32 x 32
+    "size": [dict(side=n, B=220, K=16) for n in (64, 128, 256, 512)],
+    # detail at 50 x 50 x 220 (the paper's image-detail table): 4, 8 and 16 classes
+    "detail": [dict(side=50, B=220, K=k) for k in (4, 8, 16)],
+    # depth at 32 x 32 (the paper's band-count table)
+    "bands": [dict(side=32, B=b, K=16) for b in (3, 10, 50, 100, 150, 220)],
+    # work split of the adjacent sweep at 32 x 32 x 220 (the paper's block-size table): the
+    # section-driver variants (edges in flight per 16-lane group) of the screened form
+    "variant": [dict(side=32, B=220, K=16, variant=v) for v in (2, 4, 6)],
+}
+
+
+def sweep_params(side):
+    L = 1
+    while (side >> L) >= 32:
+        L += 1
+    target = 16
+    return dict(connectivity=4, seam_connectivity=8, spclust_wght=0.15, spclust_max=1024,
+                target_regions=target, section_regions=max(target, 64) if L > 1 else 0, rnb_levels=L,
+                level_counts=[target])
+
+
+def bench_sweep(args, np, torch, hswo, synth):
+    """One point per configuration: the GPU call (median of 3 after a warm-up)
+    and the FP64 oracle on the host's threads, on the same synthetic cube."""
+    import oracle
+    threads = os.cpu_count() or 1
+    points = []
+    for cfg in SWEEPS[args.sweep]:
+        sc = synth.voronoi_scene(cfg["side"], cfg["side"], cfg["B"], cfg["K"], 30.0, 900 + cfg["side"] + cfg["B"])
+        p = sweep_params(cfg["side"])
+        kw = {k: v for k, v in p.items() if k != "rnb_levels"}
+        cube = torch.from_numpy(sc.cube).cuda()
+        if "variant" in cfg:
+            os.environ["HSWO_DRIVER_VARIANT"] = str(cfg["variant"])
+            form = "screened"
+        else:
+            form = args.form
+        fk = form_kwargs(form, args.precision)
+        times, res = [], None
+        for k in range(4):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = hswo.rhseg_segment(cube, rnb_levels=p["rnb_levels"], stats=True, **fk, **kw)
+            torch.cuda.synchronize()
+            if k:
+                times.append((time.perf_counter() - t0) * 1e3)
+        os.environ.pop("HSWO_DRIVER_VARIANT", None)
+        gpu_ms = statistics.median(times)
+        tc = time.perf_counter()
+        ref = oracle.rhseg(sc.cube, **p, n_threads=threads)
+        cpu_ms = (time.perf_counter() - tc) * 1e3
+        points.append({**cfg, "form": form, "rnb_levels": p["rnb_levels"], "gpu_ms": round(gpu_ms, 3),
+                       "oracle_ms": round(cpu_ms, 1), "speedup_vs_oracle": round(cpu_ms / gpu_ms, 2),
+                       "labels_identical_to_oracle": bool(np.array_equal(res.labels.cpu().numpy(), ref.labels)),
+                       "merges": res.stats["merges"]})
+        print(json.dumps({"sweep_point": points[-1]}), file=sys.stderr, flush=True)
+    return {"sweep": args.sweep, "cores": threads, "oracle": "FP64 oracle, cached mode, sections of a level on "
+            f"{threads} threads", "params": "w 0.15, spectral at <= 1024 regions, 4-connectivity, 32x32 leaves, "
+            "sections stop at 64, target 16; Voronoi scenes, sigma 30", "points": points}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -346,6 +409,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the runs of the forms not timed")
+    ap.add_argument("--sweep", choices=sorted(SWEEPS),
+                    help="instead of the benchmark: GPU vs oracle over one of the paper-style sweeps")
     ap.add_argument("--no-kernel-times", action="store_true",
                     help="skip the per-kernel timing step (no roofline object)")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -375,6 +440,9 @@ def main():
 
     from paper_2106_12942_amd import hswo, synth
 
+    if args.sweep:
+        print(json.dumps(bench_sweep(args, np, torch, hswo, synth)))
+        return
     if args.workload == "batch256":
         body, _ = bench_batch(args, np, torch, hswo, synth)
     else:
