@@ -19,9 +19,11 @@ Workloads
 Forms (--form): "incremental" (default): cached exact per-edge D2 and the
 spectral row cache; "screened": every pair screened each iteration, the
 spectral stage on matrix cores (--precision fp16 or bf16); "plain": every
-pair screened each iteration in FP32. Levels run batched into one launch
-(persistent) or one launch sequence per iteration (wide), replayed from a
-hipGraph. The other forms run once on the same input for the comparison, and
+pair screened each iteration in FP32, the sections of a level one after
+another (neither the precision nor the batching form); "plain_batched": the
+same FP32 screens with the sections of a level batched. Levels run batched
+into one launch (persistent) or one launch sequence per iteration (wide),
+replayed from a hipGraph. The other forms run once on the same input for the comparison, and
 must give the same labels.
 
 Output: one JSON line. `value` is dissimilarity pairs per second: the
@@ -141,6 +143,9 @@ def kernel_roofline(st, B, tag, kind=None):
 
 def form_kwargs(form, precision):
     if form == "plain":
+        # neither form: FP32 screens, and the sections of a level one after another
+        return dict(precision="fp32", incremental=False, sequential=True)
+    if form == "plain_batched":
         return dict(precision="fp32", incremental=False)
     if form == "screened":
         return dict(precision=precision, incremental=False)
@@ -210,11 +215,12 @@ def bench_rhseg(args, np, torch, hswo, synth):
         same_kt = bool(torch.equal(kt, labels))
     lab = labels.cpu().numpy()
     comparisons = {}
-    for form in ("plain", "screened", "incremental"):
-        if form == args.form or (form == "plain" and args.no_plain) or args.no_forms:
+    for form in ("plain", "plain_batched", "screened", "incremental"):
+        if form == args.form or (form.startswith("plain") and args.no_plain) or args.no_forms:
             continue
         o = torch.empty_like(labels)
-        ms, _, r = timed_steps(runner(form, o, args.graph), stream, torch, 1, 1)
+        # the unbatched plain path is a long launch sequence: eager, one warm-up and one timed call
+        ms, _, r = timed_steps(runner(form, o, args.graph and form != "plain"), stream, torch, 1, 1)
         comparisons[form] = {"ms_per_step": ms, "speedup_of_timed_form": ms / ms_per_step,
                              "labels_identical_to_timed_form": bool(torch.equal(o, labels)),
                              "precision": form_kwargs(form, args.precision)["precision"]}
@@ -224,6 +230,11 @@ def bench_rhseg(args, np, torch, hswo, synth):
             comparisons[form]["rooflines"] = {
                 kd: kernel_roofline(rs.stats, B, f"{args.workload}_{form}", kind=kd)
                 for kd in ("wide_adj", "wide_mfma") if rs.stats["kernel_launches"][hswo.KERNEL_KINDS.index(kd)]}
+    if "plain" in comparisons:
+        # the plain FP32 path (no precision form, no batching) against every form
+        pm = comparisons["plain"]["ms_per_step"]
+        out["speedup_vs_plain"] = {args.form: pm / ms_per_step,
+                                   **{f: pm / v["ms_per_step"] for f, v in comparisons.items() if f != "plain"}}
     out["forms"] = comparisons
     out["labels_identical_kernel_times_step"] = same_kt
     if not args.no_cpu_baseline:
@@ -304,6 +315,11 @@ def bench_batch(args, np, torch, hswo, synth):
                                            "precision": args.precision,
                                            "labels_identical_to_timed_form":
                                                all(bool(torch.equal(a, b)) for a, b in zip(so, outs))}
+    if "plain_sequential" in comparisons:
+        pm = comparisons["plain_sequential"]["ms_per_step"]
+        out["speedup_vs_plain"] = {args.form: pm / ms_per_step,
+                                   **{f: pm / v["ms_per_step"] for f, v in comparisons.items()
+                                      if f != "plain_sequential"}}
     out["forms"] = comparisons
     if not args.no_cpu_baseline:
         import concurrent.futures as cf
@@ -400,7 +416,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rhseg512", choices=sorted(WORKLOAD_DESC))
-    ap.add_argument("--form", default="incremental", choices=["incremental", "screened", "plain"],
+    ap.add_argument("--form", default="incremental", choices=["incremental", "screened", "plain", "plain_batched"],
                     help="form of the timed steps (the others run once for the comparison)")
     ap.add_argument("--precision", default="fp16", choices=["fp32", "bf16", "fp16"],
                     help="matrix-core screen precision of the screened form")

@@ -98,6 +98,9 @@ extern "C" {
                                      stream and report per-kernel device time in hswo_stats
                                      (ms_kernel, kernel_launches); needs stats, not with
                                      HSWO_FLAG_GRAPH */
+#define HSWO_FLAG_SEQUENTIAL_SECTIONS 32 /* run the sections of a level one after another, each
+                                             with the whole device (the unbatched path, for
+                                             comparison); same merges and labels */
 #define HSWO_FLAG_AUTOTUNE 4  /* on the first call for a shape bucket, time every section-driver
                                  variant on the call itself (all give identical results) and keep
                                  the fastest; the choice is cached per process and appended to the

@@ -456,6 +456,18 @@ int run_level(Timer* tm, const SecDev* secs, int n, const std::vector<int64_t>& 
     return HSWO_OK;
 }
 
+// A level's sections one after another (HSWO_FLAG_SEQUENTIAL_SECTIONS), or all together.
+int run_level_sections(Timer* tm, const SecDev* secs, int n, const std::vector<int64_t>& cap,
+                       const std::vector<int64_t>& stop, const LoopParams& lp, bool row_cache, int variant,
+                       bool sequential, hipStream_t stream) {
+    if (!sequential || n == 1) return run_level(tm, secs, n, cap, stop, lp, row_cache, variant, stream);
+    for (int i = 0; i < n; ++i) {
+        const int r = run_level(tm, secs + i, 1, {cap[i]}, {stop[i]}, lp, row_cache, variant, stream);
+        if (r) return r;
+    }
+    return HSWO_OK;
+}
+
 using Seq = std::function<int(hipStream_t, Timer*, int)>;
 
 std::mutex g_mu;
@@ -744,7 +756,7 @@ int check_common(const hswo_params* p, void* workspace) {
     if (!workspace) return fail(HSWO_E_INVAL, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(HSWO_E_INVAL, "workspace must be 256-byte aligned");
     if (p->flags & ~(HSWO_FLAG_MERGE_LOG | HSWO_FLAG_GRAPH | HSWO_FLAG_AUTOTUNE | HSWO_FLAG_INCREMENTAL |
-                     HSWO_FLAG_KERNEL_TIMES))
+                     HSWO_FLAG_KERNEL_TIMES | HSWO_FLAG_SEQUENTIAL_SECTIONS))
         return fail(HSWO_E_INVAL, "unknown flags 0x%x", p->flags);
     return HSWO_OK;
 }
@@ -793,6 +805,7 @@ int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_param
     add_upload(ups, lay.snap, &sd, 1);
     const LoopParams lp = loop_params(p, lay.counters);
     const bool row_cache = row_cache_on(p);
+    const bool sequential = (p->flags & HSWO_FLAG_SEQUENTIAL_SECTIONS) != 0;
     std::vector<std::vector<int64_t>> caps(L), stops(L);
     for (int d = 0; d < L; ++d)
         for (const SecPlan& s : pl.lv[d]) {
@@ -808,7 +821,8 @@ int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_param
             int maxpix = 0;
             for (const SecPlan& s : pl.lv[d]) maxpix = std::max<int>(maxpix, (int)s.cap);
             HIP_TRY(launch_init_leaves(lay.lv[d].secs, lay.lv[d].inits, (int)pl.lv[d].size(), dtype, maxpix, st));
-            const int r = run_level(tm, lay.lv[d].secs, (int)pl.lv[d].size(), caps[d], stops[d], lp, row_cache, variant, st);
+            const int r = run_level_sections(tm, lay.lv[d].secs, (int)pl.lv[d].size(), caps[d], stops[d], lp,
+                                             row_cache, variant, sequential, st);
             if (r) return r;
         }
         for (int d = L - 2; d >= 0; --d) {
@@ -824,7 +838,8 @@ int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_param
             HIP_TRY(launch_assemble(lay.lv[d].secs, lay.lv[d + 1].secs, lay.lv[d].asms, (int)secs.size(), lay.slotmap,
                                     (int)std::min<int64_t>(maxcap, 1 << 30), st));
             HIP_TRY(launch_seam(lay.lv[d].secs, lay.lv[d].asms, (int)secs.size(), lay.slotmap, (int)maxseam, st));
-            const int r = run_level(tm, lay.lv[d].secs, (int)secs.size(), caps[d], stops[d], lp, row_cache, variant, st);
+            const int r = run_level_sections(tm, lay.lv[d].secs, (int)secs.size(), caps[d], stops[d], lp, row_cache,
+                                             variant, sequential, st);
             if (r) return r;
         }
         HIP_TRY(launch_snapshot(lay.snap, 1, lay.counts, p->n_levels, (int)P, st));
@@ -1012,7 +1027,14 @@ int run_batch(int n, const hswo_section* sec, int dtype, const hswo_params* p, h
         HIP_TRY(launch_fill_u64(lay.counters, C_COUNT, 0ull, st));
         HIP_TRY(launch_init_pixels_secs(lay.secs, n, lay.max_pixels, st));
         HIP_TRY(launch_init_leaves(lay.secs, lay.inits, n, dtype, lay.max_pixels, st));
-        const int r = timed_driver(tm, lay.secs_lpt, n, lp, variant, st);
+        int r = HSWO_OK;
+        if (p->flags & HSWO_FLAG_SEQUENTIAL_SECTIONS) {
+            for (int i = 0; i < n && !r; ++i)
+                r = run_level(tm, lay.secs + i, 1, {lay.h_secs[i].R0}, {lay.h_secs[i].stop}, lp, row_cache_on(p),
+                              variant, st);
+        } else {
+            r = timed_driver(tm, lay.secs_lpt, n, lp, variant, st);
+        }
         if (r) return r;
         HIP_TRY(launch_snapshot(lay.snaps, n, lay.counts, p->n_levels, lay.max_pixels, st));
         return HSWO_OK;

@@ -164,7 +164,8 @@ def test_python_constants_match_header():
     src = open(HEADER).read()
     defs = dict(re.findall(r"#define\s+(HSWO_\w+)\s+\(?(-?\d+)\)?", src))
     for name in ("HSWO_FLAG_MERGE_LOG", "HSWO_FLAG_GRAPH", "HSWO_FLAG_AUTOTUNE", "HSWO_FLAG_INCREMENTAL",
-                 "HSWO_FLAG_KERNEL_TIMES", "HSWO_F32", "HSWO_F16", "HSWO_E_INVAL", "HSWO_E_NOMEM"):
+                 "HSWO_FLAG_KERNEL_TIMES", "HSWO_FLAG_SEQUENTIAL_SECTIONS", "HSWO_F32", "HSWO_F16", "HSWO_E_INVAL",
+                 "HSWO_E_NOMEM"):
         assert int(defs[name]) == getattr(hswo, name), name
     kinds = sorted((int(v), k) for k, v in defs.items() if k.startswith("HSWO_K_"))
     assert [k for _, k in kinds] == ["HSWO_K_" + n.upper() for n in hswo.KERNEL_KINDS]

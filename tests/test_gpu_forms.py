@@ -196,3 +196,22 @@ def test_incremental_batch_and_salt():
     r = hswo.rhseg_segment(torch.from_numpy(sc.cube).cuda(), rnb_levels=2, precision="fp16", merge_log=True,
                            incremental=True, **{k: v for k, v in p.items() if k != "rnb_levels"})
     check_against_oracle(sc.cube, r.labels.cpu().numpy(), r.log, p, "inc salt")
+
+
+@pytest.mark.parametrize("form", ["fp32", "incremental"])
+def test_sequential_sections_identical(form):
+    """Sections of a level one after another, each with the whole device: the
+    same merges and labels as the batched levels (and the oracle)."""
+    sc = synth.voronoi_scene(64, 56, 24, 14, 25.0, 57)
+    p = dict(connectivity=4, seam_connectivity=8, spclust_wght=0.5, spclust_max=300, target_regions=5,
+             section_regions=80, level_counts=[300, 64, 5])
+    _say(f"[gpu] sequential sections {form}")
+    res = hswo.rhseg_segment(torch.from_numpy(sc.cube).cuda(), rnb_levels=3, precision="fp32", merge_log=True,
+                             incremental=form == "incremental", sequential=True, stats=True, **p)
+    check_against_oracle(sc.cube, res.labels.cpu().numpy(), res.log, dict(p, rnb_levels=3), f"sequential {form}")
+    cubes = uneven_sections(5, seed0=5151)
+    res = hswo.hswo_run_batch([torch.from_numpy(c).cuda() for c in cubes], precision="fp32", merge_log=True,
+                              incremental=form == "incremental", sequential=True, **BATCH_P)
+    torch.cuda.synchronize()
+    for i, c in enumerate(cubes):
+        check_against_oracle(c, res.labels[i].cpu().numpy(), res.logs[i], BATCH_P, f"sequential batch {i}")
