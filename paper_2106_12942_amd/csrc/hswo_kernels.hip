@@ -776,6 +776,102 @@ __device__ void row_block_task(double (*rsum)[4][64], const SecDev& s, int R, in
 }
 
 // Number of block tasks of a section's row cache stage this iteration.
+// One wavefront evaluates KR pending rows against 64 columns over all bands
+// (lane = column), for a workgroup that has the whole section to itself:
+// its waves take different column chunks. Bands are added in groups of 8
+// (fixed subtrees) through a binary counter of LV levels, which is the same
+// perfect binary tree as exact_d2_wave's; the next group's column values are
+// loaded before the current group is added.
+template <int KR, int LV>
+__device__ void row_wave_task(const SecDev& s, int R, int np, bool all, int bq, int c) {
+    constexpr int GB = 8;
+    const int lane = lane_id();
+    const int B = s.B, B8 = (B + 7) & ~7;
+    const size_t kc = (size_t)s.rcap;
+    const int j = (c << 6) + lane;
+    const bool jv = j < R;
+    int ir[KR];
+#pragma unroll
+    for (int r = 0; r < KR; ++r) {
+        const int q = bq * KR + r;
+        int v = -1;
+        if (q < np) v = all ? q : s.rpend[q];
+        ir[r] = __builtin_amdgcn_readfirstlane(v);
+    }
+    const int n_j = jv ? s.npix[j] : 1;
+    const int l_j = jv ? s.label[j] : INT_MAX;
+    const double* mj = s.m64 + (jv ? j : 0);
+    double part[KR][LV];
+#pragma unroll
+    for (int r = 0; r < KR; ++r)
+#pragma unroll
+        for (int l = 0; l < LV; ++l) part[r][l] = 0.0;
+    const int ng = (B + GB - 1) / GB;
+    double cv[GB], nx[GB];
+#pragma unroll
+    for (int k = 0; k < GB; ++k) cv[k] = (k < B) ? mj[(size_t)k * kc] : 0.0;
+    for (int g = 0; g < ng; ++g) {
+        const int b0 = g * GB;
+#pragma unroll
+        for (int k = 0; k < GB; ++k) {
+            const int b = b0 + GB + k;
+            nx[k] = (b < B) ? mj[(size_t)b * kc] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < KR; ++r) {
+            if (ir[r] < 0) continue;  // wavefront-uniform
+            const double* mi = s.m64r + (size_t)ir[r] * B8 + b0;
+            double qv[GB];
+#pragma unroll
+            for (int k = 0; k < GB; ++k) {
+                const double d = (b0 + k < B) ? mi[k] - cv[k] : 0.0;
+                qv[k] = d * d;
+            }
+#pragma unroll
+            for (int h = 1; h < GB; h <<= 1)
+#pragma unroll
+                for (int k = 0; k < GB; k += 2 * h) qv[k] = qv[k] + qv[k + h];
+            counter_push<LV>(part[r], qv[0], g);
+        }
+#pragma unroll
+        for (int k = 0; k < GB; ++k) cv[k] = nx[k];
+    }
+    const int nch = (R + 63) >> 6;
+#pragma unroll
+    for (int r = 0; r < KR; ++r) {
+        if (ir[r] < 0) continue;  // wavefront-uniform
+        const int i = ir[r];
+        const int n_i = s.npix[i];
+        const double dni = (double)n_i, dnj = (double)n_j;
+        const double fac = (dni * dnj) / (double)(n_i + n_j);
+        double d2 = fac * counter_total<LV>(part[r], ng);
+        int lab = l_j, slot = j;
+        if (!jv || j == i) {
+            d2 = __builtin_huge_val();
+            lab = INT_MAX;
+            slot = -1;
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            const double d2o = __shfl_xor(d2, o);
+            const int labo = __shfl_xor(lab, o);
+            const int sloto = __shfl_xor(slot, o);
+            if (d2o < d2 || (d2o == d2 && labo < lab)) {
+                d2 = d2o;
+                lab = labo;
+                slot = sloto;
+            }
+        }
+        if (lane == 0) {
+            RowPart rp;
+            rp.d2 = d2;
+            rp.lab = lab;
+            rp.slot = slot;
+            s.rpart[(size_t)(bq * KR + r) * nch + c] = rp;
+        }
+    }
+}
+
 __device__ __forceinline__ int row_task_count(int R, int np) { return ((np + 3) / 4) * ((R + 63) >> 6); }
 
 __device__ __forceinline__ KeyD pair_key(const SecDev& s, double d2, int a, int b) {
@@ -1678,9 +1774,15 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
             }
             const bool all = rcs == 1;
             const int rows = all ? R : npend;
+            // the section has the workgroup to itself: each wavefront takes its own tasks
             const int nch = (R + 63) >> 6;
             const int ntask = row_task_count(R, rows);
-            for (int t = 0; t < ntask; ++t) row_block_task<4>(sh.u.rsum, s, R, rows, all, t / nch, t % nch);
+            if (s.B <= 512) {
+                for (int t = wave_id(); t < ntask; t += NWAVE) row_wave_task<4, 7>(s, R, rows, all, t / nch, t % nch);
+            } else {
+                for (int t = wave_id(); t < ntask; t += NWAVE) row_wave_task<4, 10>(s, R, rows, all, t / nch, t % nch);
+            }
+            __syncthreads();
             M = spectral_min_rows(sh, s, R, rows, all);
             rcs = 2;
             npend = 0;
