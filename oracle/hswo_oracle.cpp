@@ -51,6 +51,40 @@ double criterion(const double* Si, const double* Sj, int64_t ni, int64_t nj, int
     return fac * pairwise_sum(sq, P);
 }
 
+/* ---- spectral angle criterion (listed among the usable dissimilarities in
+ * Section 4.1), ranked without acos or sqrt ------------------------------- *
+ * c = <S_i, S_j> / (|S_i| |S_j|) is the cosine of the angle between the two
+ * mean spectra (the counts cancel, so band sums serve). The ranked value is
+ * D = 1 - sign(c) c^2, which equals sin^2(theta) for theta <= 90 degrees and
+ * rises monotonically to 2 at 180 degrees, so it orders pairs exactly as the
+ * angle does; like Equation 1 it is the square of the angle-like quantity
+ * sin(theta), which is why the spectral weight enters squared for both.
+ * Canonical order: dot, q_i = |S_i|^2 and q_j = |S_j|^2 are each a pairwise
+ * tree over the zero-padded band index; t = (dot * dot) / (q_i * q_j);
+ * D = 1 - t if dot >= 0 else 1 + t; D < 0 (rounding) is raised to 0; a zero
+ * spectrum (q_i * q_j == 0) gives D = 1, as for orthogonal spectra. */
+double sam(const double* Si, const double* Sj, int B) {
+    int P = 1;
+    while (P < B) P *= 2;
+    double dt[4096], qi[4096], qj[4096];
+    for (int b = 0; b < P; ++b) dt[b] = qi[b] = qj[b] = 0.0;
+    for (int b = 0; b < B; ++b) {
+        dt[b] = Si[b] * Sj[b];
+        qi[b] = Si[b] * Si[b];
+        qj[b] = Sj[b] * Sj[b];
+    }
+    const double dot = pairwise_sum(dt, P);
+    const double den = pairwise_sum(qi, P) * pairwise_sum(qj, P);
+    if (den == 0.0) return 1.0;
+    const double t = (dot * dot) / den;
+    const double d = dot >= 0.0 ? 1.0 - t : 1.0 + t;
+    return d > 0.0 ? d : 0.0;
+}
+
+double pair_value(int crit, const double* Si, const double* Sj, int64_t ni, int64_t nj, int B) {
+    return crit == ORACLE_CRIT_SAM ? sam(Si, Sj, B) : criterion(Si, Sj, ni, nj, B);
+}
+
 /* ---- merge key: (D2, lo, hi), compared lexicographically (tie-break) ----- */
 struct Key {
     double d2 = std::numeric_limits<double>::infinity();
@@ -151,7 +185,7 @@ class Pass {
   private:
     double d2(int a, int b) {
         const int lo = std::min(a, b), hi = std::max(a, b);
-        return criterion(st_.Sp(lo), st_.Sp(hi), st_.n[lo], st_.n[hi], st_.B);
+        return pair_value(p_.criterion, st_.Sp(lo), st_.Sp(hi), st_.n[lo], st_.n[hi], st_.B);
     }
     Key key(int a, int b, double v) { return {v, std::min(a, b), std::max(a, b)}; }
 
@@ -386,6 +420,11 @@ extern "C" double oracle_d2(const double* Si, const double* Sj, int64_t ni, int6
     return criterion(Si, Sj, ni, nj, B);
 }
 
+extern "C" double oracle_sam(const double* Si, const double* Sj, int32_t B) {
+    if (B < 1 || B > 4096) return std::numeric_limits<double>::quiet_NaN();
+    return sam(Si, Sj, B);
+}
+
 extern "C" int oracle_rhseg(const float* cube, int32_t H, int32_t W, int32_t B, const oracle_params* p,
                             int32_t* labels, oracle_merge* log, int64_t* n_log, int32_t* out_R,
                             int32_t* out_label, int64_t* out_n, double* out_S) {
@@ -394,6 +433,7 @@ extern "C" int oracle_rhseg(const float* cube, int32_t H, int32_t W, int32_t B, 
     if (p->connectivity != 4 && p->connectivity != 8) return -1;
     if (p->seam_connectivity != 4 && p->seam_connectivity != 8) return -1;
     if (!(p->spclust_wght >= 0.0f && p->spclust_wght <= 1.0f)) return -1;
+    if (p->criterion != ORACLE_CRIT_BSMSE && p->criterion != ORACLE_CRIT_SAM) return -1;
     if (p->target_regions < 1 || p->rnb_levels < 1 || p->rnb_levels > 16) return -1;
     if ((H >> (p->rnb_levels - 1)) < 1 || (W >> (p->rnb_levels - 1)) < 1) return -1;
     if (p->n_levels < 1 || !p->level_counts) return -1;

@@ -18,6 +18,10 @@
  *   runs again on the parent, up to level 1.
  *   Criterion (Equation 1): sqrt( n_i n_j / (n_i + n_j) * sum_b (mu_ib - mu_jb)^2 ).
  *   The oracle ranks on the squared value D2 (sqrt is monotone).
+ *   Alternative criterion (Section 4.1 lists the spectral angle among the
+ *   usable ones): the spectral angle, ranked on 1 - sign(c) c^2 with c its
+ *   cosine, i.e. sin^2 of the angle up to 90 degrees; the decision rule and
+ *   the squared weight are the same as for Equation 1.
  *
  * Readings taken where the paper is silent:
  *   one merge per iteration; the non-adjacent pair wins iff
@@ -48,7 +52,11 @@ typedef struct oracle_params {
     const int32_t* level_counts;/* strictly decreasing, last == target */
     int32_t brute;              /* 1: recompute every pair every iteration */
     int32_t n_threads;          /* worker threads over independent sections */
+    int32_t criterion;          /* ORACLE_CRIT_BSMSE (Equation 1) or ORACLE_CRIT_SAM */
 } oracle_params;
+
+#define ORACLE_CRIT_BSMSE 0 /* Equation 1, ranked on its square D2 */
+#define ORACLE_CRIT_SAM 1   /* spectral angle, ranked on 1 - sign(c) c^2 (c its cosine) */
 
 typedef struct oracle_merge {
     int32_t lo, hi;     /* region labels, lo < hi; lo survives */
@@ -59,6 +67,9 @@ typedef struct oracle_merge {
 
 /* Canonical squared criterion of Equation 1 from band sums and counts. */
 double oracle_d2(const double* Si, const double* Sj, int64_t ni, int64_t nj, int32_t B);
+
+/* Spectral angle criterion from band sums: 1 - sign(c) c^2, c = cos(angle). */
+double oracle_sam(const double* Si, const double* Sj, int32_t B);
 
 /*
  * Run RHSEG (HSWO/HSEG when rnb_levels == 1) on a float32 H x W x B cube

@@ -29,7 +29,11 @@ class _Params(ctypes.Structure):
         ("level_counts", ctypes.POINTER(ctypes.c_int32)),
         ("brute", ctypes.c_int32),
         ("n_threads", ctypes.c_int32),
+        ("criterion", ctypes.c_int32),
     ]
+
+
+CRITERIA = {"bsmse": 0, "sam": 1}
 
 
 def lib_path() -> str:
@@ -67,6 +71,8 @@ def _load(path: Optional[str] = None):
 def _bind(lib):
     lib.oracle_d2.restype = ctypes.c_double
     lib.oracle_d2.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32]
+    lib.oracle_sam.restype = ctypes.c_double
+    lib.oracle_sam.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
     lib.oracle_rhseg.restype = ctypes.c_int
     lib.oracle_rhseg.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                  ctypes.POINTER(_Params), ctypes.c_void_p, ctypes.c_void_p,
@@ -82,6 +88,13 @@ def criterion_d2(Si: np.ndarray, Sj: np.ndarray, ni: int, nj: int) -> float:
     return _load().oracle_d2(Si.ctypes.data, Sj.ctypes.data, int(ni), int(nj), int(Si.size))
 
 
+def criterion_sam(Si: np.ndarray, Sj: np.ndarray) -> float:
+    """Spectral angle criterion 1 - sign(c) c^2 (c = cosine) from band sums."""
+    Si = np.ascontiguousarray(Si, dtype=np.float64)
+    Sj = np.ascontiguousarray(Sj, dtype=np.float64)
+    return _load().oracle_sam(Si.ctypes.data, Sj.ctypes.data, int(Si.size))
+
+
 @dataclasses.dataclass
 class OracleResult:
     labels: np.ndarray        # [n_levels, H, W] int32
@@ -95,7 +108,8 @@ def rhseg(cube: np.ndarray, *, connectivity: int = 4, seam_connectivity: int = 8
           spclust_wght: float = 0.0, spclust_max: int = 0, target_regions: int = 1,
           section_regions: int = 0, rnb_levels: int = 1,
           level_counts: Optional[Sequence[int]] = None, brute: bool = False,
-          n_threads: Optional[int] = None, lib: Optional[str] = None, **_ignored) -> OracleResult:
+          n_threads: Optional[int] = None, lib: Optional[str] = None, criterion: str = "bsmse",
+          **_ignored) -> OracleResult:
     """Run the oracle on a host H x W x B cube (float32, or float16 widened exactly)."""
     cube = np.asarray(cube)
     if cube.dtype == np.float16:
@@ -117,6 +131,7 @@ def rhseg(cube: np.ndarray, *, connectivity: int = 4, seam_connectivity: int = 8
     p.level_counts = lc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
     p.brute = 1 if brute else 0
     p.n_threads = n_threads if n_threads is not None else (os.cpu_count() or 1)
+    p.criterion = CRITERIA[criterion]
     labels = np.full((len(lc), H, W), -1, dtype=np.int32)
     log = np.zeros(H * W, dtype=MERGE_DTYPE)
     n_log = ctypes.c_int64(0)

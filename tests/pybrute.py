@@ -14,6 +14,9 @@ its decisions are the mathematically exact ones; otherwise the squared
 criterion is evaluated in IEEE double in the canonical order (band sums,
 then per-band means and squared differences, summed as a pairwise tree over
 the band index zero-padded to a power of two, then the size factor).
+``criterion="sam"`` ranks on the spectral angle instead, as 1 - sign(c) c^2
+with c the cosine between the regions' band-sum vectors (rational when
+exact; otherwise dot product and squared norms as pairwise trees).
 """
 from __future__ import annotations
 
@@ -40,8 +43,43 @@ def _leaf_map(H, W, L):
     return leaf
 
 
-def _criterion(xs_i, xs_j, exact):
-    """Equation 1 squared, from the two regions' pixel vectors."""
+def _tree(terms):
+    """Pairwise tree over the band index, zero-padded to a power of two."""
+    terms = list(terms)
+    while len(terms) & (len(terms) - 1):
+        terms.append(0.0)
+    while len(terms) > 1:
+        terms = [terms[2 * k] + terms[2 * k + 1] for k in range(len(terms) // 2)]
+    return terms[0]
+
+
+def _sam(xs_i, xs_j, exact):
+    """Spectral angle ranked as 1 - sign(c) c^2, c the cosine of the angle
+    between the regions' mean spectra (equal to that of their band sums)."""
+    B = len(xs_i[0])
+    Si = [sum(Fraction(x[b]) for x in xs_i) for b in range(B)]
+    Sj = [sum(Fraction(x[b]) for x in xs_j) for b in range(B)]
+    if exact:
+        dot = sum(Si[b] * Sj[b] for b in range(B))
+        den = sum(v * v for v in Si) * sum(v * v for v in Sj)
+        if den == 0:
+            return Fraction(1)
+        t = dot * dot / den
+        return max(Fraction(0), 1 - t if dot >= 0 else 1 + t)
+    Si = [float(v) for v in Si]
+    Sj = [float(v) for v in Sj]
+    dot = _tree(Si[b] * Sj[b] for b in range(B))
+    den = _tree(v * v for v in Si) * _tree(v * v for v in Sj)
+    if den == 0.0:
+        return 1.0
+    t = (dot * dot) / den
+    return max(0.0, 1.0 - t if dot >= 0.0 else 1.0 + t)
+
+
+def _criterion(xs_i, xs_j, exact, crit="bsmse"):
+    if crit == "sam":
+        return _sam(xs_i, xs_j, exact)
+    # Equation 1 squared, from the two regions' pixel vectors
     ni, nj = len(xs_i), len(xs_j)
     B = len(xs_i[0])
     if exact:
@@ -66,7 +104,7 @@ def _criterion(xs_i, xs_j, exact):
     return fac * acc
 
 
-def _hseg_pass(cube, lab, rect, leaf, conn, seam, w, kmax, stop, log, snaps, counts, top):
+def _hseg_pass(cube, lab, rect, leaf, conn, seam, w, kmax, stop, log, snaps, counts, top, crit):
     r0, c0, h, wd = rect
     H = len(cube)
     W = len(cube[0])
@@ -118,7 +156,7 @@ def _hseg_pass(cube, lab, rect, leaf, conn, seam, w, kmax, stop, log, snaps, cou
                 isadj = (i, j) in adj
                 if not isadj and not spectral:
                     continue
-                v = _criterion(reg[i], reg[j], exact=log.exact)
+                v = _criterion(reg[i], reg[j], log.exact, crit)
                 key = (v, i, j)
                 if isadj:
                     if A is None or key < A:
@@ -147,7 +185,8 @@ class _Log(list):
 
 
 def rhseg(cube, *, connectivity=4, seam_connectivity=8, spclust_wght=0.0, spclust_max=0,
-          target_regions=1, section_regions=0, rnb_levels=1, level_counts=None, exact=False, **_):
+          target_regions=1, section_regions=0, rnb_levels=1, level_counts=None, exact=False, criterion="bsmse",
+          **_):
     """cube: nested lists or an array H x W x B. Returns (labels per level, log)."""
     cube = [[[float(v) for v in px] for px in row] for row in (cube.tolist() if hasattr(cube, "tolist") else cube)]
     H, W = len(cube), len(cube[0])
@@ -166,5 +205,5 @@ def rhseg(cube, *, connectivity=4, seam_connectivity=8, spclust_wght=0.0, spclus
         top = d == 0
         for rect in levels[d]:
             _hseg_pass(cube, lab, rect, leaf, connectivity, seam_connectivity, spclust_wght,
-                       spclust_max, target_regions if top else S, log, snaps, counts, top)
+                       spclust_max, target_regions if top else S, log, snaps, counts, top, criterion)
     return snaps, list(log)

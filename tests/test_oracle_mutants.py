@@ -41,6 +41,50 @@ MUTANTS = {
 }
 
 
+SAM_MUTANTS = {
+    "sam_sign_dropped": ("const double d = dot >= 0.0 ? 1.0 - t : 1.0 + t;", "const double d = 1.0 - t;"),
+    "sam_cosine_not_squared": ("const double t = (dot * dot) / den;", "const double t = dot / den;"),
+    "sam_norm_of_i_twice": ("pairwise_sum(qi, P) * pairwise_sum(qj, P)", "pairwise_sum(qi, P) * pairwise_sum(qi, P)"),
+    "sam_zero_spectrum_parallel": ("if (den == 0.0) return 1.0;", "if (den == 0.0) return 0.0;"),
+    "sam_last_band_dropped": ("for (int b = 0; b < B; ++b) {\n        dt[b]", "for (int b = 0; b < B - 1; ++b) {\n        dt[b]"),
+    "sam_not_clamped": ("return d > 0.0 ? d : 0.0;", "return d;"),
+    "sam_not_dispatched": ("return crit == ORACLE_CRIT_SAM ?", "return crit == -1 ?"),
+}
+
+
+def _run_sam_pins(lib):
+    """The spectral angle pins in compact form; returns the first that fails."""
+    from tests.test_oracle_sam import GRID
+    f = oracle.oracle._load(lib).oracle_sam if lib else oracle.oracle._load().oracle_sam
+
+    def sam(a, b):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        return f(a.ctypes.data, b.ctypes.data, a.size)
+
+    for a, b, want in (([3.0, 4.0], [4.0, 3.0], 49.0 / 625.0), ([3.0, 4.0], [-4.0, -3.0], 2.0 - 49.0 / 625.0),
+                       ([0.0, 0.0, 0.0], [5.0, 1.0, 2.0], 1.0), ([1.0, 2.0, 2.0], [2.0, 2.0, 1.0], 17.0 / 81.0)):
+        if abs(sam(a, b) - want) > 1e-15:
+            return "closed form"
+    rng = np.random.default_rng(9)
+    for _ in range(200):
+        a = rng.uniform(-5, 5, size=int(rng.integers(1, 40)))
+        if not all(0.0 <= sam(a, k * a) for k in (3.0, 5.0, 7.0)):
+            return "bounds"
+    for t in range(8):
+        p = GRID[t % len(GRID)]
+        H, W = 3 + t % 3, 4 + t % 2
+        cube = synth.random_cube(H, W, 1 + t % 4, seed=60 + t, kind="continuous" if t % 3 else "integer")
+        counts = [max(2, H * W // 2), 2]
+        res = oracle.rhseg(cube, **p, target_regions=2, level_counts=counts, criterion="sam", lib=lib)
+        _, log = pybrute.rhseg(cube, **p, target_regions=2, level_counts=counts, criterion="sam",
+                               exact=bool(t % 3))
+        got = [(int(m["lo"]), int(m["hi"]), int(m["kind"]), int(m["r_after"])) for m in res.log]
+        if got != [tuple(x[:4]) for x in log]:
+            return "python rational hseg"
+    return None
+
+
 def _run_pins(lib):
     """A compact pass over the pins; returns the name of the first that fails."""
     for case in GOLDEN_CASES:
@@ -91,3 +135,18 @@ def test_pins_reject_mutant(name, tmp_path):
     path.write_text(src.replace(old, new))
     lib = oracle.build(src=str(path), out=str(tmp_path / f"liboracle_{name}.so"))
     assert _run_pins(lib) is not None, f"mutant {name} survived every pin"
+
+
+def test_unmutated_oracle_passes_the_sam_pins():
+    assert _run_sam_pins(None) is None
+
+
+@pytest.mark.parametrize("name", sorted(SAM_MUTANTS))
+def test_sam_pins_reject_mutant(name, tmp_path):
+    old, new = SAM_MUTANTS[name]
+    src = open(_SRC).read()
+    assert src.count(old) == 1, f"mutation site for {name} not found exactly once"
+    path = tmp_path / "mutant.cpp"
+    path.write_text(src.replace(old, new))
+    lib = oracle.build(src=str(path), out=str(tmp_path / f"liboracle_{name}.so"))
+    assert _run_sam_pins(lib) is not None, f"mutant {name} survived every pin"
