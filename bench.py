@@ -26,6 +26,9 @@ into one launch (persistent) or one launch sequence per iteration (wide),
 replayed from a hipGraph. The other forms run once on the same input for the comparison, and
 must give the same labels.
 
+Criterion (--criterion): "bsmse" (default), the paper's Equation 1; "sam",
+the spectral angle (incremental form only, so no other form is compared).
+
 Output: one JSON line. `value` is dissimilarity pairs per second: the
 method's pairs (live adjacent pairs, plus R(R-1)/2 per iteration of the
 spectral stage, counted by the kernels) over the wall time of a step. The
@@ -172,6 +175,7 @@ def timed_steps(step, stream, torch, steps, warmup):
 
 def bench_rhseg(args, np, torch, hswo, synth):
     sc, params = synth.workload(args.workload)
+    params["criterion"] = args.criterion
     cube_h = sc.cube
     H, W, B = cube_h.shape
     dev = torch.device("cuda:0")
@@ -200,24 +204,27 @@ def bench_rhseg(args, np, torch, hswo, synth):
         "value": pairs / (ms_per_step / 1e3), "unit": "pairs/s", "ms_per_step": ms_per_step,
         "wall_ms_median": statistics.median(walls), "wall_ms_min": min(walls), "wall_ms_max": max(walls),
         "config": {"workload": args.workload, "desc": WORKLOAD_DESC[args.workload], "H": H, "W": W, "B": B,
-                   "form": args.form, "precision": fk["precision"], "graph": args.graph,
-                   "autotune": args.autotune, "driver_variant": st["driver_variant"]},
+                   "form": args.form, "precision": fk["precision"], "criterion": args.criterion,
+                   "graph": args.graph, "autotune": args.autotune, "driver_variant": st["driver_variant"]},
         "pairs_per_step": pairs, "merges_per_step": st["merges"], "exact_evaluations_per_step": st["exact_rechecks"],
         "fp32_tiles_per_step": st["fp32_tiles"], "mfma_super_tiles_per_step": st["mfma_tiles"],
     }
+    tag = f"{args.workload}_{args.form}" + ("" if args.criterion == "bsmse" else f"_{args.criterion}")
     # per-kernel device times: one more step of the timed form, eager, every launch bracketed by hipEvents
     same_kt = None
     if not args.no_kernel_times:
         kt = torch.empty_like(labels)
         _, _, rk = timed_steps(runner(args.form, kt, False, kernel_times=True), stream, torch, 1, 0)
         out["kernel_times_step_ms"] = rk.stats["ms_total"]
-        out["roofline"] = kernel_roofline(rk.stats, B, f"{args.workload}_{args.form}")
+        out["roofline"] = kernel_roofline(rk.stats, B, tag)
         same_kt = bool(torch.equal(kt, labels))
     lab = labels.cpu().numpy()
     comparisons = {}
     for form in ("plain", "plain_batched", "screened", "incremental"):
         if form == args.form or (form.startswith("plain") and args.no_plain) or args.no_forms:
             continue
+        if args.criterion != "bsmse" and form != "incremental":
+            continue  # the other criteria exist in the incremental form only
         o = torch.empty_like(labels)
         # the unbatched plain path is a long launch sequence: eager, one warm-up and one timed call
         ms, _, r = timed_steps(runner(form, o, args.graph and form != "plain"), stream, torch, 1, 1)
@@ -256,6 +263,8 @@ def bench_batch(args, np, torch, hswo, synth):
     secs = synth.batch_sections(256)
     params = dict(synth.BATCH_PARAMS)
     params.pop("rnb_levels", None)
+    params["criterion"] = args.criterion
+    other_forms = not args.no_forms and args.criterion == "bsmse"  # other criteria: incremental form only
     dev = torch.device("cuda:0")
     dc = [torch.from_numpy(c).to(dev) for c, _ in secs]
     stream = torch.cuda.Stream(dev)
@@ -284,8 +293,8 @@ def bench_batch(args, np, torch, hswo, synth):
         "value": pairs / (ms_per_step / 1e3), "unit": "pairs/s", "ms_per_step": ms_per_step,
         "wall_ms_median": statistics.median(walls), "wall_ms_min": min(walls), "wall_ms_max": max(walls),
         "config": {"workload": "batch256", "desc": WORKLOAD_DESC["batch256"], "sections": len(secs),
-                   "form": args.form, "precision": fk["precision"], "graph": args.graph,
-                   "autotune": args.autotune, "driver_variant": st["driver_variant"]},
+                   "form": args.form, "precision": fk["precision"], "criterion": args.criterion,
+                   "graph": args.graph, "autotune": args.autotune, "driver_variant": st["driver_variant"]},
         "pairs_per_step": pairs, "merges_per_step": st["merges"], "exact_evaluations_per_step": st["exact_rechecks"],
     }
     if not args.no_kernel_times:
@@ -293,9 +302,10 @@ def bench_batch(args, np, torch, hswo, synth):
         _, _, rk = timed_steps(runner(args.form, ko, False, kernel_times=True), stream, torch, 1, 0)
         out["kernel_times_step_ms"] = rk.stats["ms_total"]
         # the band count varies by section: the roofline uses the mean
-        out["roofline"] = kernel_roofline(rk.stats, Bmean, f"batch256_{args.form}")
+        out["roofline"] = kernel_roofline(rk.stats, Bmean, f"batch256_{args.form}" +
+                                          ("" if args.criterion == "bsmse" else f"_{args.criterion}"))
     comparisons = {}
-    if not args.no_plain and not args.no_forms:
+    if not args.no_plain and other_forms:
         # the plain path: 256 sequential hswo_run calls, FP32 screen, every pair each iteration
         torch.cuda.synchronize()
         ts = time.perf_counter()
@@ -308,7 +318,7 @@ def bench_batch(args, np, torch, hswo, synth):
         comparisons["plain_sequential"] = {"form": "256 sequential hswo_run calls, plain FP32", "ms_per_step": plain_ms,
                                            "speedup_of_timed_form": plain_ms / ms_per_step,
                                            "labels_identical_to_timed_form": same}
-    if args.form != "screened" and not args.no_forms:
+    if args.form != "screened" and other_forms:
         so = new_outs()
         ms, _, _ = timed_steps(runner("screened", so, args.graph), stream, torch, 1, 1)
         comparisons["screened_batched"] = {"ms_per_step": ms, "speedup_of_timed_form": ms / ms_per_step,
@@ -420,6 +430,8 @@ def main():
                     help="form of the timed steps (the others run once for the comparison)")
     ap.add_argument("--precision", default="fp16", choices=["fp32", "bf16", "fp16"],
                     help="matrix-core screen precision of the screened form")
+    ap.add_argument("--criterion", default="bsmse", choices=["bsmse", "sam"],
+                    help="dissimilarity: Equation 1 (bsmse) or the spectral angle (sam, incremental form only)")
     ap.add_argument("--no-graph", dest="graph", action="store_false", help="launch eagerly instead of a hipGraph")
     ap.add_argument("--autotune", action="store_true", help="autotune the section-driver variant first")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 comparison run")
@@ -433,6 +445,8 @@ def main():
                     help="only copy this many bytes device to device (3 times) and exit: the known-size "
                          "reference for the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
+    if args.criterion != "bsmse" and args.form != "incremental":
+        ap.error("--criterion sam is implemented in the incremental form only")
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

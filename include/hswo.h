@@ -85,6 +85,23 @@ extern "C" {
 #define HSWO_PREC_SCREEN_BF16 1 /* Gram cross-term on BF16 matrix cores, FP32 accumulate */
 #define HSWO_PREC_SCREEN_FP16 2 /* Gram cross-term on FP16 matrix cores, FP32 accumulate */
 
+/* dissimilarity criterion (Section 4.1 names several usable ones; the paper
+   evaluates Equation 1) */
+#define HSWO_CRIT_BSMSE 0 /* Equation 1, ranked on its square D2 (above) */
+#define HSWO_CRIT_SAM 1   /* spectral angle between the mean spectra, ranked on
+                             D = 1 - sign(c) c^2 with c the cosine (sin^2 of the angle up to
+                             90 degrees, rising to 2 at 180), in one fixed FP64 order:
+                               dot = pairwise tree over b of S_ib * S_jb,
+                               q_i = pairwise tree over b of S_ib * S_ib (likewise q_j),
+                               t = (dot * dot) / (q_i * q_j),
+                               D = 1 - t if dot >= 0 else 1 + t, raised to 0 if negative;
+                               D = 1 when q_i * q_j == 0 (a zero spectrum).
+                             The counts cancel, so the band sums serve. Decision rule and
+                             tie-break are those of Equation 1 with D in place of D2 (the
+                             weight enters squared: D is the square of sin(angle)), so the
+                             merge log's d2 field holds D. HSWO_FLAG_INCREMENTAL form only
+                             (other forms return HSWO_E_UNSUPPORTED). */
+
 /* flags */
 #define HSWO_FLAG_MERGE_LOG 1 /* fill merge_log (must be non-NULL) */
 #define HSWO_FLAG_GRAPH 2     /* capture the call's kernel sequence into a hipGraph on first use and
@@ -119,7 +136,8 @@ typedef struct hswo_params {
                                    all >= target_regions, last == target_regions */
     int32_t precision;          /* HSWO_PREC_* */
     int32_t flags;              /* HSWO_FLAG_* */
-} hswo_params;
+    int32_t criterion;          /* HSWO_CRIT_* dissimilarity criterion (0 = Equation 1) */
+} hswo_params;                  /* 56 bytes */
 
 typedef struct hswo_merge_rec {
     int32_t lo, hi;   /* labels of the merged regions, lo < hi; lo survives */

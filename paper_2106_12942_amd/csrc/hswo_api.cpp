@@ -95,6 +95,10 @@ int validate_params(const hswo_params* p, int rnb_levels_expected) {
     if (p->precision != HSWO_PREC_FP32 && p->precision != HSWO_PREC_SCREEN_BF16 &&
         p->precision != HSWO_PREC_SCREEN_FP16)
         return fail(HSWO_E_INVAL, "unknown precision %d", p->precision);
+    if (p->criterion != HSWO_CRIT_BSMSE && p->criterion != HSWO_CRIT_SAM)
+        return fail(HSWO_E_INVAL, "unknown criterion %d", p->criterion);
+    if (p->criterion == HSWO_CRIT_SAM && !(p->flags & HSWO_FLAG_INCREMENTAL))
+        return fail(HSWO_E_UNSUPPORTED, "criterion HSWO_CRIT_SAM is implemented in the HSWO_FLAG_INCREMENTAL form only");
     return HSWO_OK;
 }
 
@@ -248,6 +252,7 @@ Layout carve(const Plan& pl, int H, int W, const hswo_params* p, void* ws, const
             s.top = d == 0 ? 1 : 0;
             s.log_base = (int32_t)log_base;
             s.tiles = (int32_t)sp.tiles;
+            s.crit = p->criterion;
             s.label = bp.take<int32_t>(sp.cap);
             s.npix = bp.take<int32_t>(sp.cap);
             s.mark = bp.take<int32_t>(sp.cap);
@@ -267,14 +272,13 @@ Layout carve(const Plan& pl, int H, int W, const hswo_params* p, void* ws, const
                 const int64_t rc = std::min<int64_t>(sp.cap, p->spclust_max);
                 s.rcap = (int32_t)rc;
                 s.m64 = bp.take<double>(rc * pl.B);
-            s.m64r = bp.take<double>(rc * (((int64_t)pl.B + 7) / 8 * 8));
+                s.m64r = bp.take<double>(rc * (((int64_t)pl.B + 7) / 8 * 8));
+                if (p->criterion == HSWO_CRIT_SAM) s.rq = bp.take<double>(rc);
                 s.rbd = bp.take<double>(rc);
                 s.rbp = bp.take<int32_t>(rc);
-        s.rbl = bp.take<int32_t>(rc);
-            s.rbl = bp.take<int32_t>(rc);
+                s.rbl = bp.take<int32_t>(rc);
                 s.rpend = bp.take<int32_t>(rc);
-        s.rpart = bp.take<RowPart>(rc * ((rc + 63) / 64));
-            s.rpart = bp.take<RowPart>(rc * ((rc + 63) / 64));
+                s.rpart = bp.take<RowPart>(rc * ((rc + 63) / 64));
                 } else if (p->precision != HSWO_PREC_FP32 && p->spclust_wght > 0.0f && p->spclust_max > 0) {
                 const int64_t kc = std::min<int64_t>(sp.cap, p->spclust_max);
                 s.kcap = (int32_t)kc;
@@ -728,7 +732,8 @@ std::string params_key(const hswo_params* p) {
     std::string k = "c" + std::to_string(p->connectivity) + "s" + std::to_string(p->seam_connectivity) + "w" +
                     std::to_string(p->spclust_wght) + "k" + std::to_string(p->spclust_max) + "t" +
                     std::to_string(p->target_regions) + "S" + std::to_string(p->section_regions) + "L" +
-                    std::to_string(p->rnb_levels) + "P" + std::to_string(p->precision) + "F" +
+                    std::to_string(p->rnb_levels) + "P" + std::to_string(p->precision) + "C" +
+                    std::to_string(p->criterion) + "F" +
                     std::to_string(p->flags) + "l";
     for (int l = 0; l < p->n_levels; ++l) k += std::to_string(p->level_counts[l]) + ",";
     return k;
@@ -854,7 +859,8 @@ int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_param
         for (const SecPlan& s : lv) maxcap = std::max(maxcap, s.cap);
     const std::string tkey = "gfx950:rhseg:B" + std::to_string(bucket(B)) + ":R" + std::to_string(bucket(maxcap)) +
                              ":n" + std::to_string(bucket((int64_t)pl.lv[L - 1].size())) + ":P" +
-                             std::to_string(p->precision) + ":k" + std::to_string(bucket(p->spclust_max + 1));
+                             std::to_string(p->precision) + ":C" + std::to_string(p->criterion) + ":k" +
+                             std::to_string(bucket(p->spclust_max + 1));
     ExecOut eo;
     rc = execute(ups, seq, key, tkey, p->flags, stream, lay.counters, stats != nullptr, eo);
     if (rc) return rc;
@@ -911,6 +917,7 @@ BatchLayout carve_batch(int n, const hswo_section* sec, const hswo_params* p, vo
         s.top = 1;
         s.log_base = 0;
         s.tiles = (int32_t)tiles;
+        s.crit = p->criterion;
         s.label = bp.take<int32_t>(cap);
         s.npix = bp.take<int32_t>(cap);
         s.mark = bp.take<int32_t>(cap);
@@ -930,13 +937,12 @@ BatchLayout carve_batch(int n, const hswo_section* sec, const hswo_params* p, vo
             const int64_t rc = std::min<int64_t>(cap, p->spclust_max);
             s.rcap = (int32_t)rc;
             s.m64 = bp.take<double>(rc * q.B);
-        s.m64r = bp.take<double>(rc * (((int64_t)q.B + 7) / 8 * 8));
+            s.m64r = bp.take<double>(rc * (((int64_t)q.B + 7) / 8 * 8));
+            if (p->criterion == HSWO_CRIT_SAM) s.rq = bp.take<double>(rc);
             s.rbd = bp.take<double>(rc);
             s.rbp = bp.take<int32_t>(rc);
-        s.rbl = bp.take<int32_t>(rc);
             s.rbl = bp.take<int32_t>(rc);
             s.rpend = bp.take<int32_t>(rc);
-        s.rpart = bp.take<RowPart>(rc * ((rc + 63) / 64));
             s.rpart = bp.take<RowPart>(rc * ((rc + 63) / 64));
         } else if (p->precision != HSWO_PREC_FP32 && p->spclust_wght > 0.0f && p->spclust_max > 0) {
             const int64_t kc = std::min<int64_t>(cap, p->spclust_max);
@@ -1046,7 +1052,8 @@ int run_batch(int n, const hswo_section* sec, int dtype, const hswo_params* p, h
                "x" + std::to_string(sec[i].W) + "x" + std::to_string(sec[i].B) + ";";
     const std::string tkey = "gfx950:batch:B" + std::to_string(bucket(lay.max_B)) + ":R" +
                              std::to_string(bucket(lay.max_cap)) + ":n" + std::to_string(bucket(n)) + ":P" +
-                             std::to_string(p->precision) + ":k" + std::to_string(bucket(p->spclust_max + 1));
+                             std::to_string(p->precision) + ":C" + std::to_string(p->criterion) + ":k" +
+                             std::to_string(bucket(p->spclust_max + 1));
     ExecOut eo;
     rc = execute(ups, seq, key, tkey, p->flags, stream, lay.counters, stats != nullptr, eo);
     if (rc) return rc;

@@ -82,12 +82,15 @@ struct SecDev {
     float* cvec;     // [Bp] centring spectrum, fixed when the spectral stage starts
     int32_t kcap;    // rows available for the 16-bit screen (0 on the plain path)
     int32_t rcap;    // rows of the spectral row cache (0 when it is off)
+    int32_t crit;    // HSWO_CRIT_* dissimilarity criterion
     // incremental adjacent stage: exact D2 per edge slot and the edges to refresh
     double* ed2;     // [Ecap]
     int32_t* edirty; // [Ecap]
     // spectral row cache (incremental form), slots [0, rcap):
-    double* m64;     // [B][rcap] FP64 mean spectra S/n, band-major (column j = slot j)
-    double* m64r;    // [rcap][B8] the same means slot-major, B8 = B rounded up to 8
+    double* m64;     // [B][rcap] FP64 mean spectra S/n (spectral angle: the sums S), band-major
+                     //           (column j = slot j)
+    double* m64r;    // [rcap][B8] the same rows slot-major, B8 = B rounded up to 8
+    double* rq;      // [rcap] spectral angle only: |S|^2 of each slot (pairwise tree over the bands)
     double* rbd;     // [rcap] exact D2 of the row's cached pair
     int32_t* rbp;    // [rcap] partner slot of that pair (-1: none or pending)
     int32_t* rbl;    // [rcap] partner label of that pair

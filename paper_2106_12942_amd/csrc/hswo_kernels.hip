@@ -247,6 +247,7 @@ __device__ __forceinline__ float2 screen_bounds(float s, int na, int nb, float N
 
 // Canonical FP64 squared criterion, evaluated by one whole wavefront (all 64
 // lanes must call it with the same arguments; every lane gets the result).
+// With the spectral angle criterion, that criterion's value instead.
 //   fac = (n_i n_j)/(n_i + n_j); d_b = S_ib/n_i - S_jb/n_j; q_b = d_b*d_b;
 //   acc = pairwise tree over b of q_b, zero-padded to a power of two.
 // Lane l holds bands 4l..4l+3 of each 256-band chunk: two in-register levels,
@@ -254,9 +255,65 @@ __device__ __forceinline__ float2 screen_bounds(float s, int na, int nb, float N
 // pair hold the same sum). Chunk sums are parked in LDS and combined by a
 // 16-leaf tree (again butterflies, over lanes 0..15). Zero padding beyond
 // the next power of two only adds +0.0, which is exact.
+// Pairwise tree over the zero-padded band index of x_b * y_b, by one whole
+// wavefront (every lane gets the result): the lane layout of exact_d2_wave,
+// with lane c keeping chunk c's sum for the final 16-leaf tree.
+__device__ double wave_dot_tree(const double* x, const double* y, int B) {
+    const int lane = lane_id();
+    const int nch = (B + 255) >> 8;
+    double u = 0.0;
+    for (int c = 0; c < nch; ++c) {
+        double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
+        const int b = (c << 8) + (lane << 2);
+        if (b + 3 < B) {
+            q0 = x[b] * y[b];
+            q1 = x[b + 1] * y[b + 1];
+            q2 = x[b + 2] * y[b + 2];
+            q3 = x[b + 3] * y[b + 3];
+        } else {
+            if (b < B) q0 = x[b] * y[b];
+            if (b + 1 < B) q1 = x[b + 1] * y[b + 1];
+            if (b + 2 < B) q2 = x[b + 2] * y[b + 2];
+        }
+        double t = (q0 + q1) + (q2 + q3);
+        t = t + __shfl_xor(t, 1);
+        t = t + __shfl_xor(t, 2);
+        t = t + __shfl_xor(t, 4);
+        t = t + __shfl_xor(t, 8);
+        t = t + __shfl_xor(t, 16);
+        t = t + __shfl_xor(t, 32);
+        if (lane == c) u = t;
+    }
+    u = u + __shfl_xor(u, 1);
+    u = u + __shfl_xor(u, 2);
+    u = u + __shfl_xor(u, 4);
+    u = u + __shfl_xor(u, 8);
+    return __shfl(u, 0);
+}
+
+// Spectral angle criterion from the dot product of two band-sum rows and
+// their squared norms: 1 - sign(c) c^2 with c the cosine (sin^2 of the angle
+// up to 90 degrees, rising to 2 at 180); 1 for a zero row; rounding below 0
+// is raised to 0.
+__device__ __forceinline__ double sam_value(double dot, double qi, double qj) {
+    const double den = qi * qj;
+    if (den == 0.0) return 1.0;
+    const double t = (dot * dot) / den;
+    const double d = dot >= 0.0 ? 1.0 - t : 1.0 + t;
+    return d > 0.0 ? d : 0.0;
+}
+
 __device__ double exact_d2_wave(Smem& sh, const SecDev& s, int si, int sj) {
     const int lane = lane_id();
     const int B = s.B;
+    if (s.crit == HSWO_CRIT_SAM) {
+        const double* Xi = s.sums + (size_t)si * B;
+        const double* Xj = s.sums + (size_t)sj * B;
+        const double dot = wave_dot_tree(Xi, Xj, B);
+        const double qi = wave_dot_tree(Xi, Xi, B);
+        const double qj = wave_dot_tree(Xj, Xj, B);
+        return sam_value(dot, qi, qj);
+    }
     const int n_i = s.npix[si], n_j = s.npix[sj];
     const double dni = (double)n_i, dnj = (double)n_j;
     const double* Si = s.sums + (size_t)si * B;
@@ -635,18 +692,28 @@ __device__ __forceinline__ double counter_total(const double (&part)[LV], int ng
     return acc;
 }
 
-// Start the row cache of a section at R live slots: FP64 means of every slot;
-// every row is then pending (state 1).
+// Start the row cache of a section at R live slots: FP64 means of every slot
+// (spectral angle: the sums and their squared norms); every row is then
+// pending (state 1).
 __device__ void rowcache_begin(Smem& sh, const SecDev& s, int R) {
     const int B = s.B;
     const size_t kc = (size_t)s.rcap;
     const int tot = R * B;
     const int B8 = (B + 7) & ~7;
+    const bool sam = s.crit == HSWO_CRIT_SAM;
     for (int x = threadIdx.x; x < tot; x += NT) {
         const int b = x / R, i = x - b * R;
-        const double m = s.sums[(size_t)i * B + b] / (double)s.npix[i];
+        const double v = s.sums[(size_t)i * B + b];
+        const double m = sam ? v : v / (double)s.npix[i];
         s.m64[(size_t)b * kc + i] = m;
         s.m64r[(size_t)i * B8 + b] = m;
+    }
+    if (sam) {
+        for (int i = wave_id(); i < R; i += NWAVE) {
+            const double* Si = s.sums + (size_t)i * B;
+            const double q = wave_dot_tree(Si, Si, B);
+            if (lane_id() == 0) s.rq[i] = q;
+        }
     }
     for (int i = threadIdx.x; i < R; i += NT) {
         s.rbp[i] = -1;
@@ -670,7 +737,10 @@ __device__ void rowcache_begin(Smem& sh, const SecDev& s, int R) {
 // slot-major copy (the same for the whole wavefront). Each row's best
 // candidate among the 64 columns goes to rpart. Pending rows: the first np
 // slots (all) or rpend[0, np). Called by the whole block.
-template <int KR>
+// SAM: the spectral angle criterion (rows hold band sums; the tree adds the
+// products of the two rows and the result is finished with the rows' squared
+// norms).
+template <int KR, bool SAM>
 __device__ void row_block_task(double (*rsum)[4][64], const SecDev& s, int R, int np, bool all, int bq, int c) {
     constexpr int GB = 8;
     constexpr int LV = 7;  // up to 64 groups of 8 bands per wave (4096 bands over 8 waves)
@@ -714,8 +784,12 @@ __device__ void row_block_task(double (*rsum)[4][64], const SecDev& s, int R, in
                 double qv[GB];
 #pragma unroll
                 for (int k = 0; k < GB; ++k) {
-                    const double d = (b0 + k < B) ? mi[k] - cv[k] : 0.0;
-                    qv[k] = d * d;
+                    if (SAM) {
+                        qv[k] = (b0 + k < B) ? mi[k] * cv[k] : 0.0;
+                    } else {
+                        const double d = (b0 + k < B) ? mi[k] - cv[k] : 0.0;
+                        qv[k] = d * d;
+                    }
                 }
 #pragma unroll
                 for (int h = 1; h < GB; h <<= 1)
@@ -740,11 +814,16 @@ __device__ void row_block_task(double (*rsum)[4][64], const SecDev& s, int R, in
             for (int h = 1; h < NWAVE; h <<= 1)
 #pragma unroll
                 for (int k = 0; k < NWAVE; k += 2 * h) v[k] = v[k] + v[k + h];
-            const int n_i = s.npix[i];
-            const int n_j = jv ? s.npix[j] : 1;
-            const double dni = (double)n_i, dnj = (double)n_j;
-            const double fac = (dni * dnj) / (double)(n_i + n_j);
-            double d2 = fac * v[0];
+            double d2;
+            if (SAM) {
+                d2 = sam_value(v[0], s.rq[i], jv ? s.rq[j] : 1.0);
+            } else {
+                const int n_i = s.npix[i];
+                const int n_j = jv ? s.npix[j] : 1;
+                const double dni = (double)n_i, dnj = (double)n_j;
+                const double fac = (dni * dnj) / (double)(n_i + n_j);
+                d2 = fac * v[0];
+            }
             int lab = jv ? s.label[j] : INT_MAX, slot = j;
             if (!jv || j == i) {
                 d2 = __builtin_huge_val();
@@ -782,7 +861,7 @@ __device__ void row_block_task(double (*rsum)[4][64], const SecDev& s, int R, in
 // (fixed subtrees) through a binary counter of LV levels, which is the same
 // perfect binary tree as exact_d2_wave's; the next group's column values are
 // loaded before the current group is added.
-template <int KR, int LV>
+template <int KR, int LV, bool SAM>
 __device__ void row_wave_task(const SecDev& s, int R, int np, bool all, int bq, int c) {
     constexpr int GB = 8;
     const int lane = lane_id();
@@ -799,6 +878,7 @@ __device__ void row_wave_task(const SecDev& s, int R, int np, bool all, int bq, 
         ir[r] = __builtin_amdgcn_readfirstlane(v);
     }
     const int n_j = jv ? s.npix[j] : 1;
+    const double q_j = (SAM && jv) ? s.rq[j] : 1.0;
     const int l_j = jv ? s.label[j] : INT_MAX;
     const double* mj = s.m64 + (jv ? j : 0);
     double part[KR][LV];
@@ -824,8 +904,12 @@ __device__ void row_wave_task(const SecDev& s, int R, int np, bool all, int bq, 
             double qv[GB];
 #pragma unroll
             for (int k = 0; k < GB; ++k) {
-                const double d = (b0 + k < B) ? mi[k] - cv[k] : 0.0;
-                qv[k] = d * d;
+                if (SAM) {
+                    qv[k] = (b0 + k < B) ? mi[k] * cv[k] : 0.0;
+                } else {
+                    const double d = (b0 + k < B) ? mi[k] - cv[k] : 0.0;
+                    qv[k] = d * d;
+                }
             }
 #pragma unroll
             for (int h = 1; h < GB; h <<= 1)
@@ -841,10 +925,15 @@ __device__ void row_wave_task(const SecDev& s, int R, int np, bool all, int bq, 
     for (int r = 0; r < KR; ++r) {
         if (ir[r] < 0) continue;  // wavefront-uniform
         const int i = ir[r];
-        const int n_i = s.npix[i];
-        const double dni = (double)n_i, dnj = (double)n_j;
-        const double fac = (dni * dnj) / (double)(n_i + n_j);
-        double d2 = fac * counter_total<LV>(part[r], ng);
+        double d2;
+        if (SAM) {
+            d2 = sam_value(counter_total<LV>(part[r], ng), s.rq[i], q_j);
+        } else {
+            const int n_i = s.npix[i];
+            const double dni = (double)n_i, dnj = (double)n_j;
+            const double fac = (dni * dnj) / (double)(n_i + n_j);
+            d2 = fac * counter_total<LV>(part[r], ng);
+        }
         int lab = l_j, slot = j;
         if (!jv || j == i) {
             d2 = __builtin_huge_val();
@@ -1019,7 +1108,7 @@ __device__ void merge_stats(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R
         const double v = Slo[b] + Shi[b];
         Slo[b] = v;
         if (rc) {
-            const double m = v / dn;
+            const double m = s.crit == HSWO_CRIT_SAM ? v : v / dn;
             s.m64[(size_t)b * s.rcap + lo_s] = m;
             s.m64r[(size_t)lo_s * ((B + 7) & ~7) + b] = m;
         }
@@ -1033,6 +1122,10 @@ __device__ void merge_stats(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R
         nrm = block_sum_d(sh, nrm);  // contains barriers: all reads of s.npix done
     else
         __syncthreads();  // all reads of s.npix done
+    if (rc && s.crit == HSWO_CRIT_SAM && wave_id() == 1) {  // the survivor's squared norm (sums written above)
+        const double q = wave_dot_tree(Slo, Slo, B);
+        if (lane_id() == 0) s.rq[lo_s] = q;
+    }
     if (g_ready && wave_id() == 0) {  // keep the survivor's 16-bit screen row current
         if (prec == 1)
             row16<1>(s, lo_s);
@@ -1143,6 +1236,7 @@ __device__ void merge_slots(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R
                 s.m64[(size_t)b * kc + hi_s] = s.m64[(size_t)b * kc + last];
                 s.m64r[(size_t)hi_s * B8 + b] = s.m64r[(size_t)last * B8 + b];
             }
+            if (s.crit == HSWO_CRIT_SAM && tid == 0) s.rq[hi_s] = s.rq[last];
         }
         if (g_ready) {
             const uint16_t* Gsrc = s.g16 + (size_t)last * Bp;
@@ -1777,10 +1871,20 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
             // the section has the workgroup to itself: each wavefront takes its own tasks
             const int nch = (R + 63) >> 6;
             const int ntask = row_task_count(R, rows);
-            if (s.B <= 512) {
-                for (int t = wave_id(); t < ntask; t += NWAVE) row_wave_task<4, 7>(s, R, rows, all, t / nch, t % nch);
+            if (s.crit == HSWO_CRIT_SAM) {
+                if (s.B <= 512) {
+                    for (int t = wave_id(); t < ntask; t += NWAVE)
+                        row_wave_task<4, 7, true>(s, R, rows, all, t / nch, t % nch);
+                } else {
+                    for (int t = wave_id(); t < ntask; t += NWAVE)
+                        row_wave_task<4, 10, true>(s, R, rows, all, t / nch, t % nch);
+                }
+            } else if (s.B <= 512) {
+                for (int t = wave_id(); t < ntask; t += NWAVE)
+                    row_wave_task<4, 7, false>(s, R, rows, all, t / nch, t % nch);
             } else {
-                for (int t = wave_id(); t < ntask; t += NWAVE) row_wave_task<4, 10>(s, R, rows, all, t / nch, t % nch);
+                for (int t = wave_id(); t < ntask; t += NWAVE)
+                    row_wave_task<4, 10, false>(s, R, rows, all, t / nch, t % nch);
             }
             __syncthreads();
             M = spectral_min_rows(sh, s, R, rows, all);
@@ -1914,7 +2018,8 @@ __global__ void __launch_bounds__(NT) k_wide_rows(const SecDev* __restrict__ sec
             if (blockIdx.x == 0 && lp.counters) {
                 const unsigned long long pairs = (unsigned long long)np * (unsigned long long)(R - 1);
                 atomicAdd(&lp.counters[C_RECHECKS], pairs);
-                atomicAdd(&lp.counters[C_W_ROWS_FLOPS], 3ull * (unsigned long long)s.B * pairs);
+                const unsigned long long fpb = s.crit == HSWO_CRIT_SAM ? 2ull : 3ull;  // flops per band and pair
+                atomicAdd(&lp.counters[C_W_ROWS_FLOPS], fpb * (unsigned long long)s.B * pairs);
             }
         }
         pre[k + 1] = cnt;
@@ -1939,7 +2044,10 @@ __global__ void __launch_bounds__(NT) k_wide_rows(const SecDev* __restrict__ sec
         const int np = all ? R : s.st[7];
         const int nch = (R + 63) >> 6;
         const int lt = t - pre[lo];
-        row_block_task<4>(rsum, s, R, np, all, lt / nch, lt % nch);
+        if (s.crit == HSWO_CRIT_SAM)
+            row_block_task<4, true>(rsum, s, R, np, all, lt / nch, lt % nch);
+        else
+            row_block_task<4, false>(rsum, s, R, np, all, lt / nch, lt % nch);
     }
 }
 

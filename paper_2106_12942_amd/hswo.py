@@ -33,6 +33,10 @@ HSWO_FLAG_AUTOTUNE = 4
 HSWO_FLAG_INCREMENTAL = 8
 HSWO_FLAG_KERNEL_TIMES = 16
 HSWO_FLAG_SEQUENTIAL_SECTIONS = 32
+
+HSWO_CRIT_BSMSE = 0
+HSWO_CRIT_SAM = 1
+CRIT = {"bsmse": HSWO_CRIT_BSMSE, "sam": HSWO_CRIT_SAM}
 KERNEL_KINDS = ["section_driver", "wide_adj", "wide_decide", "wide_mfma", "wide_fp32", "wide_finish", "wide_rows",
                 "rowcache_prep"]
 
@@ -55,6 +59,7 @@ class Params(ctypes.Structure):
         ("level_counts", ctypes.POINTER(ctypes.c_int32)),
         ("precision", ctypes.c_int32),
         ("flags", ctypes.c_int32),
+        ("criterion", ctypes.c_int32),
     ]
 
 
@@ -145,7 +150,7 @@ def last_error() -> str:
 def make_params(*, connectivity=4, seam_connectivity=8, spclust_wght=0.0, spclust_max=0, target_regions=1,
                 section_regions=0, rnb_levels=1, level_counts: Optional[Sequence[int]] = None,
                 precision="fp32", merge_log=False, graph=False, autotune=False, incremental=False,
-                kernel_times=False, sequential=False, **_ignored):
+                kernel_times=False, sequential=False, criterion="bsmse", **_ignored):
     counts = list(level_counts) if level_counts is not None else [target_regions]
     arr = (ctypes.c_int32 * len(counts))(*counts)
     p = Params(connectivity, seam_connectivity, spclust_wght, spclust_max, target_regions, section_regions,
@@ -153,7 +158,8 @@ def make_params(*, connectivity=4, seam_connectivity=8, spclust_wght=0.0, spclus
                PREC[precision] if isinstance(precision, str) else int(precision),
                (HSWO_FLAG_MERGE_LOG if merge_log else 0) | (HSWO_FLAG_GRAPH if graph else 0) |
                (HSWO_FLAG_AUTOTUNE if autotune else 0) | (HSWO_FLAG_INCREMENTAL if incremental else 0) |
-               (HSWO_FLAG_KERNEL_TIMES if kernel_times else 0) | (HSWO_FLAG_SEQUENTIAL_SECTIONS if sequential else 0))
+               (HSWO_FLAG_KERNEL_TIMES if kernel_times else 0) | (HSWO_FLAG_SEQUENTIAL_SECTIONS if sequential else 0),
+               CRIT[criterion] if isinstance(criterion, str) else int(criterion))
     p._counts_keepalive = arr  # the struct holds a raw pointer into arr
     return p
 

@@ -36,7 +36,7 @@ def test_version_and_empty_error():
 
 
 def test_struct_layouts_match_header():
-    assert ctypes.sizeof(hswo.Params) == 48
+    assert ctypes.sizeof(hswo.Params) == 56
     assert hswo.MERGE_DTYPE.itemsize == 24
     assert ctypes.sizeof(hswo.Stats) == 328
 
@@ -72,6 +72,8 @@ def test_workspace_bytes_grows_with_the_problem():
     (dict(level_counts=[8, 1]), "below target"),
     (dict(section_regions=-1), "section_regions"),
     (dict(precision=7), "precision"),
+    (dict(criterion=2), "criterion"),
+    (dict(criterion=-1), "criterion"),
 ])
 def test_invalid_params_rejected_before_device(kw, frag):
     p = dict(BASE)
@@ -164,9 +166,29 @@ def test_python_constants_match_header():
     src = open(HEADER).read()
     defs = dict(re.findall(r"#define\s+(HSWO_\w+)\s+\(?(-?\d+)\)?", src))
     for name in ("HSWO_FLAG_MERGE_LOG", "HSWO_FLAG_GRAPH", "HSWO_FLAG_AUTOTUNE", "HSWO_FLAG_INCREMENTAL",
-                 "HSWO_FLAG_KERNEL_TIMES", "HSWO_FLAG_SEQUENTIAL_SECTIONS", "HSWO_F32", "HSWO_F16", "HSWO_E_INVAL",
+                 "HSWO_FLAG_KERNEL_TIMES", "HSWO_FLAG_SEQUENTIAL_SECTIONS", "HSWO_CRIT_BSMSE", "HSWO_CRIT_SAM",
+                 "HSWO_E_UNSUPPORTED", "HSWO_F32", "HSWO_F16", "HSWO_E_INVAL",
                  "HSWO_E_NOMEM"):
         assert int(defs[name]) == getattr(hswo, name), name
     kinds = sorted((int(v), k) for k, v in defs.items() if k.startswith("HSWO_K_"))
     assert [k for _, k in kinds] == ["HSWO_K_" + n.upper() for n in hswo.KERNEL_KINDS]
     assert int(defs["HSWO_NK"]) == len(hswo.KERNEL_KINDS)
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(precision="bf16"), dict(sequential=True)])
+def test_spectral_angle_needs_the_incremental_form(kw):
+    lib = hswo.load()
+    p = hswo.make_params(**BASE, criterion="sam", **kw)
+    assert hswo.workspace_bytes(16, 16, 4, 0, p) == 0
+    rc = lib.hswo_run(FAKE, 16, 16, 4, 0, ctypes.byref(p), FAKE, None, None, FAKE, 1 << 30, None)
+    assert rc == hswo.HSWO_E_UNSUPPORTED
+    assert "INCREMENTAL" in hswo.last_error()
+    secs = (hswo.Section * 1)(hswo.Section(FAKE, 8, 8, 4, FAKE, None))
+    assert lib.hswo_run_batch(1, secs, 0, ctypes.byref(p), None, FAKE, 1 << 30, None) == hswo.HSWO_E_UNSUPPORTED
+
+
+def test_spectral_angle_workspace_adds_the_norm_rows():
+    q = hswo.make_params(**BASE, incremental=True)
+    p = hswo.make_params(**BASE, incremental=True, criterion="sam")
+    a, b = hswo.workspace_bytes(64, 64, 32, 0, q), hswo.workspace_bytes(64, 64, 32, 0, p)
+    assert 0 < a < b
