@@ -150,8 +150,12 @@ class Pass {
         int R = (int)live_.size();
         if (top_) snapshot_levels_at_start(R);
         if (!p_.brute) init_cache();
+        if (p_.two_merges) {
+            run_two_merges(log, R);
+            return;
+        }
         while (R > stop_) {
-            const bool spectral = p_.spclust_wght > 0.0f && R <= p_.spclust_max;
+            const bool spectral = spectral_at(R);
             Key A, N = KEY_NONE;
             if (p_.brute) {
                 A = brute_adjacent();
@@ -183,6 +187,44 @@ class Pass {
     }
 
   private:
+    bool spectral_at(int R) const { return p_.spclust_wght > 0.0f && R <= p_.spclust_max; }
+    Key adjacent_min() { return p_.brute ? brute_adjacent() : cached_adjacent(); }
+    Key nonadjacent_min() {
+        if (p_.brute) return brute_nonadjacent();
+        if (!dense_on_) init_dense();
+        return cached_nonadjacent();
+    }
+    void record(const Key& k, int kind, int& R, std::vector<oracle_merge>& log) {
+        merge(k.lo, k.hi);
+        --R;
+        log.push_back({k.lo, k.hi, kind, R, k.d2});
+        if (top_) snapshot_if_level(R);
+    }
+
+    /* The step list of Section 4.1 read with two merges per iteration: step 2
+       merges the best adjacent pair A; step 3 then takes the best
+       non-adjacent pair N of the partition that step 2 left (when the
+       spectral stage is on at its region count) and merges it too iff it is
+       below w^2 times A's value. Step 3 is skipped once step 2 has reached
+       the stop count. Without any adjacent pair, the iteration falls back to
+       the one-merge rule (N merged if it exists). */
+    void run_two_merges(std::vector<oracle_merge>& log, int R) {
+        while (R > stop_) {
+            const Key A = adjacent_min();
+            if (!key_exists(A)) {
+                if (!spectral_at(R)) break;
+                const Key N = nonadjacent_min();
+                if (!key_exists(N)) break;
+                record(N, 1, R, log);
+                continue;
+            }
+            record(A, 0, R, log);
+            if (R <= stop_ || !spectral_at(R)) continue;
+            const Key N = nonadjacent_min();
+            if (key_exists(N) && A.d2 * w2_ > N.d2) record(N, 1, R, log);  // strict, as in one-merge mode
+        }
+    }
+
     double d2(int a, int b) {
         const int lo = std::min(a, b), hi = std::max(a, b);
         return pair_value(p_.criterion, st_.Sp(lo), st_.Sp(hi), st_.n[lo], st_.n[hi], st_.B);

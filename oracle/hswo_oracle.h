@@ -24,7 +24,9 @@
  *   the squared weight are the same as for Equation 1.
  *
  * Readings taken where the paper is silent:
- *   one merge per iteration; the non-adjacent pair wins iff
+ *   one merge per iteration (two_merges selects the other reading of the
+ *   step list: step 2's adjacent merge, then step 3's non-adjacent merge on
+ *   the partition it left); the non-adjacent pair wins iff
  *   D2_na < w^2 * D2_adj (strict); spectral stage active iff w > 0 and
  *   R <= spclust_max; ties broken lexicographically on (D2, lo, hi) where
  *   lo < hi are region labels; a region's label is its smallest row-major
@@ -53,6 +55,9 @@ typedef struct oracle_params {
     int32_t brute;              /* 1: recompute every pair every iteration */
     int32_t n_threads;          /* worker threads over independent sections */
     int32_t criterion;          /* ORACLE_CRIT_BSMSE (Equation 1) or ORACLE_CRIT_SAM */
+    int32_t two_merges;         /* 1: each iteration merges the best adjacent pair (step 2), then the
+                                   best non-adjacent pair of the result if it is below w^2 times the
+                                   first merge's value (step 3); 0: one merge per iteration */
 } oracle_params;
 
 #define ORACLE_CRIT_BSMSE 0 /* Equation 1, ranked on its square D2 */

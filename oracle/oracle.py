@@ -30,6 +30,7 @@ class _Params(ctypes.Structure):
         ("brute", ctypes.c_int32),
         ("n_threads", ctypes.c_int32),
         ("criterion", ctypes.c_int32),
+        ("two_merges", ctypes.c_int32),
     ]
 
 
@@ -109,7 +110,7 @@ def rhseg(cube: np.ndarray, *, connectivity: int = 4, seam_connectivity: int = 8
           section_regions: int = 0, rnb_levels: int = 1,
           level_counts: Optional[Sequence[int]] = None, brute: bool = False,
           n_threads: Optional[int] = None, lib: Optional[str] = None, criterion: str = "bsmse",
-          **_ignored) -> OracleResult:
+          two_merges: bool = False, **_ignored) -> OracleResult:
     """Run the oracle on a host H x W x B cube (float32, or float16 widened exactly)."""
     cube = np.asarray(cube)
     if cube.dtype == np.float16:
@@ -132,6 +133,7 @@ def rhseg(cube: np.ndarray, *, connectivity: int = 4, seam_connectivity: int = 8
     p.brute = 1 if brute else 0
     p.n_threads = n_threads if n_threads is not None else (os.cpu_count() or 1)
     p.criterion = CRITERIA[criterion]
+    p.two_merges = 1 if two_merges else 0
     labels = np.full((len(lc), H, W), -1, dtype=np.int32)
     log = np.zeros(H * W, dtype=MERGE_DTYPE)
     n_log = ctypes.c_int64(0)

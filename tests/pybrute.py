@@ -17,6 +17,9 @@ the band index zero-padded to a power of two, then the size factor).
 ``criterion="sam"`` ranks on the spectral angle instead, as 1 - sign(c) c^2
 with c the cosine between the regions' band-sum vectors (rational when
 exact; otherwise dot product and squared norms as pairwise trees).
+``two_merges=True`` reads the step list with two merges per iteration: the
+best adjacent pair, then the best non-adjacent pair of the resulting
+partition if it is below w^2 times the first merge's value.
 """
 from __future__ import annotations
 
@@ -104,7 +107,7 @@ def _criterion(xs_i, xs_j, exact, crit="bsmse"):
     return fac * acc
 
 
-def _hseg_pass(cube, lab, rect, leaf, conn, seam, w, kmax, stop, log, snaps, counts, top, crit):
+def _hseg_pass(cube, lab, rect, leaf, conn, seam, w, kmax, stop, log, snaps, counts, top, crit, two=False):
     r0, c0, h, wd = rect
     H = len(cube)
     W = len(cube[0])
@@ -144,7 +147,54 @@ def _hseg_pass(cube, lab, rect, leaf, conn, seam, w, kmax, stop, log, snaps, cou
         for li, cnt in enumerate(counts):
             if cnt >= R:
                 snaps[li] = [row[:] for row in lab]
-    while R > stop:
+    def best_pairs(spectral):
+        reg = regions()
+        adj = adjacency()
+        labels = sorted(reg)
+        A = None
+        N = None
+        for i_idx, i in enumerate(labels):
+            for j in labels[i_idx + 1:]:
+                isadj = (i, j) in adj
+                if not isadj and not spectral:
+                    continue
+                key = (_criterion(reg[i], reg[j], log.exact, crit), i, j)
+                if isadj:
+                    A = key if A is None or key < A else A
+                else:
+                    N = key if N is None or key < N else N
+        return A, N
+
+    def apply(win, kind):
+        _, lo, hi = win
+        for (r, c) in pix:
+            if lab[r][c] == hi:
+                lab[r][c] = lo
+        log.append((lo, hi, kind, len(regions()), win[0]))
+        if top:
+            snap(len(regions()))
+
+    def below(N, A):
+        return N[0] < (w2 * A[0] if not log.exact else Fraction(w) ** 2 * A[0])
+
+    while two and R > stop:
+        # step 2: the best adjacent pair; step 3 on the partition it leaves
+        A, N = best_pairs(w > 0 and R <= kmax)
+        if A is None:
+            if N is None or not (w > 0 and R <= kmax):
+                break
+            apply(N, 1)
+            R -= 1
+            continue
+        apply(A, 0)
+        R -= 1
+        if R <= stop or not (w > 0 and R <= kmax):
+            continue
+        _, N = best_pairs(True)
+        if N is not None and below(N, A):
+            apply(N, 1)
+            R -= 1
+    while not two and R > stop:
         reg = regions()
         adj = adjacency()
         labels = sorted(reg)
@@ -186,7 +236,7 @@ class _Log(list):
 
 def rhseg(cube, *, connectivity=4, seam_connectivity=8, spclust_wght=0.0, spclust_max=0,
           target_regions=1, section_regions=0, rnb_levels=1, level_counts=None, exact=False, criterion="bsmse",
-          **_):
+          two_merges=False, **_):
     """cube: nested lists or an array H x W x B. Returns (labels per level, log)."""
     cube = [[[float(v) for v in px] for px in row] for row in (cube.tolist() if hasattr(cube, "tolist") else cube)]
     H, W = len(cube), len(cube[0])
@@ -205,5 +255,5 @@ def rhseg(cube, *, connectivity=4, seam_connectivity=8, spclust_wght=0.0, spclus
         top = d == 0
         for rect in levels[d]:
             _hseg_pass(cube, lab, rect, leaf, connectivity, seam_connectivity, spclust_wght,
-                       spclust_max, target_regions if top else S, log, snaps, counts, top, criterion)
+                       spclust_max, target_regions if top else S, log, snaps, counts, top, criterion, two_merges)
     return snaps, list(log)

@@ -52,6 +52,47 @@ SAM_MUTANTS = {
 }
 
 
+TWO_MERGE_MUTANTS = {
+    "two_step3_vs_current_adjacent": ("if (key_exists(N) && A.d2 * w2_ > N.d2)",
+                                      "if (key_exists(N) && adjacent_min().d2 * w2_ > N.d2)"),
+    "two_step3_not_strict": ("if (key_exists(N) && A.d2 * w2_ > N.d2)", "if (key_exists(N) && A.d2 * w2_ >= N.d2)"),
+    "two_no_stop_check": ("if (R <= stop_ || !spectral_at(R)) continue;", "if (!spectral_at(R)) continue;"),
+    "two_spectral_on_count_before": ("if (R <= stop_ || !spectral_at(R)) continue;",
+                                     "if (R <= stop_ || !spectral_at(R + 1)) continue;"),
+    "two_step3_skipped": ("record(N, 1, R, log);  // strict", "(void)N;  // strict"),
+}
+
+
+def _run_two_merge_pins(lib):
+    """The two-merge pins in compact form; returns the first that fails."""
+    from tests import test_oracle_two_merges as t2
+    for w, want in ((1.0, [(1, 2, 0, 3), (0, 3, 1, 2), (0, 1, 0, 1)]), (0.5, [(1, 2, 0, 3), (1, 3, 0, 2), (0, 1, 0, 1)])):
+        res = oracle.rhseg(t2.ROW, connectivity=4, spclust_wght=w, spclust_max=10, target_regions=1,
+                           level_counts=[1], two_merges=True, lib=lib)
+        if [g[:4] for g in t2.recs(res)] != want:
+            return "hand case"
+    for kmax, target, want in ((3, 1, [(1, 2, 0, 3), (0, 3, 1, 2), (0, 1, 0, 1)]), (10, 3, [(1, 2, 0, 3)])):
+        res = oracle.rhseg(t2.ROW, connectivity=4, spclust_wght=1.0, spclust_max=kmax, target_regions=target,
+                           level_counts=[target], two_merges=True, lib=lib)
+        if [g[:4] for g in t2.recs(res)] != want:
+            return "hand case boundaries"
+    for t in range(8):
+        p = t2.GRID[t % len(t2.GRID)]
+        H, W = 4 + t % 3, 5 + t % 2
+        cube = synth.random_cube(H, W, 1 + t % 4, seed=80 + t, kind="continuous" if t % 3 else "integer")
+        counts = sorted({max(2, H * W // 2), max(2, H * W // 4), 2}, reverse=True)
+        kw = dict(p, target_regions=2, level_counts=counts, two_merges=True)
+        res = oracle.rhseg(cube, **kw, lib=lib)
+        try:
+            check_partition_levels(res.labels, counts)
+        except AssertionError:
+            return "partition"
+        _, log = pybrute.rhseg(cube, **kw)
+        if t2.recs(res) != [tuple(x) for x in log]:
+            return "python hseg"
+    return None
+
+
 def _run_sam_pins(lib):
     """The spectral angle pins in compact form; returns the first that fails."""
     from tests.test_oracle_sam import GRID
@@ -150,3 +191,18 @@ def test_sam_pins_reject_mutant(name, tmp_path):
     path.write_text(src.replace(old, new))
     lib = oracle.build(src=str(path), out=str(tmp_path / f"liboracle_{name}.so"))
     assert _run_sam_pins(lib) is not None, f"mutant {name} survived every pin"
+
+
+def test_unmutated_oracle_passes_the_two_merge_pins():
+    assert _run_two_merge_pins(None) is None
+
+
+@pytest.mark.parametrize("name", sorted(TWO_MERGE_MUTANTS))
+def test_two_merge_pins_reject_mutant(name, tmp_path):
+    old, new = TWO_MERGE_MUTANTS[name]
+    src = open(_SRC).read()
+    assert src.count(old) == 1, f"mutation site for {name} not found exactly once"
+    path = tmp_path / "mutant.cpp"
+    path.write_text(src.replace(old, new))
+    lib = oracle.build(src=str(path), out=str(tmp_path / f"liboracle_{name}.so"))
+    assert _run_two_merge_pins(lib) is not None, f"mutant {name} survived every pin"
