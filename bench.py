@@ -27,7 +27,8 @@ replayed from a hipGraph. The other forms run once on the same input for the com
 must give the same labels.
 
 Criterion (--criterion): "bsmse" (default), the paper's Equation 1; "sam",
-the spectral angle (incremental form only, so no other form is compared).
+the spectral angle. --two-merges: the two-merge reading of the HSEG steps.
+Both exist in the incremental form only, so no other form is compared.
 
 Output: one JSON line. `value` is dissimilarity pairs per second: the
 method's pairs (live adjacent pairs, plus R(R-1)/2 per iteration of the
@@ -155,6 +156,15 @@ def form_kwargs(form, precision):
     return dict(precision=precision, incremental=True)
 
 
+def variant_kwargs(args):
+    return dict(criterion=args.criterion, two_merges=args.two_merges)
+
+
+def variant_tag(args):
+    """"" for the paper's method; else a suffix naming the criterion / reading."""
+    return ("" if args.criterion == "bsmse" else f"_{args.criterion}") + ("_two" if args.two_merges else "")
+
+
 def timed_steps(step, stream, torch, steps, warmup):
     with torch.cuda.stream(stream):
         for _ in range(warmup):
@@ -175,7 +185,7 @@ def timed_steps(step, stream, torch, steps, warmup):
 
 def bench_rhseg(args, np, torch, hswo, synth):
     sc, params = synth.workload(args.workload)
-    params["criterion"] = args.criterion
+    params.update(variant_kwargs(args))
     cube_h = sc.cube
     H, W, B = cube_h.shape
     dev = torch.device("cuda:0")
@@ -205,11 +215,12 @@ def bench_rhseg(args, np, torch, hswo, synth):
         "wall_ms_median": statistics.median(walls), "wall_ms_min": min(walls), "wall_ms_max": max(walls),
         "config": {"workload": args.workload, "desc": WORKLOAD_DESC[args.workload], "H": H, "W": W, "B": B,
                    "form": args.form, "precision": fk["precision"], "criterion": args.criterion,
-                   "graph": args.graph, "autotune": args.autotune, "driver_variant": st["driver_variant"]},
+                   "two_merges": args.two_merges, "graph": args.graph, "autotune": args.autotune,
+                   "driver_variant": st["driver_variant"]},
         "pairs_per_step": pairs, "merges_per_step": st["merges"], "exact_evaluations_per_step": st["exact_rechecks"],
         "fp32_tiles_per_step": st["fp32_tiles"], "mfma_super_tiles_per_step": st["mfma_tiles"],
     }
-    tag = f"{args.workload}_{args.form}" + ("" if args.criterion == "bsmse" else f"_{args.criterion}")
+    tag = f"{args.workload}_{args.form}" + variant_tag(args)
     # per-kernel device times: one more step of the timed form, eager, every launch bracketed by hipEvents
     same_kt = None
     if not args.no_kernel_times:
@@ -223,8 +234,8 @@ def bench_rhseg(args, np, torch, hswo, synth):
     for form in ("plain", "plain_batched", "screened", "incremental"):
         if form == args.form or (form.startswith("plain") and args.no_plain) or args.no_forms:
             continue
-        if args.criterion != "bsmse" and form != "incremental":
-            continue  # the other criteria exist in the incremental form only
+        if variant_tag(args) and form != "incremental":
+            continue  # the other criterion and the two-merge reading exist in the incremental form only
         o = torch.empty_like(labels)
         # the unbatched plain path is a long launch sequence: eager, one warm-up and one timed call
         ms, _, r = timed_steps(runner(form, o, args.graph and form != "plain"), stream, torch, 1, 1)
@@ -263,8 +274,8 @@ def bench_batch(args, np, torch, hswo, synth):
     secs = synth.batch_sections(256)
     params = dict(synth.BATCH_PARAMS)
     params.pop("rnb_levels", None)
-    params["criterion"] = args.criterion
-    other_forms = not args.no_forms and args.criterion == "bsmse"  # other criteria: incremental form only
+    params.update(variant_kwargs(args))
+    other_forms = not args.no_forms and not variant_tag(args)  # the variants: incremental form only
     dev = torch.device("cuda:0")
     dc = [torch.from_numpy(c).to(dev) for c, _ in secs]
     stream = torch.cuda.Stream(dev)
@@ -294,7 +305,8 @@ def bench_batch(args, np, torch, hswo, synth):
         "wall_ms_median": statistics.median(walls), "wall_ms_min": min(walls), "wall_ms_max": max(walls),
         "config": {"workload": "batch256", "desc": WORKLOAD_DESC["batch256"], "sections": len(secs),
                    "form": args.form, "precision": fk["precision"], "criterion": args.criterion,
-                   "graph": args.graph, "autotune": args.autotune, "driver_variant": st["driver_variant"]},
+                   "two_merges": args.two_merges, "graph": args.graph, "autotune": args.autotune,
+                   "driver_variant": st["driver_variant"]},
         "pairs_per_step": pairs, "merges_per_step": st["merges"], "exact_evaluations_per_step": st["exact_rechecks"],
     }
     if not args.no_kernel_times:
@@ -302,8 +314,7 @@ def bench_batch(args, np, torch, hswo, synth):
         _, _, rk = timed_steps(runner(args.form, ko, False, kernel_times=True), stream, torch, 1, 0)
         out["kernel_times_step_ms"] = rk.stats["ms_total"]
         # the band count varies by section: the roofline uses the mean
-        out["roofline"] = kernel_roofline(rk.stats, Bmean, f"batch256_{args.form}" +
-                                          ("" if args.criterion == "bsmse" else f"_{args.criterion}"))
+        out["roofline"] = kernel_roofline(rk.stats, Bmean, f"batch256_{args.form}" + variant_tag(args))
     comparisons = {}
     if not args.no_plain and other_forms:
         # the plain path: 256 sequential hswo_run calls, FP32 screen, every pair each iteration
@@ -432,6 +443,8 @@ def main():
                     help="matrix-core screen precision of the screened form")
     ap.add_argument("--criterion", default="bsmse", choices=["bsmse", "sam"],
                     help="dissimilarity: Equation 1 (bsmse) or the spectral angle (sam, incremental form only)")
+    ap.add_argument("--two-merges", action="store_true",
+                    help="two-merge reading of the HSEG steps (incremental form only)")
     ap.add_argument("--no-graph", dest="graph", action="store_false", help="launch eagerly instead of a hipGraph")
     ap.add_argument("--autotune", action="store_true", help="autotune the section-driver variant first")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 comparison run")
@@ -445,8 +458,8 @@ def main():
                     help="only copy this many bytes device to device (3 times) and exit: the known-size "
                          "reference for the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
-    if args.criterion != "bsmse" and args.form != "incremental":
-        ap.error("--criterion sam is implemented in the incremental form only")
+    if (args.criterion != "bsmse" or args.two_merges) and args.form != "incremental":
+        ap.error("--criterion sam and --two-merges are implemented in the incremental form only")
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -118,6 +118,12 @@ extern "C" {
 #define HSWO_FLAG_SEQUENTIAL_SECTIONS 32 /* run the sections of a level one after another, each
                                              with the whole device (the unbatched path, for
                                              comparison); same merges and labels */
+#define HSWO_FLAG_TWO_MERGES 64 /* the other reading of the HSEG step list (Section 4.1): each iteration
+                                    merges the least adjacent pair (step 2), then -- when the spectral
+                                    stage is on at the count that merge left and the stop count is not
+                                    reached -- the least NON-adjacent pair of the resulting partition
+                                    if its D2 < w^2 * D2 of step 2's pair (step 3). Changes the result.
+                                    HSWO_FLAG_INCREMENTAL form only (else HSWO_E_UNSUPPORTED). */
 #define HSWO_FLAG_AUTOTUNE 4  /* on the first call for a shape bucket, time every section-driver
                                  variant on the call itself (all give identical results) and keep
                                  the fastest; the choice is cached per process and appended to the

@@ -97,6 +97,8 @@ int validate_params(const hswo_params* p, int rnb_levels_expected) {
         return fail(HSWO_E_INVAL, "unknown precision %d", p->precision);
     if (p->criterion != HSWO_CRIT_BSMSE && p->criterion != HSWO_CRIT_SAM)
         return fail(HSWO_E_INVAL, "unknown criterion %d", p->criterion);
+    if ((p->flags & HSWO_FLAG_TWO_MERGES) && !(p->flags & HSWO_FLAG_INCREMENTAL))
+        return fail(HSWO_E_UNSUPPORTED, "HSWO_FLAG_TWO_MERGES is implemented in the HSWO_FLAG_INCREMENTAL form only");
     if (p->criterion == HSWO_CRIT_SAM && !(p->flags & HSWO_FLAG_INCREMENTAL))
         return fail(HSWO_E_UNSUPPORTED, "criterion HSWO_CRIT_SAM is implemented in the HSWO_FLAG_INCREMENTAL form only");
     return HSWO_OK;
@@ -274,6 +276,7 @@ Layout carve(const Plan& pl, int H, int W, const hswo_params* p, void* ws, const
                 s.m64 = bp.take<double>(rc * pl.B);
                 s.m64r = bp.take<double>(rc * (((int64_t)pl.B + 7) / 8 * 8));
                 if (p->criterion == HSWO_CRIT_SAM) s.rq = bp.take<double>(rc);
+                if (p->flags & HSWO_FLAG_TWO_MERGES) s.abit = bp.take<uint32_t>(rc * ((rc + 31) / 32));
                 s.rbd = bp.take<double>(rc);
                 s.rbp = bp.take<int32_t>(rc);
                 s.rbl = bp.take<int32_t>(rc);
@@ -437,6 +440,9 @@ int run_level(Timer* tm, const SecDev* secs, int n, const std::vector<int64_t>& 
     }
     int64_t iters = 0;
     for (int i = 0; i < n; ++i) iters = std::max(iters, r0[i] - std::min(r0[i], stop[i]));
+    // two-merge reading: a launch makes at most one merge, and a step 3 without a pair below its
+    // threshold makes none; step 3 follows a step-2 merge (or starts the level, after the driver)
+    if (lp.two_merges) iters = 2 * iters + 1;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (tm) {
         HIP_TRY(hipEventCreate(&e0));
@@ -449,11 +455,16 @@ int run_level(Timer* tm, const SecDev* secs, int n, const std::vector<int64_t>& 
     if (row_cache) HIP_TRY(launch_rowcache_prep(secs, n, lp, stream, kt));
     for (int64_t t = 0; t < iters; ++t) {
         bool spec = false;
-        if (lp.spectral)
+        if (lp.spectral && lp.two_merges) {
+            // R after t launches lies in [r0 - t, r0 - t / 2]
+            for (int i = 0; i < n && !spec; ++i)
+                spec = r0[i] - t / 2 > stop[i] && r0[i] - t <= lp.kmax;
+        } else if (lp.spectral) {
             for (int i = 0; i < n && !spec; ++i) {
                 const int64_t R = r0[i] - t;
                 spec = R > stop[i] && R <= lp.kmax;
             }
+        }
         HIP_TRY(launch_wide_iteration(secs, n, G, lp, variant, spec, row_cache, stream, kt));
     }
     if (tm) HIP_TRY(hipEventRecord(e1, stream));
@@ -753,6 +764,7 @@ LoopParams loop_params(const hswo_params* p, unsigned long long* counters) {
     lp.precision = p->precision;
     lp.incremental = (p->flags & HSWO_FLAG_INCREMENTAL) ? 1 : 0;
     lp.phase_stop = 0;
+    lp.two_merges = (p->flags & HSWO_FLAG_TWO_MERGES) ? 1 : 0;
     lp.counters = counters;
     return lp;
 }
@@ -761,7 +773,7 @@ int check_common(const hswo_params* p, void* workspace) {
     if (!workspace) return fail(HSWO_E_INVAL, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(HSWO_E_INVAL, "workspace must be 256-byte aligned");
     if (p->flags & ~(HSWO_FLAG_MERGE_LOG | HSWO_FLAG_GRAPH | HSWO_FLAG_AUTOTUNE | HSWO_FLAG_INCREMENTAL |
-                     HSWO_FLAG_KERNEL_TIMES | HSWO_FLAG_SEQUENTIAL_SECTIONS))
+                     HSWO_FLAG_KERNEL_TIMES | HSWO_FLAG_SEQUENTIAL_SECTIONS | HSWO_FLAG_TWO_MERGES))
         return fail(HSWO_E_INVAL, "unknown flags 0x%x", p->flags);
     return HSWO_OK;
 }
@@ -939,6 +951,7 @@ BatchLayout carve_batch(int n, const hswo_section* sec, const hswo_params* p, vo
             s.m64 = bp.take<double>(rc * q.B);
             s.m64r = bp.take<double>(rc * (((int64_t)q.B + 7) / 8 * 8));
             if (p->criterion == HSWO_CRIT_SAM) s.rq = bp.take<double>(rc);
+            if (p->flags & HSWO_FLAG_TWO_MERGES) s.abit = bp.take<uint32_t>(rc * ((rc + 31) / 32));
             s.rbd = bp.take<double>(rc);
             s.rbp = bp.take<int32_t>(rc);
             s.rbl = bp.take<int32_t>(rc);

@@ -91,6 +91,7 @@ struct SecDev {
                      //           (column j = slot j)
     double* m64r;    // [rcap][B8] the same rows slot-major, B8 = B rounded up to 8
     double* rq;      // [rcap] spectral angle only: |S|^2 of each slot (pairwise tree over the bands)
+    uint32_t* abit;  // [rcap][ceil(rcap / 32)] two-merge reading only: adjacency bitmap of the live slots
     double* rbd;     // [rcap] exact D2 of the row's cached pair
     int32_t* rbp;    // [rcap] partner slot of that pair (-1: none or pending)
     int32_t* rbl;    // [rcap] partner label of that pair
@@ -105,7 +106,8 @@ struct SecDev {
                      //        [6] row cache: 0 off, 1 means ready (every row pending), 2 valid,
                      //        [7] pending rows of the row cache,
                      //        [8] incremental form: next adjacent minimum cached (wd[2], wi[8..11]),
-                     //        [9] empty edge slots left by incremental merges
+                     //        [9] empty edge slots left by incremental merges,
+                     //        [10] two-merge reading: step 3 due (threshold in wd[3])
     int32_t* parent; // label-indexed union-find parent (image or batch section)
     int32_t* mtime;  // label-indexed merge time: -1 non-top merge, k top merge, INT_MAX alive
     hswo_merge_rec* log;  // section merge log base (may be null)
@@ -148,6 +150,7 @@ struct LoopParams {
     int32_t precision;
     int32_t incremental;  // adjacent minimum from cached exact per-edge D2 (only changed edges re-scored)
     int32_t phase_stop;   // section driver: also stop at this region count (0: the pass's stop only)
+    int32_t two_merges;   // two-merge reading of the step list (adjacent merge, then non-adjacent merge)
     unsigned long long* counters;  // [C_COUNT]
 };
 

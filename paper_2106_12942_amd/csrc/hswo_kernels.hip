@@ -692,10 +692,34 @@ __device__ __forceinline__ double counter_total(const double (&part)[LV], int ng
     return acc;
 }
 
+// Adjacency bitmap of the live slots (two-merge reading: its spectral step
+// takes the least NON-adjacent pair, so the row evaluations are masked):
+// row i holds bit j iff slots i and j share an edge. Rebuilt from the edge
+// list (empty slots skipped) by the whole block.
+__device__ void abit_build(const SecDev& s, int R, int E) {
+    const int AW = (s.rcap + 31) >> 5;
+    const int nw = R * AW;
+    for (int x = threadIdx.x; x < nw; x += NT) s.abit[x] = 0u;
+    __syncthreads();
+    for (int e = threadIdx.x; e < E; e += NT) {
+        const int2 ed = s.edges[e];
+        if (ed.x >= 0) {
+            atomicOr(&s.abit[(size_t)ed.x * AW + (ed.y >> 5)], 1u << (ed.y & 31));
+            atomicOr(&s.abit[(size_t)ed.y * AW + (ed.x >> 5)], 1u << (ed.x & 31));
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ bool abit_test(const SecDev& s, int i, int j) {
+    const int AW = (s.rcap + 31) >> 5;
+    return (s.abit[(size_t)i * AW + (j >> 5)] >> (j & 31)) & 1u;
+}
+
 // Start the row cache of a section at R live slots: FP64 means of every slot
 // (spectral angle: the sums and their squared norms); every row is then
 // pending (state 1).
-__device__ void rowcache_begin(Smem& sh, const SecDev& s, int R) {
+__device__ void rowcache_begin(Smem& sh, const SecDev& s, int R, int E) {
     const int B = s.B;
     const size_t kc = (size_t)s.rcap;
     const int tot = R * B;
@@ -720,6 +744,7 @@ __device__ void rowcache_begin(Smem& sh, const SecDev& s, int R) {
         s.rbd[i] = __builtin_huge_val();
     }
     __syncthreads();
+    if (s.abit) abit_build(s, R, E);
     if (threadIdx.x == 0) {
         s.st[6] = 1;
         s.st[7] = 0;
@@ -825,7 +850,7 @@ __device__ void row_block_task(double (*rsum)[4][64], const SecDev& s, int R, in
                 d2 = fac * v[0];
             }
             int lab = jv ? s.label[j] : INT_MAX, slot = j;
-            if (!jv || j == i) {
+            if (!jv || j == i || (s.abit && abit_test(s, i, j))) {
                 d2 = __builtin_huge_val();
                 lab = INT_MAX;
                 slot = -1;
@@ -935,7 +960,7 @@ __device__ void row_wave_task(const SecDev& s, int R, int np, bool all, int bq, 
             d2 = fac * counter_total<LV>(part[r], ng);
         }
         int lab = l_j, slot = j;
-        if (!jv || j == i) {
+        if (!jv || j == i || (s.abit && abit_test(s, i, j))) {
             d2 = __builtin_huge_val();
             lab = INT_MAX;
             slot = -1;
@@ -1822,6 +1847,9 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
     int merges = s.st[3];
     bool avalid = false;  // incremental form: the least adjacent key after the last merge is known
     KeyD anext = key_none();
+    // two-merge reading: step 3 (the non-adjacent merge) is due, below thr3
+    int st3 = lp.two_merges ? s.st[10] : 0;
+    double thr3 = st3 ? s.wd[3] : 0.0;
     if (tid == 0) {
         sh.ncand = 0;
         for (int c = 0; c < C_COUNT; ++c) sh.cnt[c] = 0ull;
@@ -1863,7 +1891,7 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
         if (spectral && row_cache) {
             // exact rows: all of them when the cache starts, else the pending ones
             if (rcs == 0) {
-                rowcache_begin(sh, s, R);
+                rowcache_begin(sh, s, R, E);
                 rcs = 1;
             }
             const bool all = rcs == 1;
@@ -1929,7 +1957,20 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
 
         KeyD win;
         int kind;
-        if (!decide(spectral, A, M, T, win, kind)) break;  // no pair left (not in a connected section)
+        bool step2 = false;
+        if (st3) {
+            // two-merge reading, step 3: the least non-adjacent pair, if below w^2 times step 2's value
+            st3 = 0;
+            if (!(key_exists(M) && M.d2 < thr3)) continue;
+            win = M;
+            kind = 1;
+        } else if (lp.two_merges && key_exists(A)) {
+            win = A;  // step 2: the least adjacent pair, whatever the spectral minimum
+            kind = 0;
+            step2 = true;
+        } else if (!decide(spectral, A, M, T, win, kind)) {
+            break;  // no pair left (not in a connected section)
+        }
         CNT_ADD(C_RECHECKS, nchk);
         CNT_ADD(C_ITERS, 1);
         CNT_ADD(C_MERGES, 1);
@@ -1943,9 +1984,14 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
         ++merges;
         --R;
         if (rcs == 2) npend = sh.npend;
+        if (s.abit && rcs) abit_build(s, R, E);
         if (row_cache && rcs == 0 && lp.spectral && R <= lp.kmax && R > s.stop) {
-            rowcache_begin(sh, s, R);  // the spectral stage starts with the next iteration
+            rowcache_begin(sh, s, R, E);  // the spectral stage starts with the next iteration
             rcs = 1;
+        }
+        if (step2 && lp.spectral && R <= lp.kmax && R > s.stop) {
+            st3 = 1;
+            thr3 = lp.w2 * win.d2;
         }
         CNT_ADD(C_T_MERGE, wall_clock64() - tk0);
     }
@@ -1959,6 +2005,10 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
             s.st[7] = npend;
         }
         s.st[8] = 0;  // the driver keeps its adjacent minimum in registers
+        if (lp.two_merges) {
+            s.st[10] = st3;
+            s.wd[3] = thr3;
+        }
         if (lp.counters)
             for (int c = 0; c < C_COUNT; ++c)
                 if (sh.cnt[c]) atomicAdd(&lp.counters[c], sh.cnt[c]);
@@ -2058,7 +2108,7 @@ __global__ void __launch_bounds__(NT) k_rowcache_prep(const SecDev* __restrict__
     const SecDev& s = secs[blockIdx.x];
     const int R = s.st[0];
     if (s.rcap == 0 || R <= s.stop || R > lp.kmax || s.st[6] != 0) return;
-    rowcache_begin(sh, s, R);
+    rowcache_begin(sh, s, R, s.st[1]);
 }
 
 __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ secs, int G, LoopParams lp) {
@@ -2112,7 +2162,31 @@ __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ s
         }
         KeyD win;
         int kind;
-        if (decide(spectral, A, M, T, win, kind)) {
+        bool merge_now, step2 = false;
+        const bool st3 = lp.two_merges && s.st[10];
+        if (st3) {
+            // two-merge reading, step 3: the least non-adjacent pair, if below w^2 times step 2's value
+            merge_now = key_exists(M) && M.d2 < s.wd[3];
+            win = M;
+            kind = 1;
+        } else if (lp.two_merges && key_exists(A)) {
+            merge_now = true;  // step 2: the least adjacent pair, whatever the spectral minimum
+            win = A;
+            kind = 0;
+            step2 = true;
+        } else {
+            merge_now = decide(spectral, A, M, T, win, kind);
+        }
+        __syncthreads();  // every thread has read st[10] and wd[3]
+        if (lp.two_merges && tid == 0) {
+            s.st[10] = (step2 && lp.spectral && R - 1 <= lp.kmax && R - 1 > s.stop) ? 1 : 0;
+            s.wd[3] = step2 ? lp.w2 * win.d2 : 0.0;
+        }
+        if (!merge_now && row_cache && tid == 0) {
+            s.st[6] = rcs;  // the pending rows were folded in above
+            s.st[7] = 0;
+        }
+        if (merge_now) {
             const int stamp = s.st[3];
             decide_bytes += 16ull * (unsigned long long)E + 24ull * (unsigned long long)s.B;
             if (lp.incremental) {
@@ -2134,14 +2208,15 @@ __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ s
                 s.st[1] = E;
                 if (row_cache) s.st[6] = rcs;
             }
+            if (s.abit && rcs) abit_build(s, R - 1, E);
             if (row_cache && rcs == 0 && lp.spectral && R - 1 <= lp.kmax && R - 1 > s.stop)
-                rowcache_begin(sh, s, R - 1);
+                rowcache_begin(sh, s, R - 1, E);
         }
         if (tid == 0) {
             s.wi[0] = 1;
             if (lp.counters) {
                 atomicAdd(&lp.counters[C_ITERS], 1ull);
-                atomicAdd(&lp.counters[C_MERGES], 1ull);
+                if (merge_now) atomicAdd(&lp.counters[C_MERGES], 1ull);
                 atomicAdd(&lp.counters[C_ADJ_PAIRS], (unsigned long long)Elive);
                 atomicAdd(&lp.counters[C_RECHECKS], (unsigned long long)nchk);
                 if (spectral)
@@ -2351,6 +2426,7 @@ __global__ void k_init_leaves(const SecDev* __restrict__ secs, const InitDev* __
         s.st[7] = 0;
         s.st[8] = 0;
         s.st[9] = 0;
+        s.st[10] = 0;
     }
 }
 
@@ -2404,6 +2480,7 @@ __global__ void k_assemble(const SecDev* __restrict__ parents, const SecDev* __r
             p.st[7] = 0;
             p.st[8] = 0;
             p.st[9] = 0;
+            p.st[10] = 0;
         }
         return;
     }
@@ -2443,6 +2520,7 @@ __global__ void k_assemble(const SecDev* __restrict__ parents, const SecDev* __r
         p.st[7] = 0;
         p.st[8] = 0;
         p.st[9] = 0;
+        p.st[10] = 0;
     }
 }
 

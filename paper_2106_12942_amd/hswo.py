@@ -33,6 +33,7 @@ HSWO_FLAG_AUTOTUNE = 4
 HSWO_FLAG_INCREMENTAL = 8
 HSWO_FLAG_KERNEL_TIMES = 16
 HSWO_FLAG_SEQUENTIAL_SECTIONS = 32
+HSWO_FLAG_TWO_MERGES = 64
 
 HSWO_CRIT_BSMSE = 0
 HSWO_CRIT_SAM = 1
@@ -150,7 +151,7 @@ def last_error() -> str:
 def make_params(*, connectivity=4, seam_connectivity=8, spclust_wght=0.0, spclust_max=0, target_regions=1,
                 section_regions=0, rnb_levels=1, level_counts: Optional[Sequence[int]] = None,
                 precision="fp32", merge_log=False, graph=False, autotune=False, incremental=False,
-                kernel_times=False, sequential=False, criterion="bsmse", **_ignored):
+                kernel_times=False, sequential=False, criterion="bsmse", two_merges=False, **_ignored):
     counts = list(level_counts) if level_counts is not None else [target_regions]
     arr = (ctypes.c_int32 * len(counts))(*counts)
     p = Params(connectivity, seam_connectivity, spclust_wght, spclust_max, target_regions, section_regions,
@@ -158,7 +159,8 @@ def make_params(*, connectivity=4, seam_connectivity=8, spclust_wght=0.0, spclus
                PREC[precision] if isinstance(precision, str) else int(precision),
                (HSWO_FLAG_MERGE_LOG if merge_log else 0) | (HSWO_FLAG_GRAPH if graph else 0) |
                (HSWO_FLAG_AUTOTUNE if autotune else 0) | (HSWO_FLAG_INCREMENTAL if incremental else 0) |
-               (HSWO_FLAG_KERNEL_TIMES if kernel_times else 0) | (HSWO_FLAG_SEQUENTIAL_SECTIONS if sequential else 0),
+               (HSWO_FLAG_KERNEL_TIMES if kernel_times else 0) | (HSWO_FLAG_SEQUENTIAL_SECTIONS if sequential else 0) |
+               (HSWO_FLAG_TWO_MERGES if two_merges else 0),
                CRIT[criterion] if isinstance(criterion, str) else int(criterion))
     p._counts_keepalive = arr  # the struct holds a raw pointer into arr
     return p

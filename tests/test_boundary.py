@@ -144,7 +144,7 @@ def test_graph_flag_needs_a_stream_and_unknown_flags_rejected():
     assert lib.hswo_run(FAKE, 16, 16, 4, 0, ctypes.byref(p), FAKE, None, None, FAKE, nb, None) == hswo.HSWO_E_INVAL
     assert "non-null stream" in hswo.last_error()
     q = hswo.make_params(**BASE)
-    q.flags = 64
+    q.flags = 128
     assert lib.hswo_run(FAKE, 16, 16, 4, 0, ctypes.byref(q), FAKE, None, None, FAKE, nb, None) == hswo.HSWO_E_INVAL
 
 
@@ -166,7 +166,7 @@ def test_python_constants_match_header():
     src = open(HEADER).read()
     defs = dict(re.findall(r"#define\s+(HSWO_\w+)\s+\(?(-?\d+)\)?", src))
     for name in ("HSWO_FLAG_MERGE_LOG", "HSWO_FLAG_GRAPH", "HSWO_FLAG_AUTOTUNE", "HSWO_FLAG_INCREMENTAL",
-                 "HSWO_FLAG_KERNEL_TIMES", "HSWO_FLAG_SEQUENTIAL_SECTIONS", "HSWO_CRIT_BSMSE", "HSWO_CRIT_SAM",
+                 "HSWO_FLAG_KERNEL_TIMES", "HSWO_FLAG_SEQUENTIAL_SECTIONS", "HSWO_FLAG_TWO_MERGES", "HSWO_CRIT_BSMSE", "HSWO_CRIT_SAM",
                  "HSWO_E_UNSUPPORTED", "HSWO_F32", "HSWO_F16", "HSWO_E_INVAL",
                  "HSWO_E_NOMEM"):
         assert int(defs[name]) == getattr(hswo, name), name
@@ -192,3 +192,16 @@ def test_spectral_angle_workspace_adds_the_norm_rows():
     p = hswo.make_params(**BASE, incremental=True, criterion="sam")
     a, b = hswo.workspace_bytes(64, 64, 32, 0, q), hswo.workspace_bytes(64, 64, 32, 0, p)
     assert 0 < a < b
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(precision="fp16"), dict(sequential=True)])
+def test_two_merges_need_the_incremental_form(kw):
+    lib = hswo.load()
+    p = hswo.make_params(**BASE, two_merges=True, **kw)
+    assert hswo.workspace_bytes(16, 16, 4, 0, p) == 0
+    rc = lib.hswo_run(FAKE, 16, 16, 4, 0, ctypes.byref(p), FAKE, None, None, FAKE, 1 << 30, None)
+    assert rc == hswo.HSWO_E_UNSUPPORTED
+    assert "TWO_MERGES" in hswo.last_error()
+    q = hswo.make_params(**BASE, two_merges=True, incremental=True)
+    r = hswo.make_params(**BASE, incremental=True)
+    assert hswo.workspace_bytes(64, 64, 8, 0, q) > hswo.workspace_bytes(64, 64, 8, 0, r) > 0
