@@ -440,9 +440,8 @@ int run_level(Timer* tm, const SecDev* secs, int n, const std::vector<int64_t>& 
     }
     int64_t iters = 0;
     for (int i = 0; i < n; ++i) iters = std::max(iters, r0[i] - std::min(r0[i], stop[i]));
-    // two-merge reading: a launch makes at most one merge, and a step 3 without a pair below its
-    // threshold makes none; step 3 follows a step-2 merge (or starts the level, after the driver)
-    if (lp.two_merges) iters = 2 * iters + 1;
+    // (two-merge reading: a launch still makes exactly one merge -- a step 3 that finds no pair
+    // below its threshold goes on to the next step 2 in the same launch)
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (tm) {
         HIP_TRY(hipEventCreate(&e0));
@@ -455,16 +454,11 @@ int run_level(Timer* tm, const SecDev* secs, int n, const std::vector<int64_t>& 
     if (row_cache) HIP_TRY(launch_rowcache_prep(secs, n, lp, stream, kt));
     for (int64_t t = 0; t < iters; ++t) {
         bool spec = false;
-        if (lp.spectral && lp.two_merges) {
-            // R after t launches lies in [r0 - t, r0 - t / 2]
-            for (int i = 0; i < n && !spec; ++i)
-                spec = r0[i] - t / 2 > stop[i] && r0[i] - t <= lp.kmax;
-        } else if (lp.spectral) {
+        if (lp.spectral)
             for (int i = 0; i < n && !spec; ++i) {
                 const int64_t R = r0[i] - t;
                 spec = R > stop[i] && R <= lp.kmax;
             }
-        }
         HIP_TRY(launch_wide_iteration(secs, n, G, lp, variant, spec, row_cache, stream, kt));
     }
     if (tm) HIP_TRY(hipEventRecord(e1, stream));

@@ -1958,19 +1958,20 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
         KeyD win;
         int kind;
         bool step2 = false;
-        if (st3) {
-            // two-merge reading, step 3: the least non-adjacent pair, if below w^2 times step 2's value
-            st3 = 0;
-            if (!(key_exists(M) && M.d2 < thr3)) continue;
+        if (st3 && key_exists(M) && M.d2 < thr3) {
+            // two-merge reading, step 3: the least non-adjacent pair is below w^2 times step 2's value
             win = M;
             kind = 1;
         } else if (lp.two_merges && key_exists(A)) {
-            win = A;  // step 2: the least adjacent pair, whatever the spectral minimum
+            // step 2: the least adjacent pair, whatever the spectral minimum -- also at once when
+            // step 3 found no pair (nothing changed since, so the next iteration starts here)
+            win = A;
             kind = 0;
             step2 = true;
         } else if (!decide(spectral, A, M, T, win, kind)) {
             break;  // no pair left (not in a connected section)
         }
+        st3 = 0;
         CNT_ADD(C_RECHECKS, nchk);
         CNT_ADD(C_ITERS, 1);
         CNT_ADD(C_MERGES, 1);
@@ -2164,13 +2165,15 @@ __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ s
         int kind;
         bool merge_now, step2 = false;
         const bool st3 = lp.two_merges && s.st[10];
-        if (st3) {
-            // two-merge reading, step 3: the least non-adjacent pair, if below w^2 times step 2's value
-            merge_now = key_exists(M) && M.d2 < s.wd[3];
+        if (st3 && key_exists(M) && M.d2 < s.wd[3]) {
+            // two-merge reading, step 3: the least non-adjacent pair is below w^2 times step 2's value
+            merge_now = true;
             win = M;
             kind = 1;
         } else if (lp.two_merges && key_exists(A)) {
-            merge_now = true;  // step 2: the least adjacent pair, whatever the spectral minimum
+            // step 2: the least adjacent pair, whatever the spectral minimum -- also at once when
+            // step 3 found no pair (nothing changed since, so the next iteration starts here)
+            merge_now = true;
             win = A;
             kind = 0;
             step2 = true;
