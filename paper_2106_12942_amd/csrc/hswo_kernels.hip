@@ -371,6 +371,90 @@ __device__ __forceinline__ void score_edge_exact(Smem& sh, const SecDev& s, int 
     if (lane_id() == 0) s.ed2[e] = v;
 }
 
+// Lanes per pair of the segmented exact evaluation: the least power of two L
+// with 4L >= B when B <= 256 (a segment then holds every band in one pass);
+// 0 for wider cubes (one pair per wavefront, exact_d2_wave).
+__device__ __forceinline__ int seg_lanes(int B) {
+    if (B > 256) return 0;
+    int L = 1;
+    while (4 * L < B) L <<= 1;
+    return L;
+}
+
+// The canonical criterion of pair (si, sj) by an L-lane segment of a
+// wavefront (4L >= B): lane m of the segment holds bands 4m..4m+3 and
+// butterflies stay inside the segment. That is the perfect tree over the
+// zero-padded bands that exact_d2_wave builds (its extra zero leaves add
+// nothing), so the value is bit-identical. Every lane of the wavefront calls
+// it with the same L, each segment with its own pair; a segment without a
+// pair passes si < 0 (its result is meaningless). Kept out of line: inlined
+// at its three call sites it pushes the decision kernel into scratch.
+__device__ __noinline__ double exact_seg(const SecDev& s, int si, int sj, int L) {
+    const int B = s.B;
+    const int b = (lane_id() & (L - 1)) << 2;
+    const bool sam = s.crit == HSWO_CRIT_SAM;
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0;  // Equation 1: t0; spectral angle: dot, q_i, q_j
+    double fac = 0.0;
+    if (si >= 0) {
+        const double* Si = s.sums + (size_t)si * B;
+        const double* Sj = s.sums + (size_t)sj * B;
+        double x[4], y[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            x[k] = (b + k < B) ? Si[b + k] : 0.0;
+            y[k] = (b + k < B) ? Sj[b + k] : 0.0;
+        }
+        if (sam) {
+            t0 = (x[0] * y[0] + x[1] * y[1]) + (x[2] * y[2] + x[3] * y[3]);
+            t1 = (x[0] * x[0] + x[1] * x[1]) + (x[2] * x[2] + x[3] * x[3]);
+            t2 = (y[0] * y[0] + y[1] * y[1]) + (y[2] * y[2] + y[3] * y[3]);
+        } else {
+            const int n_i = s.npix[si], n_j = s.npix[sj];
+            const double dni = (double)n_i, dnj = (double)n_j;
+            double q[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const double d = x[k] / dni - y[k] / dnj;
+                q[k] = (b + k < B) ? d * d : 0.0;
+            }
+            t0 = (q[0] + q[1]) + (q[2] + q[3]);
+            fac = (dni * dnj) / (double)(n_i + n_j);
+        }
+    }
+    for (int o = 1; o < L; o <<= 1) {
+        t0 = t0 + __shfl_xor(t0, o);
+        if (sam) {
+            t1 = t1 + __shfl_xor(t1, o);
+            t2 = t2 + __shfl_xor(t2, o);
+        }
+    }
+    return sam ? sam_value(t0, t1, t2) : fac * t0;
+}
+
+// Exact scores of the edges list[0, n) (list == nullptr: edges [0, n)) into
+// the per-edge cache, +inf for an empty slot; 64 / L edges per wavefront
+// when the bands fit an L-lane segment. Called by the whole block.
+__device__ void score_edges(Smem& sh, const SecDev& s, const int* list, int n) {
+    const int L = seg_lanes(s.B);
+    if (L == 0) {
+        for (int i = wave_id(); i < n; i += NWAVE) score_edge_exact(sh, s, list ? list[i] : i);
+        return;
+    }
+    const int ppw = 64 / L, sub = lane_id() / L;
+    for (int i0 = wave_id() * ppw; i0 < n; i0 += NWAVE * ppw) {  // wavefront-uniform trip count
+        const int i = i0 + sub;
+        int e = -1, a = -1, b = -1;
+        if (i < n) {
+            e = list ? list[i] : i;
+            const int2 ed = s.edges[e];
+            a = ed.x;
+            b = ed.y;
+        }
+        const double v = exact_seg(s, a, b, L);
+        if (e >= 0 && (lane_id() & (L - 1)) == 0) s.ed2[e] = a >= 0 ? v : __builtin_huge_val();
+    }
+}
+
 // Exact lexicographic minimum over the first n entries of the LDS candidate
 // list. Adjacent mode: entries are edge indices; spectral mode: (i<<16)|j.
 __device__ KeyD exact_best_of_list(Smem& sh, const SecDev& s, int n, bool edge_mode) {
@@ -1313,7 +1397,7 @@ __device__ __forceinline__ void merge_pair(Smem& sh, const SecDev& s, int lo_s, 
     merge_slots(sh, s, lo_s, hi_s, R, g_ready, rc, true);
     if (inc) {  // re-score the survivor's edges; every other edge keeps its cached value
         const int nd = sh.bcast_i[2];
-        for (int i = wave_id(); i < nd; i += NWAVE) score_edge_exact(sh, s, s.edirty[i]);
+        score_edges(sh, s, s.edirty, nd);
         __syncthreads();
     }
 }
@@ -1459,7 +1543,7 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
         merge_edges_full(sh, s, lo_s, hi_s, R, E, stamp, true);
         merge_slots(sh, s, lo_s, hi_s, R, 0, rc, false);
         const int nd = sh.bcast_i[2];
-        for (int i = wave_id(); i < nd; i += NWAVE) score_edge_exact(sh, s, s.edirty[i]);
+        score_edges(sh, s, s.edirty, nd);
         nchk += nd;
         __syncthreads();
         if (tid == 0) s.st[9] = 0;
@@ -1521,26 +1605,63 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
     const int nk = sh.bcast_i[2];
     const int emptied = sh.bcast_i[3];
     const int l_surv = s.label[surv];
-    for (int q = wave_id(); q < nk; q += NWAVE) {
-        const int k = K[q];
-        const int e = L[k];
-        const int x = XL[k] == last ? hi_s : XL[k];
-        const int lx = s.label[x];
-        int a = surv, b = x, la = l_surv, lb = lx;
-        if (la > lb) {
-            a = x;
-            b = surv;
-            la = lx;
-            lb = l_surv;
+    const int Ls = seg_lanes(s.B);
+    if (Ls == 0) {
+        for (int q = wave_id(); q < nk; q += NWAVE) {
+            const int k = K[q];
+            const int e = L[k];
+            const int x = XL[k] == last ? hi_s : XL[k];
+            const int lx = s.label[x];
+            int a = surv, b = x, la = l_surv, lb = lx;
+            if (la > lb) {
+                a = x;
+                b = surv;
+                la = lx;
+                lb = l_surv;
+            }
+            KeyD kk;
+            kk.d2 = exact_d2_wave(sh, s, a, b);
+            kk.lo = la;
+            kk.hi = lb;
+            kk.si = a;
+            kk.sj = b;
+            if (lane_id() == 0) s.ed2[e] = kk.d2;
+            if (key_less(kk, best)) best = kk;
         }
-        KeyD kk;
-        kk.d2 = exact_d2_wave(sh, s, a, b);
-        kk.lo = la;
-        kk.hi = lb;
-        kk.si = a;
-        kk.sj = b;
-        if (lane_id() == 0) s.ed2[e] = kk.d2;
-        if (key_less(kk, best)) best = kk;
+    } else {
+        // 64 / Ls re-scored edges per wavefront at once
+        const int ppw = 64 / Ls, sub = lane_id() / Ls;
+        for (int q0 = wave_id() * ppw; q0 < nk; q0 += NWAVE * ppw) {  // wavefront-uniform trip count
+            const int q = q0 + sub;
+            int a = -1, b = -1, la = 0, lb = 0, e = -1;
+            if (q < nk) {
+                const int k = K[q];
+                e = L[k];
+                const int x = XL[k] == last ? hi_s : XL[k];
+                const int lx = s.label[x];
+                a = surv;
+                b = x;
+                la = l_surv;
+                lb = lx;
+                if (la > lb) {
+                    a = x;
+                    b = surv;
+                    la = lx;
+                    lb = l_surv;
+                }
+            }
+            const double v = exact_seg(s, a, b, Ls);
+            if (q < nk) {
+                KeyD kk;
+                kk.d2 = v;
+                kk.lo = la;
+                kk.hi = lb;
+                kk.si = a;
+                kk.sj = b;
+                if ((lane_id() & (Ls - 1)) == 0) s.ed2[e] = v;
+                if (key_less(kk, best)) best = kk;
+            }
+        }
     }
     nchk += nk;
     anext = block_min_key(sh, best);
@@ -1665,7 +1786,7 @@ __device__ KeyD adj_collect(Smem& sh, const SecDev& s, int E, float Ua, int& nch
 // Labels are read only for values that can still win.
 __device__ KeyD adj_incremental(Smem& sh, const SecDev& s, int E, bool init, int& nchk) {
     if (init) {
-        for (int e = wave_id(); e < E; e += NWAVE) score_edge_exact(sh, s, e);
+        score_edges(sh, s, nullptr, E);
         nchk += E;
         __syncthreads();
     }
@@ -2180,7 +2301,7 @@ __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ s
         } else {
             merge_now = decide(spectral, A, M, T, win, kind);
         }
-        __syncthreads();  // every thread has read st[10] and wd[3]
+        if (lp.two_merges) __syncthreads();  // every thread has read st[10] and wd[3] (kernel-uniform)
         if (lp.two_merges && tid == 0) {
             s.st[10] = (step2 && lp.spectral && R - 1 <= lp.kmax && R - 1 > s.stop) ? 1 : 0;
             s.wd[3] = step2 ? lp.w2 * win.d2 : 0.0;
