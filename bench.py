@@ -98,10 +98,10 @@ def kernel_roofline(st, B, tag, kind=None):
     measures in the same call on an empty kernel). Algorithmic work per launch = the kind's work over the step
     divided by its launches:
       wide_decide: bytes counted on the device by the kernel (16 per edge slot
-        read for the minimum, 24 per band per merge, 12 per live row and 16
-        per pending row per 64 live rows in the spectral stage) -> HBM bound;
-      wide_rows: 3 FP64 flops per band per exactly evaluated pair, counted on
-        the device -> FP64 vector bound (78.6 TFLOP/s);
+        read for the minimum, 24 per band per merge; in the spectral stage 12
+        per live row and 32 per pending row per 64 live rows) -> HBM bound;
+      wide_rows: 3 FP64 flops per band per exactly evaluated pair (2 for the
+        spectral angle), counted on the device -> FP64 vector bound (78.6 TFLOP/s);
       wide_mfma: 2 flops per band per unique pair of each screened section,
         counted on the device -> matrix cores;
       wide_adj: FP32 mean rows read once + 8 B per edge slot + 8 B per

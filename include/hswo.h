@@ -191,9 +191,10 @@ typedef struct hswo_stats {
        not defined): HSWO_K_WIDE_DECIDE (incremental form) bytes =
        16 per edge slot (endpoints and cached D2 read for the minimum)
        + 24 per band per merge (two FP64 sum rows read, one written)
-       + in the spectral stage 12 per live row (cached pair) and 16 per
-       pending row per 64 live rows (partial minima);
-       HSWO_K_WIDE_ROWS flops = 3 per band per pair evaluated;
+       + in the spectral stage 12 per live row (cached pair) and 32 per
+       pending row per 64 live rows (least two candidates of each 64 columns);
+       HSWO_K_WIDE_ROWS flops = 3 per band per pair evaluated (2 for the
+       spectral angle);
        HSWO_K_WIDE_ADJ bytes = per section and iteration, the FP32 mean rows
        read once (4 per band per live region) + 8 per edge slot + 8 per region;
        HSWO_K_WIDE_MFMA flops = 2 per band per unique pair of every section

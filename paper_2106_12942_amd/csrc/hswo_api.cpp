@@ -280,6 +280,9 @@ Layout carve(const Plan& pl, int H, int W, const hswo_params* p, void* ws, const
                 s.rbd = bp.take<double>(rc);
                 s.rbp = bp.take<int32_t>(rc);
                 s.rbl = bp.take<int32_t>(rc);
+                s.rbd2 = bp.take<double>(rc);
+                s.rbp2 = bp.take<int32_t>(rc);
+                s.rbl2 = bp.take<int32_t>(rc);
                 s.rpend = bp.take<int32_t>(rc);
                 s.rpart = bp.take<RowPart>(rc * ((rc + 63) / 64));
                 } else if (p->precision != HSWO_PREC_FP32 && p->spclust_wght > 0.0f && p->spclust_max > 0) {
@@ -949,6 +952,9 @@ BatchLayout carve_batch(int n, const hswo_section* sec, const hswo_params* p, vo
             s.rbd = bp.take<double>(rc);
             s.rbp = bp.take<int32_t>(rc);
             s.rbl = bp.take<int32_t>(rc);
+            s.rbd2 = bp.take<double>(rc);
+            s.rbp2 = bp.take<int32_t>(rc);
+            s.rbl2 = bp.take<int32_t>(rc);
             s.rpend = bp.take<int32_t>(rc);
             s.rpart = bp.take<RowPart>(rc * ((rc + 63) / 64));
         } else if (p->precision != HSWO_PREC_FP32 && p->spclust_wght > 0.0f && p->spclust_max > 0) {

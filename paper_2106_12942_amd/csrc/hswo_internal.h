@@ -47,10 +47,14 @@ constexpr int STILE = 128;    // matrix-core super tile edge (4 spectral tiles)
 
 // One section of one recursion level (or one independent batch section).
 // Partial result of a row-cache task: a row's best candidate among 64 columns.
+// Least and second least candidates of one row over a range of columns.
 struct RowPart {
     double d2;
     int32_t lab;   // partner label (orders equal D2 for a fixed row)
     int32_t slot;  // partner slot (-1: none)
+    double d2b;    // the second least candidate
+    int32_t labb;
+    int32_t slotb;
 };
 
 struct SecDev {
@@ -93,8 +97,12 @@ struct SecDev {
     double* rq;      // [rcap] spectral angle only: |S|^2 of each slot (pairwise tree over the bands)
     uint32_t* abit;  // [rcap][ceil(rcap / 32)] two-merge reading only: adjacency bitmap of the live slots
     double* rbd;     // [rcap] exact D2 of the row's cached pair
-    int32_t* rbp;    // [rcap] partner slot of that pair (-1: none or pending)
+    int32_t* rbp;    // [rcap] partner slot of that pair (-1: none or pending, -2: light step pending)
     int32_t* rbl;    // [rcap] partner label of that pair
+    double* rbd2;    // [rcap] second bound: the least D2 over the row's other partners at its last full
+                     //        evaluation (valid while rbp2 >= 0, i.e. while that partner is alive)
+    int32_t* rbp2;   // [rcap] partner slot of the second bound (-1: none)
+    int32_t* rbl2;   // [rcap] its partner label
     int32_t* rpend;  // [rcap] rows to re-evaluate: [0] the last merge's survivor, then stale rows
     RowPart* rpart;  // [rcap][ceil(rcap / 64)] per-row, per-64-column partial minima
     // wide mode iteration scratch

@@ -826,6 +826,7 @@ __device__ void rowcache_begin(Smem& sh, const SecDev& s, int R, int E) {
     for (int i = threadIdx.x; i < R; i += NT) {
         s.rbp[i] = -1;
         s.rbd[i] = __builtin_huge_val();
+        s.rbp2[i] = -1;
     }
     __syncthreads();
     if (s.abit) abit_build(s, R, E);
@@ -834,6 +835,77 @@ __device__ void rowcache_begin(Smem& sh, const SecDev& s, int R, int E) {
         s.st[7] = 0;
     }
     __syncthreads();
+}
+
+__device__ __forceinline__ bool cand_less(double d1, int l1, double d2, int l2) {
+    return d1 < d2 || (d1 == d2 && l1 < l2);
+}
+
+// r := the least two candidates of r and o (each holds its least two, from
+// disjoint columns), in (D2, partner label) order; symmetric in r and o.
+__device__ __forceinline__ void top2_merge(RowPart& r, const RowPart& o) {
+    if (cand_less(o.d2, o.lab, r.d2, r.lab)) {
+        if (cand_less(o.d2b, o.labb, r.d2, r.lab)) {
+            r.d2b = o.d2b;
+            r.labb = o.labb;
+            r.slotb = o.slotb;
+        } else {
+            r.d2b = r.d2;
+            r.labb = r.lab;
+            r.slotb = r.slot;
+        }
+        r.d2 = o.d2;
+        r.lab = o.lab;
+        r.slot = o.slot;
+    } else if (cand_less(o.d2, o.lab, r.d2b, r.labb)) {
+        r.d2b = o.d2;
+        r.labb = o.lab;
+        r.slotb = o.slot;
+    }
+}
+
+__device__ __forceinline__ RowPart shfl_xor_part(const RowPart& r, int o) {
+    RowPart t;
+    t.d2 = __shfl_xor(r.d2, o);
+    t.lab = __shfl_xor(r.lab, o);
+    t.slot = __shfl_xor(r.slot, o);
+    t.d2b = __shfl_xor(r.d2b, o);
+    t.labb = __shfl_xor(r.labb, o);
+    t.slotb = __shfl_xor(r.slotb, o);
+    return t;
+}
+
+// Light step of row j (marked rbp = -2 by the merge: its cached partner was
+// merged, its second bound's partner is alive), taken by the lane that holds
+// column j of the survivor's row: the row's new pair is the lesser of its
+// pair with the survivor (c, exact, masked) and its second bound, which is
+// then spent. Exact: the second bound is at or below every pair the row had
+// at its last full evaluation except its old partner, and each pair created
+// since is bounded by its other row, evaluated in full when it was created.
+__device__ __forceinline__ void light_step(const SecDev& s, int j, int surv, int lsurv, double c, double d2b, int lb,
+                                           int pb) {
+    if (!cand_less(c, lsurv, d2b, lb)) {
+        s.rbd[j] = d2b;
+        s.rbp[j] = pb;
+        s.rbl[j] = lb;
+        s.rbp2[j] = -1;
+    } else {
+        s.rbd[j] = c;
+        s.rbp[j] = surv;
+        s.rbl[j] = lsurv;
+    }
+}
+
+// One column's candidate of a row as a partial (second: none).
+__device__ __forceinline__ RowPart part_of(double d2, int lab, int slot) {
+    RowPart r;
+    r.d2 = d2;
+    r.lab = lab;
+    r.slot = slot;
+    r.d2b = __builtin_huge_val();
+    r.labb = INT_MAX;
+    r.slotb = -1;
+    return r;
 }
 
 // Exact D2 of KR pending rows against 64 columns (one block task; a pair per
@@ -870,6 +942,9 @@ __device__ void row_block_task(double (*rsum)[4][64], const SecDev& s, int R, in
         if (q < np) v = all ? q : s.rpend[q];
         ir[r] = __builtin_amdgcn_readfirstlane(v);
     }
+    // light steps ride on the survivor's row (row 0 of the pending list, finished by wave 0)
+    const bool light = !all && bq == 0 && w == 0 && jv;
+    const int lmark = light ? s.rbp[j] : 0;
     if (w < nbc) {  // wavefront-uniform
         const int b_lo = w * cs;
         const int ngw = (cs + GB - 1) / GB;
@@ -939,25 +1014,12 @@ __device__ void row_block_task(double (*rsum)[4][64], const SecDev& s, int R, in
                 lab = INT_MAX;
                 slot = -1;
             }
+            if (light && lmark == -2) light_step(s, j, i, s.label[i], d2, s.rbd2[j], s.rbl2[j], s.rbp2[j]);
             // for a fixed row the pair order (D2, lo, hi) is the order of (D2, partner label)
+            RowPart rp = part_of(d2, lab, slot);
 #pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) {
-                const double d2o = __shfl_xor(d2, o);
-                const int labo = __shfl_xor(lab, o);
-                const int sloto = __shfl_xor(slot, o);
-                if (d2o < d2 || (d2o == d2 && labo < lab)) {
-                    d2 = d2o;
-                    lab = labo;
-                    slot = sloto;
-                }
-            }
-            if (lane == 0) {
-                RowPart rp;
-                rp.d2 = d2;
-                rp.lab = lab;
-                rp.slot = slot;
-                s.rpart[(size_t)q * ((R + 63) >> 6) + c] = rp;
-            }
+            for (int o = 32; o >= 1; o >>= 1) top2_merge(rp, shfl_xor_part(rp, o));
+            if (lane == 0) s.rpart[(size_t)q * ((R + 63) >> 6) + c] = rp;
         }
     }
     __syncthreads();  // rsum is reused by the next task
@@ -989,6 +1051,9 @@ __device__ void row_wave_task(const SecDev& s, int R, int np, bool all, int bq, 
     const int n_j = jv ? s.npix[j] : 1;
     const double q_j = (SAM && jv) ? s.rq[j] : 1.0;
     const int l_j = jv ? s.label[j] : INT_MAX;
+    // light steps ride on the survivor's row (row 0 of the pending list)
+    const bool light = !all && bq == 0 && jv;
+    const int lmark = light ? s.rbp[j] : 0;
     const double* mj = s.m64 + (jv ? j : 0);
     double part[KR][LV];
 #pragma unroll
@@ -1049,22 +1114,11 @@ __device__ void row_wave_task(const SecDev& s, int R, int np, bool all, int bq, 
             lab = INT_MAX;
             slot = -1;
         }
+        if (light && r == 0 && lmark == -2) light_step(s, j, i, s.label[i], d2, s.rbd2[j], s.rbl2[j], s.rbp2[j]);
+        RowPart rp = part_of(d2, lab, slot);
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) {
-            const double d2o = __shfl_xor(d2, o);
-            const int labo = __shfl_xor(lab, o);
-            const int sloto = __shfl_xor(slot, o);
-            if (d2o < d2 || (d2o == d2 && labo < lab)) {
-                d2 = d2o;
-                lab = labo;
-                slot = sloto;
-            }
-        }
+        for (int o = 32; o >= 1; o >>= 1) top2_merge(rp, shfl_xor_part(rp, o));
         if (lane == 0) {
-            RowPart rp;
-            rp.d2 = d2;
-            rp.lab = lab;
-            rp.slot = slot;
             s.rpart[(size_t)(bq * KR + r) * nch + c] = rp;
         }
     }
@@ -1093,16 +1147,12 @@ __device__ __forceinline__ KeyD pair_key(const SecDev& s, double d2, int a, int 
 // Least pair over all live slots, from the cached rows.
 // Best pair of pending row q from its column-chunk partials.
 __device__ __forceinline__ RowPart row_from_parts(const SecDev& s, int q, int nch) {
-    RowPart b;
-    b.d2 = __builtin_huge_val();
-    b.lab = INT_MAX;
-    b.slot = -1;
-    for (int c = 0; c < nch; ++c) {
-        const RowPart rp = s.rpart[(size_t)q * nch + c];
-        if (rp.d2 < b.d2 || (rp.d2 == b.d2 && rp.lab < b.lab)) b = rp;
-    }
+    RowPart b = part_of(__builtin_huge_val(), INT_MAX, -1);
+    for (int c = 0; c < nch; ++c) top2_merge(b, s.rpart[(size_t)q * nch + c]);
     return b;
 }
+
+
 
 __device__ __forceinline__ KeyD row_key(double d2, int i, int li, int p, int lp) {
     KeyD k;
@@ -1140,21 +1190,9 @@ __device__ KeyD spectral_min_rows(Smem& sh, const SecDev& s, int R, int np, bool
         const int lane = lane_id(), sub = lane / c2, c = lane % c2;
         for (int q0 = wave_id() * rpw; q0 < np; q0 += NWAVE * rpw) {
             const int q = q0 + sub;
-            RowPart r;
-            r.d2 = __builtin_huge_val();
-            r.lab = INT_MAX;
-            r.slot = -1;
+            RowPart r = part_of(__builtin_huge_val(), INT_MAX, -1);
             if (q < np && c < nch) r = s.rpart[(size_t)q * nch + c];
-            for (int o = c2 >> 1; o >= 1; o >>= 1) {
-                const double d = __shfl_xor(r.d2, o);
-                const int l = __shfl_xor(r.lab, o);
-                const int sl = __shfl_xor(r.slot, o);
-                if (d < r.d2 || (d == r.d2 && l < r.lab)) {
-                    r.d2 = d;
-                    r.lab = l;
-                    r.slot = sl;
-                }
-            }
+            for (int o = c2 >> 1; o >= 1; o >>= 1) top2_merge(r, shfl_xor_part(r, o));
             if (c == 0 && q < np) {
                 const int i = all ? q : s.rpend[q];
                 if (np <= HOLD) held[q] = r;
@@ -1191,6 +1229,9 @@ __device__ KeyD spectral_min_rows(Smem& sh, const SecDev& s, int R, int np, bool
         s.rbd[i] = r.d2;
         s.rbp[i] = r.slot;
         s.rbl[i] = r.lab;
+        s.rbd2[i] = r.d2b;
+        s.rbp2[i] = r.slotb;
+        s.rbl2[i] = r.labb;
     }
     __syncthreads();
     return M;
@@ -1316,10 +1357,13 @@ __device__ void merge_edges_full(Smem& sh, const SecDev& s, int lo_s, int hi_s, 
 
 // Slot part of a merge: swap-remove (the last live slot moves into the freed
 // one) and, with the row cache (rc == 2), the row entries: the moved row's
-// entry follows it, partners that moved are renamed, and the survivor and
-// every row whose cached partner was one of the merged pair are listed for
-// re-evaluation (count in st[7] and sh.npend).
-__device__ void merge_slots(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int g_ready, int rc, bool screens) {
+// entries follow it, partners that moved are renamed, and the survivor and
+// every row whose cached partner was one of the merged pair are listed for a
+// full evaluation (rpend, count in st[7] and sh.npend) -- or, a row whose
+// second bound's partner is alive, marked for a light step (rbp = -2), which
+// the survivor's row evaluation takes. Kept out of line: inlined, it pushes
+// the decision kernel into scratch.
+__device__ __noinline__ void merge_slots(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int g_ready, int rc, bool screens) {
     const int tid = threadIdx.x;
     const int B = s.B, Bp = s.Bp;
     const int last = R - 1;
@@ -1364,9 +1408,23 @@ __device__ void merge_slots(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R
             if (i == lo_s || i == hi_s) continue;
             const int ni = (i == last) ? hi_s : i;
             const int p = s.rbp[i];
+            // the second bound is dropped with its partner and follows a moved one
+            const int p2 = s.rbp2[i];
+            const int np2 = (p2 == lo_s || p2 == hi_s) ? -1 : (p2 == last ? hi_s : p2);
+            if (ni != i) {
+                s.rbd2[ni] = s.rbd2[i];
+                s.rbl2[ni] = s.rbl2[i];
+            }
+            if (ni != i || np2 != p2) s.rbp2[ni] = np2;
             if (p == lo_s || p == hi_s) {
-                s.rbp[ni] = -1;
-                s.rpend[atomicAdd(&sh.npend, 1)] = ni;
+                // stale: a light step (marked -2) when its second bound's partner is alive, else a
+                // full evaluation
+                if (np2 >= 0) {
+                    s.rbp[ni] = -2;
+                } else {
+                    s.rbp[ni] = -1;
+                    s.rpend[atomicAdd(&sh.npend, 1)] = ni;
+                }
             } else {
                 // only a moved row or a moved partner changes the entry
                 const int np = (p == last) ? hi_s : p;
@@ -2280,7 +2338,7 @@ __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ s
             const int np = all ? R : s.st[7];
             M = spectral_min_rows(sh, s, R, np, all);
             rcs = 2;
-            decide_bytes += 12ull * (unsigned long long)R + 16ull * (unsigned long long)np * (unsigned long long)((R + 63) >> 6);
+            decide_bytes += 12ull * (unsigned long long)R + 32ull * (unsigned long long)np * (unsigned long long)((R + 63) >> 6);
         }
         KeyD win;
         int kind;
