@@ -195,6 +195,10 @@ typedef struct hswo_stats {
        pending row per 64 live rows (least two candidates of each 64 columns);
        HSWO_K_WIDE_ROWS flops = 3 per band per pair evaluated (2 for the
        spectral angle);
+       HSWO_K_SECTION_DRIVER (incremental form) bytes = the HSWO_K_WIDE_DECIDE
+       count for the iterations it runs + 8 per band per live region for each
+       iteration whose row-cache stage evaluates rows (every FP64 row read
+       once);
        HSWO_K_WIDE_ADJ bytes = per section and iteration, the FP32 mean rows
        read once (4 per band per live region) + 8 per edge slot + 8 per region;
        HSWO_K_WIDE_MFMA flops = 2 per band per unique pair of every section

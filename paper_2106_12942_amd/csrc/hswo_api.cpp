@@ -732,6 +732,7 @@ int fill_stats(hswo_stats* st, const ExecOut& o, int64_t launches_if_graph) {
     st->kernel_work[HSWO_K_WIDE_ROWS] = (int64_t)c[C_W_ROWS_FLOPS];
     st->kernel_work[HSWO_K_WIDE_ADJ] = (int64_t)c[C_W_ADJ_BYTES];
     st->kernel_work[HSWO_K_WIDE_MFMA] = (int64_t)c[C_W_MFMA_FLOPS];
+    st->kernel_work[HSWO_K_SECTION_DRIVER] = (int64_t)c[C_D_BYTES];
     st->ms_event_pair_overhead = o.ms_event_pair;
     return HSWO_OK;
 }

@@ -38,6 +38,7 @@ enum Counter {
     C_W_ROWS_FLOPS,   // k_wide_rows: 3 FP64 flops per band per evaluated pair
     C_W_ADJ_BYTES,    // k_wide_adj: FP32 mean rows read once + edge endpoints + counts and norms
     C_W_MFMA_FLOPS,   // k_wide_mfma: 2 flops per band per unique pair of the screened sections
+    C_D_BYTES,        // k_section_driver, incremental form: algorithmic bytes (see hswo_stats.kernel_work)
     C_COUNT
 };
 

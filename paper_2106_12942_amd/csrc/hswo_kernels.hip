@@ -2097,6 +2097,9 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
             M = spectral_min_rows(sh, s, R, rows, all);
             rcs = 2;
             npend = 0;
+            // bytes: cached pairs, partial minima, and every live FP64 row read once by the row stage
+            CNT_ADD(C_D_BYTES, 12ull * (unsigned long long)R + 32ull * (unsigned long long)rows * (unsigned long long)nch +
+                                   (rows ? 8ull * (unsigned long long)s.B * (unsigned long long)R : 0ull));
             CNT_ADD(C_SPEC_PAIRS, (unsigned long long)R * (unsigned long long)(R - 1) / 2ull);
             CNT_ADD(C_RECHECKS, (unsigned long long)rows * (unsigned long long)(R - 1));
             tk1 = wall_clock64();
@@ -2154,6 +2157,7 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
         CNT_ADD(C_RECHECKS, nchk);
         CNT_ADD(C_ITERS, 1);
         CNT_ADD(C_MERGES, 1);
+        if (lp.incremental) CNT_ADD(C_D_BYTES, 16ull * (unsigned long long)E + 24ull * (unsigned long long)s.B);
         if (lp.incremental) {
             int nre = 0;
             avalid = merge_pair_inc(sh, s, win.si, win.sj, R, E, merges, kind, win.d2, rcs, anext, nre);
