@@ -1505,6 +1505,7 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
     const int surv = (lo_s == last) ? hi_s : lo_s;
     int* L = sh.u.f.cand;
     int* L2 = sh.u.f.cand + LCAP;
+    int* XL = sh.u.f.cand + 2 * LCAP;  // per edge of L: its other endpoint (-1: the merged pair itself)
     if (tid == 0) {
         sh.bcast_i[0] = 0;  // |L|
         sh.bcast_i[1] = 0;  // |L2|
@@ -1541,10 +1542,14 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
                 const int e = e0 + u * 2 * NT + h;
                 const int a = h ? ed[u].z : ed[u].x, b = h ? ed[u].w : ed[u].y;
                 const double vv = h ? v[u].y : v[u].x;
-                const bool touch = a == lo_s || a == hi_s || b == lo_s || b == hi_s;
+                const bool ta = a == lo_s || a == hi_s, tb = b == lo_s || b == hi_s;
+                const bool touch = ta || tb;
                 if (a >= 0 && touch) {
                     const int k = atomicAdd(&sh.bcast_i[0], 1);
-                    if (k < LCAP) L[k] = e;
+                    if (k < LCAP) {
+                        L[k] = e;
+                        XL[k] = (ta && tb) ? -1 : (ta ? b : a);
+                    }
                 }
                 if (a >= 0 && !touch && (a == last || b == last)) {
                     const int k = atomicAdd(&sh.bcast_i[1], 1);
@@ -1607,9 +1612,7 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
         if (tid == 0) s.st[9] = 0;
         return false;
     }
-    // rename the moved slot in L2; note the neighbour x of each edge in L (-1:
-    // the merged pair itself)
-    int* XL = sh.u.f.cand + 2 * LCAP;
+    // rename the moved slot in L2 (the edges of L carry their neighbour in XL)
     for (int k = tid; k < n2; k += NT) {
         const int e = L2[k];
         int2 ed = s.edges[e];
@@ -1617,12 +1620,7 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
         if (ed.y == last) ed.y = hi_s;
         s.edges[e] = ed;
     }
-    for (int k = tid; k < n1; k += NT) {
-        const int2 ed = s.edges[L[k]];
-        const bool ax = ed.x == lo_s || ed.x == hi_s, bx = ed.y == lo_s || ed.y == hi_s;
-        XL[k] = (ax && bx) ? -1 : (ax ? ed.y : ed.x);
-    }
-    __syncthreads();
+    __syncthreads();  // L2 is read through before its space is reused as K below
     // one edge per neighbour survives: the least edge slot (compared in LDS
     // for a short list, by an atomic minimum per neighbour otherwise)
     const bool short_list = n1 <= 64;
@@ -2259,9 +2257,20 @@ __global__ void __launch_bounds__(NT) k_wide_rows(const SecDev* __restrict__ sec
         pre[k + 1] = cnt;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        pre[0] = 0;
-        for (int k = 0; k < n; ++k) pre[k + 1] += pre[k];
+    if (wave_id() == 0) {  // inclusive scan of the task counts, 64 sections per step
+        const int lane = lane_id();
+        int carry = 0;
+        for (int k0 = 0; k0 < n; k0 += 64) {  // wavefront-uniform
+            const int k = k0 + lane;
+            int v = k < n ? pre[k + 1] : 0;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int u = __shfl_up(v, o);
+                if (lane >= o) v += u;
+            }
+            if (k < n) pre[k + 1] = v + carry;
+            carry += __shfl(v, 63);
+        }
+        if (lane == 0) pre[0] = 0;
     }
     __syncthreads();
     const int total = pre[n];
