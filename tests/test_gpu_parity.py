@@ -153,3 +153,13 @@ def test_workload_rhseg512_full_parity(prec):
     stats = assert_parity(sc.cube, p, precision=prec, tag="rhseg512 full")
     assert stats["merges"] == 512 * 512 - 8
     _say(f"[gpu] rhseg512 {prec}: {stats}")
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("B", [1000, 4096])
+def test_wide_band_counts(B, prec):
+    """The screened and plain forms at band counts up to the maximum (4096)."""
+    sc = synth.voronoi_scene(10, 9, B, K=4, sigma=25.0, seed=B + 3)
+    p = dict(connectivity=8, seam_connectivity=8, spclust_wght=0.5, spclust_max=90, rnb_levels=2,
+             section_regions=12, target_regions=2, level_counts=[30, 2])
+    assert_parity(sc.cube, p, precision=prec, tag=f"wide bands B={B} {prec}")

@@ -91,3 +91,17 @@ def test_workload_rhseg512_full_parity(prec):
     stats = assert_parity(sc.cube, p, precision=prec, incremental=True, tag="rhseg512 incremental")
     assert stats["merges"] == 512 * 512 - 8
     _say(f"[gpu] rhseg512 incremental {prec}: {stats}")
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("crit", ["bsmse", "sam"])
+@pytest.mark.parametrize("B", [600, 1000, 4096])
+def test_wide_band_counts(B, crit, mode, monkeypatch):
+    """Band counts past 512 up to the maximum (4096): the 16-chunk tree of the
+    exact evaluator, the wide-band row tasks of the persistent driver (10
+    counter levels) and of the wide kernels (64 groups per wavefront)."""
+    _mode(monkeypatch, mode)
+    sc = synth.voronoi_scene(12, 11, B, K=5, sigma=25.0, seed=B + 7)
+    p = dict(connectivity=4, seam_connectivity=8, spclust_wght=0.5, spclust_max=100, rnb_levels=2,
+             section_regions=20, target_regions=2, level_counts=[60, 10, 2], criterion=crit)
+    assert_parity(sc.cube, p, incremental=True, tag=f"row cache wide bands B={B} {crit} {mode}")
