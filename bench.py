@@ -180,10 +180,16 @@ def variant_tag(args):
     return ("" if args.criterion == "bsmse" else f"_{args.criterion}") + ("_two" if args.two_merges else "")
 
 
-def timed_steps(step, stream, torch, steps, warmup):
+def timed_steps(step, stream, torch, steps, warmup, first=None):
+    """Time `steps` calls after `warmup` untimed ones; the first warm-up call's
+    wall time (graph capture and instantiation included) goes to first[0]."""
     with torch.cuda.stream(stream):
-        for _ in range(warmup):
+        for w in range(warmup):
+            t0 = time.perf_counter()
             step()
+            if w == 0 and first is not None:
+                stream.synchronize()
+                first.append((time.perf_counter() - t0) * 1e3)
         stream.synchronize()
         torch.cuda.synchronize()
         walls, res = [], None
@@ -220,8 +226,9 @@ def bench_rhseg(args, np, torch, hswo, synth):
                                       graph=graph, autotune=args.autotune, kernel_times=kernel_times, **fk, **kw)
         return step
 
+    first = []
     ms_per_step, walls, res = timed_steps(runner(args.form, labels, args.graph), stream, torch, args.steps,
-                                          args.warmup)
+                                          args.warmup, first)
     st = res.stats
     pairs = st["adjacent_pairs"] + st["spectral_pairs"]
     fk = form_kwargs(args.form, args.precision)
@@ -234,8 +241,26 @@ def bench_rhseg(args, np, torch, hswo, synth):
                    "driver_variant": st["driver_variant"]},
         "pairs_per_step": pairs, "merges_per_step": st["merges"], "exact_evaluations_per_step": st["exact_rechecks"],
         "fp32_tiles_per_step": st["fp32_tiles"], "mfma_super_tiles_per_step": st["mfma_tiles"],
+        "first_call_ms": first[0] if first else None,
     }
     tag = f"{args.workload}_{args.form}" + variant_tag(args)
+    # the same step with the cube first copied from pinned host memory on the call's stream (the
+    # paper's times include that transfer); value stays the device-resident rate
+    pinned = torch.from_numpy(cube_h).pin_memory()
+    step = runner(args.form, labels, args.graph)
+
+    def step_h2d():
+        cube.copy_(pinned, non_blocking=True)
+        return step()
+    ms_h2d, _, _ = timed_steps(step_h2d, stream, torch, args.steps, 1)
+    with torch.cuda.stream(stream):
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            cube.copy_(pinned, non_blocking=True)
+        stream.synchronize()
+        h2d_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    out["with_h2d"] = {"ms_per_step": ms_h2d, "value": pairs / (ms_h2d / 1e3), "h2d_ms": h2d_ms,
+                       "h2d_bytes": int(cube_h.nbytes)}
     # per-kernel device times: one more step of the timed form, eager, every launch bracketed by hipEvents
     same_kt = None
     if not args.no_kernel_times:
@@ -282,6 +307,13 @@ def bench_rhseg(args, np, torch, hswo, synth):
                                          "counted as for the GPU value"}
         out["labels_identical_to_oracle"] = bool(np.array_equal(lab, ref.labels))
         out["gpu_vs_oracle_speedup"] = cpu_s * 1e3 / ms_per_step
+        if args.single_thread_oracle:
+            # the paper's sequential baseline: the oracle on one host thread
+            tc = time.perf_counter()
+            oracle.rhseg(cube_h, **params, n_threads=1)
+            one_s = time.perf_counter() - tc
+            out["cpu_single_thread"] = {"value": pairs / one_s, "unit": "pairs/s", "seconds": one_s,
+                                        "gpu_speedup": one_s * 1e3 / ms_per_step}
     return out, B
 
 
@@ -465,6 +497,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the runs of the forms not timed")
+    ap.add_argument("--single-thread-oracle", action="store_true",
+                    help="also time the oracle on one host thread (the paper's sequential baseline; ~45 s on "
+                         "rhseg512)")
     ap.add_argument("--sweep", choices=sorted(SWEEPS),
                     help="instead of the benchmark: GPU vs oracle over one of the paper-style sweeps")
     ap.add_argument("--no-kernel-times", action="store_true",
