@@ -46,9 +46,8 @@ constexpr int ST_WORDS = 16;  // per-section state words
 constexpr int GMAX = 256;     // wide mode: most workgroups per section
 constexpr int STILE = 128;    // matrix-core super tile edge (4 spectral tiles)
 
-// One section of one recursion level (or one independent batch section).
-// Partial result of a row-cache task: a row's best candidate among 64 columns.
-// Least and second least candidates of one row over a range of columns.
+// Partial result of a row-cache task: the least and second least candidates
+// of one row over a range of columns (64, then the whole row).
 struct RowPart {
     double d2;
     int32_t lab;   // partner label (orders equal D2 for a fixed row)
@@ -58,6 +57,7 @@ struct RowPart {
     int32_t slotb;
 };
 
+// One section of one recursion level (or one independent batch section).
 struct SecDev {
     int32_t R0;      // slot capacity (regions at the start of the pass, upper bound)
     int32_t B;       // bands
@@ -105,7 +105,7 @@ struct SecDev {
     int32_t* rbp2;   // [rcap] partner slot of the second bound (-1: none)
     int32_t* rbl2;   // [rcap] its partner label
     int32_t* rpend;  // [rcap] rows to re-evaluate: [0] the last merge's survivor, then stale rows
-    RowPart* rpart;  // [rcap][ceil(rcap / 64)] per-row, per-64-column partial minima
+    RowPart* rpart;  // [rcap][ceil(rcap / 64)] per-row, per-64-column least two candidates
     // wide mode iteration scratch
     int32_t* wi;     // [16]
     double* wd;      // [4]

@@ -915,9 +915,10 @@ __device__ __forceinline__ RowPart part_of(double d2, int lab, int slot) {
 // groups of 8 bands (fixed subtrees) combined through a binary counter; the
 // nbc chunk sums are then added in tree order from LDS. Column means come from
 // the band-major copy (coalesced over the lanes), row means from the
-// slot-major copy (the same for the whole wavefront). Each row's best
-// candidate among the 64 columns goes to rpart. Pending rows: the first np
-// slots (all) or rpend[0, np). Called by the whole block.
+// slot-major copy (the same for the whole wavefront). Each row's least two
+// candidates among the 64 columns go to rpart; the lanes of the survivor's
+// row (row 0 when not `all`) also take the light steps. Pending rows: the
+// first np slots (all) or rpend[0, np). Called by the whole block.
 // SAM: the spectral angle criterion (rows hold band sums; the tree adds the
 // products of the two rows and the result is finished with the rows' squared
 // norms).
@@ -1025,7 +1026,6 @@ __device__ void row_block_task(double (*rsum)[4][64], const SecDev& s, int R, in
     __syncthreads();  // rsum is reused by the next task
 }
 
-// Number of block tasks of a section's row cache stage this iteration.
 // One wavefront evaluates KR pending rows against 64 columns over all bands
 // (lane = column), for a workgroup that has the whole section to itself:
 // its waves take different column chunks. Bands are added in groups of 8
@@ -1124,6 +1124,7 @@ __device__ void row_wave_task(const SecDev& s, int R, int np, bool all, int bq, 
     }
 }
 
+// Number of tasks of a section's row cache stage this iteration (4 rows by 64 columns each).
 __device__ __forceinline__ int row_task_count(int R, int np) { return ((np + 3) / 4) * ((R + 63) >> 6); }
 
 __device__ __forceinline__ KeyD pair_key(const SecDev& s, double d2, int a, int b) {
@@ -2095,7 +2096,7 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
             M = spectral_min_rows(sh, s, R, rows, all);
             rcs = 2;
             npend = 0;
-            // bytes: cached pairs, partial minima, and every live FP64 row read once by the row stage
+            // bytes: cached pairs, row partials, and every live FP64 row read once by the row stage
             CNT_ADD(C_D_BYTES, 12ull * (unsigned long long)R + 32ull * (unsigned long long)rows * (unsigned long long)nch +
                                    (rows ? 8ull * (unsigned long long)s.B * (unsigned long long)R : 0ull));
             CNT_ADD(C_SPEC_PAIRS, (unsigned long long)R * (unsigned long long)(R - 1) / 2ull);
