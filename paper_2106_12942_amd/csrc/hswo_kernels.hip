@@ -431,6 +431,15 @@ __device__ __noinline__ double exact_seg(const SecDev& s, int si, int sj, int L)
     return sam ? sam_value(t0, t1, t2) : fac * t0;
 }
 
+// One pair per lane, for many pairs at once (defined with the row tasks' counter).
+__device__ __noinline__ double exact_lane(const SecDev& s, int si, int sj);
+
+// A merge that re-scores more edges than this takes them one per lane
+// (exact_lane): the survivor of a region that keeps absorbing its neighbours.
+// The pass-start scoring of every edge stays in segments, which measured
+// faster there.
+constexpr int LANE_PAIRS_MIN = 256;
+
 // Exact scores of the edges list[0, n) (list == nullptr: edges [0, n)) into
 // the per-edge cache, +inf for an empty slot; 64 / L edges per wavefront
 // when the bands fit an L-lane segment. Called by the whole block.
@@ -798,6 +807,70 @@ __device__ void abit_build(const SecDev& s, int R, int E) {
 __device__ __forceinline__ bool abit_test(const SecDev& s, int i, int j) {
     const int AW = (s.rcap + 31) >> 5;
     return (s.abit[(size_t)i * AW + (j >> 5)] >> (j & 31)) & 1u;
+}
+
+// The canonical criterion of pair (si, sj) by one lane (any lanes may hold
+// different pairs; si < 0: no pair, result meaningless). The bands go in
+// fixed groups of 8 (pairwise inside a group) whose sums join a binary
+// counter of finished subtrees: the same perfect tree over the zero-padded
+// bands as exact_d2_wave, as in the row tasks. Worth it when a block has many
+// pairs to score at once (a survivor of high degree): 512 at a time instead
+// of 64 / L per wavefront. Out of line to keep its counters out of its
+// callers' registers.
+__device__ __noinline__ double exact_lane(const SecDev& s, int si, int sj) {
+    constexpr int GB = 8, LV = 10;  // up to 1023 groups: B <= 4096
+    if (si < 0) return 0.0;
+    const int B = s.B;
+    const bool sam = s.crit == HSWO_CRIT_SAM;
+    const double* Si = s.sums + (size_t)si * B;
+    const double* Sj = s.sums + (size_t)sj * B;
+    const int n_i = s.npix[si], n_j = s.npix[sj];
+    const double dni = (double)n_i, dnj = (double)n_j;
+    const int ng = (B + GB - 1) / GB;
+    if (sam) {
+        double pd[LV], pi[LV], pj[LV];
+        for (int g = 0; g < ng; ++g) {
+            const int b0 = g * GB;
+            double td[GB], ti[GB], tj[GB];
+#pragma unroll
+            for (int k = 0; k < GB; ++k) {
+                const bool in = b0 + k < B;
+                const double x = in ? Si[b0 + k] : 0.0, y = in ? Sj[b0 + k] : 0.0;
+                td[k] = x * y;
+                ti[k] = x * x;
+                tj[k] = y * y;
+            }
+#pragma unroll
+            for (int h = 1; h < GB; h <<= 1)
+#pragma unroll
+                for (int k = 0; k < GB; k += 2 * h) {
+                    td[k] = td[k] + td[k + h];
+                    ti[k] = ti[k] + ti[k + h];
+                    tj[k] = tj[k] + tj[k + h];
+                }
+            counter_push<LV>(pd, td[0], g);
+            counter_push<LV>(pi, ti[0], g);
+            counter_push<LV>(pj, tj[0], g);
+        }
+        return sam_value(counter_total<LV>(pd, ng), counter_total<LV>(pi, ng), counter_total<LV>(pj, ng));
+    }
+    double p[LV];
+    for (int g = 0; g < ng; ++g) {
+        const int b0 = g * GB;
+        double t[GB];
+#pragma unroll
+        for (int k = 0; k < GB; ++k) {
+            const bool in = b0 + k < B;
+            const double d = in ? Si[b0 + k] / dni - Sj[b0 + k] / dnj : 0.0;
+            t[k] = d * d;
+        }
+#pragma unroll
+        for (int h = 1; h < GB; h <<= 1)
+#pragma unroll
+            for (int k = 0; k < GB; k += 2 * h) t[k] = t[k] + t[k + h];
+        counter_push<LV>(p, t[0], g);
+    }
+    return ((dni * dnj) / (double)(n_i + n_j)) * counter_total<LV>(p, ng);
 }
 
 // Start the row cache of a section at R live slots: FP64 means of every slot
@@ -1662,8 +1735,41 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
     const int nk = sh.bcast_i[2];
     const int emptied = sh.bcast_i[3];
     const int l_surv = s.label[surv];
-    const int Ls = seg_lanes(s.B);
-    if (Ls == 0) {
+    const int Ls = nk > LANE_PAIRS_MIN ? -1 : seg_lanes(s.B);
+    if (Ls < 0) {
+        // a survivor of high degree: one re-scored edge per lane
+        for (int q0 = 0; q0 < nk; q0 += NT) {  // block-uniform trip count
+            const int q = q0 + tid;
+            int a = -1, b = -1, la = 0, lb = 0, e = -1;
+            if (q < nk) {
+                const int k = K[q];
+                e = L[k];
+                const int x = XL[k] == last ? hi_s : XL[k];
+                const int lx = s.label[x];
+                a = surv;
+                b = x;
+                la = l_surv;
+                lb = lx;
+                if (la > lb) {
+                    a = x;
+                    b = surv;
+                    la = lx;
+                    lb = l_surv;
+                }
+            }
+            const double v = exact_lane(s, a, b);
+            if (q < nk) {
+                KeyD kk;
+                kk.d2 = v;
+                kk.lo = la;
+                kk.hi = lb;
+                kk.si = a;
+                kk.sj = b;
+                s.ed2[e] = v;
+                if (key_less(kk, best)) best = kk;
+            }
+        }
+    } else if (Ls == 0) {
         for (int q = wave_id(); q < nk; q += NWAVE) {
             const int k = K[q];
             const int e = L[k];
