@@ -215,3 +215,33 @@ def test_sequential_sections_identical(form):
     torch.cuda.synchronize()
     for i, c in enumerate(cubes):
         check_against_oracle(c, res.labels[i].cpu().numpy(), res.logs[i], BATCH_P, f"sequential batch {i}")
+
+
+@pytest.mark.parametrize("variant", [dict(), dict(criterion="sam"), dict(two_merges=True)],
+                         ids=["incremental", "sam", "two_merges"])
+def test_graph_replays_incremental_variants(variant):
+    """The incremental form and its variants, captured once and replayed
+    three times with other eager work in between (which reuses the
+    workspace-independent state of the library); every replay must equal the
+    oracle. The section state that carries across launches -- cached
+    minimum, row cache, the two-merge step -- starts afresh on each replay."""
+    sc = synth.voronoi_scene(64, 64, 24, 12, 25.0, 73)
+    other = synth.voronoi_scene(40, 40, 24, 8, 25.0, 74)
+    p = dict(connectivity=4, seam_connectivity=8, spclust_wght=0.6, spclust_max=300, target_regions=6,
+             section_regions=64, level_counts=[200, 30, 6], **variant)
+    ref = oracle.rhseg(sc.cube, **p, rnb_levels=2)
+    stream = torch.cuda.Stream()
+    cube = torch.from_numpy(sc.cube).cuda()
+    cube2 = torch.from_numpy(other.cube).cuda()
+    ws = hswo.Workspace()
+    with torch.cuda.stream(stream):
+        out = torch.empty((len(p["level_counts"]), 64, 64), dtype=torch.int32, device="cuda")
+        for k in range(3):
+            _say(f"[gpu] incremental graph replay {k} {variant}")
+            out.fill_(-7)
+            hswo.rhseg_segment(cube, rnb_levels=2, incremental=True, graph=True, stream=stream, workspace=ws,
+                               labels_out=out, **p)
+            stream.synchronize()
+            assert np.array_equal(out.cpu().numpy(), ref.labels), f"replay {k} differs"
+            hswo.rhseg_segment(cube2, rnb_levels=2, incremental=True, stream=stream, **p)  # eager work between
+            stream.synchronize()
