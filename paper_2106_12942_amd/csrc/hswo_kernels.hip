@@ -804,6 +804,53 @@ __device__ void abit_build(const SecDev& s, int R, int E) {
     __syncthreads();
 }
 
+// The bitmap after a merge of slots lo_s and hi_s (R live slots before it),
+// without a rebuild: the survivor (slot surv: lo_s, or hi_s when lo_s is the
+// last slot) takes the union of the pair's rows; every other live row ORs
+// the pair's two bits into the survivor's; the region in the last slot moves
+// to hi_s (its row is copied, and its bit in every row follows). The first
+// two touch disjoint rows; a barrier orders the survivor row's own bits and
+// the copy after them. Called by the whole block.
+__device__ void abit_merge(const SecDev& s, int lo_s, int hi_s, int R) {
+    const int AW = (s.rcap + 31) >> 5;
+    const int last = R - 1;
+    const int surv = (lo_s == last) ? hi_s : lo_s;
+    const bool moves = hi_s != last && surv != hi_s;
+    uint32_t* rl = s.abit + (size_t)lo_s * AW;
+    uint32_t* rh = s.abit + (size_t)hi_s * AW;
+    uint32_t* rs = s.abit + (size_t)surv * AW;
+    for (int w = threadIdx.x; w < AW; w += NT) rs[w] = rl[w] | rh[w];
+    for (int y = threadIdx.x; y < R; y += NT) {
+        if (y == lo_s || y == hi_s) continue;
+        uint32_t* row = s.abit + (size_t)y * AW;
+        const uint32_t v = ((row[lo_s >> 5] >> (lo_s & 31)) | (row[hi_s >> 5] >> (hi_s & 31))) & 1u;
+        const uint32_t vl = (row[last >> 5] >> (last & 31)) & 1u;
+        if (surv == lo_s) {
+            row[lo_s >> 5] = (row[lo_s >> 5] & ~(1u << (lo_s & 31))) | (v << (lo_s & 31));
+            const uint32_t vh = moves ? vl : 0u;
+            row[hi_s >> 5] = (row[hi_s >> 5] & ~(1u << (hi_s & 31))) | (vh << (hi_s & 31));
+        } else {
+            row[hi_s >> 5] = (row[hi_s >> 5] & ~(1u << (hi_s & 31))) | (v << (hi_s & 31));
+        }
+        row[last >> 5] &= ~(1u << (last & 31));  // the last slot is empty now (the survivor is never there)
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t bl = (rs[last >> 5] >> (last & 31)) & 1u;
+        rs[lo_s >> 5] &= ~(1u << (lo_s & 31));
+        rs[hi_s >> 5] &= ~(1u << (hi_s & 31));
+        if (moves) {
+            rs[last >> 5] &= ~(1u << (last & 31));
+            rs[hi_s >> 5] |= bl << (hi_s & 31);
+        }
+    }
+    if (moves) {
+        const uint32_t* rx = s.abit + (size_t)last * AW;
+        for (int w = threadIdx.x; w < AW; w += NT) rh[w] = rx[w];
+    }
+    __syncthreads();
+}
+
 __device__ __forceinline__ bool abit_test(const SecDev& s, int i, int j) {
     const int AW = (s.rcap + 31) >> 5;
     return (s.abit[(size_t)i * AW + (j >> 5)] >> (j & 31)) & 1u;
@@ -2273,7 +2320,7 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
         ++merges;
         --R;
         if (rcs == 2) npend = sh.npend;
-        if (s.abit && rcs) abit_build(s, R, E);
+        if (s.abit && rcs) abit_merge(s, win.si, win.sj, R + 1);
         if (row_cache && rcs == 0 && lp.spectral && R <= lp.kmax && R > s.stop) {
             rowcache_begin(sh, s, R, E);  // the spectral stage starts with the next iteration
             rcs = 1;
@@ -2510,7 +2557,7 @@ __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ s
                 s.st[1] = E;
                 if (row_cache) s.st[6] = rcs;
             }
-            if (s.abit && rcs) abit_build(s, R - 1, E);
+            if (s.abit && rcs) abit_merge(s, win.si, win.sj, R);
             if (row_cache && rcs == 0 && lp.spectral && R - 1 <= lp.kmax && R - 1 > s.stop)
                 rowcache_begin(sh, s, R - 1, E);
         }
