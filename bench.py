@@ -64,7 +64,15 @@ WORKLOAD_DESC = {
               "<=256 regions; target 2; 11 levels",
     "batch256": "256 independent f32 sections, side U{32..128}, bands U{64..224 step 32}, 10-120 Voronoi "
                 "classes, sigma 30, seeds 404000+s; each merged to 256 regions; w 0.5; spectral at <=1024",
+    "rhseg1024_salt": "1024x1024x220 f32 endmember mixture (300 classes, sigma 25, seed 303, 5% identical salt "
+                      "pixels); rnb_levels 5; w 0.5; spectral at <=1024; sections stop at 256; target 8",
+    "rhseg2048_f16": "2048x2048x224 f16 endmember mixture (500 classes, sigma 25, seed 505); rnb_levels 5; w 0.5; "
+                     "spectral at <=2048; sections stop at 512; target 16",
 }
+
+# workloads whose oracle and plain-path runs take minutes: timed on the GPU only (their parity with the
+# oracle is checked by the GPU tests)
+LARGE = ("rhseg1024_salt", "rhseg2048_f16")
 
 
 def traffic_from_profiles(tag: str):
@@ -272,7 +280,8 @@ def bench_rhseg(args, np, torch, hswo, synth):
     lab = labels.cpu().numpy()
     comparisons = {}
     for form in ("plain", "plain_batched", "screened", "incremental"):
-        if form == args.form or (form.startswith("plain") and args.no_plain) or args.no_forms:
+        if form == args.form or (form.startswith("plain") and (args.no_plain or args.workload in LARGE)) or \
+                args.no_forms:
             continue
         if variant_tag(args) and form != "incremental":
             continue  # the other criterion and the two-merge reading exist in the incremental form only
@@ -295,7 +304,10 @@ def bench_rhseg(args, np, torch, hswo, synth):
                                    **{f: pm / v["ms_per_step"] for f, v in comparisons.items() if f != "plain"}}
     out["forms"] = comparisons
     out["labels_identical_kernel_times_step"] = same_kt
-    if not args.no_cpu_baseline:
+    if args.workload in LARGE:
+        out["cpu_baseline"] = None
+        out["cpu_baseline_note"] = "not run for this workload (the oracle takes minutes); parity is checked by the GPU tests"
+    elif not args.no_cpu_baseline:
         import oracle
         threads = os.cpu_count() or 1
         tc = time.perf_counter()
