@@ -387,9 +387,16 @@ int timed_driver(Timer* tm, const SecDev* secs, int n, const LoopParams& lp, int
 
 // How a level's merge loops run: persistent (one workgroup per section, one
 // launch) or wide (G workgroups per section, one launch sequence per iteration).
-int wide_max_sections() {
+int device_cus();
+
+// Levels of more sections than this run in the persistent driver. Measured:
+// the screened and plain forms gain from wide mode up to 64 sections (G >= 4,
+// on the 512x512 workload); the incremental form gains up to one workgroup per
+// section, because its row evaluations pool over the whole device (the
+// 1024x1024 salt cube's 256 leaves: 2.0 s persistent, 1.23 s wide).
+int wide_max_sections(bool incremental) {
     if (const char* e = getenv("HSWO_WIDE_MAX_SECTIONS")) return atoi(e);
-    return 64;  // measured on the 512x512 workload: its 64 leaves run faster wide (G = 4)
+    return incremental ? device_cus() : 64;
 }
 
 int device_cus() {
@@ -418,7 +425,7 @@ bool hybrid_on() {
 
 int run_level(Timer* tm, const SecDev* secs, int n, const std::vector<int64_t>& cap, const std::vector<int64_t>& stop,
               const LoopParams& lp, bool row_cache, int variant, hipStream_t stream) {
-    if (n > wide_max_sections() || (row_cache && n > ROWS_MAX_SECTIONS))
+    if (n > wide_max_sections(lp.incremental) || (row_cache && n > ROWS_MAX_SECTIONS))
         return timed_driver(tm, secs, n, lp, variant, stream);
     const int G = std::max(1, std::min(GMAX, device_cus() / n));
     // R of each section when the wide iterations start
