@@ -46,9 +46,17 @@ def _gkey(v, i, j):
 
 
 class Model:
-    """Row cache over region labels, with optional adjacency masking."""
+    """Row cache over region labels, with optional adjacency masking.
 
-    def __init__(self, S, n, labels, crit, adj=None):
+    keep_dead: a second bound whose partner merged stays as a bare lower
+    bound (its value and label); a stale row with such a bound takes the
+    light step when its pair with the survivor is at or below the bound, and
+    is evaluated in full otherwise (`fallback` counts those)."""
+
+    def __init__(self, S, n, labels, crit, adj=None, keep_dead=False):
+        self.keep_dead = keep_dead
+        self.dead = set()  # rows whose second bound's partner has merged
+        self.fallback = 0
         self.S = {int(l): S[k].copy() for k, l in enumerate(labels)}
         self.n = {int(l): float(n[k]) for k, l in enumerate(labels)}
         self.crit = _sam if crit == "sam" else _bsmse
@@ -73,13 +81,23 @@ class Model:
             self.K1[i] = row[0] if row else None
             self.K2[i] = row[1] if len(row) > 1 else None
             self.n_full += 1
-        for i in self.light:
+        for i in sorted(self.light):
             c = (self.value(i, self.surv), self.surv)
-            if c <= self.K2[i]:
+            if c <= self.K2[i]:  # also for a bare bound: it stays a lower bound of the row's old pairs
                 self.K1[i] = c if c[0] < INF else None
-            else:
+                self.n_light += 1
+            elif i not in self.dead:
                 self.K1[i], self.K2[i] = self.K2[i], None
-            self.n_light += 1
+                self.n_light += 1
+            else:  # a bare bound below the new pair: look at the row in full
+                row = sorted((self.value(i, j), j) for j in self.S if j != i)
+                row = [r for r in row if r[0] < INF]
+                self.K1[i] = row[0] if row else None
+                self.K2[i] = row[1] if len(row) > 1 else None
+                self.dead.discard(i)
+                self.fallback += 1
+        for i in self.full:
+            self.dead.discard(i)
         self.full, self.light = set(), set()
 
     def minimum(self):
@@ -128,8 +146,11 @@ class Model:
         for i in self.S:
             if i == lo:
                 continue
-            if self.K2.get(i) is not None and self.K2[i][1] in (lo, hi):
-                self.K2[i] = None  # its partner changed: no longer a live pair's key
+            if self.K2.get(i) is not None and self.K2[i][1] in (lo, hi) and i not in self.dead:
+                if self.keep_dead:
+                    self.dead.add(i)  # a bare lower bound from now on (value and partner label kept)
+                else:
+                    self.K2[i] = None  # its partner changed: no longer a live pair's key
             k = self.K1.get(i)
             if k is not None and k[1] in (lo, hi):
                 (self.light if self.K2.get(i) is not None else self.full).add(i)
@@ -153,7 +174,7 @@ def _pixel_adjacency(H, W, conn):
     return adj
 
 
-def _replay(cube, crit, kmax, two_merges=False, w=0.5, conn=4):
+def _replay(cube, crit, kmax, two_merges=False, w=0.5, conn=4, keep_dead=False):
     """Oracle merge sequence of one section; the model takes over at R = kmax."""
     H, W, B = cube.shape
     ref = oracle.rhseg(cube, connectivity=conn, spclust_wght=w, spclust_max=kmax, target_regions=2,
@@ -181,7 +202,8 @@ def _replay(cube, crit, kmax, two_merges=False, w=0.5, conn=4):
                 adj[x].add(lo)
         k += 1
     labels = sorted(regS)
-    m = Model(np.array([regS[l] for l in labels]), np.array([regn[l] for l in labels]), labels, crit, adj)
+    m = Model(np.array([regS[l] for l in labels]), np.array([regn[l] for l in labels]), labels, crit, adj,
+              keep_dead=keep_dead)
     return m, ref.log[k:]
 
 
@@ -195,11 +217,12 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("keep_dead", [False, True], ids=["bound_dropped", "bare_bound_kept"])
 @pytest.mark.parametrize("name,make,crit,two", CASES, ids=[c[0] for c in CASES])
-def test_second_bound_keeps_the_minimum(name, make, crit, two):
+def test_second_bound_keeps_the_minimum(name, make, crit, two, keep_dead):
     cube = make()
     H, W, _ = cube.shape
-    m, log = _replay(cube, crit, kmax=H * W // 2, two_merges=two, w=1.0 if two else 0.5)
+    m, log = _replay(cube, crit, kmax=H * W // 2, two_merges=two, w=1.0 if two else 0.5, keep_dead=keep_dead)
     spectral = 0
     for rec in log:
         m.evaluate()
@@ -227,3 +250,22 @@ def test_light_rows_carry_the_spectral_angle_pattern():
         m.evaluate()
     full = m.n_full - start
     assert m.n_light > 1.2 * full, (m.n_light, full)
+
+
+def test_bare_bounds_spare_full_evaluations_on_salt_ties():
+    """Identical salt spectra tie at D2 = 0: a stale row's second bound often
+    names a salt region that has merged too. Kept as a bare lower bound it
+    still allows the light step whenever the pair with the survivor is at or
+    below it."""
+    cube = synth.mixer_scene(16, 16, 8, 6, 25.0, 17, salt=0.2).cube
+    runs = {}
+    for keep in (False, True):
+        m, log = _replay(cube, "bsmse", kmax=160, w=1.0, keep_dead=keep)
+        m.evaluate()
+        start = m.n_full
+        for rec in log:
+            m.merge(int(rec["lo"]), int(rec["hi"]))
+            m.evaluate()
+            assert m.minimum() == m.check()
+        runs[keep] = (m.n_full - start + m.fallback, m.n_light)
+    assert runs[True][0] < runs[False][0], runs
