@@ -192,7 +192,9 @@ typedef struct hswo_stats {
        16 per edge slot (endpoints and cached D2 read for the minimum)
        + 24 per band per merge (two FP64 sum rows read, one written)
        + in the spectral stage 12 per live row (cached pair) and 32 per
-       pending row per 64 live rows (least two candidates of each 64 columns);
+       pending row per 64 live rows (least two candidates of each 64 columns),
+       + 8 per band per live region when rows whose second bound no longer
+       holds are evaluated in full before the minimum;
        HSWO_K_WIDE_ROWS flops = 3 per band per pair evaluated (2 for the
        spectral angle);
        HSWO_K_SECTION_DRIVER (incremental form) bytes = the HSWO_K_WIDE_DECIDE

@@ -147,6 +147,8 @@ int64_t tiles_for(int64_t cap, const hswo_params* p) {
 
 // The incremental form keeps exact spectral rows instead of screening every
 // pair each iteration (the 16-bit screen rows are then not needed).
+int bare_bounds_mode();
+
 bool row_cache_on(const hswo_params* p) {
     return (p->flags & HSWO_FLAG_INCREMENTAL) && p->spclust_wght > 0.0f && p->spclust_max > 0;
 }
@@ -255,6 +257,7 @@ Layout carve(const Plan& pl, int H, int W, const hswo_params* p, void* ws, const
             s.log_base = (int32_t)log_base;
             s.tiles = (int32_t)sp.tiles;
             s.crit = p->criterion;
+            s.bare = bare_bounds_mode();
             s.label = bp.take<int32_t>(sp.cap);
             s.npix = bp.take<int32_t>(sp.cap);
             s.mark = bp.take<int32_t>(sp.cap);
@@ -397,6 +400,16 @@ int device_cus();
 int wide_max_sections(bool incremental) {
     if (const char* e = getenv("HSWO_WIDE_MAX_SECTIONS")) return atoi(e);
     return incremental ? device_cus() : 64;
+}
+
+// Which second bounds of the row cache stay as bare bounds once their
+// partner merges (result-neutral): 1 (default) those of value 0, 0 none,
+// 2 all. HSWO_BARE_BOUNDS overrides.
+int bare_bounds_mode() {
+    const char* e = getenv("HSWO_BARE_BOUNDS");
+    if (!e) return 1;
+    const int v = atoi(e);
+    return v < 0 ? 0 : (v > 2 ? 2 : v);
 }
 
 int device_cus() {
@@ -935,6 +948,7 @@ BatchLayout carve_batch(int n, const hswo_section* sec, const hswo_params* p, vo
         s.log_base = 0;
         s.tiles = (int32_t)tiles;
         s.crit = p->criterion;
+        s.bare = bare_bounds_mode();
         s.label = bp.take<int32_t>(cap);
         s.npix = bp.take<int32_t>(cap);
         s.mark = bp.take<int32_t>(cap);

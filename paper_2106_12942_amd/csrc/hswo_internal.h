@@ -88,6 +88,8 @@ struct SecDev {
     int32_t kcap;    // rows available for the 16-bit screen (0 on the plain path)
     int32_t rcap;    // rows of the spectral row cache (0 when it is off)
     int32_t crit;    // HSWO_CRIT_* dissimilarity criterion
+    int32_t bare;    // row cache: second bounds kept bare when their partner merges -- 0 none, 1 those of
+                     // value 0, 2 all (result-neutral; more light steps, more of them fall back)
     // incremental adjacent stage: exact D2 per edge slot and the edges to refresh
     double* ed2;     // [Ecap]
     int32_t* edirty; // [Ecap]
@@ -102,7 +104,8 @@ struct SecDev {
     int32_t* rbl;    // [rcap] partner label of that pair
     double* rbd2;    // [rcap] second bound: the least D2 over the row's other partners at its last full
                      //        evaluation (valid while rbp2 >= 0, i.e. while that partner is alive)
-    int32_t* rbp2;   // [rcap] partner slot of the second bound (-1: none)
+    int32_t* rbp2;   // [rcap] partner slot of the second bound (-1: none, -3: a bound of value 0 whose
+                     //        partner has merged since; it still bounds the row's other pairs)
     int32_t* rbl2;   // [rcap] its partner label
     int32_t* rpend;  // [rcap] rows to re-evaluate: [0] the last merge's survivor, then stale rows
     RowPart* rpart;  // [rcap][ceil(rcap / 64)] per-row, per-64-column least two candidates
@@ -116,7 +119,8 @@ struct SecDev {
                      //        [7] pending rows of the row cache,
                      //        [8] incremental form: next adjacent minimum cached (wd[2], wi[8..11]),
                      //        [9] empty edge slots left by incremental merges,
-                     //        [10] two-merge reading: step 3 due (threshold in wd[3])
+                     //        [10] two-merge reading: step 3 due (threshold in wd[3]),
+                     //        [11] rows appended to the pending list by failed light steps
     int32_t* parent; // label-indexed union-find parent (image or batch section)
     int32_t* mtime;  // label-indexed merge time: -1 non-top merge, k top merge, INT_MAX alive
     hswo_merge_rec* log;  // section merge log base (may be null)

@@ -953,6 +953,7 @@ __device__ void rowcache_begin(Smem& sh, const SecDev& s, int R, int E) {
     if (threadIdx.x == 0) {
         s.st[6] = 1;
         s.st[7] = 0;
+        s.st[11] = 0;
     }
     __syncthreads();
 }
@@ -1002,17 +1003,24 @@ __device__ __forceinline__ RowPart shfl_xor_part(const RowPart& r, int o) {
 // then spent. Exact: the second bound is at or below every pair the row had
 // at its last full evaluation except its old partner, and each pair created
 // since is bounded by its other row, evaluated in full when it was created.
+// A bare bound (rbp2 = -3: its partner has merged since) still bounds the
+// row's old pairs, so the step stands when c is at or below it; otherwise the
+// row is appended to the pending list (rpend[np + k], k counted in st[11])
+// for a full evaluation before the decision.
 __device__ __forceinline__ void light_step(const SecDev& s, int j, int surv, int lsurv, double c, double d2b, int lb,
-                                           int pb) {
-    if (!cand_less(c, lsurv, d2b, lb)) {
+                                           int pb, int np) {
+    if (cand_less(c, lsurv, d2b, lb) || (c == d2b && lsurv == lb)) {
+        s.rbd[j] = c;
+        s.rbp[j] = surv;
+        s.rbl[j] = lsurv;
+    } else if (pb >= 0) {
         s.rbd[j] = d2b;
         s.rbp[j] = pb;
         s.rbl[j] = lb;
         s.rbp2[j] = -1;
     } else {
-        s.rbd[j] = c;
-        s.rbp[j] = surv;
-        s.rbl[j] = lsurv;
+        s.rbp[j] = -1;
+        s.rpend[np + atomicAdd(&s.st[11], 1)] = j;
     }
 }
 
@@ -1135,7 +1143,7 @@ __device__ void row_block_task(double (*rsum)[4][64], const SecDev& s, int R, in
                 lab = INT_MAX;
                 slot = -1;
             }
-            if (light && lmark == -2) light_step(s, j, i, s.label[i], d2, s.rbd2[j], s.rbl2[j], s.rbp2[j]);
+            if (light && lmark == -2) light_step(s, j, i, s.label[i], d2, s.rbd2[j], s.rbl2[j], s.rbp2[j], np);
             // for a fixed row the pair order (D2, lo, hi) is the order of (D2, partner label)
             RowPart rp = part_of(d2, lab, slot);
 #pragma unroll
@@ -1234,13 +1242,53 @@ __device__ void row_wave_task(const SecDev& s, int R, int np, bool all, int bq, 
             lab = INT_MAX;
             slot = -1;
         }
-        if (light && r == 0 && lmark == -2) light_step(s, j, i, s.label[i], d2, s.rbd2[j], s.rbl2[j], s.rbp2[j]);
+        if (light && r == 0 && lmark == -2) light_step(s, j, i, s.label[i], d2, s.rbd2[j], s.rbl2[j], s.rbp2[j], np);
         RowPart rp = part_of(d2, lab, slot);
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) top2_merge(rp, shfl_xor_part(rp, o));
         if (lane == 0) {
             s.rpart[(size_t)(bq * KR + r) * nch + c] = rp;
         }
+    }
+}
+
+// The rows that failed their light step (rpend[np, np + nf)) evaluated in
+// full by this block, before the decision: a wavefront task per row and
+// 64-column chunk, with the partials where the row stage puts them.
+__device__ __forceinline__ void rows_fallback_body(const SecDev& s, int R, int np, int nf) {
+    const int nch = (R + 63) >> 6;
+    const int ntask = nf * nch;
+    for (int t = wave_id(); t < ntask; t += NWAVE) {
+        const int q = np + t / nch, c = t % nch;
+        if (s.crit == HSWO_CRIT_SAM) {
+            if (s.B <= 512)
+                row_wave_task<1, 7, true>(s, R, np + nf, false, q, c);
+            else
+                row_wave_task<1, 10, true>(s, R, np + nf, false, q, c);
+        } else if (s.B <= 512) {
+            row_wave_task<1, 7, false>(s, R, np + nf, false, q, c);
+        } else {
+            row_wave_task<1, 10, false>(s, R, np + nf, false, q, c);
+        }
+    }
+}
+
+// The same with one pair per lane through exact_lane (same values), for a
+// kernel whose registers are taken: a call of the full row evaluation would
+// give it a stack.
+__device__ __forceinline__ void rows_fallback_lanes(const SecDev& s, int R, int np, int nf) {
+    const int nch = (R + 63) >> 6;
+    const int ntask = nf * nch;
+    for (int t = wave_id(); t < ntask; t += NWAVE) {
+        const int q = np + t / nch, c = t % nch;
+        const int i = s.rpend[q];
+        const int j = (c << 6) + lane_id();
+        const bool ok = j < R && j != i && !(s.abit && abit_test(s, i, j));
+        const double d2 = exact_lane(s, ok ? i : -1, j);
+        RowPart rp = ok ? part_of(d2, s.label[j], j) : part_of(__builtin_huge_val(), INT_MAX, -1);
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) top2_merge(rp, shfl_xor_part(rp, o));
+        if (lane_id() == 0) s.rpart[(size_t)q * nch + c] = rp;
     }
 }
 
@@ -1529,18 +1577,20 @@ __device__ __noinline__ void merge_slots(Smem& sh, const SecDev& s, int lo_s, in
             if (i == lo_s || i == hi_s) continue;
             const int ni = (i == last) ? hi_s : i;
             const int p = s.rbp[i];
-            // the second bound is dropped with its partner and follows a moved one
+            // the second bound follows a moved partner; when its partner is merged it stays as a
+            // bare bound (-3) by default only if its value is 0 (identical spectra, where the
+            // merged region usually ties again), else it is dropped
             const int p2 = s.rbp2[i];
-            const int np2 = (p2 == lo_s || p2 == hi_s) ? -1 : (p2 == last ? hi_s : p2);
+            const bool keep = s.bare == 2 || (s.bare == 1 && s.rbd2[i] == 0.0);
+            const int np2 = (p2 == lo_s || p2 == hi_s) ? (keep ? -3 : -1) : (p2 == last ? hi_s : p2);
             if (ni != i) {
                 s.rbd2[ni] = s.rbd2[i];
                 s.rbl2[ni] = s.rbl2[i];
             }
             if (ni != i || np2 != p2) s.rbp2[ni] = np2;
             if (p == lo_s || p == hi_s) {
-                // stale: a light step (marked -2) when its second bound's partner is alive, else a
-                // full evaluation
-                if (np2 >= 0) {
+                // stale: a light step (marked -2) when it has a second bound, else a full evaluation
+                if (np2 != -1) {
                     s.rbp[ni] = -2;
                 } else {
                     s.rbp[ni] = -1;
@@ -1561,7 +1611,10 @@ __device__ __noinline__ void merge_slots(Smem& sh, const SecDev& s, int lo_s, in
             s.rbp[surv] = -1;
         }
         __syncthreads();
-        if (tid == 0) s.st[7] = sh.npend;
+        if (tid == 0) {
+            s.st[7] = sh.npend;
+            s.st[11] = 0;  // rows the light steps will append
+        }
     }
     __syncthreads();
 }
@@ -2246,12 +2299,22 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
                     row_wave_task<4, 10, false>(s, R, rows, all, t / nch, t % nch);
             }
             __syncthreads();
-            M = spectral_min_rows(sh, s, R, rows, all);
+            // rows whose light step fell back on a full evaluation (appended by other wavefronts)
+            const int nf = all ? 0 : __hip_atomic_load(&s.st[11], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (nf > 0) {
+                rows_fallback_body(s, R, rows, nf);
+                __syncthreads();
+            }
+            M = spectral_min_rows(sh, s, R, rows + nf, all);
             rcs = 2;
             npend = 0;
             // bytes: cached pairs, row partials, and every live FP64 row read once by the row stage
-            CNT_ADD(C_D_BYTES, 12ull * (unsigned long long)R + 32ull * (unsigned long long)rows * (unsigned long long)nch +
-                                   (rows ? 8ull * (unsigned long long)s.B * (unsigned long long)R : 0ull));
+            // (once more by the fallback)
+            CNT_ADD(C_D_BYTES, 12ull * (unsigned long long)R +
+                                   32ull * (unsigned long long)(rows + nf) * (unsigned long long)nch +
+                                   (rows ? 8ull * (unsigned long long)s.B * (unsigned long long)R : 0ull) +
+                                   (nf ? 8ull * (unsigned long long)s.B * (unsigned long long)R : 0ull));
+            CNT_ADD(C_RECHECKS, (unsigned long long)nf * (unsigned long long)(R - 1));
             CNT_ADD(C_SPEC_PAIRS, (unsigned long long)R * (unsigned long long)(R - 1) / 2ull);
             CNT_ADD(C_RECHECKS, (unsigned long long)rows * (unsigned long long)(R - 1));
             tk1 = wall_clock64();
@@ -2339,6 +2402,7 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
         if (row_cache) {
             s.st[6] = rcs;
             s.st[7] = npend;
+            s.st[11] = 0;  // appended rows are folded in within their iteration
         }
         s.st[8] = 0;  // the driver keeps its adjacent minimum in registers
         if (lp.two_merges) {
@@ -2464,6 +2528,8 @@ __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ s
     const int tid = threadIdx.x;
     const int R = s.st[0];
     int E = s.st[1];
+    // rows whose light step in k_wide_rows fell back on a full evaluation
+    const int nfall = s.st[11];
     if (R <= s.stop) {
         if (tid == 0) s.wi[0] = 0;
         return;
@@ -2503,9 +2569,17 @@ __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ s
         if (spectral) {
             const bool all = rcs == 1;
             const int np = all ? R : s.st[7];
-            M = spectral_min_rows(sh, s, R, np, all);
+            const int nf = all ? 0 : nfall;
+            if (nf > 0) {
+                rows_fallback_lanes(s, R, np, nf);
+                __syncthreads();
+                nchk += nf * (R - 1);
+                decide_bytes += 8ull * (unsigned long long)s.B * (unsigned long long)R;
+            }
+            M = spectral_min_rows(sh, s, R, np + nf, all);
             rcs = 2;
-            decide_bytes += 12ull * (unsigned long long)R + 32ull * (unsigned long long)np * (unsigned long long)((R + 63) >> 6);
+            decide_bytes += 12ull * (unsigned long long)R +
+                            32ull * (unsigned long long)(np + nf) * (unsigned long long)((R + 63) >> 6);
         }
         KeyD win;
         int kind;
@@ -2534,6 +2608,7 @@ __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ s
         if (!merge_now && row_cache && tid == 0) {
             s.st[6] = rcs;  // the pending rows were folded in above
             s.st[7] = 0;
+            s.st[11] = 0;
         }
         if (merge_now) {
             const int stamp = s.st[3];
@@ -2776,6 +2851,7 @@ __global__ void k_init_leaves(const SecDev* __restrict__ secs, const InitDev* __
         s.st[8] = 0;
         s.st[9] = 0;
         s.st[10] = 0;
+        s.st[11] = 0;
     }
 }
 
@@ -2830,6 +2906,7 @@ __global__ void k_assemble(const SecDev* __restrict__ parents, const SecDev* __r
             p.st[8] = 0;
             p.st[9] = 0;
             p.st[10] = 0;
+            p.st[11] = 0;
         }
         return;
     }
@@ -2870,6 +2947,7 @@ __global__ void k_assemble(const SecDev* __restrict__ parents, const SecDev* __r
         p.st[8] = 0;
         p.st[9] = 0;
         p.st[10] = 0;
+        p.st[11] = 0;
     }
 }
 

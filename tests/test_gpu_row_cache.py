@@ -105,3 +105,34 @@ def test_wide_band_counts(B, crit, mode, monkeypatch):
     p = dict(connectivity=4, seam_connectivity=8, spclust_wght=0.5, spclust_max=100, rnb_levels=2,
              section_regions=20, target_regions=2, level_counts=[60, 10, 2], criterion=crit)
     assert_parity(sc.cube, p, incremental=True, tag=f"row cache wide bands B={B} {crit} {mode}")
+
+
+BARE_SCENES = {
+    "salt": (lambda: synth.mixer_scene(40, 40, 12, K=8, sigma=25.0, seed=7, salt=0.2).cube,
+             dict(connectivity=4, seam_connectivity=8, spclust_wght=1.0, spclust_max=1600, rnb_levels=2,
+                  section_regions=100, target_regions=5, level_counts=[300, 40, 5])),
+    "voronoi": (lambda: synth.voronoi_scene(48, 40, 16, K=10, sigma=25.0, seed=12).cube,
+                dict(connectivity=8, seam_connectivity=8, spclust_wght=0.6, spclust_max=400, rnb_levels=2,
+                     section_regions=60, target_regions=4, level_counts=[150, 20, 4])),
+}
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("variant", ["bsmse", "sam", "two_merges"])
+@pytest.mark.parametrize("scene", sorted(BARE_SCENES))
+@pytest.mark.parametrize("bare", ["0", "2"])
+def test_bare_bound_modes(bare, scene, variant, mode, monkeypatch):
+    """Second bounds whose partner merged: dropped (0), or all kept as bare
+    bounds (2; the default keeps those of value 0). Keeping them all makes
+    many light steps fail, and those rows are evaluated in full before the
+    decision (in the decision kernel in wide mode): the results must not
+    change."""
+    _mode(monkeypatch, mode)
+    monkeypatch.setenv("HSWO_BARE_BOUNDS", bare)
+    make, p = BARE_SCENES[scene]
+    p = dict(p)
+    if variant == "sam":
+        p["criterion"] = "sam"
+    elif variant == "two_merges":
+        p["two_merges"] = True
+    assert_parity(make(), p, incremental=True, tag=f"bare bounds {bare} {scene} {variant} {mode}")
