@@ -1581,8 +1581,9 @@ __device__ __noinline__ void merge_slots(Smem& sh, const SecDev& s, int lo_s, in
             // bare bound (-3) by default only if its value is 0 (identical spectra, where the
             // merged region usually ties again), else it is dropped
             const int p2 = s.rbp2[i];
-            const bool keep = s.bare == 2 || (s.bare == 1 && s.rbd2[i] == 0.0);
-            const int np2 = (p2 == lo_s || p2 == hi_s) ? (keep ? -3 : -1) : (p2 == last ? hi_s : p2);
+            int np2 = p2 == last ? hi_s : p2;
+            if (p2 == lo_s || p2 == hi_s)  // the value is read only here
+                np2 = (s.bare == 2 || (s.bare == 1 && s.rbd2[i] == 0.0)) ? -3 : -1;
             if (ni != i) {
                 s.rbd2[ni] = s.rbd2[i];
                 s.rbl2[ni] = s.rbl2[i];
