@@ -136,3 +136,17 @@ def test_bare_bound_modes(bare, scene, variant, mode, monkeypatch):
     elif variant == "two_merges":
         p["two_merges"] = True
     assert_parity(make(), p, incremental=True, tag=f"bare bounds {bare} {scene} {variant} {mode}")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_bare_bound_mode_reaches_the_device(mode, monkeypatch):
+    """The switch is read per call: keeping every bound changes the number of
+    exact evaluations (light steps replace full rows, failed ones add them)."""
+    _mode(monkeypatch, mode)
+    make, p = BARE_SCENES["voronoi"]
+    cube = make()
+    n = {}
+    for bare in ("0", "2"):
+        monkeypatch.setenv("HSWO_BARE_BOUNDS", bare)
+        n[bare] = assert_parity(cube, dict(p), incremental=True, tag=f"bare bounds count {bare} {mode}")["exact_rechecks"]
+    assert n["0"] != n["2"], n
