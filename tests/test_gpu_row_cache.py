@@ -6,7 +6,7 @@ modes (one workgroup per section, or G workgroups per section)."""
 import numpy as np
 import pytest
 
-from paper_2106_12942_amd import synth
+from paper_2106_12942_amd import hswo, synth
 from tests.test_gpu_parity import TINY, _say, assert_parity
 
 pytestmark = pytest.mark.gpu
@@ -150,3 +150,23 @@ def test_bare_bound_mode_reaches_the_device(mode, monkeypatch):
         monkeypatch.setenv("HSWO_BARE_BOUNDS", bare)
         n[bare] = assert_parity(cube, dict(p), incremental=True, tag=f"bare bounds count {bare} {mode}")["exact_rechecks"]
     assert n["0"] != n["2"], n
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("variant", ["bsmse", "sam"])
+def test_bare_bounds_batch_entry(variant, mode, monkeypatch):
+    """Every bound kept (many fallbacks) through the batched entry point:
+    each section's log and labels equal the oracle's for that section."""
+    import oracle
+    from tests.test_gpu_forms import BATCH_P, uneven_sections
+    _mode(monkeypatch, mode)
+    monkeypatch.setenv("HSWO_BARE_BOUNDS", "2")
+    p = dict(BATCH_P, criterion=variant)
+    cubes = uneven_sections(8, seed0=7171)
+    _say(f"[gpu] bare bounds batch {variant} {mode} shapes={[c.shape for c in cubes]}")
+    res = hswo.hswo_run_batch([torch.from_numpy(c).cuda() for c in cubes], merge_log=True, incremental=True, **p)
+    torch.cuda.synchronize()
+    for i, c in enumerate(cubes):
+        ref = oracle.rhseg(c, **p)
+        assert np.array_equal(res.logs[i][: len(ref.log)], ref.log), f"section {i}: merge log differs"
+        assert np.array_equal(res.labels[i].cpu().numpy(), ref.labels), f"section {i}: labels differ"
