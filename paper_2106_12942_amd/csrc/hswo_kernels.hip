@@ -1672,6 +1672,7 @@ constexpr int LCAP = CAND_CAP / 3;  // edges listed per merge by the incremental
 // list is compacted when a quarter of it is empty, and at the last merge of a
 // pass. Returns true with the least adjacent key after the merge in anext;
 // false (full pass taken) when a list would overflow.
+template <int U>
 __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int& E, int stamp, int kind,
                                double d2, int rc, KeyD& anext, int& nchk) {
     const int tid = threadIdx.x;
@@ -1692,7 +1693,7 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
     // (labels are read only to order exact ties inside the thread)
     double bv = __builtin_huge_val();
     int be = -1, bla = 0, blb = 0;
-    constexpr int U = 4;  // pairs of edge slots per thread with loads in flight together
+    // U: pairs of edge slots per thread with loads in flight together
     for (int e0 = 2 * tid; e0 < E; e0 += 2 * NT * U) {
         int4 ed[U];
         double2 v[U];
@@ -2376,7 +2377,7 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
         if (lp.incremental) CNT_ADD(C_D_BYTES, 16ull * (unsigned long long)E + 24ull * (unsigned long long)s.B);
         if (lp.incremental) {
             int nre = 0;
-            avalid = merge_pair_inc(sh, s, win.si, win.sj, R, E, merges, kind, win.d2, rcs, anext, nre);
+            avalid = merge_pair_inc<8>(sh, s, win.si, win.sj, R, E, merges, kind, win.d2, rcs, anext, nre);
             CNT_ADD(C_RECHECKS, nre);
         } else {
             merge_pair(sh, s, win.si, win.sj, R, E, merges, kind, win.d2, g_ready, prec, rcs);
@@ -2616,7 +2617,7 @@ __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ s
             decide_bytes += 16ull * (unsigned long long)E + 24ull * (unsigned long long)s.B;
             if (lp.incremental) {
                 KeyD an;
-                const bool av = merge_pair_inc(sh, s, win.si, win.sj, R, E, stamp, kind, win.d2, rcs, an, nchk);
+                const bool av = merge_pair_inc<4>(sh, s, win.si, win.sj, R, E, stamp, kind, win.d2, rcs, an, nchk);
                 if (tid == 0) {
                     s.st[8] = av ? 1 : 0;
                     s.wd[2] = an.d2;
