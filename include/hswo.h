@@ -55,6 +55,12 @@
  *   - Parameters are validated on the host before anything is enqueued; on
  *     error nothing is written and the error code is returned, with a message
  *     available from hswo_last_error(). No C++ exception crosses the ABI.
+ *   - Non-finite input: the first kernel counts NaN and infinite cube
+ *     values; when there is one, every later kernel of the call returns at
+ *     once, so nothing is merged and the label maps and the merge log are
+ *     left as they were. A call with stats (which synchronises) then returns
+ *     HSWO_E_NONFINITE and stats->nonfinite_values; an asynchronous call
+ *     (stats NULL) cannot return it -- pass stats to learn it.
  */
 #ifndef HSWO_H
 #define HSWO_H
@@ -66,14 +72,15 @@
 extern "C" {
 #endif
 
-#define HSWO_VERSION 10000 /* 1.0.0 */
+#define HSWO_VERSION 10100 /* 1.1.0 */
 
 /* return codes */
 #define HSWO_OK 0
 #define HSWO_E_INVAL (-1)       /* invalid argument */
 #define HSWO_E_NOMEM (-2)       /* workspace too small (see hswo_workspace_bytes) */
 #define HSWO_E_DEVICE (-3)      /* a HIP call failed */
-#define HSWO_E_NONFINITE (-4)   /* reserved: non-finite input found by a caller-side check */
+#define HSWO_E_NONFINITE (-4)   /* the cube holds a NaN or an infinity (reported when the call synchronises:
+                                   stats non-NULL; see "Non-finite input" below) */
 #define HSWO_E_UNSUPPORTED (-5) /* valid request this library version does not implement */
 
 /* cube element types */
@@ -104,6 +111,12 @@ extern "C" {
 
 /* flags */
 #define HSWO_FLAG_MERGE_LOG 1 /* fill merge_log (must be non-NULL) */
+#define HSWO_FLAG_DEBUG_VERIFY_BOUND 128 /* screened forms (not HSWO_FLAG_INCREMENTAL): for every pair a
+                                            screen passes on to the FP64 re-check, write the screen's
+                                            estimate, its certified bounds and the canonical D2 to
+                                            p->verify (hswo_verify_rec; up to p->verify_cap records,
+                                            hswo_stats.verify_records counts them all). Costs time;
+                                            for checking the screens' error bounds. */
 #define HSWO_FLAG_GRAPH 2     /* capture the call's kernel sequence into a hipGraph on first use and
                                  replay it on later calls with the same pointers, shapes and
                                  parameters (needs a non-null stream); graphs are cached per
@@ -124,10 +137,51 @@ extern "C" {
                                     reached -- the least NON-adjacent pair of the resulting partition
                                     if its D2 < w^2 * D2 of step 2's pair (step 3). Changes the result.
                                     HSWO_FLAG_INCREMENTAL form only (else HSWO_E_UNSUPPORTED). */
-#define HSWO_FLAG_AUTOTUNE 4  /* on the first call for a shape bucket, time every section-driver
-                                 variant on the call itself (all give identical results) and keep
-                                 the fastest; the choice is cached per process and appended to the
-                                 file named by the environment variable HSWO_TUNE_CACHE if set */
+#define HSWO_FLAG_AUTOTUNE 4  /* on the first call for a shape bucket, time candidate execution
+                                 settings (hswo_tuning: workgroups per section, which levels run
+                                 persistent, the row-stage grid, the section-driver variant) on the
+                                 call itself -- all give identical results -- and keep the fastest;
+                                 the choice is cached per process and appended to the file named by
+                                 the environment variable HSWO_TUNE_CACHE if set. Settings given
+                                 explicitly in p->tuning are not tuned. */
+
+/* Execution settings. None of them changes a merge or a label; they only
+   decide how the work is spread over the device. -1 in a field = the
+   library's default (or, with HSWO_FLAG_AUTOTUNE, the tuned value). */
+typedef struct hswo_tuning {
+    int32_t wide_max_sections;  /* recursion levels of more sections than this run in the persistent
+                                   section driver (one workgroup per section, one launch), the others
+                                   in wide mode (several workgroups per section, a launch sequence per
+                                   merge); 0 = every level persistent. Default: the device's CU count
+                                   in the incremental form, 64 in the others */
+    int32_t wide_groups;        /* wide mode: workgroups per section of the screened sweeps, 1..256;
+                                   default CUs / sections */
+    int32_t rows_grid;          /* wide mode, incremental form: workgroups of the row-stage launch,
+                                   >= 1; default 2 x CUs */
+    int32_t hybrid;             /* incremental form: 1 = the merges of a wide level before its spectral
+                                   stage run in the persistent driver first, 0 = all in wide mode;
+                                   default 1 */
+    int32_t bare_bounds;        /* incremental form: row-cache second bounds kept after their partner
+                                   merges: 0 none, 1 those of value 0, 2 all; default 1 */
+    int32_t driver_variant;     /* adjacent-sweep edges in flight per 16-lane group of the screened
+                                   forms: 2, 4 or 6; default 6 */
+} hswo_tuning;                  /* 24 bytes */
+
+/* One pair checked under HSWO_FLAG_DEBUG_VERIFY_BOUND. */
+typedef struct hswo_verify_rec {
+    int32_t lo, hi;   /* labels of the pair, lo < hi */
+    int32_t stage;    /* HSWO_SCREEN_* that passed the pair on */
+    int32_t r;        /* live regions in the section at that iteration */
+    double screen;    /* the screen's estimate of D2 */
+    double lower;     /* the certified bounds the screen relies on: lower <= D2 <= upper must hold */
+    double upper;
+    double d2;        /* the canonical FP64 D2 of the pair */
+} hswo_verify_rec;    /* 48 bytes */
+
+#define HSWO_SCREEN_ADJ_FP32 0   /* adjacent pairs, FP32 sum of squares of the mean rows */
+#define HSWO_SCREEN_SPEC_FP32 1  /* non-adjacent stage, FP32 tiles */
+#define HSWO_SCREEN_SPEC_16 2    /* non-adjacent stage, 16-bit Gram cross-term on the matrix cores
+                                    (estimate from N_i + N_j - 2 G_ij of the centred 16-bit rows) */
 
 typedef struct hswo_params {
     int32_t connectivity;       /* 4 or 8: pixel links inside a leaf section */
@@ -143,7 +197,15 @@ typedef struct hswo_params {
     int32_t precision;          /* HSWO_PREC_* */
     int32_t flags;              /* HSWO_FLAG_* */
     int32_t criterion;          /* HSWO_CRIT_* dissimilarity criterion (0 = Equation 1) */
-} hswo_params;                  /* 56 bytes */
+    int32_t screen_topk;        /* screened forms: the re-check set of an iteration is every pair whose
+                                   certified lower bound reaches the least upper bound (so it always
+                                   holds the exact minimum); an iteration whose set holds more than
+                                   screen_topk pairs counts as a fallback in hswo_stats
+                                   (screen_fallbacks). 0 = 8; >= 0 */
+    hswo_verify_rec* verify;    /* device, HSWO_FLAG_DEBUG_VERIFY_BOUND only: verify_cap records */
+    int64_t verify_cap;
+    const hswo_tuning* tuning;  /* HOST pointer, optional (NULL = defaults / autotuned) */
+} hswo_params;                  /* 80 bytes */
 
 typedef struct hswo_merge_rec {
     int32_t lo, hi;   /* labels of the merged regions, lo < hi; lo survives */
@@ -211,7 +273,14 @@ typedef struct hswo_stats {
        (bracketed launches minus back-to-back launches), ms; ms_kernel[k] minus
        kernel_launches[k] times this is the kind's launch time */
     double ms_event_pair_overhead;
-} hswo_stats;   /* 328 bytes */
+    int64_t nonfinite_values;    /* NaN or infinite cube values found (then nothing was merged) */
+    int64_t screen_iterations;   /* iterations whose decision went through a certified screen (screened
+                                    forms; adjacent and spectral stages counted separately) */
+    int64_t screen_fallbacks;    /* ... of which the re-check set held more than screen_topk pairs */
+    int64_t verify_records;      /* HSWO_FLAG_DEBUG_VERIFY_BOUND: records produced (written up to
+                                    verify_cap) */
+    hswo_tuning tuning;          /* the execution settings the call used */
+} hswo_stats;   /* 384 bytes */
 
 /* One independent section for hswo_run_batch. */
 typedef struct hswo_section {

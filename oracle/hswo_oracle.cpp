@@ -22,6 +22,7 @@
 #include <cstring>
 #include <limits>
 #include <map>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -515,6 +516,8 @@ extern "C" int oracle_rhseg(const float* cube, int32_t H, int32_t W, int32_t B, 
         const int stop = top ? p->target_regions : stopS;
         std::vector<std::vector<oracle_merge>> logs(secs.size());
         std::vector<std::vector<int>> finals(secs.size());
+        std::mutex progress_mu;
+        int done = 0;
         parallel_for((int)secs.size(), p->n_threads, [&](int s) {
             const Rect& r = secs[s];
             std::vector<int> live;
@@ -557,6 +560,10 @@ extern "C" int oracle_rhseg(const float* cube, int32_t H, int32_t W, int32_t B, 
             }
             Pass pass(st, *p, std::move(live), stop, top, r, &snap);
             pass.run(logs[s]);
+            if (p->progress) {
+                std::lock_guard<std::mutex> lk(progress_mu);
+                p->progress(d, ++done, (int32_t)secs.size());
+            }
         });
         for (auto& lg : logs) all_log.insert(all_log.end(), lg.begin(), lg.end());
     }

@@ -58,6 +58,10 @@ typedef struct oracle_params {
     int32_t two_merges;         /* 1: each iteration merges the best adjacent pair (step 2), then the
                                    best non-adjacent pair of the result if it is below w^2 times the
                                    first merge's value (step 3); 0: one merge per iteration */
+    /* optional: called after each section of a recursion level has finished
+       (depth 0 = the whole image), with how many of that level's sections are
+       done; calls are serialised. Reports progress only. */
+    void (*progress)(int32_t depth, int32_t done, int32_t total);
 } oracle_params;
 
 #define ORACLE_CRIT_BSMSE 0 /* Equation 1, ranked on its square D2 */

@@ -31,7 +31,27 @@ class _Params(ctypes.Structure):
         ("n_threads", ctypes.c_int32),
         ("criterion", ctypes.c_int32),
         ("two_merges", ctypes.c_int32),
+        ("progress", ctypes.c_void_p),
     ]
+
+
+_PROGRESS = ctypes.CFUNCTYPE(None, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32)
+
+
+def _progress_printer(tag: str):
+    """Print a line when a recursion level finishes and about every tenth of
+    its sections in between (called from the oracle's worker threads, one at a
+    time)."""
+    import sys
+    import time
+    t0 = time.perf_counter()
+
+    def cb(depth, done, total):
+        if done == total or done % max(1, total // 10) == 0:
+            print(f"[oracle] {tag} depth {depth}: {done}/{total} sections ({time.perf_counter() - t0:.0f} s)",
+                  flush=True)
+            sys.stdout.flush()
+    return _PROGRESS(cb)
 
 
 CRITERIA = {"bsmse": 0, "sam": 1}
@@ -110,8 +130,10 @@ def rhseg(cube: np.ndarray, *, connectivity: int = 4, seam_connectivity: int = 8
           section_regions: int = 0, rnb_levels: int = 1,
           level_counts: Optional[Sequence[int]] = None, brute: bool = False,
           n_threads: Optional[int] = None, lib: Optional[str] = None, criterion: str = "bsmse",
-          two_merges: bool = False, **_ignored) -> OracleResult:
-    """Run the oracle on a host H x W x B cube (float32, or float16 widened exactly)."""
+          two_merges: bool = False, progress: Optional[str] = None, **_ignored) -> OracleResult:
+    """Run the oracle on a host H x W x B cube (float32, or float16 widened exactly).
+    progress: a tag; when given, a line is printed as the sections of each
+    recursion level finish."""
     cube = np.asarray(cube)
     if cube.dtype == np.float16:
         cube = cube.astype(np.float32)  # every float16 value is a float32 value
@@ -134,6 +156,8 @@ def rhseg(cube: np.ndarray, *, connectivity: int = 4, seam_connectivity: int = 8
     p.n_threads = n_threads if n_threads is not None else (os.cpu_count() or 1)
     p.criterion = CRITERIA[criterion]
     p.two_merges = 1 if two_merges else 0
+    cb = _progress_printer(progress) if progress else None
+    p.progress = ctypes.cast(cb, ctypes.c_void_p) if cb is not None else None
     labels = np.full((len(lc), H, W), -1, dtype=np.int32)
     log = np.zeros(H * W, dtype=MERGE_DTYPE)
     n_log = ctypes.c_int64(0)

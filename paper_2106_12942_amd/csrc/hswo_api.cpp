@@ -68,6 +68,8 @@ int64_t next_pow2(int64_t x) {
 
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
+int validate_tuning(const hswo_tuning* g);
+
 int validate_params(const hswo_params* p, int rnb_levels_expected) {
     if (!p) return fail(HSWO_E_INVAL, "params is NULL");
     if (p->connectivity != 4 && p->connectivity != 8)
@@ -101,7 +103,15 @@ int validate_params(const hswo_params* p, int rnb_levels_expected) {
         return fail(HSWO_E_UNSUPPORTED, "HSWO_FLAG_TWO_MERGES is implemented in the HSWO_FLAG_INCREMENTAL form only");
     if (p->criterion == HSWO_CRIT_SAM && !(p->flags & HSWO_FLAG_INCREMENTAL))
         return fail(HSWO_E_UNSUPPORTED, "criterion HSWO_CRIT_SAM is implemented in the HSWO_FLAG_INCREMENTAL form only");
-    return HSWO_OK;
+    if (p->screen_topk < 0) return fail(HSWO_E_INVAL, "screen_topk must be >= 0");
+    if (p->flags & HSWO_FLAG_DEBUG_VERIFY_BOUND) {
+        if (p->flags & HSWO_FLAG_INCREMENTAL)
+            return fail(HSWO_E_INVAL, "HSWO_FLAG_DEBUG_VERIFY_BOUND checks the screened forms; the incremental form "
+                                      "evaluates every pair exactly");
+        if (!p->verify || p->verify_cap < 0)
+            return fail(HSWO_E_INVAL, "HSWO_FLAG_DEBUG_VERIFY_BOUND needs a verify buffer and verify_cap >= 0");
+    }
+    return validate_tuning(p->tuning);
 }
 
 int validate_shape(int H, int W, int B, int dtype) {
@@ -147,7 +157,63 @@ int64_t tiles_for(int64_t cap, const hswo_params* p) {
 
 // The incremental form keeps exact spectral rows instead of screening every
 // pair each iteration (the 16-bit screen rows are then not needed).
-int bare_bounds_mode();
+int device_cus();
+
+// Execution settings of one call (hswo_tuning, resolved: no -1 left).
+struct Tuning {
+    int wide_max = 0;   // levels of more sections run in the persistent driver
+    int wide_wg = 0;    // wide mode: workgroups per level, shared by its sections (G = wide_wg / n)
+    int rows_grid = 0;  // wide mode, incremental form: workgroups of the row-stage launch
+    int hybrid = 1;     // incremental form: pre-spectral merges of a wide level in the persistent driver
+    int bare = 1;       // row-cache second bounds kept bare: 0 none, 1 those of value 0, 2 all
+    int variant = 6;    // adjacent-sweep edges in flight per 16-lane group (screened forms)
+    std::string str() const {
+        return std::to_string(wide_max) + "," + std::to_string(wide_wg) + "," + std::to_string(rows_grid) + "," +
+               std::to_string(hybrid) + "," + std::to_string(bare) + "," + std::to_string(variant);
+    }
+};
+
+// Library defaults. Measured: the screened and plain forms gain from wide
+// mode up to 64 sections (G >= 4, on the 512x512 workload); the incremental
+// form gains up to one workgroup per section, because its row evaluations
+// pool over the whole device (the 1024x1024 salt cube's 256 leaves: 2.0 s
+// persistent, 1.23 s wide).
+Tuning default_tuning(bool incremental) {
+    Tuning t;
+    t.wide_max = incremental ? device_cus() : 64;
+    t.wide_wg = device_cus();
+    t.rows_grid = 2 * device_cus();
+    t.hybrid = 1;
+    t.bare = 1;
+    t.variant = 6;
+    return t;
+}
+
+// Overlay the fields the caller gave (hswo_tuning, -1 = not given).
+Tuning overlay(Tuning t, const hswo_tuning* g) {
+    if (!g) return t;
+    if (g->wide_max_sections >= 0) t.wide_max = g->wide_max_sections;
+    if (g->wide_groups >= 0) t.wide_wg = g->wide_groups;
+    if (g->rows_grid >= 0) t.rows_grid = g->rows_grid;
+    if (g->hybrid >= 0) t.hybrid = g->hybrid;
+    if (g->bare_bounds >= 0) t.bare = g->bare_bounds;
+    if (g->driver_variant >= 0) t.variant = g->driver_variant;
+    return t;
+}
+
+int validate_tuning(const hswo_tuning* g) {
+    if (!g) return HSWO_OK;
+    if (g->wide_max_sections < -1) return fail(HSWO_E_INVAL, "tuning.wide_max_sections must be >= -1");
+    if (g->wide_groups != -1 && (g->wide_groups < 1 || g->wide_groups > 65536))
+        return fail(HSWO_E_INVAL, "tuning.wide_groups must be -1 or in [1, 65536]");
+    if (g->rows_grid != -1 && (g->rows_grid < 1 || g->rows_grid > 65535))
+        return fail(HSWO_E_INVAL, "tuning.rows_grid must be -1 or in [1, 65535]");
+    if (g->hybrid < -1 || g->hybrid > 1) return fail(HSWO_E_INVAL, "tuning.hybrid must be -1, 0 or 1");
+    if (g->bare_bounds < -1 || g->bare_bounds > 2) return fail(HSWO_E_INVAL, "tuning.bare_bounds must be in [-1, 2]");
+    if (g->driver_variant != -1 && g->driver_variant != 2 && g->driver_variant != 4 && g->driver_variant != 6)
+        return fail(HSWO_E_INVAL, "tuning.driver_variant must be -1, 2, 4 or 6");
+    return HSWO_OK;
+}
 
 bool row_cache_on(const hswo_params* p) {
     return (p->flags & HSWO_FLAG_INCREMENTAL) && p->spclust_wght > 0.0f && p->spclust_max > 0;
@@ -198,6 +264,21 @@ Plan make_plan(int H, int W, int B, const hswo_params* p, int L) {
     return pl;
 }
 
+// Per-section sizes are int32 on the device: reject a plan whose edge or
+// tile capacity would not fit (a leaf's edge slots are h*w*4 under
+// 8-connectivity, which can pass 2^31 while h*w does not).
+int check_plan(const Plan& pl) {
+    for (size_t d = 0; d < pl.lv.size(); ++d)
+        for (const SecPlan& s : pl.lv[d]) {
+            if (s.ecap > INT32_MAX || s.cap > INT32_MAX || s.tiles > INT32_MAX)
+                return fail(HSWO_E_UNSUPPORTED,
+                            "a section of recursion depth %zu needs %lld edge slots and %lld regions; "
+                            "both must fit in int32 (use more recursion levels)",
+                            d, (long long)s.ecap, (long long)s.cap);
+        }
+    return HSWO_OK;
+}
+
 // Device-side objects of one level carved from the workspace.
 struct LevelDev {
     SecDev* secs = nullptr;
@@ -220,8 +301,8 @@ struct Layout {
 };
 
 // Carve the workspace for an RHSEG run (sizes only when ws is null).
-Layout carve(const Plan& pl, int H, int W, const hswo_params* p, void* ws, const void* cube, int32_t* labels,
-             hswo_merge_rec* log) {
+Layout carve(const Plan& pl, int H, int W, const hswo_params* p, int bare, void* ws, const void* cube,
+             int32_t* labels, hswo_merge_rec* log) {
     Layout lay;
     Bump bp;
     bp.base = reinterpret_cast<char*>(ws);
@@ -257,7 +338,7 @@ Layout carve(const Plan& pl, int H, int W, const hswo_params* p, void* ws, const
             s.log_base = (int32_t)log_base;
             s.tiles = (int32_t)sp.tiles;
             s.crit = p->criterion;
-            s.bare = bare_bounds_mode();
+            s.bare = bare;
             s.label = bp.take<int32_t>(sp.cap);
             s.npix = bp.take<int32_t>(sp.cap);
             s.mark = bp.take<int32_t>(sp.cap);
@@ -302,6 +383,13 @@ Layout carve(const Plan& pl, int H, int W, const hswo_params* p, void* ws, const
             s.wi = bp.take<int32_t>(16);
             s.wd = bp.take<double>(4);
             s.wpart = bp.take<float>(2 * GMAX);
+            if (p->flags & HSWO_FLAG_DEBUG_VERIFY_BOUND) {
+                s.vraw = bp.take<float>(sp.ecap);
+                s.vstage = bp.take<float>(CAND_CAP);
+                s.vout = p->verify;
+                s.vcap = p->verify_cap;
+                s.vcount = lay.counters ? lay.counters + C_VERIFY : nullptr;
+            }
             s.parent = lay.parent;
             s.mtime = lay.mtime;
             s.log = log ? log + log_base : nullptr;
@@ -388,30 +476,6 @@ int timed_driver(Timer* tm, const SecDev* secs, int n, const LoopParams& lp, int
     return HSWO_OK;
 }
 
-// How a level's merge loops run: persistent (one workgroup per section, one
-// launch) or wide (G workgroups per section, one launch sequence per iteration).
-int device_cus();
-
-// Levels of more sections than this run in the persistent driver. Measured:
-// the screened and plain forms gain from wide mode up to 64 sections (G >= 4,
-// on the 512x512 workload); the incremental form gains up to one workgroup per
-// section, because its row evaluations pool over the whole device (the
-// 1024x1024 salt cube's 256 leaves: 2.0 s persistent, 1.23 s wide).
-int wide_max_sections(bool incremental) {
-    if (const char* e = getenv("HSWO_WIDE_MAX_SECTIONS")) return atoi(e);
-    return incremental ? device_cus() : 64;
-}
-
-// Which second bounds of the row cache stay as bare bounds once their
-// partner merges (result-neutral): 1 (default) those of value 0, 0 none,
-// 2 all. HSWO_BARE_BOUNDS overrides.
-int bare_bounds_mode() {
-    const char* e = getenv("HSWO_BARE_BOUNDS");
-    if (!e) return 1;
-    const int v = atoi(e);
-    return v < 0 ? 0 : (v > 2 ? 2 : v);
-}
-
 int device_cus() {
     static int cus = 0;
     if (!cus) {
@@ -423,27 +487,26 @@ int device_cus() {
     return cus;
 }
 
-// One level: secs[0..n) with per-section (cap, stop). In wide mode the host
-// knows R at iteration t exactly (cap - t, until the stop count), so the
-// spectral kernels are launched only for iterations where some section can be
-// in its spectral stage.
+// One level: secs[0..n) with per-section (cap, stop). How its merge loops
+// run: persistent (one workgroup per section, one launch) when it has more
+// than tu.wide_max sections, else wide (G workgroups per section, one launch
+// sequence per iteration). In wide mode the host knows R at iteration t
+// exactly (cap - t, until the stop count), so the spectral kernels are
+// launched only for iterations where some section can be in its spectral
+// stage.
 // In the incremental form the iterations of a pass before its spectral stage
-// (R > spclust_max) need no work spread over workgroups: they run in the
-// section driver (one launch, state kept on chip) up to R = spclust_max, and
-// wide mode takes the rest. HSWO_HYBRID=0 turns this off.
-bool hybrid_on() {
-    const char* e = getenv("HSWO_HYBRID");
-    return !(e && atoi(e) == 0);
-}
-
+// (R > spclust_max) need no work spread over workgroups: with tu.hybrid they
+// run in the section driver (one launch, state kept on chip) up to
+// R = spclust_max, and wide mode takes the rest.
 int run_level(Timer* tm, const SecDev* secs, int n, const std::vector<int64_t>& cap, const std::vector<int64_t>& stop,
-              const LoopParams& lp, bool row_cache, int variant, hipStream_t stream) {
-    if (n > wide_max_sections(lp.incremental) || (row_cache && n > ROWS_MAX_SECTIONS))
+              const LoopParams& lp, bool row_cache, const Tuning& tu, hipStream_t stream) {
+    const int variant = tu.variant;
+    if (n > tu.wide_max || (row_cache && n > ROWS_MAX_SECTIONS))
         return timed_driver(tm, secs, n, lp, variant, stream);
-    const int G = std::max(1, std::min(GMAX, device_cus() / n));
+    const int G = std::max(1, std::min(GMAX, tu.wide_wg / n));
     // R of each section when the wide iterations start
     std::vector<int64_t> r0(cap);
-    if (lp.incremental && lp.spectral && hybrid_on()) {
+    if (lp.incremental && lp.spectral && tu.hybrid) {
         int64_t pre = 0;
         for (int i = 0; i < n; ++i) {
             const int64_t p = std::max<int64_t>(lp.kmax, stop[i]);
@@ -482,7 +545,7 @@ int run_level(Timer* tm, const SecDev* secs, int n, const std::vector<int64_t>& 
                 const int64_t R = r0[i] - t;
                 spec = R > stop[i] && R <= lp.kmax;
             }
-        HIP_TRY(launch_wide_iteration(secs, n, G, lp, variant, spec, row_cache, stream, kt));
+        HIP_TRY(launch_wide_iteration(secs, n, G, lp, variant, spec, row_cache, tu.rows_grid, stream, kt));
     }
     if (tm) HIP_TRY(hipEventRecord(e1, stream));
     return HSWO_OK;
@@ -490,20 +553,20 @@ int run_level(Timer* tm, const SecDev* secs, int n, const std::vector<int64_t>& 
 
 // A level's sections one after another (HSWO_FLAG_SEQUENTIAL_SECTIONS), or all together.
 int run_level_sections(Timer* tm, const SecDev* secs, int n, const std::vector<int64_t>& cap,
-                       const std::vector<int64_t>& stop, const LoopParams& lp, bool row_cache, int variant,
+                       const std::vector<int64_t>& stop, const LoopParams& lp, bool row_cache, const Tuning& tu,
                        bool sequential, hipStream_t stream) {
-    if (!sequential || n == 1) return run_level(tm, secs, n, cap, stop, lp, row_cache, variant, stream);
+    if (!sequential || n == 1) return run_level(tm, secs, n, cap, stop, lp, row_cache, tu, stream);
     for (int i = 0; i < n; ++i) {
-        const int r = run_level(tm, secs + i, 1, {cap[i]}, {stop[i]}, lp, row_cache, variant, stream);
+        const int r = run_level(tm, secs + i, 1, {cap[i]}, {stop[i]}, lp, row_cache, tu, stream);
         if (r) return r;
     }
     return HSWO_OK;
 }
 
-using Seq = std::function<int(hipStream_t, Timer*, int)>;
+using Seq = std::function<int(hipStream_t, Timer*, const Tuning&)>;
 
 std::mutex g_mu;
-std::map<std::string, int> g_tune;
+std::map<std::string, std::string> g_tune;  // bucket -> Tuning::str()
 bool g_tune_loaded = false;
 struct GraphEntry {
     hipGraph_t g = nullptr;
@@ -520,20 +583,28 @@ void tune_load_locked() {
     if (!path) return;
     FILE* f = fopen(path, "r");
     if (!f) return;
-    char key[512];
-    int v;
-    while (fscanf(f, "%511s %d", key, &v) == 2) g_tune[key] = v;
+    char key[512], val[128];
+    while (fscanf(f, "%511s %127s", key, val) == 2) g_tune[key] = val;
     fclose(f);
 }
 
-void tune_store_locked(const std::string& k, int v) {
-    g_tune[k] = v;
+void tune_store_locked(const std::string& k, const Tuning& t) {
+    g_tune[k] = t.str();
     const char* path = getenv("HSWO_TUNE_CACHE");
     if (!path) return;
     FILE* f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s %d\n", k.c_str(), v);
+    fprintf(f, "%s %s\n", k.c_str(), t.str().c_str());
     fclose(f);
+}
+
+bool tuning_from_str(const std::string& v, Tuning& t) {
+    Tuning x;
+    if (sscanf(v.c_str(), "%d,%d,%d,%d,%d,%d", &x.wide_max, &x.wide_wg, &x.rows_grid, &x.hybrid, &x.bare,
+               &x.variant) != 6)
+        return false;
+    t = x;
+    return true;
 }
 
 int bucket(int64_t x) {
@@ -546,7 +617,7 @@ struct ExecOut {
     unsigned long long counters[C_COUNT];
     double ms_total = 0.0, ms_driver = 0.0;
     int64_t driver_launches = 0;
-    int variant = 6;
+    Tuning tuning;
     double ms_kernel[HSWO_NK] = {};
     int64_t kernel_launches[HSWO_NK] = {};
     double ms_event_pair = 0.0;
@@ -593,8 +664,73 @@ int event_pair_overhead(hipStream_t stream, double* ms_out) {
     return HSWO_OK;
 }
 
+// Time one run of the sequence with settings t on the call's stream: replayed
+// from a graph when the call uses graphs (the launch overhead then matches
+// what the tuned call will see), else eager.
+int time_trial(const Seq& seq, const Tuning& t, bool graph, hipStream_t stream, float* ms) {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    if (graph) {
+        HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        const int rc = seq(stream, nullptr, t);
+        const hipError_t ec = hipStreamEndCapture(stream, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (ec != hipSuccess) return fail(HSWO_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+        const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return fail(HSWO_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+        }
+    }
+    int rc = HSWO_OK;
+    EventPair ev;
+    hipError_t e = hipEventCreate(&ev.a);
+    if (e == hipSuccess) e = hipEventCreate(&ev.b);
+    if (e == hipSuccess && graph) e = hipGraphLaunch(x, stream);  // first replay uploads the graph
+    if (e == hipSuccess) e = hipEventRecord(ev.a, stream);
+    if (e == hipSuccess) {
+        if (graph) e = hipGraphLaunch(x, stream);
+        else rc = seq(stream, nullptr, t);
+    }
+    if (e == hipSuccess && rc == HSWO_OK) e = hipEventRecord(ev.b, stream);
+    if (e == hipSuccess && rc == HSWO_OK) e = hipEventSynchronize(ev.b);
+    if (e == hipSuccess && rc == HSWO_OK) e = hipEventElapsedTime(ms, ev.a, ev.b);
+    if (x) (void)hipGraphExecDestroy(x);
+    if (g) (void)hipGraphDestroy(g);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(HSWO_E_DEVICE, "autotune trial: %s", hipGetErrorString(e));
+    return HSWO_OK;
+}
+
+// Candidate values of each setting the autotuner searches (one setting at a
+// time, the others held at the best found so far). Every candidate gives the
+// same merges and labels.
+struct Knob {
+    int Tuning::*field;
+    std::vector<int> values;
+    bool given;
+};
+
+std::vector<Knob> tune_knobs(bool incremental, const hswo_tuning* g) {
+    const int cu = device_cus();
+    std::vector<Knob> k;
+    if (incremental) {
+        k.push_back({&Tuning::wide_max, {cu, 64, 16}, g && g->wide_max_sections >= 0});
+        k.push_back({&Tuning::rows_grid, {2 * cu, cu, 4 * cu}, g && g->rows_grid >= 0});
+    } else {
+        k.push_back({&Tuning::wide_max, {64, 16, 256}, g && g->wide_max_sections >= 0});
+        k.push_back({&Tuning::wide_wg, {cu, 2 * cu, 4 * cu}, g && g->wide_groups >= 0});
+        k.push_back({&Tuning::variant, {6, 4, 2}, g && g->driver_variant >= 0});
+    }
+    return k;
+}
+
 int execute(const std::vector<Upload>& ups, const Seq& seq, const std::string& key, const std::string& tune_key,
-            int flags, hipStream_t stream, unsigned long long* d_counters, bool want_stats, ExecOut& out) {
+            int flags, hipStream_t stream, unsigned long long* d_counters, bool want_stats, const hswo_tuning* given,
+            ExecOut& out) {
     if ((flags & HSWO_FLAG_GRAPH) && stream == nullptr)
         return fail(HSWO_E_INVAL, "HSWO_FLAG_GRAPH needs a non-null stream (the null stream cannot be captured)");
     if ((flags & HSWO_FLAG_KERNEL_TIMES) && ((flags & HSWO_FLAG_GRAPH) || !want_stats))
@@ -602,45 +738,45 @@ int execute(const std::vector<Upload>& ups, const Seq& seq, const std::string& k
     for (const Upload& u : ups)
         HIP_TRY(hipMemcpyAsync(u.dst, u.bytes.data(), u.bytes.size(), hipMemcpyHostToDevice, stream));
 
-    // driver variant: environment override, tuned value, tuning run, or default
-    int variant = 6;
+    // settings: the caller's, else the tuned ones for this bucket, else a tuning run, else the defaults
+    const bool incremental = (flags & HSWO_FLAG_INCREMENTAL) != 0;
+    Tuning tu = overlay(default_tuning(incremental), given);
     bool have = false;
-    if (const char* ev = getenv("HSWO_DRIVER_VARIANT")) {
-        variant = atoi(ev);
-        have = true;
-    }
-    if (!have) {
+    {
         std::lock_guard<std::mutex> lk(g_mu);
         tune_load_locked();
         auto it = g_tune.find(tune_key);
-        if (it != g_tune.end()) {
-            variant = it->second;
+        Tuning c;
+        if (it != g_tune.end() && tuning_from_str(it->second, c)) {
+            tu = overlay(c, given);
             have = true;
         }
     }
     if (!have && (flags & HSWO_FLAG_AUTOTUNE)) {
-        // time every variant on this very problem; all write identical outputs
+        // coordinate search on this very problem; every candidate writes identical outputs
+        const bool graph = (flags & HSWO_FLAG_GRAPH) != 0;
         float best = 0.0f;
-        for (int v : DRIVER_VARIANTS) {
-            EventPair ev;
-            HIP_TRY(hipEventCreate(&ev.a));
-            HIP_TRY(hipEventCreate(&ev.b));
-            HIP_TRY(hipEventRecord(ev.a, stream));
-            int rc = seq(stream, nullptr, v);
-            if (rc) return rc;
-            HIP_TRY(hipEventRecord(ev.b, stream));
-            HIP_TRY(hipEventSynchronize(ev.b));
-            float ms = 0.0f;
-            HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
-            if (v == DRIVER_VARIANTS[0] || ms < best) {
-                best = ms;
-                variant = v;
+        int rc = time_trial(seq, tu, graph, stream, &best);
+        if (rc) return rc;
+        for (const Knob& kb : tune_knobs(incremental, given)) {
+            if (kb.given) continue;
+            for (int v : kb.values) {
+                if (tu.*kb.field == v) continue;
+                Tuning t = tu;
+                t.*kb.field = v;
+                float ms = 0.0f;
+                rc = time_trial(seq, t, graph, stream, &ms);
+                if (rc) return rc;
+                if (ms < best) {
+                    best = ms;
+                    tu = t;
+                }
             }
         }
         std::lock_guard<std::mutex> lk(g_mu);
-        tune_store_locked(tune_key, variant);
+        tune_store_locked(tune_key, tu);
     }
-    out.variant = variant;
+    out.tuning = tu;
 
     Timer tm;
     tm.kernels = (flags & HSWO_FLAG_KERNEL_TIMES) != 0;
@@ -655,7 +791,7 @@ int execute(const std::vector<Upload>& ups, const Seq& seq, const std::string& k
         HIP_TRY(hipEventRecord(tot.a, stream));
     }
     if (flags & HSWO_FLAG_GRAPH) {
-        const std::string gk = key + "|v" + std::to_string(variant);
+        const std::string gk = key + "|t" + tu.str();
         hipGraphExec_t exec = nullptr;
         {
             std::lock_guard<std::mutex> lk(g_mu);
@@ -665,7 +801,7 @@ int execute(const std::vector<Upload>& ups, const Seq& seq, const std::string& k
         if (!exec) {
             GraphEntry ge;
             HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-            const int rc = seq(stream, nullptr, variant);
+            const int rc = seq(stream, nullptr, tu);
             const hipError_t ec = hipStreamEndCapture(stream, &ge.g);
             if (rc) {
                 if (ge.g) (void)hipGraphDestroy(ge.g);
@@ -687,7 +823,7 @@ int execute(const std::vector<Upload>& ups, const Seq& seq, const std::string& k
         }
         HIP_TRY(hipGraphLaunch(exec, stream));
     } else {
-        const int rc = seq(stream, want_stats ? &tm : nullptr, variant);
+        const int rc = seq(stream, want_stats ? &tm : nullptr, tu);
         if (rc) return rc;
     }
     if (want_stats) {
@@ -736,7 +872,7 @@ int fill_stats(hswo_stats* st, const ExecOut& o, int64_t launches_if_graph) {
     st->fp32_tiles = (int64_t)c[C_FP32_TILES];
     st->mfma_tiles = (int64_t)c[C_MFMA_TILES];
     st->driver_launches = o.driver_launches ? o.driver_launches : launches_if_graph;
-    st->driver_variant = o.variant;
+    st->driver_variant = o.tuning.variant;
     st->ms_total = o.ms_total;
     st->ms_driver = o.ms_driver;
     st->ms_adjacent = (double)c[C_T_ADJ] * tick_ms;
@@ -754,16 +890,33 @@ int fill_stats(hswo_stats* st, const ExecOut& o, int64_t launches_if_graph) {
     st->kernel_work[HSWO_K_WIDE_MFMA] = (int64_t)c[C_W_MFMA_FLOPS];
     st->kernel_work[HSWO_K_SECTION_DRIVER] = (int64_t)c[C_D_BYTES];
     st->ms_event_pair_overhead = o.ms_event_pair;
+    st->nonfinite_values = (int64_t)c[C_NONFINITE];
+    st->screen_iterations = (int64_t)c[C_SCREEN_ITERS];
+    st->screen_fallbacks = (int64_t)c[C_SCREEN_FALLBACKS];
+    st->verify_records = (int64_t)c[C_VERIFY];
+    st->tuning.wide_max_sections = o.tuning.wide_max;
+    st->tuning.wide_groups = o.tuning.wide_wg;
+    st->tuning.rows_grid = o.tuning.rows_grid;
+    st->tuning.hybrid = o.tuning.hybrid;
+    st->tuning.bare_bounds = o.tuning.bare;
+    st->tuning.driver_variant = o.tuning.variant;
+    if (c[C_NONFINITE])
+        return fail(HSWO_E_NONFINITE, "the cube holds %llu NaN or infinite values; nothing was merged",
+                    (unsigned long long)c[C_NONFINITE]);
     return HSWO_OK;
 }
 
+// The weight enters the key by its bit pattern: a decimal rendering would
+// merge nearby weights (w and its neighbouring floats) into one graph.
 std::string params_key(const hswo_params* p) {
+    uint32_t wbits = 0;
+    std::memcpy(&wbits, &p->spclust_wght, sizeof(wbits));
     std::string k = "c" + std::to_string(p->connectivity) + "s" + std::to_string(p->seam_connectivity) + "w" +
-                    std::to_string(p->spclust_wght) + "k" + std::to_string(p->spclust_max) + "t" +
+                    std::to_string(wbits) + "k" + std::to_string(p->spclust_max) + "t" +
                     std::to_string(p->target_regions) + "S" + std::to_string(p->section_regions) + "L" +
                     std::to_string(p->rnb_levels) + "P" + std::to_string(p->precision) + "C" +
                     std::to_string(p->criterion) + "F" +
-                    std::to_string(p->flags) + "l";
+                    std::to_string(p->flags) + "K" + std::to_string(p->screen_topk) + "l";
     for (int l = 0; l < p->n_levels; ++l) k += std::to_string(p->level_counts[l]) + ",";
     return k;
 }
@@ -783,6 +936,7 @@ LoopParams loop_params(const hswo_params* p, unsigned long long* counters) {
     lp.incremental = (p->flags & HSWO_FLAG_INCREMENTAL) ? 1 : 0;
     lp.phase_stop = 0;
     lp.two_merges = (p->flags & HSWO_FLAG_TWO_MERGES) ? 1 : 0;
+    lp.topk = p->screen_topk > 0 ? p->screen_topk : 8;
     lp.counters = counters;
     return lp;
 }
@@ -791,7 +945,8 @@ int check_common(const hswo_params* p, void* workspace) {
     if (!workspace) return fail(HSWO_E_INVAL, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(HSWO_E_INVAL, "workspace must be 256-byte aligned");
     if (p->flags & ~(HSWO_FLAG_MERGE_LOG | HSWO_FLAG_GRAPH | HSWO_FLAG_AUTOTUNE | HSWO_FLAG_INCREMENTAL |
-                     HSWO_FLAG_KERNEL_TIMES | HSWO_FLAG_SEQUENTIAL_SECTIONS | HSWO_FLAG_TWO_MERGES))
+                     HSWO_FLAG_KERNEL_TIMES | HSWO_FLAG_SEQUENTIAL_SECTIONS | HSWO_FLAG_TWO_MERGES |
+                     HSWO_FLAG_DEBUG_VERIFY_BOUND))
         return fail(HSWO_E_INVAL, "unknown flags 0x%x", p->flags);
     return HSWO_OK;
 }
@@ -813,7 +968,10 @@ int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_param
     if (!(p->flags & HSWO_FLAG_MERGE_LOG)) merge_log = nullptr;
 
     const Plan pl = make_plan(H, W, B, p, L);
-    Layout lay = carve(pl, H, W, p, workspace, cube, labels, merge_log);
+    rc = check_plan(pl);
+    if (rc) return rc;
+    const int bare = overlay(default_tuning(false), p->tuning).bare;
+    Layout lay = carve(pl, H, W, p, bare, workspace, cube, labels, merge_log);
     if (ws_bytes < lay.bytes)
         return fail(HSWO_E_NOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes, lay.bytes);
 
@@ -848,16 +1006,17 @@ int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_param
             stops[d].push_back(s.stop);
         }
 
-    const Seq seq = [&](hipStream_t st, Timer* tm, int variant) -> int {
+    const Seq seq = [&](hipStream_t st, Timer* tm, const Tuning& tu) -> int {
         HIP_TRY(launch_fill_u64(lay.counters, C_COUNT, 0ull, st));
         HIP_TRY(launch_init_pixels(lay.parent, lay.mtime, P, st));
         {
             const int d = L - 1;
             int maxpix = 0;
             for (const SecPlan& s : pl.lv[d]) maxpix = std::max<int>(maxpix, (int)s.cap);
-            HIP_TRY(launch_init_leaves(lay.lv[d].secs, lay.lv[d].inits, (int)pl.lv[d].size(), dtype, maxpix, st));
+            HIP_TRY(launch_init_leaves(lay.lv[d].secs, lay.lv[d].inits, (int)pl.lv[d].size(), dtype, maxpix,
+                                         lay.counters, st));
             const int r = run_level_sections(tm, lay.lv[d].secs, (int)pl.lv[d].size(), caps[d], stops[d], lp,
-                                             row_cache, variant, sequential, st);
+                                             row_cache, tu, sequential, st);
             if (r) return r;
         }
         for (int d = L - 2; d >= 0; --d) {
@@ -869,30 +1028,33 @@ int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_param
                 maxseam = std::max(maxseam, (int64_t)(s.rect.w + 2 * s.rect.h));
                 HIP_TRY(launch_fill_u64(lay.lv[d].h_asms[i].hash, (size_t)s.hash_cap, ~0ull, st));
             }
-            HIP_TRY(launch_compress(lay.parent, P, st));
+            HIP_TRY(launch_compress(lay.parent, P, lay.counters, st));
             HIP_TRY(launch_assemble(lay.lv[d].secs, lay.lv[d + 1].secs, lay.lv[d].asms, (int)secs.size(), lay.slotmap,
-                                    (int)std::min<int64_t>(maxcap, 1 << 30), st));
-            HIP_TRY(launch_seam(lay.lv[d].secs, lay.lv[d].asms, (int)secs.size(), lay.slotmap, (int)maxseam, st));
+                                    (int)std::min<int64_t>(maxcap, 1 << 30), lay.counters, st));
+            HIP_TRY(launch_seam(lay.lv[d].secs, lay.lv[d].asms, (int)secs.size(), lay.slotmap, (int)maxseam,
+                                lay.counters, st));
             const int r = run_level_sections(tm, lay.lv[d].secs, (int)secs.size(), caps[d], stops[d], lp, row_cache,
-                                             variant, sequential, st);
+                                             tu, sequential, st);
             if (r) return r;
         }
-        HIP_TRY(launch_snapshot(lay.snap, 1, lay.counts, p->n_levels, (int)P, st));
+        HIP_TRY(launch_snapshot(lay.snap, 1, lay.counts, p->n_levels, (int)P, lay.counters, st));
         return HSWO_OK;
     };
 
     const std::string key = "rhseg|" + ptr_key(cube) + ptr_key(labels) + ptr_key(merge_log) + ptr_key(workspace) +
                             "|" + std::to_string(H) + "x" + std::to_string(W) + "x" + std::to_string(B) + "d" +
-                            std::to_string(dtype) + "|" + params_key(p);
+                            std::to_string(dtype) + "|" + params_key(p) + ptr_key(p->verify) +
+                            std::to_string(p->verify_cap);
     int64_t maxcap = 0;
     for (const auto& lv : pl.lv)
         for (const SecPlan& s : lv) maxcap = std::max(maxcap, s.cap);
     const std::string tkey = "gfx950:rhseg:B" + std::to_string(bucket(B)) + ":R" + std::to_string(bucket(maxcap)) +
                              ":n" + std::to_string(bucket((int64_t)pl.lv[L - 1].size())) + ":P" +
                              std::to_string(p->precision) + ":C" + std::to_string(p->criterion) + ":k" +
-                             std::to_string(bucket(p->spclust_max + 1));
+                             std::to_string(bucket(p->spclust_max + 1)) + ":I" +
+                             std::to_string((p->flags & HSWO_FLAG_INCREMENTAL) ? 1 : 0);
     ExecOut eo;
-    rc = execute(ups, seq, key, tkey, p->flags, stream, lay.counters, stats != nullptr, eo);
+    rc = execute(ups, seq, key, tkey, p->flags, stream, lay.counters, stats != nullptr, p->tuning, eo);
     if (rc) return rc;
     if (stats) return fill_stats(stats, eo, L);
     return HSWO_OK;
@@ -917,7 +1079,7 @@ struct BatchLayout {
     size_t bytes = 0;
 };
 
-BatchLayout carve_batch(int n, const hswo_section* sec, const hswo_params* p, void* ws) {
+BatchLayout carve_batch(int n, const hswo_section* sec, const hswo_params* p, int bare, void* ws) {
     BatchLayout lay;
     Bump bp;
     bp.base = reinterpret_cast<char*>(ws);
@@ -948,7 +1110,7 @@ BatchLayout carve_batch(int n, const hswo_section* sec, const hswo_params* p, vo
         s.log_base = 0;
         s.tiles = (int32_t)tiles;
         s.crit = p->criterion;
-        s.bare = bare_bounds_mode();
+        s.bare = bare;
         s.label = bp.take<int32_t>(cap);
         s.npix = bp.take<int32_t>(cap);
         s.mark = bp.take<int32_t>(cap);
@@ -993,6 +1155,13 @@ BatchLayout carve_batch(int n, const hswo_section* sec, const hswo_params* p, vo
         s.wi = bp.take<int32_t>(16);
         s.wd = bp.take<double>(4);
         s.wpart = bp.take<float>(2 * GMAX);
+        if (p->flags & HSWO_FLAG_DEBUG_VERIFY_BOUND) {
+            s.vraw = bp.take<float>(ecap);
+            s.vstage = bp.take<float>(CAND_CAP);
+            s.vout = p->verify;
+            s.vcap = p->verify_cap;
+            s.vcount = lay.counters ? lay.counters + C_VERIFY : nullptr;
+        }
         s.parent = bp.take<int32_t>(cap);
         s.mtime = bp.take<int32_t>(cap);
         s.log = (p->flags & HSWO_FLAG_MERGE_LOG) ? q.merge_log : nullptr;
@@ -1044,6 +1213,8 @@ int validate_batch(int n, const hswo_section* sec, int dtype, const hswo_params*
         if (reinterpret_cast<uintptr_t>(q.cube) % 16) return fail(HSWO_E_INVAL, "section %d: cube not 16-byte aligned", i);
         if ((p->flags & HSWO_FLAG_MERGE_LOG) && !q.merge_log)
             return fail(HSWO_E_INVAL, "section %d: MERGE_LOG flag needs merge_log", i);
+        if (grid_edges(q.H, q.W, p->connectivity) > INT32_MAX)
+            return fail(HSWO_E_UNSUPPORTED, "section %d: %dx%d needs more than 2^31 - 1 edge slots", i, q.H, q.W);
     }
     return HSWO_OK;
 }
@@ -1054,7 +1225,7 @@ int run_batch(int n, const hswo_section* sec, int dtype, const hswo_params* p, h
     if (rc) return rc;
     rc = check_common(p, workspace);
     if (rc) return rc;
-    BatchLayout lay = carve_batch(n, sec, p, workspace);
+    BatchLayout lay = carve_batch(n, sec, p, overlay(default_tuning(false), p->tuning).bare, workspace);
     if (ws_bytes < lay.bytes)
         return fail(HSWO_E_NOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes, lay.bytes);
     std::vector<Upload> ups;
@@ -1064,33 +1235,34 @@ int run_batch(int n, const hswo_section* sec, int dtype, const hswo_params* p, h
     add_upload(ups, lay.inits, lay.h_inits.data(), n);
     add_upload(ups, lay.snaps, lay.h_snaps.data(), n);
     const LoopParams lp = loop_params(p, lay.counters);
-    const Seq seq = [&](hipStream_t st, Timer* tm, int variant) -> int {
+    const Seq seq = [&](hipStream_t st, Timer* tm, const Tuning& tu) -> int {
         HIP_TRY(launch_fill_u64(lay.counters, C_COUNT, 0ull, st));
         HIP_TRY(launch_init_pixels_secs(lay.secs, n, lay.max_pixels, st));
-        HIP_TRY(launch_init_leaves(lay.secs, lay.inits, n, dtype, lay.max_pixels, st));
+        HIP_TRY(launch_init_leaves(lay.secs, lay.inits, n, dtype, lay.max_pixels, lay.counters, st));
         int r = HSWO_OK;
         if (p->flags & HSWO_FLAG_SEQUENTIAL_SECTIONS) {
             for (int i = 0; i < n && !r; ++i)
                 r = run_level(tm, lay.secs + i, 1, {lay.h_secs[i].R0}, {lay.h_secs[i].stop}, lp, row_cache_on(p),
-                              variant, st);
+                              tu, st);
         } else {
-            r = timed_driver(tm, lay.secs_lpt, n, lp, variant, st);
+            r = timed_driver(tm, lay.secs_lpt, n, lp, tu.variant, st);
         }
         if (r) return r;
-        HIP_TRY(launch_snapshot(lay.snaps, n, lay.counts, p->n_levels, lay.max_pixels, st));
+        HIP_TRY(launch_snapshot(lay.snaps, n, lay.counts, p->n_levels, lay.max_pixels, lay.counters, st));
         return HSWO_OK;
     };
     std::string key = "batch|" + std::to_string(n) + "|" + ptr_key(workspace) + "d" + std::to_string(dtype) + "|" +
-                      params_key(p) + "|";
+                      params_key(p) + ptr_key(p->verify) + std::to_string(p->verify_cap) + "|";
     for (int i = 0; i < n; ++i)
         key += ptr_key(sec[i].cube) + ptr_key(sec[i].labels) + ptr_key(sec[i].merge_log) + std::to_string(sec[i].H) +
                "x" + std::to_string(sec[i].W) + "x" + std::to_string(sec[i].B) + ";";
     const std::string tkey = "gfx950:batch:B" + std::to_string(bucket(lay.max_B)) + ":R" +
                              std::to_string(bucket(lay.max_cap)) + ":n" + std::to_string(bucket(n)) + ":P" +
                              std::to_string(p->precision) + ":C" + std::to_string(p->criterion) + ":k" +
-                             std::to_string(bucket(p->spclust_max + 1));
+                             std::to_string(bucket(p->spclust_max + 1)) + ":I" +
+                             std::to_string((p->flags & HSWO_FLAG_INCREMENTAL) ? 1 : 0);
     ExecOut eo;
-    rc = execute(ups, seq, key, tkey, p->flags, stream, lay.counters, stats != nullptr, eo);
+    rc = execute(ups, seq, key, tkey, p->flags, stream, lay.counters, stats != nullptr, p->tuning, eo);
     if (rc) return rc;
     if (stats) return fill_stats(stats, eo, 1);
     return HSWO_OK;
@@ -1109,7 +1281,8 @@ size_t hswo_workspace_bytes(int32_t H, int32_t W, int32_t B, int32_t dtype, cons
     const int L = p->rnb_levels;
     if ((H >> (L - 1)) < 1 || (W >> (L - 1)) < 1) return 0;
     const Plan pl = make_plan(H, W, B, p, L);
-    return carve(pl, H, W, p, nullptr, nullptr, nullptr, nullptr).bytes;
+    if (check_plan(pl)) return 0;
+    return carve(pl, H, W, p, 1, nullptr, nullptr, nullptr, nullptr).bytes;
 }
 
 int hswo_run(const void* cube, int32_t H, int32_t W, int32_t B, int32_t dtype, const hswo_params* p,
@@ -1133,7 +1306,7 @@ int rhseg_segment(const void* cube, int32_t H, int32_t W, int32_t B, int32_t dty
 size_t hswo_batch_workspace_bytes(int32_t n_sections, const hswo_section* sections, int32_t dtype,
                                   const hswo_params* p) {
     if (validate_batch(n_sections, sections, dtype, p)) return 0;
-    return carve_batch(n_sections, sections, p, nullptr).bytes;
+    return carve_batch(n_sections, sections, p, 1, nullptr).bytes;
 }
 
 int hswo_run_batch(int32_t n_sections, const hswo_section* sections, int32_t dtype, const hswo_params* p,

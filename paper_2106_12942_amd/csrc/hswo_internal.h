@@ -39,6 +39,11 @@ enum Counter {
     C_W_ADJ_BYTES,    // k_wide_adj: FP32 mean rows read once + edge endpoints + counts and norms
     C_W_MFMA_FLOPS,   // k_wide_mfma: 2 flops per band per unique pair of the screened sections
     C_D_BYTES,        // k_section_driver, incremental form: algorithmic bytes (see hswo_stats.kernel_work)
+    C_NONFINITE,      // non-finite cube values found at initialisation; every later kernel of the call
+                      // does nothing when this is non-zero, so no output is written
+    C_SCREEN_ITERS,   // screened decisions (adjacent and spectral stages counted separately)
+    C_SCREEN_FALLBACKS, // ... whose re-check set held more than screen_topk pairs
+    C_VERIFY,         // HSWO_FLAG_DEBUG_VERIFY_BOUND records produced
     C_COUNT
 };
 
@@ -124,6 +129,13 @@ struct SecDev {
     int32_t* parent; // label-indexed union-find parent (image or batch section)
     int32_t* mtime;  // label-indexed merge time: -1 non-top merge, k top merge, INT_MAX alive
     hswo_merge_rec* log;  // section merge log base (may be null)
+    // HSWO_FLAG_DEBUG_VERIFY_BOUND only (null otherwise): the FP32 sum of squares of each edge's
+    // adjacent screen, the FP32 sum of each spectral candidate in the LDS list, and the output
+    float* vraw;     // [Ecap]
+    float* vstage;   // [CAND_CAP]
+    hswo_verify_rec* vout;
+    int64_t vcap;
+    unsigned long long* vcount;  // records produced (counters[C_VERIFY])
 };
 
 // Leaf initialisation: where a section's pixels come from.
@@ -164,6 +176,7 @@ struct LoopParams {
     int32_t incremental;  // adjacent minimum from cached exact per-edge D2 (only changed edges re-scored)
     int32_t phase_stop;   // section driver: also stop at this region count (0: the pass's stop only)
     int32_t two_merges;   // two-merge reading of the step list (adjacent merge, then non-adjacent merge)
+    int32_t topk;         // screened forms: re-check sets larger than this count as fallbacks
     unsigned long long* counters;  // [C_COUNT]
 };
 
@@ -190,22 +203,23 @@ struct KTimer {
 hipError_t launch_init_pixels(int32_t* parent, int32_t* mtime, int64_t n, hipStream_t s);
 hipError_t launch_init_pixels_secs(const SecDev* secs, int n, int max_pixels, hipStream_t s);
 hipError_t launch_init_leaves(const SecDev* secs, const InitDev* init, int n, int dtype, int max_pixels,
-                              hipStream_t s);
+                              unsigned long long* counters, hipStream_t s);
 hipError_t launch_section_driver(const SecDev* secs, int n, const LoopParams& lp, int variant, hipStream_t s,
                                  KTimer* kt);
 constexpr int DRIVER_VARIANTS[3] = {2, 4, 6};  // adjacent-stage edges in flight per lane group
 hipError_t launch_wide_iteration(const SecDev* secs, int n, int G, const LoopParams& lp, int variant,
-                                 bool spectral_possible, bool row_cache, hipStream_t s, KTimer* kt);
+                                 bool spectral_possible, bool row_cache, int rows_grid, hipStream_t s, KTimer* kt);
+int default_rows_grid();
 constexpr int ROWS_MAX_SECTIONS = 1024;  // sections a row-cache task pool launch can cover
 hipError_t launch_rowcache_prep(const SecDev* secs, int n, const LoopParams& lp, hipStream_t s, KTimer* kt);
-hipError_t launch_compress(int32_t* parent, int64_t n, hipStream_t s);
+hipError_t launch_compress(int32_t* parent, int64_t n, const unsigned long long* gate, hipStream_t s);
 hipError_t launch_empty(hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_assemble(const SecDev* parents, const SecDev* children, const AsmDev* asm_, int n,
-                           int32_t* slotmap, int max_cap, hipStream_t s);
+                           int32_t* slotmap, int max_cap, const unsigned long long* gate, hipStream_t s);
 hipError_t launch_seam(const SecDev* parents, const AsmDev* asm_, int n, const int32_t* slotmap,
-                       int max_seam, hipStream_t s);
+                       int max_seam, const unsigned long long* gate, hipStream_t s);
 hipError_t launch_snapshot(const SnapDev* snaps, int n, const int32_t* counts, int n_levels, int max_pixels,
-                           hipStream_t s);
+                           const unsigned long long* gate, hipStream_t s);
 
 }  // namespace hswo

@@ -102,6 +102,12 @@ __device__ __forceinline__ bool key_less(const KeyD& a, const KeyD& b) {
 
 __device__ __forceinline__ bool key_exists(const KeyD& k) { return k.lo != INT_MAX; }
 
+// Non-finite input found at initialisation: every later kernel of the call
+// returns at once, so nothing is merged and no output is written.
+__device__ __forceinline__ bool gated(const unsigned long long* counters) {
+    return counters != nullptr && counters[C_NONFINITE] != 0ull;
+}
+
 struct Smem {
     union {
         struct {
@@ -464,9 +470,72 @@ __device__ void score_edges(Smem& sh, const SecDev& s, const int* list, int n) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// HSWO_FLAG_DEBUG_VERIFY_BOUND: for every pair a screen passes on to the FP64
+// re-check, the screen's estimate of D2, the certified bounds it relies on and
+// the canonical D2 go to the caller's buffer.
+// ---------------------------------------------------------------------------
+__device__ void verify_put(const SecDev& s, int lo, int hi, int stage, int R, double screen, double lower,
+                           double upper, double d2) {
+    const unsigned long long k = atomicAdd(s.vcount, 1ull);
+    if ((long long)k < s.vcap) {
+        hswo_verify_rec r;
+        r.lo = lo;
+        r.hi = hi;
+        r.stage = stage;
+        r.r = R;
+        r.screen = screen;
+        r.lower = lower;
+        r.upper = upper;
+        r.d2 = d2;
+        s.vout[k] = r;
+    }
+}
+
+// The matrix-core Gram value g_i . g_j of two 16-bit screen rows, accumulated
+// as the tile screen does (16 bands per instruction, in band order). Every
+// row of the A operand is g_i and every column of B is g_j, so each output
+// element is that dot product. Called by a whole wavefront.
+template <int PREC>
+__device__ float gram16_wave(const SecDev& s, int i, int j) {
+    typedef Fmt16<PREC> F;
+    typedef typename F::V V;
+    const int lane = lane_id();
+    const uint16_t* gi = s.g16 + (size_t)i * s.Bp;
+    const uint16_t* gj = s.g16 + (size_t)j * s.Bp;
+    f32x16 acc = {};
+    for (int kk = 0; kk < s.Bp; kk += 16) {
+        const int kc = kk + 8 * (lane >> 5);
+        const V a = *reinterpret_cast<const V*>(gi + kc);
+        const V b = *reinterpret_cast<const V*>(gj + kc);
+        acc = F::mfma(a, b, acc);
+    }
+    return __shfl(acc[0], 0);
+}
+
+// Bounds on D2 implied by a 16-bit Gram value: ||g_i - g_j||^2 lies within
+// kappa (N_i + N_j) of N_i + N_j - 2 G (FP32 accumulation), and the true mean
+// difference lies within eta_i + eta_j of g_i - g_j.
+__device__ void verify_gram16(const SecDev& s, int a, int b, float G, double fac, double& est, double& lower,
+                              double& upper) {
+    const double kappa = (2.0 * s.Bp + 64.0) * 0x1p-24;
+    const double Ni = (double)s.gn[a], Nj = (double)s.gn[b];
+    const double sh = Ni + Nj - 2.0 * (double)G;
+    const double err = kappa * (Ni + Nj);
+    const double eta = (double)s.geta[a] + (double)s.geta[b];
+    const double rl = fmax(sqrt(fmax(sh - err, 0.0)) - eta, 0.0);
+    const double rh = sqrt(fmax(sh + err, 0.0)) + eta;
+    est = fac * fmax(sh, 0.0);
+    lower = fac * rl * rl * (1.0 - 0x1p-40);
+    upper = fac * rh * rh * (1.0 + 0x1p-40);
+}
+
 // Exact lexicographic minimum over the first n entries of the LDS candidate
 // list. Adjacent mode: entries are edge indices; spectral mode: (i<<16)|j.
-__device__ KeyD exact_best_of_list(Smem& sh, const SecDev& s, int n, bool edge_mode) {
+// dbg (HSWO_FLAG_DEBUG_VERIFY_BOUND): 0 off; 1 adjacent FP32 screen; 2
+// spectral FP32 tiles; 3 / 4 the same plus the BF16 / FP16 matrix-core
+// screen; R is the section's live region count.
+__device__ KeyD exact_best_of_list(Smem& sh, const SecDev& s, int n, bool edge_mode, int dbg, int R) {
     KeyD best = key_none();
     for (int c = wave_id(); c < n; c += NWAVE) {
         const int ent = sh.u.f.cand[c];
@@ -491,6 +560,22 @@ __device__ KeyD exact_best_of_list(Smem& sh, const SecDev& s, int n, bool edge_m
         k.si = a;
         k.sj = b;
         if (key_less(k, best)) best = k;
+        if (dbg) {  // wavefront-uniform
+            const float raw = dbg == 1 ? s.vraw[ent] : s.vstage[c];
+            const float gam = (float)(2 * s.B + 32) * U32;
+            const float2 lu = screen_bounds(raw, s.npix[a], s.npix[b], s.norm[a], s.norm[b], gam);
+            const double na = (double)s.npix[a], nb = (double)s.npix[b];
+            const double fac = (na * nb) / (na + nb);
+            if (lane_id() == 0)
+                verify_put(s, la, lb, dbg == 1 ? HSWO_SCREEN_ADJ_FP32 : HSWO_SCREEN_SPEC_FP32, R, fac * (double)raw,
+                           (double)lu.x, (double)lu.y, k.d2);
+            if (dbg >= 3) {
+                const float G = dbg == 3 ? gram16_wave<1>(s, a, b) : gram16_wave<2>(s, a, b);
+                double est, lower, upper;
+                verify_gram16(s, a, b, G, fac, est, lower, upper);
+                if (lane_id() == 0) verify_put(s, la, lb, HSWO_SCREEN_SPEC_16, R, est, lower, upper, k.d2);
+            }
+        }
     }
     return block_min_key(sh, best);
 }
@@ -499,13 +584,13 @@ __device__ KeyD exact_best_of_list(Smem& sh, const SecDev& s, int n, bool edge_m
 // allows. Must be called by the whole block at a point where all appends of
 // the current round are done.
 __device__ void flush_candidates(Smem& sh, const SecDev& s, KeyD& best, int& nchk, bool edge_mode,
-                                 int keep_room) {
+                                 int keep_room, int dbg, int R) {
     __syncthreads();
     const int n = sh.ncand;
     __syncthreads();  // every thread has read n before anyone appends again
     if (n > CAND_CAP - keep_room) {
         const int m = n < CAND_CAP ? n : CAND_CAP;
-        const KeyD k = exact_best_of_list(sh, s, m, edge_mode);
+        const KeyD k = exact_best_of_list(sh, s, m, edge_mode, dbg, R);
         if (key_less(k, best)) best = k;
         nchk += m;
         if (threadIdx.x == 0) sh.ncand = 0;
@@ -2016,6 +2101,7 @@ __device__ float adj_screen_range(const SecDev& s, int e_begin, int e_end, float
             if (ma >= 0) {
                 const float2 lu = screen_bounds(mine, s.npix[ma], s.npix[mb], s.norm[ma], s.norm[mb], gam);
                 s.escr[e] = lu;
+                if (s.vraw) s.vraw[e] = mine;
                 myU = fminf(myU, lu.y);
             } else if (e < e_end) {
                 s.escr[e] = make_float2(__builtin_huge_valf(), __builtin_huge_valf());  // empty slot
@@ -2027,7 +2113,8 @@ __device__ float adj_screen_range(const SecDev& s, int e_begin, int e_end, float
 
 // Exact best adjacent pair: every edge whose lower bound reaches Ua is
 // re-scored in FP64.
-__device__ KeyD adj_collect(Smem& sh, const SecDev& s, int E, float Ua, int& nchk) {
+__device__ KeyD adj_collect(Smem& sh, const SecDev& s, int R, int E, float Ua, int& nchk) {
+    const int dbg = s.vout ? 1 : 0;
     constexpr int SPAN = NT * 16;  // edges appended between two fullness checks (<= CAND_CAP)
     const int tid = threadIdx.x;
     KeyD A = key_none();
@@ -2040,9 +2127,9 @@ __device__ KeyD adj_collect(Smem& sh, const SecDev& s, int E, float Ua, int& nch
                 if (k < CAND_CAP) sh.u.f.cand[k] = e;
             }
         }
-        flush_candidates(sh, s, A, nchk, true, SPAN);
+        flush_candidates(sh, s, A, nchk, true, SPAN, dbg, R);
     }
-    flush_candidates(sh, s, A, nchk, true, CAND_CAP);
+    flush_candidates(sh, s, A, nchk, true, CAND_CAP, dbg, R);
     return A;
 }
 
@@ -2145,9 +2232,12 @@ __device__ float fp32_tiles(Smem& sh, const SecDev& s, int R, bool use16, float 
 // Exact best non-adjacent candidate: re-screen every tile whose least lower
 // bound reaches theta (and is below T), collect its pairs with lower <= theta
 // and < T, re-score them in FP64.
+// prec16: the 16-bit screen that flagged the tiles (0 none, 1 BF16, 2 FP16),
+// for HSWO_FLAG_DEBUG_VERIFY_BOUND.
 __device__ KeyD spectral_collect(Smem& sh, const SecDev& s, int R, double T, double theta, float gam, int& nchk,
-                                 int& nresc) {
+                                 int& nresc, int prec16) {
     const int tid = threadIdx.x;
+    const int dbg = s.vout ? 2 + prec16 : 0;
     const int ty = tid >> 5, tx = tid & 31;
     const int nT = (R + TILE - 1) / TILE;
     const int ntiles = nT * (nT + 1) / 2;
@@ -2177,15 +2267,18 @@ __device__ KeyD spectral_collect(Smem& sh, const SecDev& s, int R, double T, dou
                         const float lo = screen_bounds(acc[a][c], s.npix[i], s.npix[j], s.norm[i], s.norm[j], gam).x;
                         if ((double)lo <= theta && (double)lo < T) {
                             const int k = atomicAdd(&sh.ncand, 1);
-                            if (k < CAND_CAP) sh.u.f.cand[k] = (int)(((unsigned)i << 16) | (unsigned)j);
+                            if (k < CAND_CAP) {
+                                sh.u.f.cand[k] = (int)(((unsigned)i << 16) | (unsigned)j);
+                                if (dbg) s.vstage[k] = acc[a][c];
+                            }
                         }
                     }
                 }
-            flush_candidates(sh, s, M, nchk, false, TILE * TILE);
+            flush_candidates(sh, s, M, nchk, false, TILE * TILE, dbg, R);
         }
         __syncthreads();  // tlist is rewritten by the next chunk
     }
-    flush_candidates(sh, s, M, nchk, false, CAND_CAP);
+    flush_candidates(sh, s, M, nchk, false, CAND_CAP, dbg, R);
     return M;
 }
 
@@ -2219,7 +2312,7 @@ template <int EPG>
 __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict__ secs, int n_sec,
                                                        LoopParams lp) {
     __shared__ Smem sh;
-    if ((int)blockIdx.x >= n_sec) return;
+    if ((int)blockIdx.x >= n_sec || gated(lp.counters)) return;
     const SecDev& s = secs[blockIdx.x];
     const int tid = threadIdx.x;
     int R = s.st[0];
@@ -2263,7 +2356,10 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
         } else {
             const float myU = adj_screen_range<EPG>(s, 0, E, gam);
             const float Ua = block_min_f2(sh, myU, myU).x;
-            A = adj_collect(sh, s, E, Ua, nchk);
+            const int c0 = nchk;
+            A = adj_collect(sh, s, R, E, Ua, nchk);
+            CNT_ADD(C_SCREEN_ITERS, 1);
+            CNT_ADD(C_SCREEN_FALLBACKS, nchk - c0 > lp.topk ? 1 : 0);
         }
         CNT_ADD(C_ADJ_PAIRS, E - s.st[9]);
         unsigned long long tk1 = wall_clock64();
@@ -2345,7 +2441,10 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
             int nf = 0, nresc = 0;
             const float Us = fp32_tiles(sh, s, R, use16, gam, 0, 1, nf);
             const double theta = fmin((double)Us, T);
-            M = spectral_collect(sh, s, R, T, theta, gam, nchk, nresc);
+            const int c1 = nchk;
+            M = spectral_collect(sh, s, R, T, theta, gam, nchk, nresc, use16 ? prec : 0);
+            CNT_ADD(C_SCREEN_ITERS, 1);
+            CNT_ADD(C_SCREEN_FALLBACKS, nchk - c1 > lp.topk ? 1 : 0);
             CNT_ADD(C_FP32_TILES, nf);
             CNT_ADD(C_SPEC_PAIRS, (unsigned long long)R * (unsigned long long)(R - 1) / 2ull);
             CNT_ADD(C_RESCANS, nresc);
@@ -2435,6 +2534,7 @@ template <int EPG>
 __global__ void __launch_bounds__(NT) k_wide_adj(const SecDev* __restrict__ secs, int G,
                                                  unsigned long long* counters) {
     __shared__ float red[NWAVE];  // only a block minimum: keep LDS small so several blocks fit a CU
+    if (gated(counters)) return;
     const SecDev& s = secs[blockIdx.y];
     const int R = s.st[0], E = s.st[1];
     if (R <= s.stop) return;
@@ -2458,6 +2558,7 @@ __global__ void __launch_bounds__(NT) k_wide_adj(const SecDev* __restrict__ secs
 __global__ void __launch_bounds__(NT) k_wide_rows(const SecDev* __restrict__ secs, int n, LoopParams lp) {
     __shared__ double rsum[NWAVE][4][64];
     __shared__ int pre[ROWS_MAX_SECTIONS + 1];
+    if (gated(lp.counters)) return;
     // tasks of every section of the level in one pool: section k owns tasks
     // [pre[k], pre[k + 1])
     for (int k = threadIdx.x; k < n; k += NT) {
@@ -2518,6 +2619,7 @@ __global__ void __launch_bounds__(NT) k_wide_rows(const SecDev* __restrict__ sec
 // stage (one workgroup per section).
 __global__ void __launch_bounds__(NT) k_rowcache_prep(const SecDev* __restrict__ secs, LoopParams lp) {
     __shared__ Smem sh;
+    if (gated(lp.counters)) return;
     const SecDev& s = secs[blockIdx.x];
     const int R = s.st[0];
     if (s.rcap == 0 || R <= s.stop || R > lp.kmax || s.st[6] != 0) return;
@@ -2526,6 +2628,7 @@ __global__ void __launch_bounds__(NT) k_rowcache_prep(const SecDev* __restrict__
 
 __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ secs, int G, LoopParams lp) {
     __shared__ Smem sh;
+    if (gated(lp.counters)) return;
     const SecDev& s = secs[blockIdx.x];
     const int tid = threadIdx.x;
     const int R = s.st[0];
@@ -2556,7 +2659,11 @@ __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ s
     } else {
         float Ua = __builtin_huge_valf();
         for (int g = 0; g < G; ++g) Ua = fminf(Ua, s.wpart[g]);
-        A = adj_collect(sh, s, E, Ua, nchk);
+        A = adj_collect(sh, s, R, E, Ua, nchk);
+        if (tid == 0 && lp.counters) {
+            atomicAdd(&lp.counters[C_SCREEN_ITERS], 1ull);
+            if (nchk > lp.topk) atomicAdd(&lp.counters[C_SCREEN_FALLBACKS], 1ull);
+        }
     }
     const int Elive = E - s.st[9];
     const bool spectral = lp.spectral && R <= lp.kmax;
@@ -2684,6 +2791,7 @@ __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ s
 template <int PREC>
 __global__ void __launch_bounds__(NT) k_wide_mfma(const SecDev* __restrict__ secs, int G, LoopParams lp) {
     __shared__ Smem sh;
+    if (gated(lp.counters)) return;
     const SecDev s = secs[blockIdx.y];
     if (s.wi[0] != 2 || !s.wi[5]) return;
     const int R = s.st[0];
@@ -2698,6 +2806,7 @@ __global__ void __launch_bounds__(NT) k_wide_mfma(const SecDev* __restrict__ sec
 
 __global__ void __launch_bounds__(NT) k_wide_fp32(const SecDev* __restrict__ secs, int G, LoopParams lp) {
     __shared__ Smem sh;
+    if (gated(lp.counters)) return;
     const SecDev& s = secs[blockIdx.y];
     if (s.wi[0] != 2) return;
     const float gam = (float)(2 * s.B + 32) * U32;
@@ -2711,6 +2820,7 @@ __global__ void __launch_bounds__(NT) k_wide_fp32(const SecDev* __restrict__ sec
 
 __global__ void __launch_bounds__(NT) k_wide_finish(const SecDev* __restrict__ secs, int G, LoopParams lp) {
     __shared__ Smem sh;
+    if (gated(lp.counters)) return;
     const SecDev& s = secs[blockIdx.x];
     const int tid = threadIdx.x;
     if (s.wi[0] != 2) return;
@@ -2731,7 +2841,12 @@ __global__ void __launch_bounds__(NT) k_wide_finish(const SecDev* __restrict__ s
     for (int g = 0; g < G; ++g) Us = fminf(Us, s.wpart[GMAX + g]);
     const double theta = fmin((double)Us, T);
     const float gam = (float)(2 * s.B + 32) * U32;
-    const KeyD M = spectral_collect(sh, s, R, T, theta, gam, nchk, nresc);
+    const int c1 = nchk;
+    const KeyD M = spectral_collect(sh, s, R, T, theta, gam, nchk, nresc, s.wi[5] ? prec : 0);
+    if (tid == 0 && lp.counters) {
+        atomicAdd(&lp.counters[C_SCREEN_ITERS], 1ull);
+        if (nchk - c1 > lp.topk) atomicAdd(&lp.counters[C_SCREEN_FALLBACKS], 1ull);
+    }
     KeyD win;
     int kind;
     if (decide(true, A, M, T, win, kind)) {
@@ -2783,24 +2898,28 @@ __device__ __forceinline__ float load_px<__half>(const void* cube, size_t idx) {
 // pixel index, one pixel, band sums = its spectrum; plus the section's grid
 // edges under 4- or 8-connectivity.
 template <typename T>
-__global__ void k_init_leaves(const SecDev* __restrict__ secs, const InitDev* __restrict__ init) {
+__global__ void k_init_leaves(const SecDev* __restrict__ secs, const InitDev* __restrict__ init,
+                              unsigned long long* counters) {
     const SecDev& s = secs[blockIdx.y];
     const InitDev in = init[blockIdx.y];
     const int h = in.h, w = in.w, B = s.B, Bp = s.Bp;
     const int P = h * w;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    // band sums and mean rows
+    // band sums and mean rows; non-finite values are counted (the call then stops)
+    unsigned nonfinite = 0;
     for (int64_t idx = t0; idx < (int64_t)P * Bp; idx += stride) {
         const int k = (int)(idx / Bp), b = (int)(idx % Bp);
         const int r = k / w, c = k % w;
         float v = 0.0f;
         if (b < B) {
             v = load_px<T>(in.cube, ((size_t)(in.r0 + r) * in.img_w + (in.c0 + c)) * B + b);
+            nonfinite += isfinite(v) ? 0u : 1u;
             s.sums[(size_t)k * B + b] = (double)v;
         }
         s.mean[(size_t)k * Bp + b] = v;
     }
+    if (nonfinite) atomicAdd(&counters[C_NONFINITE], (unsigned long long)nonfinite);
     // per-pixel region data
     for (int64_t k = t0; k < P; k += stride) {
         const int r = (int)k / w, c = (int)k % w;
@@ -2860,7 +2979,8 @@ __global__ void k_init_leaves(const SecDev* __restrict__ secs, const InitDev* __
 // Path compression of the label union-find: parent[p] becomes p's root.
 // Concurrent updates only ever store an ancestor, so every walk still ends
 // at the root.
-__global__ void k_compress(int32_t* parent, int64_t n) {
+__global__ void k_compress(int32_t* parent, int64_t n, const unsigned long long* gate) {
+    if (gated(gate)) return;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
         int x = parent[p];
         for (int64_t step = 0; step < n; ++step) {  // a chain is never longer than n
@@ -2882,7 +3002,8 @@ __global__ void k_fill_u64(unsigned long long* p, size_t n, unsigned long long v
 // Reassembly (Figure 4.4), part 1: the parent's regions are the live regions
 // of its four children in order TL, TR, BL, BR; children's edges are kept.
 __global__ void k_assemble(const SecDev* __restrict__ parents, const SecDev* __restrict__ children,
-                           const AsmDev* __restrict__ asm_, int32_t* slotmap) {
+                           const AsmDev* __restrict__ asm_, int32_t* slotmap, const unsigned long long* gate) {
+    if (gated(gate)) return;
     const SecDev p = parents[blockIdx.y];
     const AsmDev a = asm_[blockIdx.y];
     int off[5], eoff[5];
@@ -2966,7 +3087,8 @@ __device__ __forceinline__ unsigned long long mix64(unsigned long long x) {
 // (pixel pairs in different quadrants that are neighbours under the seam
 // connectivity), one edge per distinct region pair.
 __global__ void k_seam(const SecDev* __restrict__ parents, const AsmDev* __restrict__ asm_,
-                       const int32_t* __restrict__ slotmap) {
+                       const int32_t* __restrict__ slotmap, const unsigned long long* gate) {
+    if (gated(gate)) return;
     const SecDev p = parents[blockIdx.y];
     const AsmDev a = asm_[blockIdx.y];
     const int h0 = a.h / 2, w0 = a.w / 2;
@@ -3019,7 +3141,9 @@ __global__ void k_seam(const SecDev* __restrict__ parents, const AsmDev* __restr
 // Label maps of the requested hierarchy levels of a top pass. A level with
 // count c is the state after k = max(0, R_start - c) top-pass merges: walk
 // from the pixel's region at the start of the pass along merges made before k.
-__global__ void k_snapshot(const SnapDev* __restrict__ snaps, const int32_t* __restrict__ counts, int n_levels) {
+__global__ void k_snapshot(const SnapDev* __restrict__ snaps, const int32_t* __restrict__ counts, int n_levels,
+                           const unsigned long long* gate) {
+    if (gated(gate)) return;
     const SnapDev sd = snaps[blockIdx.y];
     const int P = sd.h * sd.w;
     const int Rs = sd.st[2];
@@ -3059,12 +3183,12 @@ hipError_t launch_init_pixels_secs(const SecDev* secs, int n, int max_pixels, hi
 }
 
 hipError_t launch_init_leaves(const SecDev* secs, const InitDev* init, int n, int dtype, int max_pixels,
-                              hipStream_t s) {
+                              unsigned long long* counters, hipStream_t s) {
     const dim3 grid(grid_for((int64_t)max_pixels * 8, 256, 1024), n);
     if (dtype == HSWO_F16)
-        hipLaunchKernelGGL(k_init_leaves<__half>, grid, dim3(256), 0, s, secs, init);
+        hipLaunchKernelGGL(k_init_leaves<__half>, grid, dim3(256), 0, s, secs, init, counters);
     else
-        hipLaunchKernelGGL(k_init_leaves<float>, grid, dim3(256), 0, s, secs, init);
+        hipLaunchKernelGGL(k_init_leaves<float>, grid, dim3(256), 0, s, secs, init, counters);
     return hipGetLastError();
 }
 
@@ -3098,7 +3222,7 @@ hipError_t launch_section_driver(const SecDev* secs, int n, const LoopParams& lp
     return hipGetLastError();
 }
 
-int rows_grid() {
+int default_rows_grid() {
     static int g = 0;
     if (!g) {
         int dev = 0, cus = 0;
@@ -3116,10 +3240,10 @@ hipError_t launch_rowcache_prep(const SecDev* secs, int n, const LoopParams& lp,
 }
 
 hipError_t launch_wide_iteration(const SecDev* secs, int n, int G, const LoopParams& lp, int variant,
-                                 bool spectral_possible, bool row_cache, hipStream_t s, KTimer* kt) {
+                                 bool spectral_possible, bool row_cache, int rows_grid, hipStream_t s, KTimer* kt) {
     const dim3 grid(G, n);
     if (row_cache) {  // incremental form: cached adjacent values and spectral rows
-        if (spectral_possible) KLAUNCH(HSWO_K_WIDE_ROWS, k_wide_rows, dim3(rows_grid()), dim3(NT), secs, n, lp);
+        if (spectral_possible) KLAUNCH(HSWO_K_WIDE_ROWS, k_wide_rows, dim3(rows_grid), dim3(NT), secs, n, lp);
         KLAUNCH(HSWO_K_WIDE_DECIDE, k_wide_decide, dim3(n), dim3(NT), secs, G, lp);
         return hipGetLastError();
     }
@@ -3143,8 +3267,8 @@ hipError_t launch_wide_iteration(const SecDev* secs, int n, int G, const LoopPar
     return hipGetLastError();
 }
 
-hipError_t launch_compress(int32_t* parent, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_compress, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, parent, n);
+hipError_t launch_compress(int32_t* parent, int64_t n, const unsigned long long* gate, hipStream_t s) {
+    hipLaunchKernelGGL(k_compress, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, parent, n, gate);
     return hipGetLastError();
 }
 
@@ -3159,23 +3283,23 @@ hipError_t launch_fill_u64(unsigned long long* p, size_t n, unsigned long long v
 }
 
 hipError_t launch_assemble(const SecDev* parents, const SecDev* children, const AsmDev* asm_, int n,
-                           int32_t* slotmap, int max_cap, hipStream_t s) {
+                           int32_t* slotmap, int max_cap, const unsigned long long* gate, hipStream_t s) {
     const dim3 grid(grid_for((int64_t)max_cap * 64, 256, 512), n);
-    hipLaunchKernelGGL(k_assemble, grid, dim3(256), 0, s, parents, children, asm_, slotmap);
+    hipLaunchKernelGGL(k_assemble, grid, dim3(256), 0, s, parents, children, asm_, slotmap, gate);
     return hipGetLastError();
 }
 
 hipError_t launch_seam(const SecDev* parents, const AsmDev* asm_, int n, const int32_t* slotmap, int max_seam,
-                       hipStream_t s) {
+                       const unsigned long long* gate, hipStream_t s) {
     const dim3 grid(grid_for((int64_t)max_seam * 4, 256, 256), n);
-    hipLaunchKernelGGL(k_seam, grid, dim3(256), 0, s, parents, asm_, slotmap);
+    hipLaunchKernelGGL(k_seam, grid, dim3(256), 0, s, parents, asm_, slotmap, gate);
     return hipGetLastError();
 }
 
 hipError_t launch_snapshot(const SnapDev* snaps, int n, const int32_t* counts, int n_levels, int max_pixels,
-                           hipStream_t s) {
+                           const unsigned long long* gate, hipStream_t s) {
     const dim3 grid(grid_for((int64_t)max_pixels * n_levels, 256, 4096), n);
-    hipLaunchKernelGGL(k_snapshot, grid, dim3(256), 0, s, snaps, counts, n_levels);
+    hipLaunchKernelGGL(k_snapshot, grid, dim3(256), 0, s, snaps, counts, n_levels, gate);
     return hipGetLastError();
 }
 

@@ -34,6 +34,7 @@ HSWO_FLAG_INCREMENTAL = 8
 HSWO_FLAG_KERNEL_TIMES = 16
 HSWO_FLAG_SEQUENTIAL_SECTIONS = 32
 HSWO_FLAG_TWO_MERGES = 64
+HSWO_FLAG_DEBUG_VERIFY_BOUND = 128
 
 HSWO_CRIT_BSMSE = 0
 HSWO_CRIT_SAM = 1
@@ -42,9 +43,20 @@ KERNEL_KINDS = ["section_driver", "wide_adj", "wide_decide", "wide_mfma", "wide_
                 "rowcache_prep"]
 
 MERGE_DTYPE = np.dtype([("lo", "<i4"), ("hi", "<i4"), ("kind", "<i4"), ("r_after", "<i4"), ("d2", "<f8")])
+VERIFY_DTYPE = np.dtype([("lo", "<i4"), ("hi", "<i4"), ("stage", "<i4"), ("r", "<i4"), ("screen", "<f8"),
+                         ("lower", "<f8"), ("upper", "<f8"), ("d2", "<f8")])
+SCREEN_STAGES = {0: "adjacent_fp32", 1: "spectral_fp32", 2: "spectral_16bit"}
+TUNING_FIELDS = ["wide_max_sections", "wide_groups", "rows_grid", "hybrid", "bare_bounds", "driver_variant"]
 
 EXPORTS = ["hswo_version", "hswo_last_error", "hswo_workspace_bytes", "hswo_run", "rhseg_segment",
            "hswo_batch_workspace_bytes", "hswo_run_batch"]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int32) for f in TUNING_FIELDS]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f in TUNING_FIELDS}
 
 
 class Params(ctypes.Structure):
@@ -61,6 +73,10 @@ class Params(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("flags", ctypes.c_int32),
         ("criterion", ctypes.c_int32),
+        ("screen_topk", ctypes.c_int32),
+        ("verify", ctypes.c_void_p),
+        ("verify_cap", ctypes.c_int64),
+        ("tuning", ctypes.POINTER(Tuning)),
     ]
 
 
@@ -86,13 +102,22 @@ class Stats(ctypes.Structure):
         ("kernel_launches", ctypes.c_int64 * 8),
         ("kernel_work", ctypes.c_int64 * 8),
         ("ms_event_pair_overhead", ctypes.c_double),
+        ("nonfinite_values", ctypes.c_int64),
+        ("screen_iterations", ctypes.c_int64),
+        ("screen_fallbacks", ctypes.c_int64),
+        ("verify_records", ctypes.c_int64),
+        ("tuning", Tuning),
     ]
 
     def as_dict(self):
         d = {}
         for k, _ in self._fields_:
             v = getattr(self, k)
-            d[k] = list(v) if k in ("ms_kernel", "kernel_launches", "kernel_work") else v
+            if k in ("ms_kernel", "kernel_launches", "kernel_work"):
+                v = list(v)
+            elif k == "tuning":
+                v = v.as_dict()
+            d[k] = v
         return d
 
 
@@ -148,21 +173,41 @@ def last_error() -> str:
     return load().hswo_last_error().decode()
 
 
+# hswo_tuning fields applied to calls that pass no tuning of their own (None:
+# the library's defaults). The library itself reads no environment.
+DEFAULT_TUNING: Optional[dict] = None
+
+
+def make_tuning(tuning: Optional[dict]) -> Optional[Tuning]:
+    """hswo_tuning from a dict of its fields (missing ones -1: library default or autotuned)."""
+    if tuning is None:
+        return None
+    unknown = set(tuning) - set(TUNING_FIELDS)
+    if unknown:
+        raise ValueError(f"unknown tuning fields {sorted(unknown)}")
+    return Tuning(*[int(tuning.get(f, -1)) for f in TUNING_FIELDS])
+
+
 def make_params(*, connectivity=4, seam_connectivity=8, spclust_wght=0.0, spclust_max=0, target_regions=1,
                 section_regions=0, rnb_levels=1, level_counts: Optional[Sequence[int]] = None,
                 precision="fp32", merge_log=False, graph=False, autotune=False, incremental=False,
-                kernel_times=False, sequential=False, criterion="bsmse", two_merges=False, **_ignored):
+                kernel_times=False, sequential=False, criterion="bsmse", two_merges=False, screen_topk=0,
+                verify_ptr=None, verify_cap=0, tuning: Optional[dict] = None, **_ignored):
     counts = list(level_counts) if level_counts is not None else [target_regions]
     arr = (ctypes.c_int32 * len(counts))(*counts)
+    tu = make_tuning(tuning if tuning is not None else DEFAULT_TUNING)
     p = Params(connectivity, seam_connectivity, spclust_wght, spclust_max, target_regions, section_regions,
                rnb_levels, len(counts), ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32)),
                PREC[precision] if isinstance(precision, str) else int(precision),
                (HSWO_FLAG_MERGE_LOG if merge_log else 0) | (HSWO_FLAG_GRAPH if graph else 0) |
                (HSWO_FLAG_AUTOTUNE if autotune else 0) | (HSWO_FLAG_INCREMENTAL if incremental else 0) |
                (HSWO_FLAG_KERNEL_TIMES if kernel_times else 0) | (HSWO_FLAG_SEQUENTIAL_SECTIONS if sequential else 0) |
-               (HSWO_FLAG_TWO_MERGES if two_merges else 0),
-               CRIT[criterion] if isinstance(criterion, str) else int(criterion))
-    p._counts_keepalive = arr  # the struct holds a raw pointer into arr
+               (HSWO_FLAG_TWO_MERGES if two_merges else 0) | (HSWO_FLAG_DEBUG_VERIFY_BOUND if verify_ptr else 0),
+               CRIT[criterion] if isinstance(criterion, str) else int(criterion),
+               int(screen_topk), verify_ptr, int(verify_cap),
+               ctypes.pointer(tu) if tu is not None else None)
+    p._counts_keepalive = arr  # the struct holds raw pointers into arr and tu
+    p._tuning_keepalive = tu
     return p
 
 
@@ -185,10 +230,49 @@ class Result:
     labels: "object"           # torch int32 [n_levels, H, W] on the device
     log: Optional[np.ndarray]  # MERGE_DTYPE records (host copy) or None
     stats: Optional[dict]
+    verify: Optional[np.ndarray] = None  # VERIFY_DTYPE records (verify_cap > 0) or None
+
+
+def _verify_buffer(params: dict, device):
+    """Device buffer for HSWO_FLAG_DEBUG_VERIFY_BOUND records when params asks
+    for one (verify_cap > 0); sets the pointer in params."""
+    import torch
+    cap = int(params.pop("verify_cap", 0))
+    if cap <= 0:
+        return None, 0
+    t = torch.empty((cap * VERIFY_DTYPE.itemsize,), dtype=torch.uint8, device=device)
+    params["verify_ptr"] = t.data_ptr()
+    params["verify_cap"] = cap
+    return t, cap
+
+
+def _verify_records(t, cap, st, s):
+    if t is None:
+        return None
+    s.synchronize()
+    n = min(cap, int(st.verify_records)) if st is not None else cap
+    return np.frombuffer(t.cpu().numpy().tobytes(), dtype=VERIFY_DTYPE)[:n].copy()
 
 
 def workspace_bytes(H, W, B, dtype_code, params: Params) -> int:
     return int(load().hswo_workspace_bytes(H, W, B, dtype_code, ctypes.byref(params)))
+
+
+def _order_streams(s, device):
+    """The call runs on stream s; the inputs and outputs were made (copied,
+    allocated) on the current stream, so s first waits for that stream."""
+    import torch
+    cur = torch.cuda.current_stream(device)
+    if s != cur:
+        s.wait_stream(cur)
+
+
+def _keep_alive(s, *tensors):
+    """Tell the caching allocator that stream s uses these tensors, so their
+    memory is not handed out again before s has finished with them."""
+    for t in tensors:
+        if t is not None:
+            t.record_stream(s)
 
 
 def _aligned_workspace(nbytes: int, device):
@@ -208,6 +292,9 @@ def _segment(entry: str, cube, rnb_levels: int, merge_log: bool, stats: bool, st
     code = _dtype_code(cube)
     params = dict(params)
     params["rnb_levels"] = rnb_levels
+    vt, vcap = _verify_buffer(params, cube.device)
+    if vt is not None and not stats:
+        raise ValueError("verify_cap needs stats=True (the record count comes from the stats)")
     p = make_params(**params, merge_log=merge_log)
     lib = load()
     s = stream if stream is not None else torch.cuda.current_stream(cube.device)
@@ -236,15 +323,17 @@ def _segment(entry: str, cube, rnb_levels: int, merge_log: bool, stats: bool, st
     log_t = torch.empty((max(n_merges, 1) * MERGE_DTYPE.itemsize,), dtype=torch.uint8, device=cube.device) \
         if merge_log else None
     st = Stats() if stats else None
+    _order_streams(s, cube.device)
     _check(call(labels.data_ptr(), log_t.data_ptr() if log_t is not None else None,
                 ctypes.byref(st) if st is not None else None, ws_ptr, nb))
-    # keep the workspace alive until the stream has consumed it
-    ws.record_stream(s)
+    # keep every buffer the call reads or writes alive until its stream has consumed it
+    _keep_alive(s, ws, cube, labels, log_t, vt)
     log = None
     if log_t is not None:
         s.synchronize()
         log = np.frombuffer(log_t.cpu().numpy().tobytes(), dtype=MERGE_DTYPE)[:max(n_merges, 0)]
-    return Result(labels=labels, log=log, stats=st.as_dict() if st is not None else None)
+    return Result(labels=labels, log=log, stats=st.as_dict() if st is not None else None,
+                  verify=_verify_records(vt, vcap, st, s))
 
 
 class Workspace:
@@ -320,9 +409,10 @@ def hswo_run_batch(cubes, *, merge_log: bool = False, stats: bool = False, strea
     else:
         ws, ws_ptr = _aligned_workspace(nb, dev)
     st = Stats() if stats else None
+    _order_streams(s, dev)
     _check(lib.hswo_run_batch(n, secs, code, ctypes.byref(p), ctypes.byref(st) if st is not None else None, ws_ptr,
                               nb, s.cuda_stream))
-    ws.record_stream(s)
+    _keep_alive(s, ws, *cubes, *labs, *(logs_t or []))
     logs = None
     if logs_t is not None:
         s.synchronize()

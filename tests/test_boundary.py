@@ -32,13 +32,19 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version_and_empty_error():
-    assert hswo.load().hswo_version() == 10000
+    assert hswo.load().hswo_version() == 10100
 
 
 def test_struct_layouts_match_header():
-    assert ctypes.sizeof(hswo.Params) == 56
+    assert ctypes.sizeof(hswo.Params) == 80
     assert hswo.MERGE_DTYPE.itemsize == 24
-    assert ctypes.sizeof(hswo.Stats) == 328
+    assert ctypes.sizeof(hswo.Stats) == 384
+    assert ctypes.sizeof(hswo.Tuning) == 24
+    assert hswo.VERIFY_DTYPE.itemsize == 48
+    src = open(HEADER).read()
+    for name, size in (("hswo_params", 80), ("hswo_stats", 384), ("hswo_tuning", 24), ("hswo_verify_rec", 48),
+                       ("hswo_merge_rec", 24)):
+        assert re.search(r"\}\s*%s;\s*/\*\s*%d bytes" % (name, size), src), name
 
 
 BASE = dict(connectivity=4, seam_connectivity=8, spclust_wght=0.5, spclust_max=256, target_regions=2,
@@ -144,8 +150,9 @@ def test_graph_flag_needs_a_stream_and_unknown_flags_rejected():
     assert lib.hswo_run(FAKE, 16, 16, 4, 0, ctypes.byref(p), FAKE, None, None, FAKE, nb, None) == hswo.HSWO_E_INVAL
     assert "non-null stream" in hswo.last_error()
     q = hswo.make_params(**BASE)
-    q.flags = 128
+    q.flags = 256
     assert lib.hswo_run(FAKE, 16, 16, 4, 0, ctypes.byref(q), FAKE, None, None, FAKE, nb, None) == hswo.HSWO_E_INVAL
+    assert "unknown flags" in hswo.last_error()
 
 
 def test_kernel_times_flag_needs_stats_and_no_graph():
@@ -166,8 +173,9 @@ def test_python_constants_match_header():
     src = open(HEADER).read()
     defs = dict(re.findall(r"#define\s+(HSWO_\w+)\s+\(?(-?\d+)\)?", src))
     for name in ("HSWO_FLAG_MERGE_LOG", "HSWO_FLAG_GRAPH", "HSWO_FLAG_AUTOTUNE", "HSWO_FLAG_INCREMENTAL",
-                 "HSWO_FLAG_KERNEL_TIMES", "HSWO_FLAG_SEQUENTIAL_SECTIONS", "HSWO_FLAG_TWO_MERGES", "HSWO_CRIT_BSMSE", "HSWO_CRIT_SAM",
-                 "HSWO_E_UNSUPPORTED", "HSWO_F32", "HSWO_F16", "HSWO_E_INVAL",
+                 "HSWO_FLAG_KERNEL_TIMES", "HSWO_FLAG_SEQUENTIAL_SECTIONS", "HSWO_FLAG_TWO_MERGES",
+                 "HSWO_FLAG_DEBUG_VERIFY_BOUND", "HSWO_CRIT_BSMSE", "HSWO_CRIT_SAM",
+                 "HSWO_E_UNSUPPORTED", "HSWO_F32", "HSWO_F16", "HSWO_E_INVAL", "HSWO_E_NONFINITE",
                  "HSWO_E_NOMEM"):
         assert int(defs[name]) == getattr(hswo, name), name
     kinds = sorted((int(v), k) for k, v in defs.items() if k.startswith("HSWO_K_"))
@@ -205,3 +213,55 @@ def test_two_merges_need_the_incremental_form(kw):
     q = hswo.make_params(**BASE, two_merges=True, incremental=True)
     r = hswo.make_params(**BASE, incremental=True)
     assert hswo.workspace_bytes(64, 64, 8, 0, q) > hswo.workspace_bytes(64, 64, 8, 0, r) > 0
+
+
+def test_verify_bound_flag_checked():
+    lib = hswo.load()
+    # the incremental form evaluates every pair exactly: nothing to verify
+    p = hswo.make_params(**BASE, incremental=True, verify_ptr=FAKE, verify_cap=16)
+    assert hswo.workspace_bytes(16, 16, 4, 0, p) == 0
+    assert lib.hswo_run(FAKE, 16, 16, 4, 0, ctypes.byref(p), FAKE, None, None, FAKE, 1 << 30, None) == hswo.HSWO_E_INVAL
+    assert "VERIFY" in hswo.last_error()
+    q = hswo.make_params(**BASE, precision="bf16", verify_ptr=FAKE, verify_cap=16)
+    q.verify = None
+    assert lib.hswo_run(FAKE, 16, 16, 4, 0, ctypes.byref(q), FAKE, None, None, FAKE, 1 << 30, None) == hswo.HSWO_E_INVAL
+    r = hswo.make_params(**BASE, precision="bf16", verify_ptr=FAKE, verify_cap=16)
+    plain = hswo.make_params(**BASE, precision="bf16")
+    # the flag adds per-edge screen sums and a candidate staging row per section
+    assert hswo.workspace_bytes(64, 64, 8, 0, r) > hswo.workspace_bytes(64, 64, 8, 0, plain) > 0
+
+
+@pytest.mark.parametrize("field,value", [("wide_max_sections", -2), ("wide_groups", 0), ("rows_grid", 70000),
+                                         ("hybrid", 2), ("bare_bounds", 3), ("driver_variant", 5)])
+def test_invalid_tuning_rejected(field, value):
+    lib = hswo.load()
+    p = hswo.make_params(**BASE, tuning={field: value})
+    assert hswo.workspace_bytes(16, 16, 4, 0, p) == 0
+    assert lib.hswo_run(FAKE, 16, 16, 4, 0, ctypes.byref(p), FAKE, None, None, FAKE, 1 << 30, None) == hswo.HSWO_E_INVAL
+    assert "tuning." + field in hswo.last_error()
+
+
+def test_valid_tuning_and_topk_accepted_by_the_workspace_query():
+    p = hswo.make_params(**BASE, tuning=dict(wide_max_sections=0, rows_grid=512, hybrid=0, bare_bounds=2,
+                                             driver_variant=4), screen_topk=3)
+    assert hswo.workspace_bytes(64, 64, 8, 0, p) == hswo.workspace_bytes(64, 64, 8, 0, hswo.make_params(**BASE))
+    with pytest.raises(ValueError):
+        hswo.make_tuning({"no_such_knob": 1})
+    q = hswo.make_params(**BASE, screen_topk=-1)
+    assert hswo.workspace_bytes(64, 64, 8, 0, q) == 0
+
+
+def test_edge_capacity_beyond_int32_rejected():
+    """A 32768 x 32768 leaf under 8-connectivity has 2^32 edge slots (h*w
+    itself is 2^30 < 2^31): the call is refused before any device work."""
+    lib = hswo.load()
+    p = hswo.make_params(**dict(BASE, connectivity=8))
+    assert hswo.workspace_bytes(32768, 32768, 1, 0, p) == 0
+    rc = lib.hswo_run(FAKE, 32768, 32768, 1, 0, ctypes.byref(p), FAKE, None, None, FAKE, 1 << 40, None)
+    assert rc == hswo.HSWO_E_UNSUPPORTED
+    assert "int32" in hswo.last_error()
+    # two recursion levels: 16384 x 16384 leaves need 2^30 slots each, which fits
+    p2 = hswo.make_params(**dict(BASE, connectivity=8, rnb_levels=2))
+    assert hswo.workspace_bytes(32768, 32768, 1, 0, p2) > 0
+    secs = (hswo.Section * 1)(hswo.Section(FAKE, 32768, 32768, 1, FAKE, None))
+    assert lib.hswo_run_batch(1, secs, 0, ctypes.byref(p), None, FAKE, 1 << 40, None) == hswo.HSWO_E_UNSUPPORTED

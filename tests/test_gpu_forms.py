@@ -79,7 +79,7 @@ def test_driver_variants_identical(variant, monkeypatch):
     sc = synth.voronoi_scene(48, 48, 40, 15, 25.0, 31)
     p = dict(connectivity=4, seam_connectivity=8, spclust_wght=0.5, spclust_max=400, target_regions=4,
              section_regions=100, level_counts=[300, 40, 4])
-    monkeypatch.setenv("HSWO_DRIVER_VARIANT", str(variant))
+    monkeypatch.setattr(hswo, "DEFAULT_TUNING", {"driver_variant": variant})
     _say(f"[gpu] driver variant {variant}")
     res = hswo.rhseg_segment(torch.from_numpy(sc.cube).cuda(), rnb_levels=2, precision="fp16", merge_log=True,
                              stats=True, **p)
@@ -89,7 +89,6 @@ def test_driver_variants_identical(variant, monkeypatch):
 
 def test_autotune_chooses_a_variant_and_keeps_results(tmp_path, monkeypatch):
     monkeypatch.setenv("HSWO_TUNE_CACHE", str(tmp_path / "tune.txt"))
-    monkeypatch.delenv("HSWO_DRIVER_VARIANT", raising=False)
     cubes = uneven_sections(5, seed0=999)
     _say("[gpu] autotune batch")
     dc = [torch.from_numpy(c).cuda() for c in cubes]
@@ -156,7 +155,7 @@ def test_graph_batch_replays():
 def test_level_modes_identical(mode, prec, monkeypatch):
     """Every level run by the persistent driver, or every level in wide mode
     (G workgroups per section, one launch sequence per iteration)."""
-    monkeypatch.setenv("HSWO_WIDE_MAX_SECTIONS", "0" if mode == "persistent" else "100000")
+    monkeypatch.setattr(hswo, "DEFAULT_TUNING", {"wide_max_sections": 0 if mode == "persistent" else 100000})
     sc = synth.voronoi_scene(96, 80, 20, 14, 25.0, 55)
     p = dict(connectivity=4, seam_connectivity=8, spclust_wght=0.5, spclust_max=300, target_regions=5,
              section_regions=80, level_counts=[300, 64, 5])
@@ -171,7 +170,7 @@ def test_level_modes_identical(mode, prec, monkeypatch):
 def test_incremental_adjacent_identical(mode, prec, monkeypatch):
     """Cached exact per-edge D2, re-scoring only what a merge changed: the
     same merges and labels as the full sweep (and the oracle)."""
-    monkeypatch.setenv("HSWO_WIDE_MAX_SECTIONS", "0" if mode == "persistent" else "100000")
+    monkeypatch.setattr(hswo, "DEFAULT_TUNING", {"wide_max_sections": 0 if mode == "persistent" else 100000})
     sc = synth.voronoi_scene(96, 80, 20, 14, 25.0, 56)
     p = dict(connectivity=4, seam_connectivity=8, spclust_wght=0.5, spclust_max=300, target_regions=5,
              section_regions=80, level_counts=[300, 64, 5])

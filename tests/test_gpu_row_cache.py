@@ -17,7 +17,7 @@ MODES = ["persistent", "wide"]
 
 
 def _mode(monkeypatch, mode):
-    monkeypatch.setenv("HSWO_WIDE_MAX_SECTIONS", "0" if mode == "persistent" else "100000")
+    monkeypatch.setattr(hswo, "DEFAULT_TUNING", {"wide_max_sections": 0 if mode == "persistent" else 100000})
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -128,7 +128,7 @@ def test_bare_bound_modes(bare, scene, variant, mode, monkeypatch):
     decision (in the decision kernel in wide mode): the results must not
     change."""
     _mode(monkeypatch, mode)
-    monkeypatch.setenv("HSWO_BARE_BOUNDS", bare)
+    monkeypatch.setattr(hswo, "DEFAULT_TUNING", dict(hswo.DEFAULT_TUNING or {}, bare_bounds=int(bare)))
     make, p = BARE_SCENES[scene]
     p = dict(p)
     if variant == "sam":
@@ -147,7 +147,7 @@ def test_bare_bound_mode_reaches_the_device(mode, monkeypatch):
     cube = make()
     n = {}
     for bare in ("0", "2"):
-        monkeypatch.setenv("HSWO_BARE_BOUNDS", bare)
+        monkeypatch.setattr(hswo, "DEFAULT_TUNING", dict(hswo.DEFAULT_TUNING or {}, bare_bounds=int(bare)))
         n[bare] = assert_parity(cube, dict(p), incremental=True, tag=f"bare bounds count {bare} {mode}")["exact_rechecks"]
     assert n["0"] != n["2"], n
 
@@ -160,7 +160,7 @@ def test_bare_bounds_batch_entry(variant, mode, monkeypatch):
     import oracle
     from tests.test_gpu_forms import BATCH_P, uneven_sections
     _mode(monkeypatch, mode)
-    monkeypatch.setenv("HSWO_BARE_BOUNDS", "2")
+    monkeypatch.setattr(hswo, "DEFAULT_TUNING", dict(hswo.DEFAULT_TUNING or {}, bare_bounds=2))
     p = dict(BATCH_P, criterion=variant)
     cubes = uneven_sections(8, seed0=7171)
     _say(f"[gpu] bare bounds batch {variant} {mode} shapes={[c.shape for c in cubes]}")

@@ -22,7 +22,7 @@ TWO = dict(two_merges=True)
 
 
 def _mode(monkeypatch, mode):
-    monkeypatch.setenv("HSWO_WIDE_MAX_SECTIONS", "0" if mode == "persistent" else "100000")
+    monkeypatch.setattr(hswo, "DEFAULT_TUNING", {"wide_max_sections": 0 if mode == "persistent" else 100000})
 
 
 def _spectral_merges(cube, p):
@@ -89,7 +89,7 @@ def test_spectral_angle(mode, monkeypatch):
 
 
 def test_hybrid_levels_off(monkeypatch):
-    monkeypatch.setenv("HSWO_HYBRID", "0")
+    monkeypatch.setattr(hswo, "DEFAULT_TUNING", {"hybrid": 0})
     sc = synth.voronoi_scene(48, 40, 16, K=10, sigma=25.0, seed=3)
     p = dict(connectivity=4, seam_connectivity=8, spclust_wght=0.5, spclust_max=120, rnb_levels=2,
              section_regions=50, target_regions=4, level_counts=[200, 4], **TWO)
