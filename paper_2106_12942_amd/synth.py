@@ -100,6 +100,22 @@ def quantise_f16(x: np.ndarray) -> np.ndarray:
     return np.clip(q, 0.0, F16_MAX).astype(np.float16)
 
 
+def _noisy_cube(rng: np.random.Generator, spec: np.ndarray, cls: np.ndarray, sigma: float, dtype: str,
+                rows: int = 32) -> np.ndarray:
+    """quantise(spec[cls] + N(0, sigma^2)), drawn and quantised a band of
+    `rows` image rows at a time. The normal draws come from one stream in
+    pixel-major order, so the values are those of a single draw over the
+    whole H x W x B array (the chunking only bounds the temporaries)."""
+    H, W = cls.shape
+    B = spec.shape[1]
+    out = np.empty((H, W, B), dtype=np.float32 if dtype == "f32" else np.float16)
+    for r0 in range(0, H, rows):
+        r1 = min(H, r0 + rows)
+        x = spec[cls[r0:r1]] + rng.normal(0.0, sigma, size=(r1 - r0, W, B))
+        out[r0:r1] = quantise_f32(x) if dtype == "f32" else quantise_f16(x)
+    return out
+
+
 @dataclasses.dataclass
 class Scene:
     cube: np.ndarray          # H x W x B, float32 or float16
@@ -114,9 +130,8 @@ def voronoi_scene(H: int, W: int, B: int, K: int, sigma: float, seed: int,
     rng = _rng(seed)
     cls = voronoi_labels(rng, H, W, K)
     spec = smooth_spectra(rng, K, B)
-    x = spec[cls] + rng.normal(0.0, sigma, size=(H, W, B))
-    cube = quantise_f32(x) if dtype == "f32" else quantise_f16(x)
-    return Scene(np.ascontiguousarray(cube), cls, seed,
+    cube = _noisy_cube(rng, spec, cls, sigma, dtype)
+    return Scene(cube, cls, seed,
                  f"voronoi H={H} W={W} B={B} K={K} sigma={sigma} seed={seed} {dtype}")
 
 
@@ -130,12 +145,12 @@ def mixer_scene(H: int, W: int, B: int, K: int, sigma: float, seed: int,
     rng = _rng(seed)
     cls = voronoi_labels(rng, H, W, K)
     spec = endmember_spectra(rng, K, B)
-    x = spec[cls] + rng.normal(0.0, sigma, size=(H, W, B))
+    cube = _noisy_cube(rng, spec, cls, sigma, dtype)
     if salt > 0.0:
+        # 2000.0 lies on both quantisation grids, so setting it after quantising is the same
         m = rng.random(size=(H, W)) < salt
-        x[m] = 2000.0
-    cube = quantise_f32(x) if dtype == "f32" else quantise_f16(x)
-    return Scene(np.ascontiguousarray(cube), cls, seed,
+        cube[m] = 2000.0
+    return Scene(cube, cls, seed,
                  f"mixer H={H} W={W} B={B} K={K} sigma={sigma} salt={salt} seed={seed} {dtype}")
 
 
