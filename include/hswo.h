@@ -338,6 +338,28 @@ int hswo_run_batch(int32_t n_sections, const hswo_section* sections, int32_t dty
                    const hswo_params* p, hswo_stats* stats, void* workspace, size_t ws_bytes,
                    void* hip_stream);
 
+/*
+ * For callers that cannot allocate device memory (code under stream capture,
+ * serving loops and harnesses that forbid hipMalloc): rhseg_segment without a
+ * workspace argument. The scratch is the library's own static device array of
+ * HSWO_NOALLOC_SCRATCH_BYTES (one copy per GPU, held from the library's first
+ * use of that GPU until the process ends); the call allocates nothing, creates
+ * no event or graph, and otherwise behaves as rhseg_segment (same merges,
+ * labels, merge log and errors).
+ *   - A shape and parameters whose scratch exceeds HSWO_NOALLOC_SCRATCH_BYTES
+ *     (see hswo_workspace_bytes) return HSWO_E_NOMEM before anything is
+ *     enqueued; p->flags may not hold HSWO_FLAG_GRAPH, HSWO_FLAG_AUTOTUNE or
+ *     HSWO_FLAG_KERNEL_TIMES (HSWO_E_INVAL). With stats the call synchronises
+ *     the stream and fills the counters; its device times are 0.
+ *   - Every call on one GPU shares that GPU's array: calls that overlap on
+ *     one GPU (from two threads, or on two streams) race and must not be
+ *     made. The array keeps the last call's contents; no call depends on them.
+ */
+#define HSWO_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20) /* 256 MiB */
+int rhseg_segment_noalloc(const void* cube, int32_t H, int32_t W, int32_t B, int32_t dtype,
+                          const hswo_params* p, int32_t rnb_levels, int32_t* labels,
+                          hswo_merge_rec* merge_log, hswo_stats* stats, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

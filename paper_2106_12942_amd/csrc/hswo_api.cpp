@@ -728,9 +728,11 @@ std::vector<Knob> tune_knobs(bool incremental, const hswo_tuning* g) {
     return k;
 }
 
+// noalloc: the call creates no event, graph or tuning trial (rhseg_segment_noalloc); with stats it
+// still copies the counters back and synchronises, but reports no device times.
 int execute(const std::vector<Upload>& ups, const Seq& seq, const std::string& key, const std::string& tune_key,
             int flags, hipStream_t stream, unsigned long long* d_counters, bool want_stats, const hswo_tuning* given,
-            ExecOut& out) {
+            ExecOut& out, bool noalloc = false) {
     if ((flags & HSWO_FLAG_GRAPH) && stream == nullptr)
         return fail(HSWO_E_INVAL, "HSWO_FLAG_GRAPH needs a non-null stream (the null stream cannot be captured)");
     if ((flags & HSWO_FLAG_KERNEL_TIMES) && ((flags & HSWO_FLAG_GRAPH) || !want_stats))
@@ -785,7 +787,8 @@ int execute(const std::vector<Upload>& ups, const Seq& seq, const std::string& k
         if (rc) return rc;
     }
     EventPair tot;
-    if (want_stats) {
+    const bool timed = want_stats && !noalloc;
+    if (timed) {
         HIP_TRY(hipEventCreate(&tot.a));
         HIP_TRY(hipEventCreate(&tot.b));
         HIP_TRY(hipEventRecord(tot.a, stream));
@@ -823,10 +826,13 @@ int execute(const std::vector<Upload>& ups, const Seq& seq, const std::string& k
         }
         HIP_TRY(hipGraphLaunch(exec, stream));
     } else {
-        const int rc = seq(stream, want_stats ? &tm : nullptr, tu);
+        const int rc = seq(stream, timed ? &tm : nullptr, tu);
         if (rc) return rc;
     }
-    if (want_stats) {
+    if (want_stats && !timed) {
+        HIP_TRY(hipMemcpyAsync(out.counters, d_counters, sizeof(out.counters), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+    } else if (want_stats) {
         HIP_TRY(hipEventRecord(tot.b, stream));
         HIP_TRY(hipMemcpyAsync(out.counters, d_counters, sizeof(out.counters), hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
@@ -951,19 +957,26 @@ int check_common(const hswo_params* p, void* workspace) {
     return HSWO_OK;
 }
 
+// get_scratch non-null: the no-allocation entry point. Everything is validated
+// on the host first (the scratch size included); only then is the scratch's
+// device address fetched through get_scratch (ws_bytes is its size).
 int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_params* p, int L, int32_t* labels,
               hswo_merge_rec* merge_log, hswo_stats* stats, void* workspace, size_t ws_bytes,
-              hipStream_t stream) {
+              hipStream_t stream, int (*get_scratch)(void**) = nullptr) {
+    const bool noalloc = get_scratch != nullptr;
     int rc = validate_shape(H, W, B, dtype);
     if (rc) return rc;
     rc = validate_params(p, L);
     if (rc) return rc;
+    if (noalloc && (p->flags & (HSWO_FLAG_GRAPH | HSWO_FLAG_AUTOTUNE | HSWO_FLAG_KERNEL_TIMES)))
+        return fail(HSWO_E_INVAL, "rhseg_segment_noalloc takes none of HSWO_FLAG_GRAPH, HSWO_FLAG_AUTOTUNE and "
+                                  "HSWO_FLAG_KERNEL_TIMES (each creates graphs or events)");
     if (!cube || !labels) return fail(HSWO_E_INVAL, "cube and labels must be device pointers");
     if (reinterpret_cast<uintptr_t>(cube) % 16) return fail(HSWO_E_INVAL, "cube must be 16-byte aligned");
     if ((H >> (L - 1)) < 1 || (W >> (L - 1)) < 1)
         return fail(HSWO_E_INVAL, "rnb_levels=%d leaves empty sections for %dx%d", L, H, W);
     if ((p->flags & HSWO_FLAG_MERGE_LOG) && !merge_log) return fail(HSWO_E_INVAL, "MERGE_LOG flag needs merge_log");
-    rc = check_common(p, workspace);
+    rc = check_common(p, noalloc ? reinterpret_cast<void*>(256) : workspace);
     if (rc) return rc;
     if (!(p->flags & HSWO_FLAG_MERGE_LOG)) merge_log = nullptr;
 
@@ -971,6 +984,16 @@ int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_param
     rc = check_plan(pl);
     if (rc) return rc;
     const int bare = overlay(default_tuning(false), p->tuning).bare;
+    if (noalloc) {
+        const size_t need = carve(pl, H, W, p, bare, nullptr, cube, labels, merge_log).bytes;
+        if (need > ws_bytes)
+            return fail(HSWO_E_NOMEM,
+                        "this call needs %zu bytes of scratch; rhseg_segment_noalloc has a fixed %zu "
+                        "(HSWO_NOALLOC_SCRATCH_BYTES): call rhseg_segment with a workspace instead",
+                        need, ws_bytes);
+        rc = get_scratch(&workspace);
+        if (rc) return rc;
+    }
     Layout lay = carve(pl, H, W, p, bare, workspace, cube, labels, merge_log);
     if (ws_bytes < lay.bytes)
         return fail(HSWO_E_NOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes, lay.bytes);
@@ -1054,7 +1077,7 @@ int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_param
                              std::to_string(bucket(p->spclust_max + 1)) + ":I" +
                              std::to_string((p->flags & HSWO_FLAG_INCREMENTAL) ? 1 : 0);
     ExecOut eo;
-    rc = execute(ups, seq, key, tkey, p->flags, stream, lay.counters, stats != nullptr, p->tuning, eo);
+    rc = execute(ups, seq, key, tkey, p->flags, stream, lay.counters, stats != nullptr, p->tuning, eo, noalloc);
     if (rc) return rc;
     if (stats) return fill_stats(stats, eo, L);
     return HSWO_OK;
@@ -1269,6 +1292,21 @@ int run_batch(int n, const hswo_section* sec, int dtype, const hswo_params* p, h
 }
 
 }  // namespace
+
+namespace hswo {
+
+int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+
+void clear_error() { g_err.clear(); }
+
+int rhseg_in_scratch(const void* cube, int H, int W, int B, int dtype, const hswo_params* p, int L,
+                     int32_t* labels, hswo_merge_rec* merge_log, hswo_stats* stats, int (*get_scratch)(void**),
+                     size_t scratch_bytes, hipStream_t stream) {
+    return run_rhseg(cube, H, W, B, dtype, p, L, labels, merge_log, stats, nullptr, scratch_bytes, stream,
+                     get_scratch);
+}
+
+}  // namespace hswo
 
 extern "C" {
 

@@ -222,4 +222,15 @@ hipError_t launch_seam(const SecDev* parents, const AsmDev* asm_, int n, const i
 hipError_t launch_snapshot(const SnapDev* snaps, int n, const int32_t* counts, int n_levels, int max_pixels,
                            const unsigned long long* gate, hipStream_t s);
 
+// host runtime (hswo_api.cpp), for the no-allocation entry point (hswo_noalloc.hip)
+int set_error(int code, const char* msg);  // sets hswo_last_error(); returns code
+void clear_error();
+// RHSEG as rhseg_segment, with a fixed device scratch of scratch_bytes as the workspace and no event,
+// graph or tuning trial created; refuses HSWO_FLAG_GRAPH, HSWO_FLAG_AUTOTUNE and
+// HSWO_FLAG_KERNEL_TIMES. Every argument is validated on the host (the scratch size included) before
+// get_scratch is called for the scratch's device address on the current device.
+int rhseg_in_scratch(const void* cube, int H, int W, int B, int dtype, const hswo_params* p, int L,
+                     int32_t* labels, hswo_merge_rec* merge_log, hswo_stats* stats, int (*get_scratch)(void**),
+                     size_t scratch_bytes, hipStream_t stream);
+
 }  // namespace hswo

@@ -49,7 +49,9 @@ SCREEN_STAGES = {0: "adjacent_fp32", 1: "spectral_fp32", 2: "spectral_16bit"}
 TUNING_FIELDS = ["wide_max_sections", "wide_groups", "rows_grid", "hybrid", "bare_bounds", "driver_variant"]
 
 EXPORTS = ["hswo_version", "hswo_last_error", "hswo_workspace_bytes", "hswo_run", "rhseg_segment",
-           "hswo_batch_workspace_bytes", "hswo_run_batch"]
+           "hswo_batch_workspace_bytes", "hswo_run_batch", "rhseg_segment_noalloc"]
+# device scratch of rhseg_segment_noalloc (the library's static array, per GPU)
+HSWO_NOALLOC_SCRATCH_BYTES = 256 << 20
 
 
 class Tuning(ctypes.Structure):
@@ -145,6 +147,15 @@ def load() -> ctypes.CDLL:
     """Load libhswo.so; raises if it has not been built."""
     global _lib
     if _lib is None:
+        # libhswo links the system HIP runtime, torch its own copy; the device
+        # must be opened by torch's first (the other order leaves torch with no
+        # GPU), so a process that has a GPU initialises torch's before loading
+        try:
+            import torch
+            if torch.cuda.is_available():
+                torch.cuda.init()
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                                "or python -m paper_2106_12942_amd.build")
@@ -165,6 +176,9 @@ def load() -> ctypes.CDLL:
         lib.hswo_run_batch.restype = ctypes.c_int
         lib.hswo_run_batch.argtypes = [i32, ctypes.POINTER(Section), i32, ctypes.POINTER(Params),
                                        ctypes.POINTER(Stats), vp, sz, vp]
+        lib.rhseg_segment_noalloc.restype = ctypes.c_int
+        lib.rhseg_segment_noalloc.argtypes = [vp, i32, i32, i32, i32, ctypes.POINTER(Params), i32, vp, vp,
+                                              ctypes.POINTER(Stats), vp]
         _lib = lib
     return _lib
 
@@ -355,6 +369,45 @@ def rhseg_segment(cube, *, rnb_levels: int = 1, merge_log: bool = False, stats: 
                   workspace: Optional[Workspace] = None, labels_out=None, **params) -> Result:
     """RHSEG of a device cube H x W x B (C entry point rhseg_segment)."""
     return _segment("rhseg_segment", cube, rnb_levels, merge_log, stats, stream, params, workspace, labels_out)
+
+
+def rhseg_segment_noalloc(cube, labels_out, *, rnb_levels: int = 1, merge_log_out=None, stats: bool = False,
+                          stream=None, **params) -> Result:
+    """RHSEG of a device cube H x W x B with the library's static device
+    scratch (C entry point rhseg_segment_noalloc): nothing is allocated by this
+    call, so the caller passes the outputs -- labels_out, a contiguous int32
+    [n_levels, H, W] device tensor, and optionally merge_log_out, a uint8
+    device tensor of at least (H*W - target) * 24 bytes. Returns the labels
+    tensor, the merge records (a host copy, after a stream sync) when
+    merge_log_out is given, and the stats when asked for."""
+    import torch
+    if not cube.is_cuda or not cube.is_contiguous():
+        raise ValueError("cube must be a contiguous device tensor (this entry point makes no copy)")
+    H, W, B = cube.shape
+    code = _dtype_code(cube)
+    params = dict(params)
+    params["rnb_levels"] = rnb_levels
+    p = make_params(**params, merge_log=merge_log_out is not None)
+    if tuple(labels_out.shape) != (p.n_levels, H, W) or labels_out.dtype != torch.int32 or \
+            not labels_out.is_contiguous():
+        raise ValueError("labels_out must be a contiguous int32 [n_levels, H, W] device tensor")
+    n_merges = H * W - params.get("target_regions", 1)
+    if merge_log_out is not None and merge_log_out.numel() * merge_log_out.element_size() < \
+            max(n_merges, 0) * MERGE_DTYPE.itemsize:
+        raise ValueError("merge_log_out is too small")
+    s = stream if stream is not None else torch.cuda.current_stream(cube.device)
+    st = Stats() if stats else None
+    _order_streams(s, cube.device)
+    _check(load().rhseg_segment_noalloc(cube.data_ptr(), H, W, B, code, ctypes.byref(p), rnb_levels,
+                                        labels_out.data_ptr(),
+                                        merge_log_out.data_ptr() if merge_log_out is not None else None,
+                                        ctypes.byref(st) if st is not None else None, s.cuda_stream))
+    _keep_alive(s, cube, labels_out, merge_log_out)
+    log = None
+    if merge_log_out is not None:
+        s.synchronize()
+        log = np.frombuffer(merge_log_out.cpu().numpy().tobytes(), dtype=MERGE_DTYPE)[:max(n_merges, 0)]
+    return Result(labels=labels_out, log=log, stats=st.as_dict() if st is not None else None)
 
 
 def hswo_run(cube, *, merge_log: bool = False, stats: bool = False, stream=None,
