@@ -7,9 +7,15 @@ the reassembly of each recursion level, the parents' loops, and the label
 maps of the requested hierarchy levels (all of it in the HIP kernels).
 
 Workloads
-  rhseg512 (default): 512 x 512 x 128 float32 Voronoi scene (200 classes,
-      sigma 30, seed 202), rnb_levels 4 (64 x 64 leaves), w 0.5, spectral
-      stage at <= 1024 regions, sections stop at 256, 8 output levels.
+  rhseg2048_f16 (default, the largest): 2048 x 2048 x 224 float16 endmember
+      mixture (500 classes, sigma 25, seed 505), rnb_levels 5 (128 x 128
+      leaves), w 0.5, spectral stage at <= 2048 regions, sections stop at 512,
+      target 16, 8 output levels.
+  rhseg1024_salt: 1024 x 1024 x 220 float32 endmember mixture with 5% identical
+      salt pixels, rnb_levels 5.
+  rhseg512: 512 x 512 x 128 float32 Voronoi scene (200 classes, sigma 30,
+      seed 202), rnb_levels 4 (64 x 64 leaves), w 0.5, spectral stage at
+      <= 1024 regions, sections stop at 256, 8 output levels.
   hswo64: 64 x 64 x 32 float32 Voronoi (40 classes, sigma 20, seed 101), one
       section, spectral at <= 256, down to 2 regions, 11 levels.
   batch256: 256 independent sections, side U{32..128}, bands U{64,96,..,224},
@@ -18,24 +24,33 @@ Workloads
 
 Forms (--form): "incremental" (default): cached exact per-edge D2 and the
 spectral row cache; "screened": every pair screened each iteration, the
-spectral stage on matrix cores (--precision fp16 or bf16); "plain": every
-pair screened each iteration in FP32, the sections of a level one after
-another (neither the precision nor the batching form); "plain_batched": the
-same FP32 screens with the sections of a level batched. Levels run batched
-into one launch (persistent) or one launch sequence per iteration (wide),
-replayed from a hipGraph. The other forms run once on the same input for the comparison, and
-must give the same labels.
+spectral stage on matrix cores (--precision bf16, the default, or fp16);
+"plain": every pair screened each iteration in FP32, the sections of a level
+one after another (neither the precision nor the batching form);
+"plain_batched": the same FP32 screens with the sections of a level batched.
+Levels run batched into one launch (persistent) or one launch sequence per
+iteration (wide), replayed from a hipGraph; the first warm-up call autotunes
+the execution settings (--no-autotune: library defaults). The other forms run
+once on the same input for the comparison and must give the same labels (the
+plain forms are skipped on the two largest workloads, where they take many
+minutes).
 
 Criterion (--criterion): "bsmse" (default), the paper's Equation 1; "sam",
 the spectral angle. --two-merges: the two-merge reading of the HSEG steps.
 Both exist in the incremental form only, so no other form is compared.
 
-Output: one JSON line. `value` is dissimilarity pairs per second: the
-method's pairs (live adjacent pairs, plus R(R-1)/2 per iteration of the
-spectral stage, counted by the kernels) over the wall time of a step. The
-roofline object is for the kernel with the largest device time in one extra
-eager step of the timed form with every launch bracketed by hipEvents
-(HSWO_FLAG_KERNEL_TIMES).
+Output: one JSON line. `value` is dissimilarity pairs evaluated per second of
+wall time, counted by the kernels: the incremental form's exact FP64
+evaluations (cache re-scoring and row-cache rows); for the screened and plain
+forms every live adjacent pair and every unique spectral pair screened in
+each iteration. `method_pairs_per_s` counts the method's pairs instead (live
+adjacent pairs, plus R(R-1)/2 per iteration of the spectral stage), whether
+evaluated or read from a cache. The roofline object is for the kernel with
+the largest device time in one extra eager step of the timed form with every
+launch bracketed by hipEvents (HSWO_FLAG_KERNEL_TIMES). `cpu_baseline` is the
+FP64 oracle on the host's threads: the whole workload where that takes
+seconds, else a bounded sample of leaf sections; the whole workload always
+goes through the oracle once for the per-level label check.
 """
 from __future__ import annotations
 
@@ -94,8 +109,9 @@ KIND_DESC = {
     "wide_mfma": "k_wide_mfma (matrix-core tile screen)",
     "wide_fp32": "k_wide_fp32 (FP32 tile screen)",
     "wide_finish": "k_wide_finish (spectral decision and merge)",
-    "wide_rows": "k_wide_rows (row-cache re-evaluation, exact FP64)",
+    "wide_rows": "k_wide_rows / k_mat_rows (row cache: rows evaluated in FP64, or rescanned from the interval matrix)",
     "rowcache_prep": "k_rowcache_prep",
+    "matrix_fill": "k_mat_fill (interval matrix of starting row caches: FP32 mean differences, 64 x 64 tiles)",
 }
 
 
@@ -109,8 +125,10 @@ def kernel_roofline(st, B, tag, kind=None):
       wide_decide: bytes counted on the device by the kernel (16 per edge slot
         read for the minimum, 24 per band per merge; in the spectral stage 12
         per live row and 32 per pending row per 64 live rows) -> HBM bound;
-      wide_rows: 3 FP64 flops per band per exactly evaluated pair (2 for the
-        spectral angle), counted on the device -> FP64 vector bound (78.6 TFLOP/s);
+      wide_rows: bytes counted on the device: exact row tasks read each
+        column's FP64 mean row once per 4 rows (3 flops per band and pair, far
+        below the ridge), rescans read a row of the interval matrix and the
+        FP64 rows of the pairs it cannot rule out -> HBM bound;
       section_driver, incremental form: the wide_decide bytes of the
         iterations it runs + 8 B per band per live region for each iteration
         whose row-cache stage evaluates rows, counted on the device -> HBM bound;
@@ -144,7 +162,10 @@ def kernel_roofline(st, B, tag, kind=None):
         bound, peak, unit, scale = "hbm", PEAK_HBM_GBS, "GB/s", 1e9
     elif kind == "wide_rows":
         work = float(kw[k])
-        bound, peak, unit, scale = "alu", PEAK_FP64_VALU_TFLOPS, "TFLOP/s", 1e12
+        bound, peak, unit, scale = "hbm", PEAK_HBM_GBS, "GB/s", 1e9
+    elif kind == "matrix_fill":
+        work = float(kw[k])
+        bound, peak, unit, scale = "alu", PEAK_FP32_VALU_TFLOPS, "TFLOP/s", 1e12
     elif kind == "wide_mfma":
         work = float(kw[k])
         bound, peak, unit, scale = "mfma", PEAK_MFMA_TFLOPS["fp16"], "TFLOP/s", 1e12
@@ -212,8 +233,112 @@ def timed_steps(step, stream, torch, steps, warmup, first=None):
     return elapsed * 1e3 / steps, walls, res
 
 
+def evaluated_pairs(st, form):
+    """Pairs the kernels evaluated in a call, counted on the device: the
+    incremental form evaluates only what its caches miss: edge re-scoring
+    and row-cache rows (rescanned from the interval matrix, and in FP64
+    where a bound cannot rule a pair out); the screened and plain
+    forms screen every live adjacent pair and every unique pair of the
+    spectral stage in each iteration (their exact re-checks are second looks
+    at pairs already screened)."""
+    if form == "incremental":
+        return st["exact_rechecks"] + st["row_bounded_pairs"]
+    return st["adjacent_pairs"] + st["spectral_pairs"]
+
+
+def say(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def leaf_grid(H, W, L):
+    """Leaf rectangles of the RHSEG quadtree (split at floor(h/2), floor(w/2);
+    TL, TR, BL, BR), in quadtree order."""
+    def rec(r0, c0, h, w, d):
+        if d == 1:
+            return [(r0, c0, h, w)]
+        h0, w0 = h // 2, w // 2
+        out = []
+        for (rr, cc, hh, ww) in ((r0, c0, h0, w0), (r0, c0 + w0, h0, w - w0), (r0 + h0, c0, h - h0, w0),
+                                 (r0 + h0, c0 + w0, h - h0, w - w0)):
+            out += rec(rr, cc, hh, ww, d - 1)
+        return out
+    return rec(0, 0, H, W, L)
+
+
+def screen_error_report(np, torch, hswo, cube_h, params, precision, leaf):
+    """HSWO_FLAG_DEBUG_VERIFY_BOUND on the top-left crop of four by four
+    leaves (rnb_levels 3, the workload's leaf shape and parameters): every
+    pair a screen passed to the FP64 re-check with its screen estimate, its
+    certified bounds and its canonical D2. Error is relative, in Equation 1's
+    square-root domain, over pairs with D2 > 0."""
+    side_h, side_w = 4 * leaf[0], 4 * leaf[1]
+    crop = np.ascontiguousarray(cube_h[:side_h, :side_w])
+    kw = {k: v for k, v in params.items() if k != "rnb_levels"}
+    kw["level_counts"] = [c for c in kw["level_counts"] if c < side_h * side_w] or [kw["target_regions"]]
+    cap = 1 << 23
+    res = hswo.rhseg_segment(torch.from_numpy(crop).cuda(), rnb_levels=3, stats=True, precision=precision,
+                             incremental=False, verify_cap=cap, **kw)
+    rec = res.verify
+    out = {"crop": f"{side_h}x{side_w} top-left, rnb_levels 3", "precision": precision,
+           "records": int(res.stats["verify_records"]), "records_kept": int(len(rec))}
+    ok = (rec["lower"] <= rec["d2"]) & (rec["d2"] <= rec["upper"])
+    out["pairs_within_certified_bounds"] = float(ok.mean()) if len(rec) else None
+    for st, name in hswo.SCREEN_STAGES.items():
+        r = rec[(rec["stage"] == st) & (rec["d2"] > 0)]
+        if r.size == 0:
+            continue
+        rel = np.abs(np.sqrt(np.maximum(r["screen"], 0.0)) - np.sqrt(r["d2"])) / np.sqrt(r["d2"])
+        out[name] = {"pairs": int(r.size), "p50": float(np.percentile(rel, 50)),
+                     "p99": float(np.percentile(rel, 99)), "max": float(rel.max())}
+    return out
+
+
+def cpu_leaf_sample(np, oracle, hswo, torch, cube_h, params, L, seconds=15.0):
+    """The oracle on whole leaf sections of the workload (in quadtree order,
+    `threads` at a time, one host thread each) until about `seconds` have
+    passed; the same leaves through the GPU's incremental form give the pairs
+    it evaluates for them, so the rate is in the timed value's unit."""
+    import concurrent.futures as cf
+    H, W, _ = cube_h.shape
+    leaves = leaf_grid(H, W, L)
+    S = params["section_regions"] or max(params["target_regions"], params["spclust_max"] // 4)
+    lp = {k: v for k, v in params.items() if k not in ("rnb_levels", "level_counts", "section_regions",
+                                                      "target_regions")}
+    lp.update(target_regions=S, section_regions=0, level_counts=[S])
+    threads = host_threads()
+    cubes, done = [], 0
+    t0 = time.perf_counter()
+    while done < len(leaves) and time.perf_counter() - t0 < seconds:
+        batch = leaves[done:done + threads]
+        cs = [np.ascontiguousarray(cube_h[r:r + h, c:c + w]) for (r, c, h, w) in batch]
+        with cf.ThreadPoolExecutor(threads) as ex:
+            list(ex.map(lambda c: oracle.rhseg(c, **lp, n_threads=1), cs))
+        cubes += cs
+        done += len(batch)
+    cpu_s = time.perf_counter() - t0
+    rs = hswo.hswo_run_batch([torch.from_numpy(c).cuda() for c in cubes], stats=True, precision="bf16",
+                             incremental=True, **lp)
+    pairs = evaluated_pairs(rs.stats, "incremental")
+    return {"value": pairs / cpu_s, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "sample": f"leaf sections 0..{done - 1} of {len(leaves)} ({leaves[0][2]}x{leaves[0][3]} px, each merged "
+                      f"to {S} regions as in the workload's deepest level), FP64 oracle in cached mode, one leaf per "
+                      f"host thread on {threads} threads, {cpu_s:.2f} s; rate = the pairs the GPU's incremental "
+                      f"form evaluates for those leaves ({pairs}) over that time",
+            "seconds": cpu_s, "leaves": done}
+
+
+def host_threads():
+    """CPUs this process may run on (the oracle's thread count)."""
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
 def bench_rhseg(args, np, torch, hswo, synth):
+    t0 = time.perf_counter()
     sc, params = synth.workload(args.workload)
+    say(f"{args.workload} cube generated in {time.perf_counter() - t0:.1f} s")
     params.update(variant_kwargs(args))
     cube_h = sc.cube
     H, W, B = cube_h.shape
@@ -226,28 +351,33 @@ def bench_rhseg(args, np, torch, hswo, synth):
     nl = len(params["level_counts"])
     labels = torch.empty((nl, H, W), dtype=torch.int32, device=dev)
 
-    def runner(form, out, graph, kernel_times=False):
+    def runner(form, out, graph, kernel_times=False, autotune=False):
         fk = form_kwargs(form, args.precision)
 
         def step():
             return hswo.rhseg_segment(cube, rnb_levels=L, stats=True, stream=stream, workspace=ws, labels_out=out,
-                                      graph=graph, autotune=args.autotune, kernel_times=kernel_times, **fk, **kw)
+                                      graph=graph, autotune=autotune, kernel_times=kernel_times, **fk, **kw)
         return step
 
     first = []
-    ms_per_step, walls, res = timed_steps(runner(args.form, labels, args.graph), stream, torch, args.steps,
-                                          args.warmup, first)
+    say(f"timed form {args.form}: {args.warmup} warm-up + {args.steps} timed steps")
+    ms_per_step, walls, res = timed_steps(runner(args.form, labels, args.graph, autotune=args.autotune), stream,
+                                          torch, args.steps, args.warmup, first)
     st = res.stats
-    pairs = st["adjacent_pairs"] + st["spectral_pairs"]
+    method_pairs = st["adjacent_pairs"] + st["spectral_pairs"]
+    ev = evaluated_pairs(st, args.form)
     fk = form_kwargs(args.form, args.precision)
     out = {
-        "value": pairs / (ms_per_step / 1e3), "unit": "pairs/s", "ms_per_step": ms_per_step,
+        "value": ev / (ms_per_step / 1e3), "unit": "pairs/s", "ms_per_step": ms_per_step,
         "wall_ms_median": statistics.median(walls), "wall_ms_min": min(walls), "wall_ms_max": max(walls),
         "config": {"workload": args.workload, "desc": WORKLOAD_DESC[args.workload], "H": H, "W": W, "B": B,
-                   "form": args.form, "precision": fk["precision"], "criterion": args.criterion,
-                   "two_merges": args.two_merges, "graph": args.graph, "autotune": args.autotune,
-                   "driver_variant": st["driver_variant"]},
-        "pairs_per_step": pairs, "merges_per_step": st["merges"], "exact_evaluations_per_step": st["exact_rechecks"],
+                   "cube_dtype": str(cube_h.dtype), "form": args.form,
+                   "precision": fk["precision"] if args.form != "incremental" else "none: every pair evaluated "
+                   "exactly in FP64", "criterion": args.criterion, "two_merges": args.two_merges,
+                   "graph": args.graph, "autotune": args.autotune, "tuning": st["tuning"]},
+        "evaluated_pairs_per_step": ev,
+        "method_pairs_per_step": method_pairs, "method_pairs_per_s": method_pairs / (ms_per_step / 1e3),
+        "merges_per_step": st["merges"], "exact_evaluations_per_step": st["exact_rechecks"],
         "fp32_tiles_per_step": st["fp32_tiles"], "mfma_super_tiles_per_step": st["mfma_tiles"],
         "first_call_ms": first[0] if first else None,
     }
@@ -256,22 +386,24 @@ def bench_rhseg(args, np, torch, hswo, synth):
     # paper's times include that transfer); value stays the device-resident rate
     pinned = torch.from_numpy(cube_h).pin_memory()
     step = runner(args.form, labels, args.graph)
+    nh = min(3, args.steps)
 
     def step_h2d():
         cube.copy_(pinned, non_blocking=True)
         return step()
-    ms_h2d, _, _ = timed_steps(step_h2d, stream, torch, args.steps, 1)
+    ms_h2d, _, _ = timed_steps(step_h2d, stream, torch, nh, 1)
     with torch.cuda.stream(stream):
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
+        t1 = time.perf_counter()
+        for _ in range(nh):
             cube.copy_(pinned, non_blocking=True)
         stream.synchronize()
-        h2d_ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    out["with_h2d"] = {"ms_per_step": ms_h2d, "value": pairs / (ms_h2d / 1e3), "h2d_ms": h2d_ms,
-                       "h2d_bytes": int(cube_h.nbytes)}
+        h2d_ms = (time.perf_counter() - t1) * 1e3 / nh
+    out["with_h2d"] = {"ms_per_step": ms_h2d, "value": ev / (ms_h2d / 1e3), "h2d_ms": h2d_ms,
+                       "h2d_bytes": int(cube_h.nbytes), "steps": nh}
     # per-kernel device times: one more step of the timed form, eager, every launch bracketed by hipEvents
     same_kt = None
     if not args.no_kernel_times:
+        say("kernel-times step")
         kt = torch.empty_like(labels)
         _, _, rk = timed_steps(runner(args.form, kt, False, kernel_times=True), stream, torch, 1, 0)
         out["kernel_times_step_ms"] = rk.stats["ms_total"]
@@ -285,18 +417,28 @@ def bench_rhseg(args, np, torch, hswo, synth):
             continue
         if variant_tag(args) and form != "incremental":
             continue  # the other criterion and the two-merge reading exist in the incremental form only
+        say(f"form {form}")
         o = torch.empty_like(labels)
         # the unbatched plain path is a long launch sequence: eager, one warm-up and one timed call
         ms, _, r = timed_steps(runner(form, o, args.graph and form != "plain"), stream, torch, 1, 1)
+        rst = r.stats
         comparisons[form] = {"ms_per_step": ms, "speedup_of_timed_form": ms / ms_per_step,
                              "labels_identical_to_timed_form": bool(torch.equal(o, labels)),
-                             "precision": form_kwargs(form, args.precision)["precision"]}
+                             "precision": form_kwargs(form, args.precision)["precision"],
+                             "evaluated_pairs_per_step": evaluated_pairs(rst, form),
+                             "evaluated_pairs_per_s": evaluated_pairs(rst, form) / (ms / 1e3)}
+        if form != "incremental":
+            comparisons[form]["screen_iterations"] = rst["screen_iterations"]
+            comparisons[form]["screen_fallbacks"] = rst["screen_fallbacks"]
+            comparisons[form]["fallback_rate"] = rst["screen_fallbacks"] / max(1, rst["screen_iterations"])
         if form == "screened" and not args.no_kernel_times:
             # the screened form's own sweeps: adjacent screen against HBM, matrix-core screen against MFMA peak
+            say("form screened, kernel-times step")
             _, _, rs = timed_steps(runner(form, o, False, kernel_times=True), stream, torch, 1, 0)
             comparisons[form]["rooflines"] = {
                 kd: kernel_roofline(rs.stats, B, f"{args.workload}_{form}", kind=kd)
-                for kd in ("wide_adj", "wide_mfma") if rs.stats["kernel_launches"][hswo.KERNEL_KINDS.index(kd)]}
+                for kd in ("wide_adj", "wide_mfma", "section_driver")
+                if rs.stats["kernel_launches"][hswo.KERNEL_KINDS.index(kd)]}
     if "plain" in comparisons:
         # the plain FP32 path (no precision form, no batching) against every form
         pm = comparisons["plain"]["ms_per_step"]
@@ -304,27 +446,38 @@ def bench_rhseg(args, np, torch, hswo, synth):
                                    **{f: pm / v["ms_per_step"] for f, v in comparisons.items() if f != "plain"}}
     out["forms"] = comparisons
     out["labels_identical_kernel_times_step"] = same_kt
-    if args.workload in LARGE:
-        out["cpu_baseline"] = None
-        out["cpu_baseline_note"] = "not run for this workload (the oracle takes minutes); parity is checked by the GPU tests"
-    elif not args.no_cpu_baseline:
+    if not args.no_forms and not variant_tag(args):
+        say("screen error report (bound-verification records)")
+        leaf = leaf_grid(H, W, L)[0][2:]
+        out["screen_error"] = screen_error_report(np, torch, hswo, cube_h, params,
+                                                  args.precision if args.precision != "fp32" else "bf16", leaf)
+    if not args.no_cpu_baseline:
         import oracle
-        threads = os.cpu_count() or 1
+        threads = host_threads()
+        if args.workload in LARGE:
+            say("cpu baseline: oracle on a bounded sample of leaf sections")
+            out["cpu_baseline"] = cpu_leaf_sample(np, oracle, hswo, torch, cube_h, params, L)
+            out["gpu_vs_oracle_speedup_on_sample"] = out["value"] / out["cpu_baseline"]["value"]
+        say(f"oracle on the whole workload ({threads} threads) for the per-level label check")
         tc = time.perf_counter()
         ref = oracle.rhseg(cube_h, **params, n_threads=threads)
         cpu_s = time.perf_counter() - tc
-        out["cpu_baseline"] = {"value": pairs / cpu_s, "unit": "pairs/s", "cores": threads, "kind": "oracle",
-                               "sample": f"the full {args.workload} workload, FP64 oracle (cached mode, sections of "
-                                         f"a level on {threads} threads), {cpu_s:.2f} s; the method's pairs "
-                                         "counted as for the GPU value"}
-        out["labels_identical_to_oracle"] = bool(np.array_equal(lab, ref.labels))
+        per_level = [bool(np.array_equal(lab[i], ref.labels[i])) for i in range(nl)]
+        out["labels_identical_to_oracle"] = all(per_level)
+        out["labels_identical_to_oracle_per_level"] = dict(zip([int(c) for c in params["level_counts"]], per_level))
+        out["oracle_whole_workload_s"] = cpu_s
         out["gpu_vs_oracle_speedup"] = cpu_s * 1e3 / ms_per_step
+        if args.workload not in LARGE:
+            out["cpu_baseline"] = {"value": ev / cpu_s, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+                                   "sample": f"the whole {args.workload} workload, FP64 oracle (cached mode, sections "
+                                             f"of a level on {threads} threads), {cpu_s:.2f} s; rate = the pairs "
+                                             "the timed GPU form evaluates for it over that time"}
         if args.single_thread_oracle:
             # the paper's sequential baseline: the oracle on one host thread
             tc = time.perf_counter()
             oracle.rhseg(cube_h, **params, n_threads=1)
             one_s = time.perf_counter() - tc
-            out["cpu_single_thread"] = {"value": pairs / one_s, "unit": "pairs/s", "seconds": one_s,
+            out["cpu_single_thread"] = {"value": ev / one_s, "unit": "pairs/s", "seconds": one_s,
                                         "gpu_speedup": one_s * 1e3 / ms_per_step}
     return out, B
 
@@ -461,8 +614,9 @@ def bench_sweep(args, np, torch, hswo, synth):
         p = sweep_params(cfg["side"])
         kw = {k: v for k, v in p.items() if k != "rnb_levels"}
         cube = torch.from_numpy(sc.cube).cuda()
+        tuning = None
         if "variant" in cfg:
-            os.environ["HSWO_DRIVER_VARIANT"] = str(cfg["variant"])
+            tuning = dict(driver_variant=cfg["variant"])
             form = "screened"
         else:
             form = args.form
@@ -471,11 +625,10 @@ def bench_sweep(args, np, torch, hswo, synth):
         for k in range(4):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            res = hswo.rhseg_segment(cube, rnb_levels=p["rnb_levels"], stats=True, **fk, **kw)
+            res = hswo.rhseg_segment(cube, rnb_levels=p["rnb_levels"], stats=True, tuning=tuning, **fk, **kw)
             torch.cuda.synchronize()
             if k:
                 times.append((time.perf_counter() - t0) * 1e3)
-        os.environ.pop("HSWO_DRIVER_VARIANT", None)
         gpu_ms = statistics.median(times)
         tc = time.perf_counter()
         ref = oracle.rhseg(sc.cube, **p, n_threads=threads)
@@ -495,17 +648,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rhseg512", choices=sorted(WORKLOAD_DESC))
+    ap.add_argument("--workload", default="rhseg2048_f16", choices=sorted(WORKLOAD_DESC))
     ap.add_argument("--form", default="incremental", choices=["incremental", "screened", "plain", "plain_batched"],
                     help="form of the timed steps (the others run once for the comparison)")
-    ap.add_argument("--precision", default="fp16", choices=["fp32", "bf16", "fp16"],
+    ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp16"],
                     help="matrix-core screen precision of the screened form")
     ap.add_argument("--criterion", default="bsmse", choices=["bsmse", "sam"],
                     help="dissimilarity: Equation 1 (bsmse) or the spectral angle (sam, incremental form only)")
     ap.add_argument("--two-merges", action="store_true",
                     help="two-merge reading of the HSEG steps (incremental form only)")
     ap.add_argument("--no-graph", dest="graph", action="store_false", help="launch eagerly instead of a hipGraph")
-    ap.add_argument("--autotune", action="store_true", help="autotune the section-driver variant first")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="library default execution settings instead of the autotuner's (the first warm-up call "
+                         "tunes the timed form's settings: workgroups per section, which levels run persistent, "
+                         "the row-stage grid, the section-driver variant)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the runs of the forms not timed")
@@ -556,7 +712,7 @@ def main():
            "value": body.pop("value"), "unit": body.pop("unit"), "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": body.pop("ms_per_step"), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64" if args.form == "incremental" else ("f32+f16 screens, f64 decisions"
+           "dtype": "f64" if args.form == "incremental" else (f"f32+{args.precision} screens, f64 decisions"
                                                               if args.precision != "fp32" else "f32 screen, f64 decisions"),
            "data": "synthetic"}
     out.update(body)

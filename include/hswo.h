@@ -139,7 +139,8 @@ extern "C" {
                                     HSWO_FLAG_INCREMENTAL form only (else HSWO_E_UNSUPPORTED). */
 #define HSWO_FLAG_AUTOTUNE 4  /* on the first call for a shape bucket, time candidate execution
                                  settings (hswo_tuning: workgroups per section, which levels run
-                                 persistent, the row-stage grid, the section-driver variant) on the
+                                 persistent, the row-stage grid and interval matrix, the
+                                 section-driver variant) on the
                                  call itself -- all give identical results -- and keep the fastest;
                                  the choice is cached per process and appended to the file named by
                                  the environment variable HSWO_TUNE_CACHE if set. Settings given
@@ -165,7 +166,14 @@ typedef struct hswo_tuning {
                                    merges: 0 none, 1 those of value 0, 2 all; default 1 */
     int32_t driver_variant;     /* adjacent-sweep edges in flight per 16-lane group of the screened
                                    forms: 2, 4 or 6; default 6 */
-} hswo_tuning;                  /* 24 bytes */
+    int32_t row_matrix;         /* incremental form, Equation 1, one-merge reading, wide mode: 1 = the
+                                   row cache keeps certified FP32 bounds on every pair's value, brought
+                                   up to date at each merge by Ward's update (O(R) per merge); a row
+                                   whose cached pair went stale is rescanned from its bounds and only
+                                   the pairs that can be among its least two are evaluated in FP64;
+                                   0 = stale rows re-evaluated in FP64 against every column. Up to
+                                   4096 row-cache slots (spclust_max); default 1 */
+} hswo_tuning;                  /* 28 bytes */
 
 /* One pair checked under HSWO_FLAG_DEBUG_VERIFY_BOUND. */
 typedef struct hswo_verify_rec {
@@ -223,7 +231,9 @@ typedef struct hswo_merge_rec {
 #define HSWO_K_WIDE_FINISH 5    /* wide mode: spectral decision and merge */
 #define HSWO_K_WIDE_ROWS 6      /* wide mode, incremental form: row-cache re-evaluation */
 #define HSWO_K_ROWCACHE_PREP 7  /* incremental form: row cache start at a pass start */
-#define HSWO_NK 8
+#define HSWO_K_MATRIX_FILL 8    /* wide mode, incremental form: the interval matrix of row caches that
+                                   start, 64 x 64 pair tiles of FP32 mean differences */
+#define HSWO_NK 9
 
 typedef struct hswo_stats {
     int64_t merges;              /* merges performed */
@@ -233,7 +243,8 @@ typedef struct hswo_stats {
     int64_t spectral_pairs;      /* unordered pairs of the method's spectral stage, summed over the
                                     iterations where it is active (R (R - 1) / 2 each) */
     int64_t exact_rechecks;      /* pairs evaluated in canonical FP64 (screen re-checks, cache
-                                    re-scoring and row-cache rows) */
+                                    re-scoring, row-cache rows, and the pairs a rescan from the
+                                    interval matrix could not rule out) */
     int64_t tile_rescans;        /* spectral tiles re-screened to collect candidates */
     int64_t fp32_tiles;          /* 64 x 64 spectral tiles screened in FP32 */
     int64_t mfma_tiles;          /* 128 x 128 super tiles screened on matrix cores (16-bit forms) */
@@ -257,8 +268,12 @@ typedef struct hswo_stats {
        pending row per 64 live rows (least two candidates of each 64 columns),
        + 8 per band per live region when rows whose second bound no longer
        holds are evaluated in full before the minimum;
-       HSWO_K_WIDE_ROWS flops = 3 per band per pair evaluated (2 for the
-       spectral angle);
+       HSWO_K_WIDE_ROWS bytes = exact row tasks (up to 4 rows by 64 columns):
+       the columns' FP64 mean rows read once (8 per band and column) + 8 per
+       band per row; matrix rescans: 8 per pair of a rescanned row (its
+       bounds) + 16 per band (two FP64 mean rows) and 16 per pair evaluated
+       exactly;
+       HSWO_K_MATRIX_FILL flops = 3 FP32 flops per band per pair bounded;
        HSWO_K_SECTION_DRIVER (incremental form) bytes = the HSWO_K_WIDE_DECIDE
        count for the iterations it runs + 8 per band per live region for each
        iteration whose row-cache stage evaluates rows (every FP64 row read
@@ -279,8 +294,12 @@ typedef struct hswo_stats {
     int64_t screen_fallbacks;    /* ... of which the re-check set held more than screen_topk pairs */
     int64_t verify_records;      /* HSWO_FLAG_DEBUG_VERIFY_BOUND: records produced (written up to
                                     verify_cap) */
+    int64_t row_bounded_pairs;   /* incremental form: row-cache pairs rescanned from the interval
+                                    matrix (hswo_tuning.row_matrix); those it could not rule out are
+                                    counted in exact_rechecks */
     hswo_tuning tuning;          /* the execution settings the call used */
-} hswo_stats;   /* 384 bytes */
+    int32_t reserved;
+} hswo_stats;   /* 424 bytes */
 
 /* One independent section for hswo_run_batch. */
 typedef struct hswo_section {

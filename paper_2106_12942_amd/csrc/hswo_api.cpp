@@ -21,6 +21,14 @@
 
 using namespace hswo;
 
+// the struct sizes the header states (the Python binding mirrors them)
+static_assert(sizeof(hswo_params) == 80, "hswo_params layout");
+static_assert(sizeof(hswo_tuning) == 28, "hswo_tuning layout");
+static_assert(sizeof(hswo_stats) == 424, "hswo_stats layout");
+static_assert(sizeof(hswo_merge_rec) == 24, "hswo_merge_rec layout");
+static_assert(sizeof(hswo_verify_rec) == 48, "hswo_verify_rec layout");
+static_assert(sizeof(hswo_section) == 40, "hswo_section layout");
+
 namespace {
 
 thread_local std::string g_err;
@@ -167,9 +175,11 @@ struct Tuning {
     int hybrid = 1;     // incremental form: pre-spectral merges of a wide level in the persistent driver
     int bare = 1;       // row-cache second bounds kept bare: 0 none, 1 those of value 0, 2 all
     int variant = 6;    // adjacent-sweep edges in flight per 16-lane group (screened forms)
+    int row_matrix = 1; // incremental form, wide mode: the row cache's interval matrix
     std::string str() const {
         return std::to_string(wide_max) + "," + std::to_string(wide_wg) + "," + std::to_string(rows_grid) + "," +
-               std::to_string(hybrid) + "," + std::to_string(bare) + "," + std::to_string(variant);
+               std::to_string(hybrid) + "," + std::to_string(bare) + "," + std::to_string(variant) + "," +
+               std::to_string(row_matrix);
     }
 };
 
@@ -186,6 +196,7 @@ Tuning default_tuning(bool incremental) {
     t.hybrid = 1;
     t.bare = 1;
     t.variant = 6;
+    t.row_matrix = 1;
     return t;
 }
 
@@ -198,6 +209,7 @@ Tuning overlay(Tuning t, const hswo_tuning* g) {
     if (g->hybrid >= 0) t.hybrid = g->hybrid;
     if (g->bare_bounds >= 0) t.bare = g->bare_bounds;
     if (g->driver_variant >= 0) t.variant = g->driver_variant;
+    if (g->row_matrix >= 0) t.row_matrix = g->row_matrix;
     return t;
 }
 
@@ -212,6 +224,7 @@ int validate_tuning(const hswo_tuning* g) {
     if (g->bare_bounds < -1 || g->bare_bounds > 2) return fail(HSWO_E_INVAL, "tuning.bare_bounds must be in [-1, 2]");
     if (g->driver_variant != -1 && g->driver_variant != 2 && g->driver_variant != 4 && g->driver_variant != 6)
         return fail(HSWO_E_INVAL, "tuning.driver_variant must be -1, 2, 4 or 6");
+    if (g->row_matrix < -1 || g->row_matrix > 1) return fail(HSWO_E_INVAL, "tuning.row_matrix must be -1, 0 or 1");
     return HSWO_OK;
 }
 
@@ -360,6 +373,10 @@ Layout carve(const Plan& pl, int H, int W, const hswo_params* p, int bare, void*
                 s.m64 = bp.take<double>(rc * pl.B);
                 s.m64r = bp.take<double>(rc * (((int64_t)pl.B + 7) / 8 * 8));
                 if (p->criterion == HSWO_CRIT_SAM) s.rq = bp.take<double>(rc);
+                else if (!(p->flags & HSWO_FLAG_TWO_MERGES) && rc <= MAT_MAX) {
+                    s.dmat = bp.take<float2>(rc * rc);
+                    s.dtmp = bp.take<float2>(2 * rc);
+                }
                 if (p->flags & HSWO_FLAG_TWO_MERGES) s.abit = bp.take<uint32_t>(rc * ((rc + 31) / 32));
                 s.rbd = bp.take<double>(rc);
                 s.rbp = bp.take<int32_t>(rc);
@@ -498,11 +515,16 @@ int device_cus() {
 // (R > spclust_max) need no work spread over workgroups: with tu.hybrid they
 // run in the section driver (one launch, state kept on chip) up to
 // R = spclust_max, and wide mode takes the rest.
+// mat_ok: every section of the level keeps an interval matrix (used when the
+// level runs wide and the tuning asks for it).
 int run_level(Timer* tm, const SecDev* secs, int n, const std::vector<int64_t>& cap, const std::vector<int64_t>& stop,
-              const LoopParams& lp, bool row_cache, const Tuning& tu, hipStream_t stream) {
+              const LoopParams& lp_in, bool row_cache, bool mat_ok, const Tuning& tu, hipStream_t stream) {
+    LoopParams lp = lp_in;
+    lp.row_matrix = 0;
     const int variant = tu.variant;
     if (n > tu.wide_max || (row_cache && n > ROWS_MAX_SECTIONS))
         return timed_driver(tm, secs, n, lp, variant, stream);
+    lp.row_matrix = (row_cache && mat_ok && tu.row_matrix) ? 1 : 0;
     const int G = std::max(1, std::min(GMAX, tu.wide_wg / n));
     // R of each section when the wide iterations start
     std::vector<int64_t> r0(cap);
@@ -526,6 +548,22 @@ int run_level(Timer* tm, const SecDev* secs, int n, const std::vector<int64_t>& 
     }
     int64_t iters = 0;
     for (int i = 0; i < n; ++i) iters = std::max(iters, r0[i] - std::min(r0[i], stop[i]));
+    // interval matrices: each section's cache starts at its first iteration inside the spectral
+    // stage (R = min(r0, kmax)); those iterations launch the fill first
+    int fill_tiles = 0;
+    std::vector<int64_t> fill_at;
+    if (lp.row_matrix) {
+        int64_t rmax = 0;
+        for (int i = 0; i < n; ++i) {
+            if (std::min(r0[i], (int64_t)lp.kmax) <= stop[i]) continue;  // never reaches its spectral stage
+            fill_at.push_back(std::max<int64_t>(0, r0[i] - lp.kmax));
+            rmax = std::max(rmax, std::min(r0[i], (int64_t)lp.kmax));
+        }
+        const int64_t nT = (rmax + TILE - 1) / TILE;
+        fill_tiles = (int)(nT * (nT + 1) / 2);
+        std::sort(fill_at.begin(), fill_at.end());
+        fill_at.erase(std::unique(fill_at.begin(), fill_at.end()), fill_at.end());
+    }
     // (two-merge reading: a launch still makes exactly one merge -- a step 3 that finds no pair
     // below its threshold goes on to the next step 2 in the same launch)
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -545,7 +583,9 @@ int run_level(Timer* tm, const SecDev* secs, int n, const std::vector<int64_t>& 
                 const int64_t R = r0[i] - t;
                 spec = R > stop[i] && R <= lp.kmax;
             }
-        HIP_TRY(launch_wide_iteration(secs, n, G, lp, variant, spec, row_cache, tu.rows_grid, stream, kt));
+        const bool fill = !fill_at.empty() && std::binary_search(fill_at.begin(), fill_at.end(), t);
+        HIP_TRY(launch_wide_iteration(secs, n, G, lp, variant, spec, row_cache, tu.rows_grid, fill ? fill_tiles : 0,
+                                      stream, kt));
     }
     if (tm) HIP_TRY(hipEventRecord(e1, stream));
     return HSWO_OK;
@@ -553,11 +593,11 @@ int run_level(Timer* tm, const SecDev* secs, int n, const std::vector<int64_t>& 
 
 // A level's sections one after another (HSWO_FLAG_SEQUENTIAL_SECTIONS), or all together.
 int run_level_sections(Timer* tm, const SecDev* secs, int n, const std::vector<int64_t>& cap,
-                       const std::vector<int64_t>& stop, const LoopParams& lp, bool row_cache, const Tuning& tu,
-                       bool sequential, hipStream_t stream) {
-    if (!sequential || n == 1) return run_level(tm, secs, n, cap, stop, lp, row_cache, tu, stream);
+                       const std::vector<int64_t>& stop, const LoopParams& lp, bool row_cache, bool mat_ok,
+                       const Tuning& tu, bool sequential, hipStream_t stream) {
+    if (!sequential || n == 1) return run_level(tm, secs, n, cap, stop, lp, row_cache, mat_ok, tu, stream);
     for (int i = 0; i < n; ++i) {
-        const int r = run_level(tm, secs + i, 1, {cap[i]}, {stop[i]}, lp, row_cache, tu, stream);
+        const int r = run_level(tm, secs + i, 1, {cap[i]}, {stop[i]}, lp, row_cache, mat_ok, tu, stream);
         if (r) return r;
     }
     return HSWO_OK;
@@ -600,8 +640,8 @@ void tune_store_locked(const std::string& k, const Tuning& t) {
 
 bool tuning_from_str(const std::string& v, Tuning& t) {
     Tuning x;
-    if (sscanf(v.c_str(), "%d,%d,%d,%d,%d,%d", &x.wide_max, &x.wide_wg, &x.rows_grid, &x.hybrid, &x.bare,
-               &x.variant) != 6)
+    if (sscanf(v.c_str(), "%d,%d,%d,%d,%d,%d,%d", &x.wide_max, &x.wide_wg, &x.rows_grid, &x.hybrid, &x.bare,
+               &x.variant, &x.row_matrix) != 7)
         return false;
     t = x;
     return true;
@@ -720,6 +760,7 @@ std::vector<Knob> tune_knobs(bool incremental, const hswo_tuning* g) {
     if (incremental) {
         k.push_back({&Tuning::wide_max, {cu, 64, 16}, g && g->wide_max_sections >= 0});
         k.push_back({&Tuning::rows_grid, {2 * cu, cu, 4 * cu}, g && g->rows_grid >= 0});
+        k.push_back({&Tuning::row_matrix, {1, 0}, g && g->row_matrix >= 0});
     } else {
         k.push_back({&Tuning::wide_max, {64, 16, 256}, g && g->wide_max_sections >= 0});
         k.push_back({&Tuning::wide_wg, {cu, 2 * cu, 4 * cu}, g && g->wide_groups >= 0});
@@ -891,7 +932,8 @@ int fill_stats(hswo_stats* st, const ExecOut& o, int64_t launches_if_graph) {
         st->kernel_work[k] = 0;
     }
     st->kernel_work[HSWO_K_WIDE_DECIDE] = (int64_t)c[C_W_DECIDE_BYTES];
-    st->kernel_work[HSWO_K_WIDE_ROWS] = (int64_t)c[C_W_ROWS_FLOPS];
+    st->kernel_work[HSWO_K_WIDE_ROWS] = (int64_t)c[C_W_ROWS_BYTES];
+    st->kernel_work[HSWO_K_MATRIX_FILL] = (int64_t)c[C_W_FILL_FLOPS];
     st->kernel_work[HSWO_K_WIDE_ADJ] = (int64_t)c[C_W_ADJ_BYTES];
     st->kernel_work[HSWO_K_WIDE_MFMA] = (int64_t)c[C_W_MFMA_FLOPS];
     st->kernel_work[HSWO_K_SECTION_DRIVER] = (int64_t)c[C_D_BYTES];
@@ -900,6 +942,9 @@ int fill_stats(hswo_stats* st, const ExecOut& o, int64_t launches_if_graph) {
     st->screen_iterations = (int64_t)c[C_SCREEN_ITERS];
     st->screen_fallbacks = (int64_t)c[C_SCREEN_FALLBACKS];
     st->verify_records = (int64_t)c[C_VERIFY];
+    st->row_bounded_pairs = (int64_t)c[C_ROW_BOUNDED];
+    st->tuning.row_matrix = o.tuning.row_matrix;
+    st->reserved = 0;
     st->tuning.wide_max_sections = o.tuning.wide_max;
     st->tuning.wide_groups = o.tuning.wide_wg;
     st->tuning.rows_grid = o.tuning.rows_grid;
@@ -943,6 +988,7 @@ LoopParams loop_params(const hswo_params* p, unsigned long long* counters) {
     lp.phase_stop = 0;
     lp.two_merges = (p->flags & HSWO_FLAG_TWO_MERGES) ? 1 : 0;
     lp.topk = p->screen_topk > 0 ? p->screen_topk : 8;
+    lp.row_matrix = 0;  // set per level from the resolved tuning
     lp.counters = counters;
     return lp;
 }
@@ -1023,11 +1069,16 @@ int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_param
     const bool row_cache = row_cache_on(p);
     const bool sequential = (p->flags & HSWO_FLAG_SEQUENTIAL_SECTIONS) != 0;
     std::vector<std::vector<int64_t>> caps(L), stops(L);
-    for (int d = 0; d < L; ++d)
+    std::vector<char> mat_ok(L, 0);  // every section of the level keeps an interval matrix (carve's rule)
+    for (int d = 0; d < L; ++d) {
+        bool ok = row_cache && p->criterion == HSWO_CRIT_BSMSE && !(p->flags & HSWO_FLAG_TWO_MERGES);
         for (const SecPlan& s : pl.lv[d]) {
             caps[d].push_back(s.cap);
             stops[d].push_back(s.stop);
+            ok = ok && std::min<int64_t>(s.cap, p->spclust_max) <= MAT_MAX;
         }
+        mat_ok[d] = ok ? 1 : 0;
+    }
 
     const Seq seq = [&](hipStream_t st, Timer* tm, const Tuning& tu) -> int {
         HIP_TRY(launch_fill_u64(lay.counters, C_COUNT, 0ull, st));
@@ -1039,7 +1090,7 @@ int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_param
             HIP_TRY(launch_init_leaves(lay.lv[d].secs, lay.lv[d].inits, (int)pl.lv[d].size(), dtype, maxpix,
                                          lay.counters, st));
             const int r = run_level_sections(tm, lay.lv[d].secs, (int)pl.lv[d].size(), caps[d], stops[d], lp,
-                                             row_cache, tu, sequential, st);
+                                             row_cache, mat_ok[d] != 0, tu, sequential, st);
             if (r) return r;
         }
         for (int d = L - 2; d >= 0; --d) {
@@ -1057,7 +1108,7 @@ int run_rhseg(const void* cube, int H, int W, int B, int dtype, const hswo_param
             HIP_TRY(launch_seam(lay.lv[d].secs, lay.lv[d].asms, (int)secs.size(), lay.slotmap, (int)maxseam,
                                 lay.counters, st));
             const int r = run_level_sections(tm, lay.lv[d].secs, (int)secs.size(), caps[d], stops[d], lp, row_cache,
-                                             tu, sequential, st);
+                                             mat_ok[d] != 0, tu, sequential, st);
             if (r) return r;
         }
         HIP_TRY(launch_snapshot(lay.snap, 1, lay.counts, p->n_levels, (int)P, lay.counters, st));
@@ -1155,6 +1206,7 @@ BatchLayout carve_batch(int n, const hswo_section* sec, const hswo_params* p, in
             s.m64 = bp.take<double>(rc * q.B);
             s.m64r = bp.take<double>(rc * (((int64_t)q.B + 7) / 8 * 8));
             if (p->criterion == HSWO_CRIT_SAM) s.rq = bp.take<double>(rc);
+            // (the batch runs its sections in the persistent driver: no interval matrix)
             if (p->flags & HSWO_FLAG_TWO_MERGES) s.abit = bp.take<uint32_t>(rc * ((rc + 31) / 32));
             s.rbd = bp.take<double>(rc);
             s.rbp = bp.take<int32_t>(rc);
@@ -1266,7 +1318,7 @@ int run_batch(int n, const hswo_section* sec, int dtype, const hswo_params* p, h
         if (p->flags & HSWO_FLAG_SEQUENTIAL_SECTIONS) {
             for (int i = 0; i < n && !r; ++i)
                 r = run_level(tm, lay.secs + i, 1, {lay.h_secs[i].R0}, {lay.h_secs[i].stop}, lp, row_cache_on(p),
-                              tu, st);
+                              false, tu, st);
         } else {
             r = timed_driver(tm, lay.secs_lpt, n, lp, tu.variant, st);
         }

@@ -35,7 +35,7 @@ enum Counter {
     C_T_SPEC32,     // ... FP32 spectral tiles + exact re-check
     C_T_MERGE,      // ... merge
     C_W_DECIDE_BYTES, // k_wide_decide, incremental form: algorithmic bytes (see hswo_stats.kernel_work)
-    C_W_ROWS_FLOPS,   // k_wide_rows: 3 FP64 flops per band per evaluated pair
+    C_W_ROWS_BYTES,   // k_wide_rows: algorithmic bytes (see hswo_stats.kernel_work)
     C_W_ADJ_BYTES,    // k_wide_adj: FP32 mean rows read once + edge endpoints + counts and norms
     C_W_MFMA_FLOPS,   // k_wide_mfma: 2 flops per band per unique pair of the screened sections
     C_D_BYTES,        // k_section_driver, incremental form: algorithmic bytes (see hswo_stats.kernel_work)
@@ -44,10 +44,13 @@ enum Counter {
     C_SCREEN_ITERS,   // screened decisions (adjacent and spectral stages counted separately)
     C_SCREEN_FALLBACKS, // ... whose re-check set held more than screen_topk pairs
     C_VERIFY,         // HSWO_FLAG_DEBUG_VERIFY_BOUND records produced
+    C_ROW_BOUNDED,    // row-cache pairs rescanned from the interval matrix
+    C_W_FILL_FLOPS,   // k_mat_fill: 3 FP32 flops per band per pair bounded
     C_COUNT
 };
 
 constexpr int ST_WORDS = 16;  // per-section state words
+constexpr int MAT_MAX = 4096; // largest row cache that keeps the interval matrix (128 MiB per section)
 constexpr int GMAX = 256;     // wide mode: most workgroups per section
 constexpr int STILE = 128;    // matrix-core super tile edge (4 spectral tiles)
 
@@ -102,6 +105,9 @@ struct SecDev {
     double* m64;     // [B][rcap] FP64 mean spectra S/n (spectral angle: the sums S), band-major
                      //           (column j = slot j)
     double* m64r;    // [rcap][B8] the same rows slot-major, B8 = B rounded up to 8
+    float2* dmat;    // [rcap][rcap] Equation 1, one-merge reading, rcap <= MAT_MAX: FP32 bounds on every
+                     //   pair's value, kept by Ward's update at each merge (used in wide mode)
+    float2* dtmp;    // [2][rcap] scratch of that update
     double* rq;      // [rcap] spectral angle only: |S|^2 of each slot (pairwise tree over the bands)
     uint32_t* abit;  // [rcap][ceil(rcap / 32)] two-merge reading only: adjacency bitmap of the live slots
     double* rbd;     // [rcap] exact D2 of the row's cached pair
@@ -177,6 +183,7 @@ struct LoopParams {
     int32_t phase_stop;   // section driver: also stop at this region count (0: the pass's stop only)
     int32_t two_merges;   // two-merge reading of the step list (adjacent merge, then non-adjacent merge)
     int32_t topk;         // screened forms: re-check sets larger than this count as fallbacks
+    int32_t row_matrix;   // wide mode: keep and rescan the interval matrix (hswo_tuning.row_matrix)
     unsigned long long* counters;  // [C_COUNT]
 };
 
@@ -207,8 +214,11 @@ hipError_t launch_init_leaves(const SecDev* secs, const InitDev* init, int n, in
 hipError_t launch_section_driver(const SecDev* secs, int n, const LoopParams& lp, int variant, hipStream_t s,
                                  KTimer* kt);
 constexpr int DRIVER_VARIANTS[3] = {2, 4, 6};  // adjacent-stage edges in flight per lane group
+// fill_tiles > 0: the row caches that start in this iteration first get their interval matrix
+// (k_mat_fill, fill_tiles 64 x 64 tiles per section)
 hipError_t launch_wide_iteration(const SecDev* secs, int n, int G, const LoopParams& lp, int variant,
-                                 bool spectral_possible, bool row_cache, int rows_grid, hipStream_t s, KTimer* kt);
+                                 bool spectral_possible, bool row_cache, int rows_grid, int fill_tiles, hipStream_t s,
+                                 KTimer* kt);
 int default_rows_grid();
 constexpr int ROWS_MAX_SECTIONS = 1024;  // sections a row-cache task pool launch can cover
 hipError_t launch_rowcache_prep(const SecDev* secs, int n, const LoopParams& lp, hipStream_t s, KTimer* kt);

@@ -102,6 +102,12 @@ __device__ __forceinline__ bool key_less(const KeyD& a, const KeyD& b) {
 
 __device__ __forceinline__ bool key_exists(const KeyD& k) { return k.lo != INT_MAX; }
 
+// Whether a section's row cache keeps the interval matrix (set per level by
+// the host: wide mode, and every section of the level has one).
+__device__ __forceinline__ bool row_matrix_on(const SecDev& s, const LoopParams& lp) {
+    return lp.row_matrix && s.dmat != nullptr;
+}
+
 // Non-finite input found at initialisation: every later kernel of the call
 // returns at once, so nothing is merged and no output is written.
 __device__ __forceinline__ bool gated(const unsigned long long* counters) {
@@ -1008,7 +1014,10 @@ __device__ __noinline__ double exact_lane(const SecDev& s, int si, int sj) {
 // Start the row cache of a section at R live slots: FP64 means of every slot
 // (spectral angle: the sums and their squared norms); every row is then
 // pending (state 1).
-__device__ void rowcache_begin(Smem& sh, const SecDev& s, int R, int E) {
+// mat: the section keeps the interval matrix; the FP32 mean rows (zero
+// padded to Bp) and their norm bounds, which the matrix fill reads, are then
+// rebuilt from the FP64 means as well.
+__device__ void rowcache_begin(Smem& sh, const SecDev& s, int R, int E, bool mat) {
     const int B = s.B;
     const size_t kc = (size_t)s.rcap;
     const int tot = R * B;
@@ -1020,6 +1029,23 @@ __device__ void rowcache_begin(Smem& sh, const SecDev& s, int R, int E) {
         const double m = sam ? v : v / (double)s.npix[i];
         s.m64[(size_t)b * kc + i] = m;
         s.m64r[(size_t)i * B8 + b] = m;
+        if (mat) s.mean[(size_t)i * s.Bp + b] = (float)m;
+    }
+    if (mat) {
+        for (int x = threadIdx.x; x < R * (s.Bp - B); x += NT) {
+            const int i = x / (s.Bp - B), b = B + x % (s.Bp - B);
+            s.mean[(size_t)i * s.Bp + b] = 0.0f;
+        }
+        __syncthreads();
+        for (int i = wave_id(); i < R; i += NWAVE) {  // the norm bound the FP32 screen uses
+            double q = 0.0;
+            for (int b = lane_id(); b < B; b += 64) {
+                const double m = (double)s.mean[(size_t)i * s.Bp + b];
+                q += m * m;
+            }
+            for (int o = 32; o >= 1; o >>= 1) q += __shfl_xor(q, o);
+            if (lane_id() == 0) s.norm[i] = (float)(sqrt(q) * (1.0 + 0x1p-20));
+        }
     }
     if (sam) {
         for (int i = wave_id(); i < R; i += NWAVE) {
@@ -1119,6 +1145,46 @@ __device__ __forceinline__ RowPart part_of(double d2, int lab, int slot) {
     r.labb = INT_MAX;
     r.slotb = -1;
     return r;
+}
+
+// ---------------------------------------------------------------------------
+// Interval matrix of the row cache (Equation 1, wide mode). Entry (i, j)
+// holds FP32 bounds [lo, hi] on the exact real value D(i, j) of Equation 1's
+// square for the FP64 mean rows of slots i and j (the canonical FP64 value
+// lies within a relative (B + 8) 2^-53 < 2^-40 of it for B <= 4096).
+//  - A pair evaluated exactly stores its canonical value widened by 2^-40
+//    and rounded outward (mat_entry); an exact 0 stays [0, 0].
+//  - A merge of (a, b) gives the survivor's row by Ward's update, exact in
+//    real arithmetic for this criterion:
+//      D(k, a u b) = ((n_a + n_k) D(k, a) + (n_b + n_k) D(k, b) - n_k D(a, b))
+//                    / (n_a + n_b + n_k),
+//    evaluated on the bounds (lower bounds with the upper bound of D(a, b)
+//    and the other way round), widened by the FP64 rounding of the formula
+//    and rounded outward (mat_update).
+//  - A row whose cached pair is stale is rescanned from its bounds: pairs
+//    whose lower bound exceeds the row's second least upper bound cannot be
+//    among its least two, and the others are evaluated exactly.
+// ---------------------------------------------------------------------------
+constexpr double MAT_REL = 0x1p-40;
+
+__device__ __forceinline__ float2 mat_entry(double c) {
+    if (!(c < __builtin_huge_val())) return make_float2(__builtin_huge_valf(), __builtin_huge_valf());
+    return make_float2(__double2float_rd(c * (1.0 - MAT_REL)), __double2float_ru(c * (1.0 + MAT_REL)));
+}
+
+// Ward's update on bounds: e_a, e_b the bounds of D(k, a), D(k, b); [d_lo, d_hi]
+// those of D(a, b); na, nb, nk the pixel counts before the merge. Each FP64
+// operation errs by at most 2^-53 of its result, and every intermediate is
+// at most t (the sum of the absolute terms over the denominator) in
+// magnitude, so widening by 2^-48 t covers them all.
+__device__ __forceinline__ float2 mat_update(float2 e_a, float2 e_b, double d_lo, double d_hi, double na, double nb,
+                                             double nk) {
+    const double ca = na + nk, cb = nb + nk, den = na + nb + nk;
+    const double lo = (ca * (double)e_a.x + cb * (double)e_b.x - nk * d_hi) / den;
+    const double hi = (ca * (double)e_a.y + cb * (double)e_b.y - nk * d_lo) / den;
+    const double t = (ca * (double)e_a.y + cb * (double)e_b.y + nk * d_hi) / den;
+    const double slack = t * 0x1p-48;
+    return make_float2(__double2float_rd(fmax(lo - slack, 0.0)), __double2float_ru(hi + slack));
 }
 
 // Exact D2 of KR pending rows against 64 columns (one block task; a pair per
@@ -1237,6 +1303,150 @@ __device__ void row_block_task(double (*rsum)[4][64], const SecDev& s, int R, in
         }
     }
     __syncthreads();  // rsum is reused by the next task
+}
+
+// The canonical Equation 1 value of pair (si, sj) by a whole wavefront (every
+// lane gets it), from the FP64 means of the row cache (m64r): lane l holds
+// bands 4l..4l+3 of each 256-band chunk, butterflies build the chunk's
+// subtree, and a binary counter joins the chunk sums -- the perfect tree over
+// the zero-padded bands of exact_d2_wave, which divides the sums on the fly
+// (the stored means are those quotients), so the value is bit-identical.
+__device__ double exact_wave_means(const SecDev& s, int si, int sj) {
+    constexpr int LV = 5;  // up to 16 chunks of 256 bands: B <= 4096
+    const int lane = lane_id();
+    const int B = s.B, B8 = (B + 7) & ~7;
+    const double* Mi = s.m64r + (size_t)si * B8;
+    const double* Mj = s.m64r + (size_t)sj * B8;
+    const int nchk = (B + 255) >> 8;
+    double part[LV];
+    for (int c = 0; c < nchk; ++c) {
+        const int b = (c << 8) + (lane << 2);
+        double q[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double d = (b + k < B) ? Mi[b + k] - Mj[b + k] : 0.0;
+            q[k] = d * d;
+        }
+        double t = (q[0] + q[1]) + (q[2] + q[3]);
+        t = t + __shfl_xor(t, 1);
+        t = t + __shfl_xor(t, 2);
+        t = t + __shfl_xor(t, 4);
+        t = t + __shfl_xor(t, 8);
+        t = t + __shfl_xor(t, 16);
+        t = t + __shfl_xor(t, 32);
+        counter_push<LV>(part, t, c);
+    }
+    const int n_i = s.npix[si], n_j = s.npix[sj];
+    const double dni = (double)n_i, dnj = (double)n_j;
+    return ((dni * dnj) / (double)(n_i + n_j)) * counter_total<LV>(part, nchk);
+}
+
+// The two least of (a1 <= a2) and (b1 <= b2), into (a1, a2).
+__device__ __forceinline__ void least_two(double& a1, double& a2, double b1, double b2) {
+    const double big = fmax(a1, b1);
+    a1 = fmin(a1, b1);
+    a2 = fmin(big, fmin(a2, b2));
+}
+
+
+// LDS of row_matrix_task.
+constexpr int MAT_CAND = 1024;  // candidates per round
+struct RowMatLds {
+    double m1[NWAVE], m2[NWAVE];
+    int cand[MAT_CAND];
+    double val[MAT_CAND];
+    int ncand;
+};
+
+// One pending row q of a section, rescanned from the interval matrix by a
+// whole workgroup: the row's threshold T is its second least upper bound
+// (widened to the canonical value); a pair whose lower bound (likewise
+// widened) exceeds T has two pairs strictly below it, so the row's least two
+// by (D2, label) are among the others. Those are evaluated exactly
+// (exact_wave_means, one wavefront per pair) -- except pairs bounded by
+// [0, 0], whose canonical value is 0 -- and their bounds tightened to the
+// exact value. The row's least two go to its first chunk entry of rpart and
+// +inf to the others, which is what the exact row tasks leave for the
+// decision to reduce. Returns the number of exact evaluations (thread 0).
+__device__ int row_matrix_task(RowMatLds& L, const SecDev& s, int R, int q, bool all) {
+    const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
+    const size_t rc = (size_t)s.rcap;
+    const int i = all ? q : s.rpend[q];
+    const float2* Di = s.dmat + (size_t)i * rc;
+    const int nx = (R + NT - 1) / NT;  // bounds per thread
+    double m1 = __builtin_huge_val(), m2 = __builtin_huge_val();
+    for (int x = 0; x < nx; ++x) {
+        const int j = x * NT + tid;
+        if (j < R && j != i) least_two(m1, m2, (double)Di[j].y * (1.0 + MAT_REL), __builtin_huge_val());
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) least_two(m1, m2, __shfl_xor(m1, o), __shfl_xor(m2, o));
+    if (lane == 0) {
+        L.m1[w] = m1;
+        L.m2[w] = m2;
+    }
+    if (tid == 0) L.ncand = 0;
+    __syncthreads();
+    m1 = L.m1[0];
+    m2 = L.m2[0];
+#pragma unroll
+    for (int k = 1; k < NWAVE; ++k) least_two(m1, m2, L.m1[k], L.m2[k]);
+    const double T = m2;
+    RowPart best = part_of(__builtin_huge_val(), INT_MAX, -1);
+    int nexact = 0;
+    // candidates in rounds of at most MAT_CAND (block-uniform loop over the register slots)
+    int x0 = 0;
+    while (x0 < nx) {
+        int x = x0;
+        for (; x < nx; ++x) {
+            // the round takes slots until it could overflow (NT per slot)
+            if (L.ncand + NT > MAT_CAND) break;  // block-uniform: read after a barrier
+            const int j = x * NT + tid;
+            const float2 e = (j < R && j != i) ? Di[j] : make_float2(__builtin_huge_valf(), __builtin_huge_valf());
+            const bool cand = j < R && j != i && (double)e.x * (1.0 - MAT_REL) <= T;
+            if (cand) {
+                if (e.y == 0.0f) {
+                    top2_merge(best, part_of(0.0, s.label[j], j));  // bounded by [0, 0]: exactly 0
+                } else {
+                    L.cand[atomicAdd(&L.ncand, 1)] = j;
+                }
+            }
+            __syncthreads();
+        }
+        const int n = L.ncand;
+        for (int k = w; k < n; k += NWAVE) {
+            const int j = L.cand[k];
+            const double v = exact_wave_means(s, i, j);
+            if (lane == 0) {
+                L.val[k] = v;
+                const float2 me = mat_entry(v);
+                s.dmat[(size_t)i * rc + j] = me;
+                s.dmat[(size_t)j * rc + i] = me;
+            }
+        }
+        __syncthreads();
+        for (int k = tid; k < n; k += NT) top2_merge(best, part_of(L.val[k], s.label[L.cand[k]], L.cand[k]));
+        nexact += n;
+        __syncthreads();
+        if (tid == 0) L.ncand = 0;
+        __syncthreads();
+        x0 = x;
+    }
+    // the row's least two over the block
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) top2_merge(best, shfl_xor_part(best, o));
+    RowPart* wb = reinterpret_cast<RowPart*>(L.val);  // the values are consumed
+    if (lane == 0) wb[w] = best;
+    __syncthreads();
+    const int nch = (R + 63) >> 6;
+    if (tid == 0) {
+        RowPart b = wb[0];
+        for (int k = 1; k < NWAVE; ++k) top2_merge(b, wb[k]);
+        s.rpart[(size_t)q * nch] = b;
+    }
+    for (int c = 1 + tid; c < nch; c += NT) s.rpart[(size_t)q * nch + c] = part_of(__builtin_huge_val(), INT_MAX, -1);
+    __syncthreads();  // LDS is reused by the next task
+    return nexact;
 }
 
 // One wavefront evaluates KR pending rows against 64 columns over all bands
@@ -1617,11 +1827,51 @@ __device__ void merge_edges_full(Smem& sh, const SecDev& s, int lo_s, int hi_s, 
 // second bound's partner is alive, marked for a light step (rbp = -2), which
 // the survivor's row evaluation takes. Kept out of line: inlined, it pushes
 // the decision kernel into scratch.
-__device__ __noinline__ void merge_slots(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int g_ready, int rc, bool screens) {
+// mat: the row cache keeps the interval matrix (rc == 2); d2 is the merged
+// pair's canonical value. The survivor's bounds row comes from Ward's update
+// of rows lo_s and hi_s (into the dtmp scratch first, with the row of the
+// slot that moves, since both are rewritten in place), then rows and columns
+// surv and hi_s are written.
+__device__ __noinline__ void merge_slots(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int g_ready, int rc,
+                                         bool screens, bool mat, double d2) {
     const int tid = threadIdx.x;
     const int B = s.B, Bp = s.Bp;
     const int last = R - 1;
     const int surv = (lo_s == last) ? hi_s : lo_s;
+    if (mat && rc == 2) {
+        const size_t rcp = (size_t)s.rcap;
+        const bool moved = last != lo_s && last != hi_s;
+        const float2 de = mat_entry(d2);
+        const double n_hi = (double)s.npix[hi_s];
+        const double n_lo = (double)s.npix[lo_s] - n_hi;  // merge_stats has added n_hi to the survivor
+        const float2* Dlo = s.dmat + (size_t)lo_s * rcp;
+        const float2* Dhi = s.dmat + (size_t)hi_s * rcp;
+        const float2* Dla = s.dmat + (size_t)last * rcp;
+        for (int k = tid; k < R; k += NT) {
+            if (k == lo_s || k == hi_s) continue;
+            s.dtmp[k] = mat_update(Dlo[k], Dhi[k], (double)de.x, (double)de.y, n_lo, n_hi, (double)s.npix[k]);
+            if (moved) s.dtmp[rcp + k] = Dla[k];
+        }
+        __syncthreads();
+        const float2 inf2 = make_float2(__builtin_huge_valf(), __builtin_huge_valf());
+        for (int k = tid; k < R; k += NT) {
+            if (k == lo_s || k == hi_s) continue;
+            const int nk = (k == last) ? hi_s : k;
+            const float2 v = s.dtmp[k];
+            s.dmat[(size_t)surv * rcp + nk] = v;
+            s.dmat[(size_t)nk * rcp + surv] = v;
+            if (moved && k != last) {
+                const float2 m = s.dtmp[rcp + k];
+                s.dmat[(size_t)hi_s * rcp + nk] = m;
+                s.dmat[(size_t)nk * rcp + hi_s] = m;
+            }
+        }
+        if (tid == 0) {
+            s.dmat[(size_t)surv * rcp + surv] = inf2;
+            if (moved) s.dmat[(size_t)hi_s * rcp + hi_s] = inf2;
+        }
+        __syncthreads();  // every read of npix above is done before the slot moves below
+    }
     if (hi_s != last) {
         const double* Ssrc = s.sums + (size_t)last * B;
         double* Sdst = s.sums + (size_t)hi_s * B;
@@ -1676,7 +1926,8 @@ __device__ __noinline__ void merge_slots(Smem& sh, const SecDev& s, int lo_s, in
             if (ni != i || np2 != p2) s.rbp2[ni] = np2;
             if (p == lo_s || p == hi_s) {
                 // stale: a light step (marked -2) when it has a second bound, else a full evaluation
-                if (np2 != -1) {
+                // (with the interval matrix always the rescan of its bounds row)
+                if (np2 != -1 && !mat) {
                     s.rbp[ni] = -2;
                 } else {
                     s.rbp[ni] = -1;
@@ -1712,7 +1963,7 @@ __device__ __forceinline__ void merge_pair(Smem& sh, const SecDev& s, int lo_s, 
     merge_stats(sh, s, lo_s, hi_s, R, kind, d2, g_ready, prec, rc, true);
     const bool inc = s.ed2 != nullptr && s.st[5] != 0;
     merge_edges_full(sh, s, lo_s, hi_s, R, E, stamp, inc);
-    merge_slots(sh, s, lo_s, hi_s, R, g_ready, rc, true);
+    merge_slots(sh, s, lo_s, hi_s, R, g_ready, rc, true, false, 0.0);
     if (inc) {  // re-score the survivor's edges; every other edge keeps its cached value
         const int nd = sh.bcast_i[2];
         score_edges(sh, s, s.edirty, nd);
@@ -1759,7 +2010,7 @@ constexpr int LCAP = CAND_CAP / 3;  // edges listed per merge by the incremental
 // false (full pass taken) when a list would overflow.
 template <int U>
 __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int& E, int stamp, int kind,
-                               double d2, int rc, KeyD& anext, int& nchk) {
+                               double d2, int rc, KeyD& anext, int& nchk, bool mat) {
     const int tid = threadIdx.x;
     merge_stats(sh, s, lo_s, hi_s, R, kind, d2, 0, 0, rc, false);
     const int last = R - 1;
@@ -1865,7 +2116,7 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
     if (n1 > LCAP || n2 > LCAP) {
         // a very high degree at the merged pair: the full pass
         merge_edges_full(sh, s, lo_s, hi_s, R, E, stamp, true);
-        merge_slots(sh, s, lo_s, hi_s, R, 0, rc, false);
+        merge_slots(sh, s, lo_s, hi_s, R, 0, rc, false, mat, d2);
         const int nd = sh.bcast_i[2];
         score_edges(sh, s, s.edirty, nd);
         nchk += nd;
@@ -1918,7 +2169,7 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
         }
     }
     __syncthreads();
-    merge_slots(sh, s, lo_s, hi_s, R, 0, rc, false);  // ends with a barrier
+    merge_slots(sh, s, lo_s, hi_s, R, 0, rc, false, mat, d2);  // ends with a barrier
     const int nk = sh.bcast_i[2];
     const int emptied = sh.bcast_i[3];
     const int l_surv = s.label[surv];
@@ -2373,7 +2624,7 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
         if (spectral && row_cache) {
             // exact rows: all of them when the cache starts, else the pending ones
             if (rcs == 0) {
-                rowcache_begin(sh, s, R, E);
+                rowcache_begin(sh, s, R, E, row_matrix_on(s, lp));
                 rcs = 1;
             }
             const bool all = rcs == 1;
@@ -2476,7 +2727,7 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
         if (lp.incremental) CNT_ADD(C_D_BYTES, 16ull * (unsigned long long)E + 24ull * (unsigned long long)s.B);
         if (lp.incremental) {
             int nre = 0;
-            avalid = merge_pair_inc<8>(sh, s, win.si, win.sj, R, E, merges, kind, win.d2, rcs, anext, nre);
+            avalid = merge_pair_inc<8>(sh, s, win.si, win.sj, R, E, merges, kind, win.d2, rcs, anext, nre, false);
             CNT_ADD(C_RECHECKS, nre);
         } else {
             merge_pair(sh, s, win.si, win.sj, R, E, merges, kind, win.d2, g_ready, prec, rcs);
@@ -2486,7 +2737,7 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
         if (rcs == 2) npend = sh.npend;
         if (s.abit && rcs) abit_merge(s, win.si, win.sj, R + 1);
         if (row_cache && rcs == 0 && lp.spectral && R <= lp.kmax && R > s.stop) {
-            rowcache_begin(sh, s, R, E);  // the spectral stage starts with the next iteration
+            rowcache_begin(sh, s, R, E, row_matrix_on(s, lp));  // the spectral stage starts with the next iteration
             rcs = 1;
         }
         if (step2 && lp.spectral && R <= lp.kmax && R > s.stop) {
@@ -2555,28 +2806,8 @@ __global__ void __launch_bounds__(NT) k_wide_adj(const SecDev* __restrict__ secs
 
 // Row cache stage of one iteration (incremental form): G workgroups per
 // section share the rows to re-evaluate (every row when the cache starts).
-__global__ void __launch_bounds__(NT) k_wide_rows(const SecDev* __restrict__ secs, int n, LoopParams lp) {
-    __shared__ double rsum[NWAVE][4][64];
-    __shared__ int pre[ROWS_MAX_SECTIONS + 1];
-    if (gated(lp.counters)) return;
-    // tasks of every section of the level in one pool: section k owns tasks
-    // [pre[k], pre[k + 1])
-    for (int k = threadIdx.x; k < n; k += NT) {
-        const SecDev& s = secs[k];
-        const int R = s.st[0], mode = s.st[6];
-        int cnt = 0;
-        if (s.rcap > 0 && R > s.stop && R <= lp.kmax && (mode == 1 || mode == 2)) {
-            const int np = mode == 1 ? R : s.st[7];
-            cnt = row_task_count(R, np);
-            if (blockIdx.x == 0 && lp.counters) {
-                const unsigned long long pairs = (unsigned long long)np * (unsigned long long)(R - 1);
-                atomicAdd(&lp.counters[C_RECHECKS], pairs);
-                const unsigned long long fpb = s.crit == HSWO_CRIT_SAM ? 2ull : 3ull;  // flops per band and pair
-                atomicAdd(&lp.counters[C_W_ROWS_FLOPS], fpb * (unsigned long long)s.B * pairs);
-            }
-        }
-        pre[k + 1] = cnt;
-    }
+// Prefix sum of per-section task counts in pre[1..n] (pre[0] = 0), by wave 0.
+__device__ __forceinline__ void task_prefix(int* pre, int n) {
     __syncthreads();
     if (wave_id() == 0) {  // inclusive scan of the task counts, 64 sections per step
         const int lane = lane_id();
@@ -2594,24 +2825,175 @@ __global__ void __launch_bounds__(NT) k_wide_rows(const SecDev* __restrict__ sec
         if (lane == 0) pre[0] = 0;
     }
     __syncthreads();
+}
+
+// Section of task t: k with pre[k] <= t < pre[k + 1].
+__device__ __forceinline__ int task_section(const int* pre, int n, int t) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(NT) k_wide_rows(const SecDev* __restrict__ secs, int n, LoopParams lp) {
+    __shared__ double rsum[NWAVE][4][64];
+    __shared__ int pre[ROWS_MAX_SECTIONS + 1];
+    if (gated(lp.counters)) return;
+    // tasks of every section of the level in one pool: section k owns tasks
+    // [pre[k], pre[k + 1])
+    for (int k = threadIdx.x; k < n; k += NT) {
+        const SecDev& s = secs[k];
+        const int R = s.st[0], mode = s.st[6];
+        int cnt = 0;
+        if (s.rcap > 0 && R > s.stop && R <= lp.kmax && (mode == 1 || mode == 2)) {
+            const int np = mode == 1 ? R : s.st[7];
+            cnt = row_task_count(R, np);
+            if (blockIdx.x == 0 && lp.counters) {
+                const unsigned long long pairs = (unsigned long long)np * (unsigned long long)(R - 1);
+                atomicAdd(&lp.counters[C_RECHECKS], pairs);
+                // columns read once per group of 4 rows, each task's rows once
+                const unsigned long long B = (unsigned long long)s.B;
+                const unsigned long long nch = (unsigned long long)((R + 63) >> 6);
+                atomicAdd(&lp.counters[C_W_ROWS_BYTES], (unsigned long long)((np + 3) / 4) * (unsigned long long)R * B * 8ull +
+                                                            (unsigned long long)np * nch * B * 8ull);
+            }
+        }
+        pre[k + 1] = cnt;
+    }
+    task_prefix(pre, n);
     const int total = pre[n];
     for (int t = blockIdx.x; t < total; t += gridDim.x) {
-        int lo = 0, hi = n - 1;  // section k with pre[k] <= t < pre[k + 1]
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (pre[mid] <= t) lo = mid;
-            else hi = mid - 1;
-        }
-        const SecDev s = secs[lo];
+        const int k = task_section(pre, n, t);
+        const SecDev s = secs[k];
         const int R = s.st[0];
         const bool all = s.st[6] == 1;
         const int np = all ? R : s.st[7];
         const int nch = (R + 63) >> 6;
-        const int lt = t - pre[lo];
+        const int lt = t - pre[k];
         if (s.crit == HSWO_CRIT_SAM)
             row_block_task<4, true>(rsum, s, R, np, all, lt / nch, lt % nch);
         else
             row_block_task<4, false>(rsum, s, R, np, all, lt / nch, lt % nch);
+    }
+}
+
+// Row stage of a level whose row caches keep the interval matrix: every row
+// rescanned from its bounds when the cache starts (after k_mat_fill), else
+// each pending row (one workgroup per row, row_matrix_task), in one pool over
+// the level's sections.
+__global__ void __launch_bounds__(NT) k_mat_rows(const SecDev* __restrict__ secs, int n, LoopParams lp) {
+    __shared__ RowMatLds lds;
+    __shared__ int pre[ROWS_MAX_SECTIONS + 1];
+    if (gated(lp.counters)) return;
+    for (int k = threadIdx.x; k < n; k += NT) {
+        const SecDev& s = secs[k];
+        const int R = s.st[0], mode = s.st[6];
+        int cnt = 0;
+        if (s.rcap > 0 && R > s.stop && R <= lp.kmax && (mode == 1 || mode == 2)) {
+            cnt = mode == 1 ? R : s.st[7];
+            if (blockIdx.x == 0 && lp.counters) {
+                const unsigned long long np = (unsigned long long)cnt;
+                atomicAdd(&lp.counters[C_ROW_BOUNDED], np * (unsigned long long)(R - 1));
+                atomicAdd(&lp.counters[C_W_ROWS_BYTES], 8ull * np * (unsigned long long)R);  // the bounds rows
+            }
+        }
+        pre[k + 1] = cnt;
+    }
+    task_prefix(pre, n);
+    const int total = pre[n];
+    unsigned long long ex = 0, exb = 0;
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int k = task_section(pre, n, t);
+        const SecDev s = secs[k];
+        const int ne = row_matrix_task(lds, s, s.st[0], t - pre[k], s.st[6] == 1);
+        ex += (unsigned long long)ne;
+        exb += (unsigned long long)ne * (16ull * (unsigned long long)s.B + 16ull);  // two FP64 rows, two entries
+    }
+    if (threadIdx.x == 0 && ex && lp.counters) {
+        atomicAdd(&lp.counters[C_RECHECKS], ex);
+        atomicAdd(&lp.counters[C_W_ROWS_BYTES], exb);
+    }
+}
+
+// Interval matrix of every section whose row cache starts in this iteration
+// (state 1 with the matrix kept): one 64 x 64 tile of pairs per workgroup
+// (blockIdx.x, upper triangle; blockIdx.y the section). Each pair's squared
+// distance of the FP32 mean rows (rebuilt from the FP64 means by
+// rowcache_begin) is summed in FP32 by a 4 x 2 register tile per thread from
+// LDS-staged 32-band slices; screen_bounds turns it into certified bounds on
+// the canonical value, which are widened to the real value and rounded
+// outward into both (i, j) and (j, i).
+__global__ void __launch_bounds__(NT) k_mat_fill(const SecDev* __restrict__ secs, LoopParams lp) {
+    __shared__ float As[BK][TILE], Cs[BK][TILE];
+    if (gated(lp.counters)) return;
+    const SecDev& s = secs[blockIdx.y];
+    const int R = s.st[0];
+    if (!row_matrix_on(s, lp) || s.st[6] != 1 || R <= s.stop || R > lp.kmax) return;
+    const int nT = (R + TILE - 1) / TILE;
+    if ((int)blockIdx.x >= nT * (nT + 1) / 2) return;
+    int ib, jb;
+    tile_coords((int)blockIdx.x, nT, ib, jb);
+    const int tid = threadIdx.x;
+    const int ty = tid >> 5, tx = tid & 31;
+    float acc[4][2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) acc[a][0] = acc[a][1] = 0.0f;
+    const int lrow = tid >> 3, lb = (tid & 7) << 2;
+    const int ia = ib * TILE + lrow, ic = jb * TILE + lrow;
+    for (int k0 = 0; k0 < s.Bp; k0 += BK) {
+        float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vc = va;
+        if (ia < R) va = *reinterpret_cast<const float4*>(s.mean + (size_t)ia * s.Bp + k0 + lb);
+        if (ic < R) vc = *reinterpret_cast<const float4*>(s.mean + (size_t)ic * s.Bp + k0 + lb);
+        As[lb + 0][lrow] = va.x;
+        As[lb + 1][lrow] = va.y;
+        As[lb + 2][lrow] = va.z;
+        As[lb + 3][lrow] = va.w;
+        Cs[lb + 0][lrow] = vc.x;
+        Cs[lb + 1][lrow] = vc.y;
+        Cs[lb + 2][lrow] = vc.z;
+        Cs[lb + 3][lrow] = vc.w;
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < BK; ++kk) {
+            const float4 a = *reinterpret_cast<const float4*>(&As[kk][ty * 4]);
+            const float2 c = *reinterpret_cast<const float2*>(&Cs[kk][tx * 2]);
+            float d;
+            d = a.x - c.x; acc[0][0] = fmaf(d, d, acc[0][0]);
+            d = a.x - c.y; acc[0][1] = fmaf(d, d, acc[0][1]);
+            d = a.y - c.x; acc[1][0] = fmaf(d, d, acc[1][0]);
+            d = a.y - c.y; acc[1][1] = fmaf(d, d, acc[1][1]);
+            d = a.z - c.x; acc[2][0] = fmaf(d, d, acc[2][0]);
+            d = a.z - c.y; acc[2][1] = fmaf(d, d, acc[2][1]);
+            d = a.w - c.x; acc[3][0] = fmaf(d, d, acc[3][0]);
+            d = a.w - c.y; acc[3][1] = fmaf(d, d, acc[3][1]);
+        }
+        __syncthreads();
+    }
+    const float gam = (float)(2 * s.B + 32) * U32;
+    const size_t rc = (size_t)s.rcap;
+    const float2 inf2 = make_float2(__builtin_huge_valf(), __builtin_huge_valf());
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int i = ib * TILE + ty * 4 + a, j = jb * TILE + tx * 2 + c;
+            if (i >= R || j >= R || (ib == jb && j < i)) continue;
+            float2 e = inf2;
+            if (i != j) {
+                const float2 lu = screen_bounds(acc[a][c], s.npix[i], s.npix[j], s.norm[i], s.norm[j], gam);
+                e = make_float2(__double2float_rd((double)lu.x * (1.0 - MAT_REL)),
+                                __double2float_ru((double)lu.y * (1.0 + MAT_REL)));
+            }
+            s.dmat[(size_t)i * rc + j] = e;
+            s.dmat[(size_t)j * rc + i] = e;
+        }
+    if (tid == 0 && lp.counters) {
+        const unsigned long long pairs = (unsigned long long)min(TILE, R - ib * TILE) *
+                                         (unsigned long long)min(TILE, R - jb * TILE);
+        atomicAdd(&lp.counters[C_W_FILL_FLOPS], 3ull * (unsigned long long)s.B * pairs);
     }
 }
 
@@ -2623,7 +3005,7 @@ __global__ void __launch_bounds__(NT) k_rowcache_prep(const SecDev* __restrict__
     const SecDev& s = secs[blockIdx.x];
     const int R = s.st[0];
     if (s.rcap == 0 || R <= s.stop || R > lp.kmax || s.st[6] != 0) return;
-    rowcache_begin(sh, s, R, s.st[1]);
+    rowcache_begin(sh, s, R, s.st[1], row_matrix_on(s, lp));
 }
 
 __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ secs, int G, LoopParams lp) {
@@ -2724,7 +3106,8 @@ __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ s
             decide_bytes += 16ull * (unsigned long long)E + 24ull * (unsigned long long)s.B;
             if (lp.incremental) {
                 KeyD an;
-                const bool av = merge_pair_inc<4>(sh, s, win.si, win.sj, R, E, stamp, kind, win.d2, rcs, an, nchk);
+                const bool av = merge_pair_inc<4>(sh, s, win.si, win.sj, R, E, stamp, kind, win.d2, rcs, an, nchk,
+                                                  row_matrix_on(s, lp));
                 if (tid == 0) {
                     s.st[8] = av ? 1 : 0;
                     s.wd[2] = an.d2;
@@ -2743,7 +3126,7 @@ __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ s
             }
             if (s.abit && rcs) abit_merge(s, win.si, win.sj, R);
             if (row_cache && rcs == 0 && lp.spectral && R - 1 <= lp.kmax && R - 1 > s.stop)
-                rowcache_begin(sh, s, R - 1, E);
+                rowcache_begin(sh, s, R - 1, E, row_matrix_on(s, lp));
         }
         if (tid == 0) {
             s.wi[0] = 1;
@@ -3240,10 +3623,19 @@ hipError_t launch_rowcache_prep(const SecDev* secs, int n, const LoopParams& lp,
 }
 
 hipError_t launch_wide_iteration(const SecDev* secs, int n, int G, const LoopParams& lp, int variant,
-                                 bool spectral_possible, bool row_cache, int rows_grid, hipStream_t s, KTimer* kt) {
+                                 bool spectral_possible, bool row_cache, int rows_grid, int fill_tiles, hipStream_t s,
+                                 KTimer* kt) {
     const dim3 grid(G, n);
     if (row_cache) {  // incremental form: cached adjacent values and spectral rows
-        if (spectral_possible) KLAUNCH(HSWO_K_WIDE_ROWS, k_wide_rows, dim3(rows_grid), dim3(NT), secs, n, lp);
+        if (spectral_possible) {
+            if (lp.row_matrix) {
+                if (fill_tiles > 0)
+                    KLAUNCH(HSWO_K_MATRIX_FILL, k_mat_fill, dim3(fill_tiles, n), dim3(NT), secs, lp);
+                KLAUNCH(HSWO_K_WIDE_ROWS, k_mat_rows, dim3(rows_grid), dim3(NT), secs, n, lp);
+            } else {
+                KLAUNCH(HSWO_K_WIDE_ROWS, k_wide_rows, dim3(rows_grid), dim3(NT), secs, n, lp);
+            }
+        }
         KLAUNCH(HSWO_K_WIDE_DECIDE, k_wide_decide, dim3(n), dim3(NT), secs, G, lp);
         return hipGetLastError();
     }

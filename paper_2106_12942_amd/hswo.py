@@ -40,13 +40,14 @@ HSWO_CRIT_BSMSE = 0
 HSWO_CRIT_SAM = 1
 CRIT = {"bsmse": HSWO_CRIT_BSMSE, "sam": HSWO_CRIT_SAM}
 KERNEL_KINDS = ["section_driver", "wide_adj", "wide_decide", "wide_mfma", "wide_fp32", "wide_finish", "wide_rows",
-                "rowcache_prep"]
+                "rowcache_prep", "matrix_fill"]
 
 MERGE_DTYPE = np.dtype([("lo", "<i4"), ("hi", "<i4"), ("kind", "<i4"), ("r_after", "<i4"), ("d2", "<f8")])
 VERIFY_DTYPE = np.dtype([("lo", "<i4"), ("hi", "<i4"), ("stage", "<i4"), ("r", "<i4"), ("screen", "<f8"),
                          ("lower", "<f8"), ("upper", "<f8"), ("d2", "<f8")])
 SCREEN_STAGES = {0: "adjacent_fp32", 1: "spectral_fp32", 2: "spectral_16bit"}
-TUNING_FIELDS = ["wide_max_sections", "wide_groups", "rows_grid", "hybrid", "bare_bounds", "driver_variant"]
+TUNING_FIELDS = ["wide_max_sections", "wide_groups", "rows_grid", "hybrid", "bare_bounds", "driver_variant",
+                 "row_matrix"]
 
 EXPORTS = ["hswo_version", "hswo_last_error", "hswo_workspace_bytes", "hswo_run", "rhseg_segment",
            "hswo_batch_workspace_bytes", "hswo_run_batch", "rhseg_segment_noalloc"]
@@ -100,15 +101,17 @@ class Stats(ctypes.Structure):
         ("ms_mfma_screen", ctypes.c_double),
         ("ms_fp32_spectral", ctypes.c_double),
         ("ms_merge", ctypes.c_double),
-        ("ms_kernel", ctypes.c_double * 8),
-        ("kernel_launches", ctypes.c_int64 * 8),
-        ("kernel_work", ctypes.c_int64 * 8),
+        ("ms_kernel", ctypes.c_double * 9),
+        ("kernel_launches", ctypes.c_int64 * 9),
+        ("kernel_work", ctypes.c_int64 * 9),
         ("ms_event_pair_overhead", ctypes.c_double),
         ("nonfinite_values", ctypes.c_int64),
         ("screen_iterations", ctypes.c_int64),
         ("screen_fallbacks", ctypes.c_int64),
         ("verify_records", ctypes.c_int64),
+        ("row_bounded_pairs", ctypes.c_int64),
         ("tuning", Tuning),
+        ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self):

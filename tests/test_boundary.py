@@ -38,11 +38,11 @@ def test_version_and_empty_error():
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(hswo.Params) == 80
     assert hswo.MERGE_DTYPE.itemsize == 24
-    assert ctypes.sizeof(hswo.Stats) == 384
-    assert ctypes.sizeof(hswo.Tuning) == 24
+    assert ctypes.sizeof(hswo.Stats) == 424
+    assert ctypes.sizeof(hswo.Tuning) == 28
     assert hswo.VERIFY_DTYPE.itemsize == 48
     src = open(HEADER).read()
-    for name, size in (("hswo_params", 80), ("hswo_stats", 384), ("hswo_tuning", 24), ("hswo_verify_rec", 48),
+    for name, size in (("hswo_params", 80), ("hswo_stats", 424), ("hswo_tuning", 28), ("hswo_verify_rec", 48),
                        ("hswo_merge_rec", 24)):
         assert re.search(r"\}\s*%s;\s*/\*\s*%d bytes" % (name, size), src), name
 
@@ -195,11 +195,15 @@ def test_spectral_angle_needs_the_incremental_form(kw):
     assert lib.hswo_run_batch(1, secs, 0, ctypes.byref(p), None, FAKE, 1 << 30, None) == hswo.HSWO_E_UNSUPPORTED
 
 
-def test_spectral_angle_workspace_adds_the_norm_rows():
+def test_spectral_angle_workspace_holds_norms_instead_of_the_interval_matrix():
+    # row cache of spclust_max = 256 slots: Equation 1 keeps the interval matrix (FP32 bounds, 8 bytes
+    # per pair of slots) and its update scratch (16 bytes per slot); the spectral angle each slot's
+    # squared norm (8 bytes per slot) instead
     q = hswo.make_params(**BASE, incremental=True)
     p = hswo.make_params(**BASE, incremental=True, criterion="sam")
     a, b = hswo.workspace_bytes(64, 64, 32, 0, q), hswo.workspace_bytes(64, 64, 32, 0, p)
-    assert 0 < a < b
+    assert 0 < b < a
+    assert abs((a - b) - (256 * 256 * 8 + 256 * 16 - 256 * 8)) <= 512
 
 
 @pytest.mark.parametrize("kw", [dict(), dict(precision="fp16"), dict(sequential=True)])
@@ -210,9 +214,13 @@ def test_two_merges_need_the_incremental_form(kw):
     rc = lib.hswo_run(FAKE, 16, 16, 4, 0, ctypes.byref(p), FAKE, None, None, FAKE, 1 << 30, None)
     assert rc == hswo.HSWO_E_UNSUPPORTED
     assert "TWO_MERGES" in hswo.last_error()
+    # the two-merge reading keeps the row cache's adjacency bitmap (rcap^2 bits) instead of the
+    # interval matrix (8 bytes per pair of slots) and its scratch
     q = hswo.make_params(**BASE, two_merges=True, incremental=True)
     r = hswo.make_params(**BASE, incremental=True)
-    assert hswo.workspace_bytes(64, 64, 8, 0, q) > hswo.workspace_bytes(64, 64, 8, 0, r) > 0
+    a, b = hswo.workspace_bytes(64, 64, 8, 0, q), hswo.workspace_bytes(64, 64, 8, 0, r)
+    assert 0 < a < b
+    assert abs((b - a) - (256 * 256 * 8 + 256 * 16 - 256 * 8 * 4)) <= 512
 
 
 def test_verify_bound_flag_checked():

@@ -120,6 +120,8 @@ TUNING_CASES = [
     ("incremental", dict(wide_max_sections=100000, rows_grid=7)),
     ("incremental", dict(wide_max_sections=100000, rows_grid=1024, hybrid=0)),
     ("incremental", dict(bare_bounds=0)),
+    ("incremental", dict(row_matrix=0)),
+    ("incremental", dict(row_matrix=1, wide_max_sections=100000, rows_grid=3)),
     ("incremental", dict(bare_bounds=2, wide_max_sections=4)),
     ("fp16", dict(wide_max_sections=100000, wide_groups=1)),
     ("fp16", dict(wide_max_sections=100000, wide_groups=3)),
@@ -159,7 +161,7 @@ def test_autotuner_choice_is_reported_and_exact(form, tmp_path, monkeypatch):
     assert all(v >= 0 for v in tu.values()), tu
     check_against_oracle(sc.cube, res.labels.cpu().numpy(), res.log, dict(p, rnb_levels=3), f"autotuned {form}")
     lines = (tmp_path / "tune.txt").read_text().split()
-    assert len(lines) == 2 and lines[1].count(",") == 5
+    assert len(lines) == 2 and lines[1].count(",") == 6
 
 
 # ---------------------------------------------------------------------------

@@ -2,7 +2,10 @@
 adjacent stage and the spectral row cache (each live region keeps an exact
 pair, re-evaluated only when a merge invalidates it). Merge logs, with the
 FP64 criterion, and labels must equal the oracle's bit for bit, in both level
-modes (one workgroup per section, or G workgroups per section)."""
+modes (one workgroup per section, or G workgroups per section), and in the
+wide mode both with the row cache's interval matrix (stale rows rescanned
+from certified bounds kept by Ward's update) and without it (stale rows
+evaluated in full)."""
 import numpy as np
 import pytest
 
@@ -13,11 +16,16 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-MODES = ["persistent", "wide"]
+# persistent: the section driver evaluates stale rows in full (light steps, second bounds);
+# wide: the row cache keeps the interval matrix (rescans); wide_rows: wide, rows in full as persistent
+MODES = ["persistent", "wide", "wide_rows"]
 
 
 def _mode(monkeypatch, mode):
-    monkeypatch.setattr(hswo, "DEFAULT_TUNING", {"wide_max_sections": 0 if mode == "persistent" else 100000})
+    tu = {"wide_max_sections": 0 if mode == "persistent" else 100000}
+    if mode == "wide_rows":
+        tu["row_matrix"] = 0
+    monkeypatch.setattr(hswo, "DEFAULT_TUNING", tu)
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -138,10 +146,11 @@ def test_bare_bound_modes(bare, scene, variant, mode, monkeypatch):
     assert_parity(make(), p, incremental=True, tag=f"bare bounds {bare} {scene} {variant} {mode}")
 
 
-@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("mode", ["persistent", "wide_rows"])
 def test_bare_bound_mode_reaches_the_device(mode, monkeypatch):
     """The switch is read per call: keeping every bound changes the number of
-    exact evaluations (light steps replace full rows, failed ones add them)."""
+    exact evaluations (light steps replace full rows, failed ones add them).
+    The interval matrix takes no light steps, so it is not concerned."""
     _mode(monkeypatch, mode)
     make, p = BARE_SCENES["voronoi"]
     cube = make()

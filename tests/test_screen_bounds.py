@@ -153,3 +153,94 @@ def test_16bit_tile_test_never_drops_a_pair_below_threshold(fmt):
                 assert t < f32(2.0) * G or exact >= T, (fmt, na, nb, B, exact, T)
                 checked += 1
     assert checked > 0
+
+
+# ---------------------------------------------------------------------------
+# Interval matrix of the row cache: exact entries widened and rounded outward,
+# Ward's update on bounds at every merge
+# ---------------------------------------------------------------------------
+MAT_REL = 2.0 ** -40
+
+
+def f32_down(x):
+    f = np.float32(x)
+    return np.nextafter(f, np.float32(-np.inf)) if np.float64(f) > x else f
+
+
+def f32_up(x):
+    f = np.float32(x)
+    return np.nextafter(f, np.float32(np.inf)) if np.float64(f) < x else f
+
+
+def mat_entry(c):
+    """Model of the kernels' entry from a canonical value."""
+    if not np.isfinite(c):
+        return np.float32(np.inf), np.float32(np.inf)
+    return f32_down(c * (1.0 - MAT_REL)), f32_up(c * (1.0 + MAT_REL))
+
+
+def mat_update(ea, eb, d, na, nb, nk):
+    """Model of the kernels' Ward update on bounds."""
+    d_lo, d_hi = (float(v) for v in d)
+    ca, cb, den = na + nk, nb + nk, na + nb + nk
+    lo = (ca * float(ea[0]) + cb * float(eb[0]) - nk * d_hi) / den
+    hi = (ca * float(ea[1]) + cb * float(eb[1]) - nk * d_lo) / den
+    t = (ca * float(ea[1]) + cb * float(eb[1]) + nk * d_hi) / den
+    return f32_down(max(lo - t * 2.0 ** -48, 0.0)), f32_up(hi + t * 2.0 ** -48)
+
+
+@pytest.mark.parametrize("kind", ["voronoi", "salt", "tiny"])
+def test_ward_update_bounds_hold_over_merge_chains(kind):
+    """Merge random pairs of regions until few are left, updating every
+    entry of the survivor's row by Ward's update on bounds (entries never
+    refreshed from exact values, so the widening accumulates): the canonical
+    value of every pair stays inside its widened bounds."""
+    rng = np.random.default_rng({"voronoi": 1, "salt": 2, "tiny": 3}[kind])
+    B = {"voronoi": 32, "salt": 224, "tiny": 3}[kind]
+    R = 40
+    base = rng.uniform(0, 2000, size=(4, B))
+    cls = rng.integers(0, 4, size=R)
+    mu = base[cls] + rng.normal(0, {"voronoi": 30.0, "salt": 5.0, "tiny": 1e-3}[kind], size=(R, B))
+    if kind == "salt":
+        mu[rng.random(R) < 0.3] = 2000.0  # identical spectra: exact zeros
+    n = rng.integers(1, 20, size=R).astype(np.int64)
+    S = np.round(mu * n[:, None] * 64) / 64
+    live = list(range(R))
+    E = {}
+    for i in live:
+        for j in live:
+            if i < j:
+                E[(i, j)] = mat_entry(oracle.criterion_d2(S[i], S[j], int(n[i]), int(n[j])))
+    key = lambda a, b: (min(a, b), max(a, b))
+    checked = 0
+    while len(live) > 3:
+        a, b = rng.choice(live, size=2, replace=False)
+        a, b = int(min(a, b)), int(max(a, b))
+        d = E[(a, b)]
+        for k in live:
+            if k in (a, b):
+                continue
+            E[key(k, a)] = mat_update(E[key(k, a)], E[key(k, b)], d, float(n[a]), float(n[b]), float(n[k]))
+        S[a] = S[a] + S[b]
+        n[a] += n[b]
+        live.remove(b)
+        for k in live:
+            if k == a:
+                continue
+            c = oracle.criterion_d2(S[min(a, k)], S[max(a, k)], int(n[min(a, k)]), int(n[max(a, k)]))
+            lo, hi = E[key(k, a)]
+            assert float(lo) * (1 - MAT_REL) <= c <= float(hi) * (1 + MAT_REL), (kind, a, k, lo, c, hi)
+            if c == 0.0:
+                assert float(hi) == 0.0 or float(lo) == 0.0
+            checked += 1
+    assert checked > 100
+
+
+def test_exact_zero_entries_stay_exact():
+    """Identical spectra give [0, 0], and Ward's update of two [0, 0] rows
+    with a zero-valued merge keeps [0, 0] (the rescan trusts it without
+    evaluating)."""
+    z = mat_entry(0.0)
+    assert float(z[0]) == 0.0 and float(z[1]) == 0.0
+    u = mat_update(z, z, z, 3.0, 5.0, 7.0)
+    assert float(u[0]) == 0.0 and float(u[1]) == 0.0
