@@ -364,6 +364,10 @@ Layout carve(const Plan& pl, int H, int W, const hswo_params* p, int bare, void*
             if (p->flags & HSWO_FLAG_INCREMENTAL) {
                 s.ed2 = bp.take<double>(sp.ecap);
                 s.edirty = bp.take<int32_t>(sp.ecap);
+                s.rmin = bp.take<int32_t>(sp.cap);
+                s.rmax = bp.take<int32_t>(sp.cap);
+                s.cmd2 = bp.take<double>((sp.ecap + ECH - 1) / ECH);
+                s.cme = bp.take<int32_t>((sp.ecap + ECH - 1) / ECH);
             }
             s.tstat = bp.take<float2>(sp.tiles);
             s.tflag = bp.take<int32_t>(sp.tiles);
@@ -1197,6 +1201,10 @@ BatchLayout carve_batch(int n, const hswo_section* sec, const hswo_params* p, in
         if (p->flags & HSWO_FLAG_INCREMENTAL) {
             s.ed2 = bp.take<double>(ecap);
             s.edirty = bp.take<int32_t>(ecap);
+            s.rmin = bp.take<int32_t>(cap);
+            s.rmax = bp.take<int32_t>(cap);
+            s.cmd2 = bp.take<double>((ecap + ECH - 1) / ECH);
+            s.cme = bp.take<int32_t>((ecap + ECH - 1) / ECH);
         }
         s.tstat = bp.take<float2>(tiles);
         s.tflag = bp.take<int32_t>(tiles);

@@ -51,6 +51,8 @@ enum Counter {
 
 constexpr int ST_WORDS = 16;  // per-section state words
 constexpr int MAT_MAX = 4096; // largest row cache that keeps the interval matrix (128 MiB per section)
+constexpr int ECH = 256;      // edge slots per chunk of the incremental form's per-chunk minima
+constexpr int EIDX_MIN = 8192; // wide mode: edge lists at least this long go through the edge index in a merge
 constexpr int GMAX = 256;     // wide mode: most workgroups per section
 constexpr int STILE = 128;    // matrix-core super tile edge (4 spectral tiles)
 
@@ -101,6 +103,12 @@ struct SecDev {
     // incremental adjacent stage: exact D2 per edge slot and the edges to refresh
     double* ed2;     // [Ecap]
     int32_t* edirty; // [Ecap]
+    // its edge index: per live slot the range of edge slots that can touch it, per chunk of ECH
+    // edge slots the least cached key (value, edge slot or -1); valid while st[12] = 1
+    int32_t* rmin;   // [R0]
+    int32_t* rmax;   // [R0]
+    double* cmd2;    // [ceil(Ecap / ECH)]
+    int32_t* cme;    // [ceil(Ecap / ECH)]
     // spectral row cache (incremental form), slots [0, rcap):
     double* m64;     // [B][rcap] FP64 mean spectra S/n (spectral angle: the sums S), band-major
                      //           (column j = slot j)
@@ -131,7 +139,8 @@ struct SecDev {
                      //        [8] incremental form: next adjacent minimum cached (wd[2], wi[8..11]),
                      //        [9] empty edge slots left by incremental merges,
                      //        [10] two-merge reading: step 3 due (threshold in wd[3]),
-                     //        [11] rows appended to the pending list by failed light steps
+                     //        [11] rows appended to the pending list by failed light steps,
+                     //        [12] incremental form: edge index (slot ranges, chunk minima) valid
     int32_t* parent; // label-indexed union-find parent (image or batch section)
     int32_t* mtime;  // label-indexed merge time: -1 non-top merge, k top merge, INT_MAX alive
     hswo_merge_rec* log;  // section merge log base (may be null)

@@ -138,6 +138,7 @@ struct Smem {
     int npend;               // rows appended to the row cache's pending list
     int tlist[TLIST];        // tiles gathered for a pass (one barrier instead of one per tile)
     int bcast_i[4];
+    int idx[8];              // incremental merge: slot ranges and the chunk range scanned
     unsigned long long cnt[C_COUNT];  // per-block counters and stage clocks (thread 0 only)
 };
 
@@ -1997,7 +1998,171 @@ __device__ void compact_edges(Smem& sh, const SecDev& s, int& E) {
     __syncthreads();
 }
 
+// Edge index of the incremental form: for every live slot the range
+// [rmin, rmax] of edge slots that can touch it (conservative: a merge gives
+// the survivor the union of both ranges, a moving slot keeps its range), and
+// for every chunk of ECH edge slots the least key (D2, lo, hi) of its cached
+// values (cmd2, cme: value and edge slot, -1 for none). Rebuilt from scratch
+// when st[12] is 0 (pass start, compaction).
+
+// Least key of chunk c into cmd2[c] / cme[c]; one wavefront.
+__device__ void chunk_min_wave(const SecDev& s, int c, int E) {
+    const int lane = lane_id();
+    KeyD best = key_none();
+#pragma unroll
+    for (int k = 0; k < ECH / 64; ++k) {
+        const int e = c * ECH + k * 64 + lane;
+        if (e < E) {
+            const double v = s.ed2[e];
+            if (v < __builtin_huge_val() && v <= best.d2) {  // labels only for a candidate
+                const int2 ed = s.edges[e];
+                const int la = s.label[ed.x], lb = s.label[ed.y];
+                KeyD kk;
+                kk.d2 = v;
+                kk.lo = min(la, lb);
+                kk.hi = max(la, lb);
+                kk.si = e;  // the edge slot rides in si
+                kk.sj = 0;
+                if (key_less(kk, best)) best = kk;
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const KeyD x = shfl_key(best, o);
+        if (key_less(x, best)) best = x;
+    }
+    if (lane == 0) {
+        s.cmd2[c] = best.d2;
+        s.cme[c] = key_exists(best) ? best.si : -1;
+    }
+}
+
+// Ranges and chunk minima from scratch (st[12] = 1 after); whole block.
+__device__ __noinline__ void edge_index_build(const SecDev& s, int R, int E) {
+    for (int i = threadIdx.x; i < R; i += NT) {
+        s.rmin[i] = INT_MAX;
+        s.rmax[i] = -1;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < E; e += NT) {
+        const int2 ed = s.edges[e];
+        if (ed.x >= 0) {
+            atomicMin(&s.rmin[ed.x], e);
+            atomicMax(&s.rmax[ed.x], e);
+            atomicMin(&s.rmin[ed.y], e);
+            atomicMax(&s.rmax[ed.y], e);
+        }
+    }
+    for (int c = wave_id(); c < (E + ECH - 1) / ECH; c += NWAVE) chunk_min_wave(s, c, E);
+    __syncthreads();
+    if (threadIdx.x == 0) s.st[12] = 1;
+    __syncthreads();
+}
+
+// The least adjacent key over every chunk's minimum, with its slots; whole block.
+__device__ KeyD chunks_min_key(Smem& sh, const SecDev& s, int E) {
+    KeyD best = key_none();
+    for (int c = threadIdx.x; c < (E + ECH - 1) / ECH; c += NT) {
+        const int e = s.cme[c];
+        if (e < 0) continue;
+        const int2 ed = s.edges[e];
+        const int la = s.label[ed.x], lb = s.label[ed.y];
+        KeyD k;
+        k.d2 = s.cmd2[c];
+        if (la < lb) {
+            k.lo = la;
+            k.hi = lb;
+            k.si = ed.x;
+            k.sj = ed.y;
+        } else {
+            k.lo = lb;
+            k.hi = la;
+            k.si = ed.y;
+            k.sj = ed.x;
+        }
+        if (key_less(k, best)) best = k;
+    }
+    return block_min_key(sh, best);
+}
+
 constexpr int LCAP = CAND_CAP / 3;  // edges listed per merge by the incremental form (L, L2, neighbours)
+
+// The index path of merge_pair_inc's edge listing: the edges touching the
+// merged pair go to L (their other endpoint to XL), those touching the slot
+// that moves to L2, scanning only the chunks of the slot ranges; the ranges
+// and the first chunk range go to sh.idx (ua, ub, ma, mb, a0, a1). Whole
+// block, ends with a barrier.
+__device__ __noinline__ void merge_index_scan(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int E, int* L,
+                                              int* XL, int* L2) {
+    if (s.st[12] == 0) edge_index_build(s, R, E);
+    const int last = R - 1;
+    const bool moved = last != lo_s && last != hi_s;
+    const int ua = min(s.rmin[lo_s], s.rmin[hi_s]);
+    const int ub = max(s.rmax[lo_s], s.rmax[hi_s]);
+    const int ma = moved ? s.rmin[last] : INT_MAX;
+    const int mb = moved ? s.rmax[last] : -1;
+    const int tid = threadIdx.x;
+    int a0 = 0, a1 = 0, b0 = 0, b1 = 0;  // chunk-aligned [a0, a1) and [b0, b1)
+    if (ua <= ub) {
+        a0 = (ua / ECH) * ECH;
+        a1 = min(E, (ub / ECH + 1) * ECH);
+    }
+    if (ma <= mb) {
+        b0 = (ma / ECH) * ECH;
+        b1 = min(E, (mb / ECH + 1) * ECH);
+    }
+    for (int pass = 0; pass < 2; ++pass) {  // block-uniform
+        const int r0 = pass ? b0 : a0, r1 = pass ? b1 : a1;
+        for (int e = r0 + tid; e < r1; e += NT) {
+            if (pass && e >= a0 && e < a1) continue;  // scanned in the first pass
+            const int2 ed = s.edges[e];
+            const int a = ed.x, b = ed.y;
+            if (a < 0) continue;
+            const bool ta = a == lo_s || a == hi_s, tb = b == lo_s || b == hi_s;
+            if (ta || tb) {
+                const int k = atomicAdd(&sh.bcast_i[0], 1);
+                if (k < LCAP) {
+                    L[k] = e;
+                    XL[k] = (ta && tb) ? -1 : (ta ? b : a);
+                }
+            } else if (a == last || b == last) {
+                const int k = atomicAdd(&sh.bcast_i[1], 1);
+                if (k < LCAP) L2[k] = e;
+            }
+        }
+    }
+    if (tid == 0) {
+        sh.idx[0] = ua;
+        sh.idx[1] = ub;
+        sh.idx[2] = ma;
+        sh.idx[3] = mb;
+        sh.idx[4] = a0;
+        sh.idx[5] = a1;
+    }
+    __syncthreads();
+}
+
+// The index path's end of a merge: the chunk minima of [a0, a1) anew (every
+// changed edge is there), the survivor's and the moved slot's ranges, and
+// the least key over all chunks.
+__device__ __noinline__ KeyD merge_index_finish(Smem& sh, const SecDev& s, int a0, int a1, int surv, int hi_s,
+                                                bool moved, int ua, int ub, int ma, int mb, int E) {
+    __syncthreads();  // the re-scored values are written
+    for (int c = a0 / ECH + wave_id(); c < (a1 + ECH - 1) / ECH; c += NWAVE) chunk_min_wave(s, c, E);
+    if (threadIdx.x == 0) {
+        s.rmin[surv] = ua;
+        s.rmax[surv] = ub;
+        if (moved) {
+            s.rmin[hi_s] = ma;
+            s.rmax[hi_s] = mb;
+        }
+    }
+    __syncthreads();
+    return chunks_min_key(sh, s, E);
+}
+
+
 
 // Merge in the incremental form (every edge slot holds its exact D2). One
 // pass over the edge slots lists the edges that touch the merged pair (L)
@@ -2009,8 +2174,11 @@ constexpr int LCAP = CAND_CAP / 3;  // edges listed per merge by the incremental
 // pass. Returns true with the least adjacent key after the merge in anext;
 // false (full pass taken) when a list would overflow.
 template <int U>
+// eidx_min: edge lists at least this long go through the edge index (the
+// persistent driver, whose merges follow one another in one launch, gains
+// from it at any length; a wide-mode decision launch only on long lists).
 __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int& E, int stamp, int kind,
-                               double d2, int rc, KeyD& anext, int& nchk, bool mat) {
+                               double d2, int rc, KeyD& anext, int& nchk, bool mat, int eidx_min) {
     const int tid = threadIdx.x;
     merge_stats(sh, s, lo_s, hi_s, R, kind, d2, 0, 0, rc, false);
     const int last = R - 1;
@@ -2025,76 +2193,99 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
         sh.bcast_i[3] = 0;  // emptied slots
     }
     __syncthreads();
-    // least cached D2 of this thread's edges that do not touch the merged pair
-    // (labels are read only to order exact ties inside the thread)
+    // A long edge list goes through its index: every edge that touches the
+    // merged pair lies in the union of their slot ranges, every edge of the
+    // slot that moves in its range, so only the chunks of those ranges are
+    // scanned; the next adjacent minimum is then the least of the chunk
+    // minima, those of the changed chunks taken anew. A short list takes one
+    // pass over every slot, which also yields the least key of the edges the
+    // merge cannot change (the index is then rebuilt when it is next used).
+    const bool use_index = E >= eidx_min;  // block-uniform
+    const bool moved = last != lo_s && last != hi_s;
+    int ua = 0, ub = -1, ma = INT_MAX, mb = -1;
+    int a0 = 0, a1 = 0;  // the first chunk range the index path scanned
+    double vmin = __builtin_huge_val();
     double bv = __builtin_huge_val();
-    int be = -1, bla = 0, blb = 0;
-    // U: pairs of edge slots per thread with loads in flight together
-    for (int e0 = 2 * tid; e0 < E; e0 += 2 * NT * U) {
-        int4 ed[U];
-        double2 v[U];
+    int be = -1;
+    if (use_index) {
+        merge_index_scan(sh, s, lo_s, hi_s, R, E, L, XL, L2);
+        ua = sh.idx[0];
+        ub = sh.idx[1];
+        ma = sh.idx[2];
+        mb = sh.idx[3];
+        a0 = sh.idx[4];
+        a1 = sh.idx[5];
+    } else {
+        // least cached D2 of this thread's edges that do not touch the merged pair
+        // (labels are read only to order exact ties inside the thread)
+        int bla = 0, blb = 0;
+        // U: pairs of edge slots per thread with loads in flight together
+        for (int e0 = 2 * tid; e0 < E; e0 += 2 * NT * U) {
+            int4 ed[U];
+            double2 v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = e0 + u * 2 * NT;
-            ed[u] = make_int4(-1, -1, -1, -1);
-            v[u] = make_double2(__builtin_huge_val(), __builtin_huge_val());
-            if (e + 1 < E) {
-                ed[u] = *reinterpret_cast<const int4*>(s.edges + e);
-                v[u] = *reinterpret_cast<const double2*>(s.ed2 + e);
-            } else if (e < E) {
-                const int2 x = s.edges[e];
-                ed[u] = make_int4(x.x, x.y, -1, -1);
-                v[u].x = s.ed2[e];
+            for (int u = 0; u < U; ++u) {
+                const int e = e0 + u * 2 * NT;
+                ed[u] = make_int4(-1, -1, -1, -1);
+                v[u] = make_double2(__builtin_huge_val(), __builtin_huge_val());
+                if (e + 1 < E) {
+                    ed[u] = *reinterpret_cast<const int4*>(s.edges + e);
+                    v[u] = *reinterpret_cast<const double2*>(s.ed2 + e);
+                } else if (e < E) {
+                    const int2 x = s.edges[e];
+                    ed[u] = make_int4(x.x, x.y, -1, -1);
+                    v[u].x = s.ed2[e];
+                }
             }
-        }
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+            for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int e = e0 + u * 2 * NT + h;
-                const int a = h ? ed[u].z : ed[u].x, b = h ? ed[u].w : ed[u].y;
-                const double vv = h ? v[u].y : v[u].x;
-                const bool ta = a == lo_s || a == hi_s, tb = b == lo_s || b == hi_s;
-                const bool touch = ta || tb;
-                if (a >= 0 && touch) {
-                    const int k = atomicAdd(&sh.bcast_i[0], 1);
-                    if (k < LCAP) {
-                        L[k] = e;
-                        XL[k] = (ta && tb) ? -1 : (ta ? b : a);
-                    }
-                }
-                if (a >= 0 && !touch && (a == last || b == last)) {
-                    const int k = atomicAdd(&sh.bcast_i[1], 1);
-                    if (k < LCAP) L2[k] = e;
-                }
-                if (a >= 0 && !touch) {
-                    if (vv < bv) {
-                        bv = vv;
-                        be = e;
-                        bla = -1;  // labels not loaded
-                    } else if (vv == bv && vv < __builtin_huge_val()) {
-                        // exact tie: order by (lo, hi) labels
-                        if (bla < 0) {
-                            const int2 x = s.edges[be];
-                            const int p = s.label[x.x], q = s.label[x.y];
-                            bla = min(p, q);
-                            blb = max(p, q);
+                for (int h = 0; h < 2; ++h) {
+                    const int e = e0 + u * 2 * NT + h;
+                    const int a = h ? ed[u].z : ed[u].x, b = h ? ed[u].w : ed[u].y;
+                    const double vv = h ? v[u].y : v[u].x;
+                    const bool ta = a == lo_s || a == hi_s, tb = b == lo_s || b == hi_s;
+                    const bool touch = ta || tb;
+                    if (a >= 0 && touch) {
+                        const int k = atomicAdd(&sh.bcast_i[0], 1);
+                        if (k < LCAP) {
+                            L[k] = e;
+                            XL[k] = (ta && tb) ? -1 : (ta ? b : a);
                         }
-                        const int p = s.label[a], q = s.label[b];
-                        const int lo = min(p, q), hi = max(p, q);
-                        if (lo < bla || (lo == bla && hi < blb)) {
+                    }
+                    if (a >= 0 && !touch && (a == last || b == last)) {
+                        const int k = atomicAdd(&sh.bcast_i[1], 1);
+                        if (k < LCAP) L2[k] = e;
+                    }
+                    if (a >= 0 && !touch) {
+                        if (vv < bv) {
+                            bv = vv;
                             be = e;
-                            bla = lo;
-                            blb = hi;
+                            bla = -1;  // labels not loaded
+                        } else if (vv == bv && vv < __builtin_huge_val()) {
+                            // exact tie: order by (lo, hi) labels
+                            if (bla < 0) {
+                                const int2 x = s.edges[be];
+                                const int p = s.label[x.x], q = s.label[x.y];
+                                bla = min(p, q);
+                                blb = max(p, q);
+                            }
+                            const int p = s.label[a], q = s.label[b];
+                            const int lo = min(p, q), hi = max(p, q);
+                            if (lo < bla || (lo == bla && hi < blb)) {
+                                be = e;
+                                bla = lo;
+                                blb = hi;
+                            }
                         }
                     }
                 }
-            }
+        }
+        __syncthreads();
+        vmin = block_min_d(sh, bv);
     }
-    __syncthreads();
-    const double vmin = block_min_d(sh, bv);
     KeyD best = key_none();
-    if (be >= 0 && bv == vmin) {
+    if (!use_index && be >= 0 && bv == vmin) {
         const int2 x = s.edges[be];
         const int a = x.x, b = x.y;
         const int na = (a == last) ? hi_s : a, nb = (b == last) ? hi_s : b;
@@ -2121,7 +2312,10 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
         score_edges(sh, s, s.edirty, nd);
         nchk += nd;
         __syncthreads();
-        if (tid == 0) s.st[9] = 0;
+        if (tid == 0) {
+            s.st[9] = 0;
+            s.st[12] = 0;  // the edge list was compacted: ranges and chunk minima are rebuilt
+        }
         return false;
     }
     // rename the moved slot in L2 (the edges of L carry their neighbour in XL)
@@ -2265,12 +2459,20 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
         }
     }
     nchk += nk;
-    anext = block_min_key(sh, best);
+    if (use_index) {
+        anext = merge_index_finish(sh, s, a0, a1, surv, hi_s, moved, ua, ub, ma, mb, E);
+    } else {
+        anext = block_min_key(sh, best);  // the re-scored edges and the least of the others
+        if (tid == 0) s.st[12] = 0;        // the index was not kept up to date
+    }
     const int empty = s.st[9] + emptied;
     __syncthreads();  // every thread has read st[9]
     if (4 * empty > E || R - 1 <= s.stop) {
         compact_edges(sh, s, E);
-        if (tid == 0) s.st[9] = 0;
+        if (tid == 0) {
+            s.st[9] = 0;
+            s.st[12] = 0;  // slot numbers changed: ranges and chunk minima are rebuilt
+        }
     } else if (tid == 0) {
         s.st[9] = empty;
     }
@@ -2727,7 +2929,7 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
         if (lp.incremental) CNT_ADD(C_D_BYTES, 16ull * (unsigned long long)E + 24ull * (unsigned long long)s.B);
         if (lp.incremental) {
             int nre = 0;
-            avalid = merge_pair_inc<8>(sh, s, win.si, win.sj, R, E, merges, kind, win.d2, rcs, anext, nre, false);
+            avalid = merge_pair_inc<8>(sh, s, win.si, win.sj, R, E, merges, kind, win.d2, rcs, anext, nre, false, 0);
             CNT_ADD(C_RECHECKS, nre);
         } else {
             merge_pair(sh, s, win.si, win.sj, R, E, merges, kind, win.d2, g_ready, prec, rcs);
@@ -3107,7 +3309,7 @@ __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ s
             if (lp.incremental) {
                 KeyD an;
                 const bool av = merge_pair_inc<4>(sh, s, win.si, win.sj, R, E, stamp, kind, win.d2, rcs, an, nchk,
-                                                  row_matrix_on(s, lp));
+                                                  row_matrix_on(s, lp), EIDX_MIN);
                 if (tid == 0) {
                     s.st[8] = av ? 1 : 0;
                     s.wd[2] = an.d2;
@@ -3356,6 +3558,7 @@ __global__ void k_init_leaves(const SecDev* __restrict__ secs, const InitDev* __
         s.st[9] = 0;
         s.st[10] = 0;
         s.st[11] = 0;
+        s.st[12] = 0;
     }
 }
 
@@ -3413,6 +3616,7 @@ __global__ void k_assemble(const SecDev* __restrict__ parents, const SecDev* __r
             p.st[9] = 0;
             p.st[10] = 0;
             p.st[11] = 0;
+            p.st[12] = 0;
         }
         return;
     }
@@ -3454,6 +3658,7 @@ __global__ void k_assemble(const SecDev* __restrict__ parents, const SecDev* __r
         p.st[9] = 0;
         p.st[10] = 0;
         p.st[11] = 0;
+        p.st[12] = 0;
     }
 }
 
