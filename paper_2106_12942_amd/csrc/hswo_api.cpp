@@ -379,7 +379,7 @@ Layout carve(const Plan& pl, int H, int W, const hswo_params* p, int bare, void*
                 if (p->criterion == HSWO_CRIT_SAM) s.rq = bp.take<double>(rc);
                 else if (!(p->flags & HSWO_FLAG_TWO_MERGES) && rc <= MAT_MAX) {
                     s.dmat = bp.take<float2>(rc * rc);
-                    s.dtmp = bp.take<float2>(2 * rc);
+                    s.msl = bp.take<int32_t>(rc);
                 }
                 if (p->flags & HSWO_FLAG_TWO_MERGES) s.abit = bp.take<uint32_t>(rc * ((rc + 31) / 32));
                 s.rbd = bp.take<double>(rc);

@@ -111,11 +111,13 @@ struct SecDev {
     int32_t* cme;    // [ceil(Ecap / ECH)]
     // spectral row cache (incremental form), slots [0, rcap):
     double* m64;     // [B][rcap] FP64 mean spectra S/n (spectral angle: the sums S), band-major
-                     //           (column j = slot j)
+                     //           (column j = slot j); not kept with the interval matrix, which has no
+                     //           exact row tasks
     double* m64r;    // [rcap][B8] the same rows slot-major, B8 = B rounded up to 8
     float2* dmat;    // [rcap][rcap] Equation 1, one-merge reading, rcap <= MAT_MAX: FP32 bounds on every
-                     //   pair's value, kept by Ward's update at each merge (used in wide mode)
-    float2* dtmp;    // [2][rcap] scratch of that update
+                     //   pair's value, kept by Ward's update at each merge (used in wide mode); its rows
+                     //   and columns are indexed by msl, not by slot
+    int32_t* msl;    // [rcap] matrix row of each live slot (the identity when the cache starts)
     double* rq;      // [rcap] spectral angle only: |S|^2 of each slot (pairwise tree over the bands)
     uint32_t* abit;  // [rcap][ceil(rcap / 32)] two-merge reading only: adjacency bitmap of the live slots
     double* rbd;     // [rcap] exact D2 of the row's cached pair

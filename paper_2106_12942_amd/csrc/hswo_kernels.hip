@@ -444,6 +444,32 @@ __device__ __noinline__ double exact_seg(const SecDev& s, int si, int sj, int L)
     return sam ? sam_value(t0, t1, t2) : fac * t0;
 }
 
+// exact_seg for Equation 1 from the row cache's FP64 means (m64r, the stored
+// quotients S / n), so no division per band: the same bands, tree and
+// factor, hence the same value. For slots whose means are current (row cache
+// running).
+__device__ __noinline__ double exact_seg_means(const SecDev& s, int si, int sj, int L) {
+    const int B = s.B, B8 = (B + 7) & ~7;
+    const int b = (lane_id() & (L - 1)) << 2;
+    double t0 = 0.0, fac = 0.0;
+    if (si >= 0) {
+        const double* Mi = s.m64r + (size_t)si * B8;
+        const double* Mj = s.m64r + (size_t)sj * B8;
+        double q[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double d = (b + k < B) ? Mi[b + k] - Mj[b + k] : 0.0;
+            q[k] = d * d;
+        }
+        t0 = (q[0] + q[1]) + (q[2] + q[3]);
+        const int n_i = s.npix[si], n_j = s.npix[sj];
+        const double dni = (double)n_i, dnj = (double)n_j;
+        fac = (dni * dnj) / (double)(n_i + n_j);
+    }
+    for (int o = 1; o < L; o <<= 1) t0 = t0 + __shfl_xor(t0, o);
+    return fac * t0;
+}
+
 // One pair per lane, for many pairs at once (defined with the row tasks' counter).
 __device__ __noinline__ double exact_lane(const SecDev& s, int si, int sj);
 
@@ -1028,11 +1054,12 @@ __device__ void rowcache_begin(Smem& sh, const SecDev& s, int R, int E, bool mat
         const int b = x / R, i = x - b * R;
         const double v = s.sums[(size_t)i * B + b];
         const double m = sam ? v : v / (double)s.npix[i];
-        s.m64[(size_t)b * kc + i] = m;
+        if (!mat) s.m64[(size_t)b * kc + i] = m;  // the exact row tasks' columns (the matrix has its own)
         s.m64r[(size_t)i * B8 + b] = m;
         if (mat) s.mean[(size_t)i * s.Bp + b] = (float)m;
     }
     if (mat) {
+        for (int i = threadIdx.x; i < R; i += NT) s.msl[i] = i;  // matrix row of each slot
         for (int x = threadIdx.x; x < R * (s.Bp - B); x += NT) {
             const int i = x / (s.Bp - B), b = B + x % (s.Bp - B);
             s.mean[(size_t)i * s.Bp + b] = 0.0f;
@@ -1175,15 +1202,16 @@ __device__ __forceinline__ float2 mat_entry(double c) {
 
 // Ward's update on bounds: e_a, e_b the bounds of D(k, a), D(k, b); [d_lo, d_hi]
 // those of D(a, b); na, nb, nk the pixel counts before the merge. Each FP64
-// operation errs by at most 2^-53 of its result, and every intermediate is
-// at most t (the sum of the absolute terms over the denominator) in
-// magnitude, so widening by 2^-48 t covers them all.
+// operation errs by at most 2^-53 of its result; scaled by the reciprocal of
+// the denominator every intermediate is at most t (the sum of the absolute
+// terms over the denominator) in magnitude, so widening by 2^-48 t covers
+// the few roundings of each bound.
 __device__ __forceinline__ float2 mat_update(float2 e_a, float2 e_b, double d_lo, double d_hi, double na, double nb,
                                              double nk) {
-    const double ca = na + nk, cb = nb + nk, den = na + nb + nk;
-    const double lo = (ca * (double)e_a.x + cb * (double)e_b.x - nk * d_hi) / den;
-    const double hi = (ca * (double)e_a.y + cb * (double)e_b.y - nk * d_lo) / den;
-    const double t = (ca * (double)e_a.y + cb * (double)e_b.y + nk * d_hi) / den;
+    const double ca = na + nk, cb = nb + nk, inv = 1.0 / (na + nb + nk);
+    const double lo = (ca * (double)e_a.x + cb * (double)e_b.x - nk * d_hi) * inv;
+    const double hi = (ca * (double)e_a.y + cb * (double)e_b.y - nk * d_lo) * inv;
+    const double t = (ca * (double)e_a.y + cb * (double)e_b.y + nk * d_hi) * inv;
     const double slack = t * 0x1p-48;
     return make_float2(__double2float_rd(fmax(lo - slack, 0.0)), __double2float_ru(hi + slack));
 }
@@ -1373,12 +1401,13 @@ __device__ int row_matrix_task(RowMatLds& L, const SecDev& s, int R, int q, bool
     const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
     const size_t rc = (size_t)s.rcap;
     const int i = all ? q : s.rpend[q];
-    const float2* Di = s.dmat + (size_t)i * rc;
+    const int mi = s.msl[i];
+    const float2* Di = s.dmat + (size_t)mi * rc;
     const int nx = (R + NT - 1) / NT;  // bounds per thread
     double m1 = __builtin_huge_val(), m2 = __builtin_huge_val();
     for (int x = 0; x < nx; ++x) {
         const int j = x * NT + tid;
-        if (j < R && j != i) least_two(m1, m2, (double)Di[j].y * (1.0 + MAT_REL), __builtin_huge_val());
+        if (j < R && j != i) least_two(m1, m2, (double)Di[s.msl[j]].y * (1.0 + MAT_REL), __builtin_huge_val());
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) least_two(m1, m2, __shfl_xor(m1, o), __shfl_xor(m2, o));
@@ -1403,7 +1432,7 @@ __device__ int row_matrix_task(RowMatLds& L, const SecDev& s, int R, int q, bool
             // the round takes slots until it could overflow (NT per slot)
             if (L.ncand + NT > MAT_CAND) break;  // block-uniform: read after a barrier
             const int j = x * NT + tid;
-            const float2 e = (j < R && j != i) ? Di[j] : make_float2(__builtin_huge_valf(), __builtin_huge_valf());
+            const float2 e = (j < R && j != i) ? Di[s.msl[j]] : make_float2(__builtin_huge_valf(), __builtin_huge_valf());
             const bool cand = j < R && j != i && (double)e.x * (1.0 - MAT_REL) <= T;
             if (cand) {
                 if (e.y == 0.0f) {
@@ -1421,8 +1450,9 @@ __device__ int row_matrix_task(RowMatLds& L, const SecDev& s, int R, int q, bool
             if (lane == 0) {
                 L.val[k] = v;
                 const float2 me = mat_entry(v);
-                s.dmat[(size_t)i * rc + j] = me;
-                s.dmat[(size_t)j * rc + i] = me;
+                const int mj = s.msl[j];
+                s.dmat[(size_t)mi * rc + mj] = me;
+                s.dmat[(size_t)mj * rc + mi] = me;
             }
         }
         __syncthreads();
@@ -1709,7 +1739,7 @@ __device__ KeyD spectral_min_rows(Smem& sh, const SecDev& s, int R, int np, bool
 // screens: keep the FP32 mean row and its norm bound current (the screened
 // and plain forms read them; the incremental form does not).
 __device__ void merge_stats(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int kind, double d2, int g_ready,
-                            int prec, int rc, bool screens) {
+                            int prec, int rc, bool screens, bool mat) {
     const int tid = threadIdx.x;
     const int B = s.B, Bp = s.Bp;
     const int lo_l = s.label[lo_s], hi_l = s.label[hi_s];
@@ -1724,7 +1754,7 @@ __device__ void merge_stats(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R
         Slo[b] = v;
         if (rc) {
             const double m = s.crit == HSWO_CRIT_SAM ? v : v / dn;
-            s.m64[(size_t)b * s.rcap + lo_s] = m;
+            if (!mat) s.m64[(size_t)b * s.rcap + lo_s] = m;
             s.m64r[(size_t)lo_s * ((B + 7) & ~7) + b] = m;
         }
         if (screens) {
@@ -1830,9 +1860,8 @@ __device__ void merge_edges_full(Smem& sh, const SecDev& s, int lo_s, int hi_s, 
 // the decision kernel into scratch.
 // mat: the row cache keeps the interval matrix (rc == 2); d2 is the merged
 // pair's canonical value. The survivor's bounds row comes from Ward's update
-// of rows lo_s and hi_s (into the dtmp scratch first, with the row of the
-// slot that moves, since both are rewritten in place), then rows and columns
-// surv and hi_s are written.
+// of its and the merged region's matrix rows; matrix rows are indexed
+// through msl, so moving a slot moves no matrix entry.
 __device__ __noinline__ void merge_slots(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int g_ready, int rc,
                                          bool screens, bool mat, double d2) {
     const int tid = threadIdx.x;
@@ -1840,38 +1869,28 @@ __device__ __noinline__ void merge_slots(Smem& sh, const SecDev& s, int lo_s, in
     const int last = R - 1;
     const int surv = (lo_s == last) ? hi_s : lo_s;
     if (mat && rc == 2) {
+        // the survivor keeps matrix row ml (its row and column rewritten in place: every thread
+        // reads and writes its own entries of row ml, and no column it writes is read); row mh
+        // is dropped, and the slot that moves takes its matrix row along (below)
         const size_t rcp = (size_t)s.rcap;
-        const bool moved = last != lo_s && last != hi_s;
         const float2 de = mat_entry(d2);
         const double n_hi = (double)s.npix[hi_s];
         const double n_lo = (double)s.npix[lo_s] - n_hi;  // merge_stats has added n_hi to the survivor
-        const float2* Dlo = s.dmat + (size_t)lo_s * rcp;
-        const float2* Dhi = s.dmat + (size_t)hi_s * rcp;
-        const float2* Dla = s.dmat + (size_t)last * rcp;
+        const int ml = s.msl[lo_s], mh = s.msl[hi_s];
+        float2* Dl = s.dmat + (size_t)ml * rcp;
+        const float2* Dh = s.dmat + (size_t)mh * rcp;
         for (int k = tid; k < R; k += NT) {
             if (k == lo_s || k == hi_s) continue;
-            s.dtmp[k] = mat_update(Dlo[k], Dhi[k], (double)de.x, (double)de.y, n_lo, n_hi, (double)s.npix[k]);
-            if (moved) s.dtmp[rcp + k] = Dla[k];
+            const int mk = s.msl[k];
+            const float2 v = mat_update(Dl[mk], Dh[mk], (double)de.x, (double)de.y, n_lo, n_hi, (double)s.npix[k]);
+            Dl[mk] = v;
+            s.dmat[(size_t)mk * rcp + ml] = v;
         }
-        __syncthreads();
-        const float2 inf2 = make_float2(__builtin_huge_valf(), __builtin_huge_valf());
-        for (int k = tid; k < R; k += NT) {
-            if (k == lo_s || k == hi_s) continue;
-            const int nk = (k == last) ? hi_s : k;
-            const float2 v = s.dtmp[k];
-            s.dmat[(size_t)surv * rcp + nk] = v;
-            s.dmat[(size_t)nk * rcp + surv] = v;
-            if (moved && k != last) {
-                const float2 m = s.dtmp[rcp + k];
-                s.dmat[(size_t)hi_s * rcp + nk] = m;
-                s.dmat[(size_t)nk * rcp + hi_s] = m;
-            }
-        }
+        __syncthreads();  // every read of npix and msl above is done before the slot moves below
         if (tid == 0) {
-            s.dmat[(size_t)surv * rcp + surv] = inf2;
-            if (moved) s.dmat[(size_t)hi_s * rcp + hi_s] = inf2;
+            if (lo_s == last) s.msl[hi_s] = ml;          // the survivor moves into hi_s
+            else if (hi_s != last) s.msl[hi_s] = s.msl[last];
         }
-        __syncthreads();  // every read of npix above is done before the slot moves below
     }
     if (hi_s != last) {
         const double* Ssrc = s.sums + (size_t)last * B;
@@ -1891,7 +1910,7 @@ __device__ __noinline__ void merge_slots(Smem& sh, const SecDev& s, int lo_s, in
         if (rc) {
             const size_t kc = (size_t)s.rcap, B8 = (size_t)((B + 7) & ~7);
             for (int b = tid; b < B; b += NT) {
-                s.m64[(size_t)b * kc + hi_s] = s.m64[(size_t)b * kc + last];
+                if (!mat) s.m64[(size_t)b * kc + hi_s] = s.m64[(size_t)b * kc + last];
                 s.m64r[(size_t)hi_s * B8 + b] = s.m64r[(size_t)last * B8 + b];
             }
             if (s.crit == HSWO_CRIT_SAM && tid == 0) s.rq[hi_s] = s.rq[last];
@@ -1915,16 +1934,20 @@ __device__ __noinline__ void merge_slots(Smem& sh, const SecDev& s, int lo_s, in
             const int p = s.rbp[i];
             // the second bound follows a moved partner; when its partner is merged it stays as a
             // bare bound (-3) by default only if its value is 0 (identical spectra, where the
-            // merged region usually ties again), else it is dropped
-            const int p2 = s.rbp2[i];
-            int np2 = p2 == last ? hi_s : p2;
-            if (p2 == lo_s || p2 == hi_s)  // the value is read only here
-                np2 = (s.bare == 2 || (s.bare == 1 && s.rbd2[i] == 0.0)) ? -3 : -1;
-            if (ni != i) {
-                s.rbd2[ni] = s.rbd2[i];
-                s.rbl2[ni] = s.rbl2[i];
+            // merged region usually ties again), else it is dropped (the interval matrix keeps
+            // no second bounds)
+            int np2 = -1;
+            if (!mat) {
+                const int p2 = s.rbp2[i];
+                np2 = p2 == last ? hi_s : p2;
+                if (p2 == lo_s || p2 == hi_s)  // the value is read only here
+                    np2 = (s.bare == 2 || (s.bare == 1 && s.rbd2[i] == 0.0)) ? -3 : -1;
+                if (ni != i) {
+                    s.rbd2[ni] = s.rbd2[i];
+                    s.rbl2[ni] = s.rbl2[i];
+                }
+                if (ni != i || np2 != p2) s.rbp2[ni] = np2;
             }
-            if (ni != i || np2 != p2) s.rbp2[ni] = np2;
             if (p == lo_s || p == hi_s) {
                 // stale: a light step (marked -2) when it has a second bound, else a full evaluation
                 // (with the interval matrix always the rescan of its bounds row)
@@ -1961,7 +1984,7 @@ __device__ __noinline__ void merge_slots(Smem& sh, const SecDev& s, int lo_s, in
 // maintained, 2 rows maintained).
 __device__ __forceinline__ void merge_pair(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int& E, int stamp,
                            int kind, double d2, int g_ready, int prec, int rc) {
-    merge_stats(sh, s, lo_s, hi_s, R, kind, d2, g_ready, prec, rc, true);
+    merge_stats(sh, s, lo_s, hi_s, R, kind, d2, g_ready, prec, rc, true, false);
     const bool inc = s.ed2 != nullptr && s.st[5] != 0;
     merge_edges_full(sh, s, lo_s, hi_s, R, E, stamp, inc);
     merge_slots(sh, s, lo_s, hi_s, R, g_ready, rc, true, false, 0.0);
@@ -2180,7 +2203,7 @@ template <int U>
 __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int& E, int stamp, int kind,
                                double d2, int rc, KeyD& anext, int& nchk, bool mat, int eidx_min) {
     const int tid = threadIdx.x;
-    merge_stats(sh, s, lo_s, hi_s, R, kind, d2, 0, 0, rc, false);
+    merge_stats(sh, s, lo_s, hi_s, R, kind, d2, 0, 0, rc, false, mat);
     const int last = R - 1;
     const int surv = (lo_s == last) ? hi_s : lo_s;
     int* L = sh.u.f.cand;
@@ -2368,6 +2391,9 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
     const int emptied = sh.bcast_i[3];
     const int l_surv = s.label[surv];
     const int Ls = nk > LANE_PAIRS_MIN ? -1 : seg_lanes(s.B);
+    // with the row cache running the FP64 means of every live slot are current (the survivor's
+    // written above): Equation 1 from them, without a division per band
+    const bool means = rc != 0 && s.crit == HSWO_CRIT_BSMSE;
     if (Ls < 0) {
         // a survivor of high degree: one re-scored edge per lane
         for (int q0 = 0; q0 < nk; q0 += NT) {  // block-uniform trip count
@@ -2445,7 +2471,7 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
                     lb = l_surv;
                 }
             }
-            const double v = exact_seg(s, a, b, Ls);
+            const double v = means ? exact_seg_means(s, a, b, Ls) : exact_seg(s, a, b, Ls);
             if (q < nk) {
                 KeyD kk;
                 kk.d2 = v;

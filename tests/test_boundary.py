@@ -197,13 +197,13 @@ def test_spectral_angle_needs_the_incremental_form(kw):
 
 def test_spectral_angle_workspace_holds_norms_instead_of_the_interval_matrix():
     # row cache of spclust_max = 256 slots: Equation 1 keeps the interval matrix (FP32 bounds, 8 bytes
-    # per pair of slots) and its update scratch (16 bytes per slot); the spectral angle each slot's
-    # squared norm (8 bytes per slot) instead
+    # per pair of slots, and a 4-byte matrix row per slot); the spectral angle each slot's squared
+    # norm (8 bytes per slot) instead
     q = hswo.make_params(**BASE, incremental=True)
     p = hswo.make_params(**BASE, incremental=True, criterion="sam")
     a, b = hswo.workspace_bytes(64, 64, 32, 0, q), hswo.workspace_bytes(64, 64, 32, 0, p)
     assert 0 < b < a
-    assert abs((a - b) - (256 * 256 * 8 + 256 * 16 - 256 * 8)) <= 512
+    assert abs((a - b) - (256 * 256 * 8 + 256 * 4 - 256 * 8)) <= 512
 
 
 @pytest.mark.parametrize("kw", [dict(), dict(precision="fp16"), dict(sequential=True)])
@@ -215,12 +215,12 @@ def test_two_merges_need_the_incremental_form(kw):
     assert rc == hswo.HSWO_E_UNSUPPORTED
     assert "TWO_MERGES" in hswo.last_error()
     # the two-merge reading keeps the row cache's adjacency bitmap (rcap^2 bits) instead of the
-    # interval matrix (8 bytes per pair of slots) and its scratch
+    # interval matrix (8 bytes per pair of slots and 4 per slot)
     q = hswo.make_params(**BASE, two_merges=True, incremental=True)
     r = hswo.make_params(**BASE, incremental=True)
     a, b = hswo.workspace_bytes(64, 64, 8, 0, q), hswo.workspace_bytes(64, 64, 8, 0, r)
     assert 0 < a < b
-    assert abs((b - a) - (256 * 256 * 8 + 256 * 16 - 256 * 8 * 4)) <= 512
+    assert abs((b - a) - (256 * 256 * 8 + 256 * 4 - 256 * 8 * 4)) <= 512
 
 
 def test_verify_bound_flag_checked():
