@@ -23,6 +23,7 @@
 #include <limits>
 #include <map>
 #include <mutex>
+#include <set>
 #include <thread>
 #include <vector>
 
@@ -155,6 +156,10 @@ class Pass {
             run_two_merges(log, R);
             return;
         }
+        if (p_.multi_merge) {
+            run_multi_merge(log, R);
+            return;
+        }
         while (R > stop_) {
             const bool spectral = spectral_at(R);
             Key A, N = KEY_NONE;
@@ -166,20 +171,9 @@ class Pass {
                 A = cached_adjacent();
                 if (spectral) N = cached_nonadjacent();
             }
-            /* Step 3 of the HSEG loop: the non-adjacent pair is merged when it
-               is smaller than the (weighted) adjacent minimum; one merge per
-               iteration. */
             Key win;
             int kind;
-            if (spectral && key_exists(N) && (!key_exists(A) || N.d2 < w2_ * A.d2)) {
-                win = N;
-                kind = 1;
-            } else if (key_exists(A)) {
-                win = A;
-                kind = 0;
-            } else {
-                break;
-            }
+            if (!winner(spectral, A, N, win, kind)) break;
             merge(win.lo, win.hi);
             --R;
             log.push_back({win.lo, win.hi, kind, R, win.d2});
@@ -188,6 +182,21 @@ class Pass {
     }
 
   private:
+    /* Step 3 of the HSEG loop: the non-adjacent pair is merged when it is
+       smaller than the (weighted) adjacent minimum, else the adjacent pair;
+       false when there is no pair at all. */
+    bool winner(bool spectral, const Key& A, const Key& N, Key& win, int& kind) const {
+        if (spectral && key_exists(N) && (!key_exists(A) || N.d2 < w2_ * A.d2)) {
+            win = N;
+            kind = 1;
+        } else if (key_exists(A)) {
+            win = A;
+            kind = 0;
+        } else {
+            return false;
+        }
+        return true;
+    }
     bool spectral_at(int R) const { return p_.spclust_wght > 0.0f && R <= p_.spclust_max; }
     Key adjacent_min() { return p_.brute ? brute_adjacent() : cached_adjacent(); }
     Key nonadjacent_min() {
@@ -225,6 +234,66 @@ class Pass {
             if (key_exists(N) && A.d2 * w2_ > N.d2) record(N, 1, R, log);  // strict, as in one-merge mode
         }
     }
+
+    /* Several merges per step, the future-work item of Section 6.2 read for
+       identical regions. A step starts like a one-merge iteration: the
+       adjacent minimum A, the non-adjacent minimum N when the spectral stage
+       is on, and the one-merge rule's winner. A winner above 0 is the step's
+       only merge. A winner of value 0 opens a step of several merges: the
+       zero-valued pairs are ranked the way the one-merge rule ranks them at
+       that moment -- adjacent pairs first, by (lo, hi), then (spectral stage
+       on) non-adjacent pairs, by (lo, hi) -- and taken greedily, a pair being
+       skipped when one of its regions is already taken. The taken pairs are
+       disjoint, so merging them one after another in that order changes
+       neither the value nor the adjacency of a pair still to come; the step
+       stops early at the pass's stop count. Its first merge is the winner. */
+    void run_multi_merge(std::vector<oracle_merge>& log, int R) {
+        while (R > stop_) {
+            const bool spectral = spectral_at(R);
+            if (!p_.brute && spectral && !dense_on_) init_dense();
+            const Key A = adjacent_min();
+            const Key N = spectral ? nonadjacent_min() : KEY_NONE;
+            Key win;
+            int kind;
+            if (!winner(spectral, A, N, win, kind)) break;
+            if (win.d2 != 0.0) {
+                record(win, kind, R, log);
+                continue;
+            }
+            std::vector<Key> za, zn;
+            for (int i : live_)
+                for (auto& kv : st_.adj[i])
+                    if (i < kv.first && value_of(i, kv.first, kv.second) == 0.0) za.push_back(key(i, kv.first, 0.0));
+            if (spectral)
+                for (size_t a = 0; a < live_.size(); ++a)
+                    for (size_t b = a + 1; b < live_.size(); ++b) {
+                        const int i = live_[a], j = live_[b];
+                        if (st_.adj[i].count(j)) continue;
+                        if (nonadjacent_value(i, j) == 0.0) zn.push_back(key(i, j, 0.0));
+                    }
+            std::sort(za.begin(), za.end(), key_less);
+            std::sort(zn.begin(), zn.end(), key_less);
+            std::vector<std::pair<Key, int>> take;
+            std::set<int> used;  /* labels taken in this step */
+            for (int pass = 0; pass < 2; ++pass)
+                for (const Key& k : pass == 0 ? za : zn)
+                    if (!used.count(k.lo) && !used.count(k.hi)) {
+                        used.insert(k.lo);
+                        used.insert(k.hi);
+                        take.push_back({k, pass});
+                    }
+            for (size_t t = 0; t < take.size() && R > stop_; ++t) {
+                const Key& k = take[t].first;
+                merge(k.lo, k.hi);
+                --R;
+                log.push_back({k.lo, k.hi, take[t].second + (t ? 2 : 0), R, k.d2});
+                if (top_) snapshot_if_level(R);
+            }
+        }
+    }
+    /* the value of an adjacent pair: recomputed (brute) or the cached one */
+    double value_of(int i, int j, double cached) { return p_.brute ? d2(i, j) : cached; }
+    double nonadjacent_value(int i, int j) { return p_.brute ? d2(i, j) : Dat(didx_[i], didx_[j]); }
 
     double d2(int a, int b) {
         const int lo = std::min(a, b), hi = std::max(a, b);
@@ -477,6 +546,7 @@ extern "C" int oracle_rhseg(const float* cube, int32_t H, int32_t W, int32_t B, 
     if (p->seam_connectivity != 4 && p->seam_connectivity != 8) return -1;
     if (!(p->spclust_wght >= 0.0f && p->spclust_wght <= 1.0f)) return -1;
     if (p->criterion != ORACLE_CRIT_BSMSE && p->criterion != ORACLE_CRIT_SAM) return -1;
+    if (p->multi_merge && (p->two_merges || p->criterion != ORACLE_CRIT_BSMSE)) return -1;
     if (p->target_regions < 1 || p->rnb_levels < 1 || p->rnb_levels > 16) return -1;
     if ((H >> (p->rnb_levels - 1)) < 1 || (W >> (p->rnb_levels - 1)) < 1) return -1;
     if (p->n_levels < 1 || !p->level_counts) return -1;

@@ -58,6 +58,13 @@ typedef struct oracle_params {
     int32_t two_merges;         /* 1: each iteration merges the best adjacent pair (step 2), then the
                                    best non-adjacent pair of the result if it is below w^2 times the
                                    first merge's value (step 3); 0: one merge per iteration */
+    int32_t multi_merge;        /* 1: several merges per step for identical regions: a step whose
+                                   one-merge winner has the value 0 merges every pair of a greedy
+                                   disjoint set of zero-valued pairs, taken in the one-merge rule's
+                                   order (adjacent pairs by (lo, hi), then, with the spectral stage
+                                   on at the step's start, non-adjacent pairs by (lo, hi)), until the
+                                   pass's stop count; later merges of a step carry kind + 2 in the
+                                   log. Equation 1 only, not with two_merges */
     /* optional: called after each section of a recursion level has finished
        (depth 0 = the whole image), with how many of that level's sections are
        done; calls are serialised. Reports progress only. */
@@ -69,7 +76,8 @@ typedef struct oracle_params {
 
 typedef struct oracle_merge {
     int32_t lo, hi;     /* region labels, lo < hi; lo survives */
-    int32_t kind;       /* 0 adjacent, 1 non-adjacent (spectral) */
+    int32_t kind;       /* 0 adjacent, 1 non-adjacent (spectral); + 2 for the second and later
+                           merges of one step (multi_merge) */
     int32_t r_after;    /* live regions in the section after this merge */
     double d2;          /* canonical FP64 squared criterion */
 } oracle_merge;

@@ -31,6 +31,7 @@ class _Params(ctypes.Structure):
         ("n_threads", ctypes.c_int32),
         ("criterion", ctypes.c_int32),
         ("two_merges", ctypes.c_int32),
+        ("multi_merge", ctypes.c_int32),
         ("progress", ctypes.c_void_p),
     ]
 
@@ -130,7 +131,8 @@ def rhseg(cube: np.ndarray, *, connectivity: int = 4, seam_connectivity: int = 8
           section_regions: int = 0, rnb_levels: int = 1,
           level_counts: Optional[Sequence[int]] = None, brute: bool = False,
           n_threads: Optional[int] = None, lib: Optional[str] = None, criterion: str = "bsmse",
-          two_merges: bool = False, progress: Optional[str] = None, **_ignored) -> OracleResult:
+          two_merges: bool = False, multi_merge: bool = False, progress: Optional[str] = None,
+          **_ignored) -> OracleResult:
     """Run the oracle on a host H x W x B cube (float32, or float16 widened exactly).
     progress: a tag; when given, a line is printed as the sections of each
     recursion level finish."""
@@ -156,6 +158,7 @@ def rhseg(cube: np.ndarray, *, connectivity: int = 4, seam_connectivity: int = 8
     p.n_threads = n_threads if n_threads is not None else (os.cpu_count() or 1)
     p.criterion = CRITERIA[criterion]
     p.two_merges = 1 if two_merges else 0
+    p.multi_merge = 1 if multi_merge else 0
     cb = _progress_printer(progress) if progress else None
     p.progress = ctypes.cast(cb, ctypes.c_void_p) if cb is not None else None
     labels = np.full((len(lc), H, W), -1, dtype=np.int32)

@@ -20,6 +20,15 @@ exact; otherwise dot product and squared norms as pairwise trees).
 ``two_merges=True`` reads the step list with two merges per iteration: the
 best adjacent pair, then the best non-adjacent pair of the resulting
 partition if it is below w^2 times the first merge's value.
+``multi_merge=True`` merges identical regions several at a time (the
+future-work item of Section 6.2): when a step's one-merge winner has the
+value 0, the step merges a greedy disjoint set of the zero-valued pairs, in
+the order adjacent pairs by (lo, hi) then (spectral stage on at the step's
+start) non-adjacent pairs by (lo, hi), one after another until the stop
+count; its later merges are logged with kind + 2. Here the zero pairs are
+found by re-deriving regions and adjacency before every merge of the step
+and taking the least eligible zero pair whose regions the step has not
+touched yet, rather than from one ranked list.
 """
 from __future__ import annotations
 
@@ -107,7 +116,8 @@ def _criterion(xs_i, xs_j, exact, crit="bsmse"):
     return fac * acc
 
 
-def _hseg_pass(cube, lab, rect, leaf, conn, seam, w, kmax, stop, log, snaps, counts, top, crit, two=False):
+def _hseg_pass(cube, lab, rect, leaf, conn, seam, w, kmax, stop, log, snaps, counts, top, crit, two=False,
+               multi=False):
     r0, c0, h, wd = rect
     H = len(cube)
     W = len(cube[0])
@@ -194,7 +204,51 @@ def _hseg_pass(cube, lab, rect, leaf, conn, seam, w, kmax, stop, log, snaps, cou
         if N is not None and below(N, A):
             apply(N, 1)
             R -= 1
-    while not two and R > stop:
+    while multi and R > stop:
+        spectral = w > 0 and R <= kmax
+        A, N = best_pairs(spectral)
+        if spectral and N is not None and (A is None or below(N, A)):
+            win, kind = N, 1
+        elif A is not None:
+            win, kind = A, 0
+        else:
+            break
+        if win[0] != 0:
+            apply(win, kind)
+            R -= 1
+            continue
+        # a step of several merges: each time the least zero-valued pair (adjacent ones first,
+        # non-adjacent ones only with the spectral stage on at the step's start) whose two regions
+        # no merge of this step has touched
+        touched = set()
+        first = True
+        while R > stop:
+            reg = regions()
+            adj = adjacency()
+            labels = sorted(l for l in reg if l not in touched)
+            pick = None
+            for want_adj in (True, False):
+                if not want_adj and not spectral:
+                    break
+                for i_idx, i in enumerate(labels):
+                    for j in labels[i_idx + 1:]:
+                        if ((i, j) in adj) != want_adj:
+                            continue
+                        if _criterion(reg[i], reg[j], log.exact, crit) == 0:
+                            pick = (0.0 if not log.exact else Fraction(0), i, j)
+                            break
+                    if pick is not None:
+                        break
+                if pick is not None:
+                    k = 0 if want_adj else 1
+                    break
+            if pick is None:
+                break
+            apply(pick, k + (0 if first else 2))
+            R -= 1
+            first = False
+            touched.update(pick[1:])
+    while not two and not multi and R > stop:
         reg = regions()
         adj = adjacency()
         labels = sorted(reg)
@@ -236,7 +290,7 @@ class _Log(list):
 
 def rhseg(cube, *, connectivity=4, seam_connectivity=8, spclust_wght=0.0, spclust_max=0,
           target_regions=1, section_regions=0, rnb_levels=1, level_counts=None, exact=False, criterion="bsmse",
-          two_merges=False, **_):
+          two_merges=False, multi_merge=False, **_):
     """cube: nested lists or an array H x W x B. Returns (labels per level, log)."""
     cube = [[[float(v) for v in px] for px in row] for row in (cube.tolist() if hasattr(cube, "tolist") else cube)]
     H, W = len(cube), len(cube[0])
@@ -255,5 +309,6 @@ def rhseg(cube, *, connectivity=4, seam_connectivity=8, spclust_wght=0.0, spclus
         top = d == 0
         for rect in levels[d]:
             _hseg_pass(cube, lab, rect, leaf, connectivity, seam_connectivity, spclust_wght,
-                       spclust_max, target_regions if top else S, log, snaps, counts, top, criterion, two_merges)
+                       spclust_max, target_regions if top else S, log, snaps, counts, top, criterion, two_merges,
+                       multi_merge)
     return snaps, list(log)

@@ -63,6 +63,50 @@ TWO_MERGE_MUTANTS = {
 }
 
 
+MULTI_MERGE_MUTANTS = {
+    "multi_taken_not_marked": ("                        used.insert(k.lo);\n                        used.insert(k.hi);\n",
+                               "                        used.insert(k.lo);\n"),
+    "multi_nonadjacent_first": ("for (const Key& k : pass == 0 ? za : zn)", "for (const Key& k : pass == 0 ? zn : za)"),
+    "multi_no_stop_check": ("t < take.size() && R > stop_; ++t", "t < take.size(); ++t"),
+    "multi_no_continuation_kind": ("take[t].second + (t ? 2 : 0)", "take[t].second"),
+    "multi_spectral_storms_one_at_a_time": ("            if (win.d2 != 0.0) {\n                record(win, kind, R, log);",
+                                            "            if (win.d2 != 0.0 || kind == 1) {\n                record(win, kind, R, log);"),
+    "multi_nonadjacent_without_spectral": ("            if (spectral)\n                for (size_t a = 0;",
+                                           "            if (true)\n                for (size_t a = 0;"),
+}
+
+
+def _run_multi_merge_pins(lib):
+    """The multi-merge pins in compact form; returns the first that fails."""
+    from tests import test_oracle_multi_merge as tm
+    for vals, want in ((tm.STRIP_A, [(0, 1, 0, 5), (4, 5, 2, 4), (0, 2, 0, 3), (0, 4, 1, 2), (0, 3, 0, 1)]),
+                       (tm.STRIP_B, [(0, 2, 1, 6), (1, 3, 3, 5), (4, 6, 3, 4), (0, 4, 1, 3), (1, 5, 3, 2),
+                                     (0, 1, 0, 1)])):
+        res = oracle.rhseg(tm.strip(vals), connectivity=4, spclust_wght=0.5, spclust_max=10, target_regions=1,
+                           level_counts=[1], multi_merge=True, lib=lib)
+        if [g[:4] for g in tm.recs(res)] != want:
+            return "hand strips"
+    res = oracle.rhseg(tm.strip(tm.STRIP_A), connectivity=4, spclust_wght=0.5, spclust_max=10, target_regions=5,
+                       level_counts=[5], multi_merge=True, lib=lib)
+    if [g[:4] for g in tm.recs(res)] != [(0, 1, 0, 5)]:
+        return "hand strip stop count"
+    for t in range(10):
+        p = tm.GRID[t % len(tm.GRID)]
+        H, W = 4 + t % 3, 5 + t % 2
+        cube = tm.tie_cube(H, W, 1 + t % 2, 90 + t)
+        counts = sorted({max(2, H * W // 2), max(2, H * W // 4), 2}, reverse=True)
+        kw = dict(p, target_regions=2, level_counts=counts, multi_merge=True)
+        res = oracle.rhseg(cube, **kw, lib=lib)
+        try:
+            check_partition_levels(res.labels, counts)
+        except AssertionError:
+            return "partition"
+        _, log = pybrute.rhseg(cube, **kw)
+        if tm.recs(res) != [tuple(x) for x in log]:
+            return "python hseg"
+    return None
+
+
 def _run_two_merge_pins(lib):
     """The two-merge pins in compact form; returns the first that fails."""
     from tests import test_oracle_two_merges as t2
@@ -206,3 +250,33 @@ def test_two_merge_pins_reject_mutant(name, tmp_path):
     path.write_text(src.replace(old, new))
     lib = oracle.build(src=str(path), out=str(tmp_path / f"liboracle_{name}.so"))
     assert _run_two_merge_pins(lib) is not None, f"mutant {name} survived every pin"
+
+
+def test_unmutated_oracle_passes_the_multi_merge_pins():
+    assert _run_multi_merge_pins(None) is None
+
+
+@pytest.mark.parametrize("name", sorted(MULTI_MERGE_MUTANTS))
+def test_multi_merge_pins_reject_mutant(name, tmp_path):
+    # some of these mutants merge a region twice, which can leave the oracle's union-find with a
+    # cycle (a hang) or its tables inconsistent (a crash): the pins run in a child process with a
+    # time limit, and a hang or a crash counts as a rejection
+    import subprocess
+    import sys
+    old, new = MULTI_MERGE_MUTANTS[name]
+    src = open(_SRC).read()
+    assert src.count(old) == 1, f"mutation site for {name} not found exactly once"
+    path = tmp_path / "mutant.cpp"
+    path.write_text(src.replace(old, new))
+    lib = oracle.build(src=str(path), out=str(tmp_path / f"liboracle_{name}.so"))
+    code = ("import sys; from tests.test_oracle_mutants import _run_multi_merge_pins as f; "
+            "print('PINS', f(sys.argv[1]))")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    try:
+        out = subprocess.run([sys.executable, "-c", code, lib], cwd=root, capture_output=True, text=True,
+                             timeout=30)
+    except subprocess.TimeoutExpired:
+        return  # hung: rejected
+    if out.returncode != 0:
+        return  # crashed: rejected
+    assert "PINS None" not in out.stdout, f"mutant {name} survived every pin"
