@@ -137,6 +137,16 @@ extern "C" {
                                     reached -- the least NON-adjacent pair of the resulting partition
                                     if its D2 < w^2 * D2 of step 2's pair (step 3). Changes the result.
                                     HSWO_FLAG_INCREMENTAL form only (else HSWO_E_UNSUPPORTED). */
+#define HSWO_FLAG_MULTI_MERGE 256 /* several merges per step for identical regions (Section 6.2): a
+                                     step whose winner has the value 0 merges a greedy disjoint set
+                                     of zero-valued pairs -- adjacent pairs by (lo, hi), then, with the
+                                     spectral stage on at the step's start, non-adjacent pairs by
+                                     (lo, hi), skipping a pair one of whose regions is taken -- one
+                                     after another until the stop count; other steps merge one pair.
+                                     Later merges of a step carry kind + 2 in the merge log. Changes
+                                     the result. HSWO_FLAG_INCREMENTAL form and Equation 1 only (else
+                                     HSWO_E_UNSUPPORTED), not with HSWO_FLAG_TWO_MERGES (HSWO_E_INVAL);
+                                     every level runs in the persistent section driver. */
 #define HSWO_FLAG_AUTOTUNE 4  /* on the first call for a shape bucket, time candidate execution
                                  settings (hswo_tuning: workgroups per section, which levels run
                                  persistent, the row-stage grid and interval matrix, the
@@ -217,7 +227,8 @@ typedef struct hswo_params {
 
 typedef struct hswo_merge_rec {
     int32_t lo, hi;   /* labels of the merged regions, lo < hi; lo survives */
-    int32_t kind;     /* 0 adjacent (spatial stage), 1 non-adjacent (spectral stage) */
+    int32_t kind;     /* 0 adjacent (spatial stage), 1 non-adjacent (spectral stage); + 2 for the
+                         second and later merges of one step (HSWO_FLAG_MULTI_MERGE) */
     int32_t r_after;  /* live regions in the section after the merge */
     double d2;        /* the canonical FP64 squared criterion of the merge */
 } hswo_merge_rec;     /* 24 bytes */

@@ -109,6 +109,13 @@ int validate_params(const hswo_params* p, int rnb_levels_expected) {
         return fail(HSWO_E_INVAL, "unknown criterion %d", p->criterion);
     if ((p->flags & HSWO_FLAG_TWO_MERGES) && !(p->flags & HSWO_FLAG_INCREMENTAL))
         return fail(HSWO_E_UNSUPPORTED, "HSWO_FLAG_TWO_MERGES is implemented in the HSWO_FLAG_INCREMENTAL form only");
+    if (p->flags & HSWO_FLAG_MULTI_MERGE) {
+        if (!(p->flags & HSWO_FLAG_INCREMENTAL) || p->criterion != HSWO_CRIT_BSMSE)
+            return fail(HSWO_E_UNSUPPORTED,
+                        "HSWO_FLAG_MULTI_MERGE is implemented in the HSWO_FLAG_INCREMENTAL form with Equation 1 only");
+        if (p->flags & HSWO_FLAG_TWO_MERGES)
+            return fail(HSWO_E_INVAL, "HSWO_FLAG_MULTI_MERGE and HSWO_FLAG_TWO_MERGES are different readings");
+    }
     if (p->criterion == HSWO_CRIT_SAM && !(p->flags & HSWO_FLAG_INCREMENTAL))
         return fail(HSWO_E_UNSUPPORTED, "criterion HSWO_CRIT_SAM is implemented in the HSWO_FLAG_INCREMENTAL form only");
     if (p->screen_topk < 0) return fail(HSWO_E_INVAL, "screen_topk must be >= 0");
@@ -142,6 +149,19 @@ struct Bump {
         return p;
     }
 };
+
+// Scratch of the several-merges-per-step reading: sort keys and payloads for
+// up to max(ecap, cap) entries (a power of two), per-slot places and the
+// step's pair list.
+void take_multi(Bump& bp, SecDev& s, int64_t cap, int64_t ecap) {
+    int64_t z = 1;
+    while (z < std::max(cap, ecap)) z <<= 1;
+    s.zcap = (int32_t)z;
+    s.zkey = bp.take<unsigned long long>(z);
+    s.zval = bp.take<unsigned long long>(z);
+    s.zuse = bp.take<int32_t>(cap);
+    s.zlist = bp.take<int4>(cap / 2 + 1);
+}
 
 struct SecPlan {
     Rect rect;
@@ -368,6 +388,7 @@ Layout carve(const Plan& pl, int H, int W, const hswo_params* p, int bare, void*
                 s.rmax = bp.take<int32_t>(sp.cap);
                 s.cmd2 = bp.take<double>((sp.ecap + ECH - 1) / ECH);
                 s.cme = bp.take<int32_t>((sp.ecap + ECH - 1) / ECH);
+                if (p->flags & HSWO_FLAG_MULTI_MERGE) take_multi(bp, s, sp.cap, sp.ecap);
             }
             s.tstat = bp.take<float2>(sp.tiles);
             s.tflag = bp.take<int32_t>(sp.tiles);
@@ -377,7 +398,7 @@ Layout carve(const Plan& pl, int H, int W, const hswo_params* p, int bare, void*
                 s.m64 = bp.take<double>(rc * pl.B);
                 s.m64r = bp.take<double>(rc * (((int64_t)pl.B + 7) / 8 * 8));
                 if (p->criterion == HSWO_CRIT_SAM) s.rq = bp.take<double>(rc);
-                else if (!(p->flags & HSWO_FLAG_TWO_MERGES) && rc <= MAT_MAX) {
+                else if (!(p->flags & (HSWO_FLAG_TWO_MERGES | HSWO_FLAG_MULTI_MERGE)) && rc <= MAT_MAX) {
                     s.dmat = bp.take<float2>(rc * rc);
                     s.msl = bp.take<int32_t>(rc);
                 }
@@ -526,7 +547,7 @@ int run_level(Timer* tm, const SecDev* secs, int n, const std::vector<int64_t>& 
     LoopParams lp = lp_in;
     lp.row_matrix = 0;
     const int variant = tu.variant;
-    if (n > tu.wide_max || (row_cache && n > ROWS_MAX_SECTIONS))
+    if (n > tu.wide_max || (row_cache && n > ROWS_MAX_SECTIONS) || lp.multi_merge)
         return timed_driver(tm, secs, n, lp, variant, stream);
     lp.row_matrix = (row_cache && mat_ok && tu.row_matrix) ? 1 : 0;
     const int G = std::max(1, std::min(GMAX, tu.wide_wg / n));
@@ -993,6 +1014,7 @@ LoopParams loop_params(const hswo_params* p, unsigned long long* counters) {
     lp.two_merges = (p->flags & HSWO_FLAG_TWO_MERGES) ? 1 : 0;
     lp.topk = p->screen_topk > 0 ? p->screen_topk : 8;
     lp.row_matrix = 0;  // set per level from the resolved tuning
+    lp.multi_merge = (p->flags & HSWO_FLAG_MULTI_MERGE) ? 1 : 0;
     lp.counters = counters;
     return lp;
 }
@@ -1002,7 +1024,7 @@ int check_common(const hswo_params* p, void* workspace) {
     if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(HSWO_E_INVAL, "workspace must be 256-byte aligned");
     if (p->flags & ~(HSWO_FLAG_MERGE_LOG | HSWO_FLAG_GRAPH | HSWO_FLAG_AUTOTUNE | HSWO_FLAG_INCREMENTAL |
                      HSWO_FLAG_KERNEL_TIMES | HSWO_FLAG_SEQUENTIAL_SECTIONS | HSWO_FLAG_TWO_MERGES |
-                     HSWO_FLAG_DEBUG_VERIFY_BOUND))
+                     HSWO_FLAG_DEBUG_VERIFY_BOUND | HSWO_FLAG_MULTI_MERGE))
         return fail(HSWO_E_INVAL, "unknown flags 0x%x", p->flags);
     return HSWO_OK;
 }
@@ -1205,6 +1227,7 @@ BatchLayout carve_batch(int n, const hswo_section* sec, const hswo_params* p, in
             s.rmax = bp.take<int32_t>(cap);
             s.cmd2 = bp.take<double>((ecap + ECH - 1) / ECH);
             s.cme = bp.take<int32_t>((ecap + ECH - 1) / ECH);
+            if (p->flags & HSWO_FLAG_MULTI_MERGE) take_multi(bp, s, cap, ecap);
         }
         s.tstat = bp.take<float2>(tiles);
         s.tflag = bp.take<int32_t>(tiles);

@@ -130,6 +130,12 @@ struct SecDev {
     int32_t* rbl2;   // [rcap] its partner label
     int32_t* rpend;  // [rcap] rows to re-evaluate: [0] the last merge's survivor, then stale rows
     RowPart* rpart;  // [rcap][ceil(rcap / 64)] per-row, per-64-column least two candidates
+    // several merges per step (HSWO_FLAG_MULTI_MERGE, persistent driver): a step's zero-valued pairs
+    unsigned long long* zkey;  // [zcap] sort keys (labels, or a mean-row hash and a label)
+    unsigned long long* zval;  // [zcap] what goes with each key (slots)
+    int32_t* zuse;   // [R0] per slot: taken by the step, then its place in the step's list (-1: none)
+    int4* zlist;     // [R0 / 2 + 1] the step's pairs in merge order: slot of lo, slot of hi, kind
+    int32_t zcap;    // a power of two >= max(Ecap, R0)
     // wide mode iteration scratch
     int32_t* wi;     // [16]
     double* wd;      // [4]
@@ -195,6 +201,7 @@ struct LoopParams {
     int32_t two_merges;   // two-merge reading of the step list (adjacent merge, then non-adjacent merge)
     int32_t topk;         // screened forms: re-check sets larger than this count as fallbacks
     int32_t row_matrix;   // wide mode: keep and rescan the interval matrix (hswo_tuning.row_matrix)
+    int32_t multi_merge;  // several merges per step for identical regions (HSWO_FLAG_MULTI_MERGE)
     unsigned long long* counters;  // [C_COUNT]
 };
 

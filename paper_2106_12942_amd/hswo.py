@@ -35,6 +35,7 @@ HSWO_FLAG_KERNEL_TIMES = 16
 HSWO_FLAG_SEQUENTIAL_SECTIONS = 32
 HSWO_FLAG_TWO_MERGES = 64
 HSWO_FLAG_DEBUG_VERIFY_BOUND = 128
+HSWO_FLAG_MULTI_MERGE = 256
 
 HSWO_CRIT_BSMSE = 0
 HSWO_CRIT_SAM = 1
@@ -208,8 +209,8 @@ def make_tuning(tuning: Optional[dict]) -> Optional[Tuning]:
 def make_params(*, connectivity=4, seam_connectivity=8, spclust_wght=0.0, spclust_max=0, target_regions=1,
                 section_regions=0, rnb_levels=1, level_counts: Optional[Sequence[int]] = None,
                 precision="fp32", merge_log=False, graph=False, autotune=False, incremental=False,
-                kernel_times=False, sequential=False, criterion="bsmse", two_merges=False, screen_topk=0,
-                verify_ptr=None, verify_cap=0, tuning: Optional[dict] = None, **_ignored):
+                kernel_times=False, sequential=False, criterion="bsmse", two_merges=False, multi_merge=False,
+                screen_topk=0, verify_ptr=None, verify_cap=0, tuning: Optional[dict] = None, **_ignored):
     counts = list(level_counts) if level_counts is not None else [target_regions]
     arr = (ctypes.c_int32 * len(counts))(*counts)
     tu = make_tuning(tuning if tuning is not None else DEFAULT_TUNING)
@@ -219,7 +220,8 @@ def make_params(*, connectivity=4, seam_connectivity=8, spclust_wght=0.0, spclus
                (HSWO_FLAG_MERGE_LOG if merge_log else 0) | (HSWO_FLAG_GRAPH if graph else 0) |
                (HSWO_FLAG_AUTOTUNE if autotune else 0) | (HSWO_FLAG_INCREMENTAL if incremental else 0) |
                (HSWO_FLAG_KERNEL_TIMES if kernel_times else 0) | (HSWO_FLAG_SEQUENTIAL_SECTIONS if sequential else 0) |
-               (HSWO_FLAG_TWO_MERGES if two_merges else 0) | (HSWO_FLAG_DEBUG_VERIFY_BOUND if verify_ptr else 0),
+               (HSWO_FLAG_TWO_MERGES if two_merges else 0) | (HSWO_FLAG_DEBUG_VERIFY_BOUND if verify_ptr else 0) |
+               (HSWO_FLAG_MULTI_MERGE if multi_merge else 0),
                CRIT[criterion] if isinstance(criterion, str) else int(criterion),
                int(screen_topk), verify_ptr, int(verify_cap),
                ctypes.pointer(tu) if tu is not None else None)

@@ -150,7 +150,7 @@ def test_graph_flag_needs_a_stream_and_unknown_flags_rejected():
     assert lib.hswo_run(FAKE, 16, 16, 4, 0, ctypes.byref(p), FAKE, None, None, FAKE, nb, None) == hswo.HSWO_E_INVAL
     assert "non-null stream" in hswo.last_error()
     q = hswo.make_params(**BASE)
-    q.flags = 256
+    q.flags = 512
     assert lib.hswo_run(FAKE, 16, 16, 4, 0, ctypes.byref(q), FAKE, None, None, FAKE, nb, None) == hswo.HSWO_E_INVAL
     assert "unknown flags" in hswo.last_error()
 
@@ -273,3 +273,26 @@ def test_edge_capacity_beyond_int32_rejected():
     assert hswo.workspace_bytes(32768, 32768, 1, 0, p2) > 0
     secs = (hswo.Section * 1)(hswo.Section(FAKE, 32768, 32768, 1, FAKE, None))
     assert lib.hswo_run_batch(1, secs, 0, ctypes.byref(p), None, FAKE, 1 << 40, None) == hswo.HSWO_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("kw,code", [(dict(), hswo.HSWO_E_UNSUPPORTED),
+                                     (dict(incremental=True, criterion="sam"), hswo.HSWO_E_UNSUPPORTED),
+                                     (dict(incremental=True, two_merges=True), hswo.HSWO_E_INVAL)])
+def test_multi_merge_form_checked(kw, code):
+    lib = hswo.load()
+    p = hswo.make_params(**BASE, multi_merge=True, **kw)
+    assert hswo.workspace_bytes(16, 16, 4, 0, p) == 0
+    rc = lib.hswo_run(FAKE, 16, 16, 4, 0, ctypes.byref(p), FAKE, None, None, FAKE, 1 << 30, None)
+    assert rc == code
+    assert "MULTI_MERGE" in hswo.last_error()
+
+
+def test_multi_merge_workspace_holds_the_step_scratch_instead_of_the_interval_matrix():
+    # 64 x 64 HSWO: 4096 slots, 8064 edge slots -> sort keys and payloads for 8192 entries
+    # (8 + 8 bytes), a place per slot (4 bytes) and 2049 listed pairs (16 bytes); the interval
+    # matrix of the 256 row-cache slots (8 bytes per pair, 4 per slot) is not kept
+    q = hswo.make_params(**BASE, incremental=True)
+    m = hswo.make_params(**BASE, incremental=True, multi_merge=True)
+    a, b = hswo.workspace_bytes(64, 64, 8, 0, q), hswo.workspace_bytes(64, 64, 8, 0, m)
+    want = 16 * 8192 + 4 * 4096 + 16 * 2049 - (8 * 256 * 256 + 4 * 256)
+    assert abs((b - a) - want) <= 6 * 256
