@@ -670,6 +670,9 @@ def main():
                          "rhseg512)")
     ap.add_argument("--sweep", choices=sorted(SWEEPS),
                     help="instead of the benchmark: GPU vs oracle over one of the paper-style sweeps")
+    ap.add_argument("--no-sweeps", action="store_true",
+                    help="skip the paper-style sweep points (band count, image detail, adjacent-sweep variant) "
+                         "appended to the benchmark line")
     ap.add_argument("--no-kernel-times", action="store_true",
                     help="skip the per-kernel timing step (no roofline object)")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -716,6 +719,13 @@ def main():
                                                               if args.precision != "fp32" else "f32 screen, f64 decisions"),
            "data": "synthetic"}
     out.update(body)
+    if not args.no_sweeps:
+        # the paper-style sweeps (GPU against the oracle, labels compared), small enough to ride along
+        out["sweeps"] = {}
+        for name in ("bands", "detail", "variant"):
+            a = argparse.Namespace(**vars(args))
+            a.sweep = name
+            out["sweeps"][name] = bench_sweep(a, np, torch, hswo, synth)
     print(json.dumps(out))
 
 

@@ -176,7 +176,7 @@ typedef struct hswo_tuning {
                                    merges: 0 none, 1 those of value 0, 2 all; default 1 */
     int32_t driver_variant;     /* adjacent-sweep edges in flight per 16-lane group of the screened
                                    forms: 2, 4 or 6; default 6 */
-    int32_t row_matrix;         /* incremental form, Equation 1, one-merge reading, wide mode: 1 = the
+    int32_t row_matrix;         /* incremental form, Equation 1, one-merge reading: 1 = the
                                    row cache keeps certified FP32 bounds on every pair's value, brought
                                    up to date at each merge by Ward's update (O(R) per merge); a row
                                    whose cached pair went stale is rescanned from its bounds and only

@@ -399,7 +399,10 @@ Layout carve(const Plan& pl, int H, int W, const hswo_params* p, int bare, void*
                 s.m64r = bp.take<double>(rc * (((int64_t)pl.B + 7) / 8 * 8));
                 if (p->criterion == HSWO_CRIT_SAM) s.rq = bp.take<double>(rc);
                 else if (!(p->flags & (HSWO_FLAG_TWO_MERGES | HSWO_FLAG_MULTI_MERGE)) && rc <= MAT_MAX) {
-                    s.dmat = bp.take<float2>(rc * rc);
+                    int64_t n16 = (rc + 15) / 16;
+                    if (n16 % 2 == 0) ++n16;
+                    s.mstride = (int32_t)(n16 * 16);
+                    s.dmat = bp.take<float2>(rc * s.mstride);
                     s.msl = bp.take<int32_t>(rc);
                 }
                 if (p->flags & HSWO_FLAG_TWO_MERGES) s.abit = bp.take<uint32_t>(rc * ((rc + 31) / 32));
@@ -540,16 +543,15 @@ int device_cus() {
 // (R > spclust_max) need no work spread over workgroups: with tu.hybrid they
 // run in the section driver (one launch, state kept on chip) up to
 // R = spclust_max, and wide mode takes the rest.
-// mat_ok: every section of the level keeps an interval matrix (used when the
-// level runs wide and the tuning asks for it).
+// mat_ok: every section of the level keeps an interval matrix (used, in either
+// mode, when the tuning asks for it).
 int run_level(Timer* tm, const SecDev* secs, int n, const std::vector<int64_t>& cap, const std::vector<int64_t>& stop,
               const LoopParams& lp_in, bool row_cache, bool mat_ok, const Tuning& tu, hipStream_t stream) {
     LoopParams lp = lp_in;
-    lp.row_matrix = 0;
+    lp.row_matrix = (row_cache && mat_ok && tu.row_matrix) ? 1 : 0;
     const int variant = tu.variant;
     if (n > tu.wide_max || (row_cache && n > ROWS_MAX_SECTIONS) || lp.multi_merge)
         return timed_driver(tm, secs, n, lp, variant, stream);
-    lp.row_matrix = (row_cache && mat_ok && tu.row_matrix) ? 1 : 0;
     const int G = std::max(1, std::min(GMAX, tu.wide_wg / n));
     // R of each section when the wide iterations start
     std::vector<int64_t> r0(cap);
@@ -783,7 +785,7 @@ std::vector<Knob> tune_knobs(bool incremental, const hswo_tuning* g) {
     const int cu = device_cus();
     std::vector<Knob> k;
     if (incremental) {
-        k.push_back({&Tuning::wide_max, {cu, 64, 16}, g && g->wide_max_sections >= 0});
+        k.push_back({&Tuning::wide_max, {cu, 64, 16, 4, 0}, g && g->wide_max_sections >= 0});
         k.push_back({&Tuning::rows_grid, {2 * cu, cu, 4 * cu}, g && g->rows_grid >= 0});
         k.push_back({&Tuning::row_matrix, {1, 0}, g && g->row_matrix >= 0});
     } else {

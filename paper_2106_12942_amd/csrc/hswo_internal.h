@@ -118,6 +118,8 @@ struct SecDev {
                      //   pair's value, kept by Ward's update at each merge (used in wide mode); its rows
                      //   and columns are indexed by msl, not by slot
     int32_t* msl;    // [rcap] matrix row of each live slot (the identity when the cache starts)
+    int32_t mstride; // entries between matrix rows: rcap rounded up to an odd multiple of 16 (128 bytes),
+                     // so the entries of a column fall on different memory channels
     double* rq;      // [rcap] spectral angle only: |S|^2 of each slot (pairwise tree over the bands)
     uint32_t* abit;  // [rcap][ceil(rcap / 32)] two-merge reading only: adjacency bitmap of the live slots
     double* rbd;     // [rcap] exact D2 of the row's cached pair

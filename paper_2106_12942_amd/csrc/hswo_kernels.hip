@@ -1400,7 +1400,7 @@ struct RowMatLds {
 // decision to reduce. Returns the number of exact evaluations (thread 0).
 __device__ int row_matrix_task(RowMatLds& L, const SecDev& s, int R, int q, bool all) {
     const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
-    const size_t rc = (size_t)s.rcap;
+    const size_t rc = (size_t)s.mstride;
     const int i = all ? q : s.rpend[q];
     const int mi = s.msl[i];
     const float2* Di = s.dmat + (size_t)mi * rc;
@@ -1873,7 +1873,7 @@ __device__ __noinline__ void merge_slots(Smem& sh, const SecDev& s, int lo_s, in
         // the survivor keeps matrix row ml (its row and column rewritten in place: every thread
         // reads and writes its own entries of row ml, and no column it writes is read); row mh
         // is dropped, and the slot that moves takes its matrix row along (below)
-        const size_t rcp = (size_t)s.rcap;
+        const size_t rcp = (size_t)s.mstride;
         const float2 de = mat_entry(d2);
         const double n_hi = (double)s.npix[hi_s];
         const double n_lo = (double)s.npix[lo_s] - n_hi;  // merge_stats has added n_hi to the survivor
@@ -2784,6 +2784,76 @@ __device__ __forceinline__ bool decide(bool spectral, const KeyD& A, const KeyD&
     return false;
 }
 
+// One 64 x 64 tile t (upper triangle, numbered as the spectral tiles) of a
+// section's interval matrix, by the whole block. Each pair's squared distance
+// of the FP32 mean rows (rebuilt from the FP64 means by rowcache_begin) is
+// summed in FP32 by a 4 x 2 register tile per thread from LDS-staged 32-band
+// slices (As, Cs: BK bands of the two row blocks, row pitch P);
+// screen_bounds turns it into certified bounds on the canonical value, which
+// are widened to the real value and rounded outward into both (i, j) and
+// (j, i). Returns the tile's pairs.
+template <int P>
+__device__ unsigned long long mat_fill_tile(float (*As)[P], float (*Cs)[P], const SecDev& s, int R, int t) {
+    const int nT = (R + TILE - 1) / TILE;
+    int ib, jb;
+    tile_coords(t, nT, ib, jb);
+    const int tid = threadIdx.x;
+    const int ty = tid >> 5, tx = tid & 31;
+    float acc[4][2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) acc[a][0] = acc[a][1] = 0.0f;
+    const int lrow = tid >> 3, lb = (tid & 7) << 2;
+    const int ia = ib * TILE + lrow, ic = jb * TILE + lrow;
+    for (int k0 = 0; k0 < s.Bp; k0 += BK) {
+        float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vc = va;
+        if (ia < R) va = *reinterpret_cast<const float4*>(s.mean + (size_t)ia * s.Bp + k0 + lb);
+        if (ic < R) vc = *reinterpret_cast<const float4*>(s.mean + (size_t)ic * s.Bp + k0 + lb);
+        As[lb + 0][lrow] = va.x;
+        As[lb + 1][lrow] = va.y;
+        As[lb + 2][lrow] = va.z;
+        As[lb + 3][lrow] = va.w;
+        Cs[lb + 0][lrow] = vc.x;
+        Cs[lb + 1][lrow] = vc.y;
+        Cs[lb + 2][lrow] = vc.z;
+        Cs[lb + 3][lrow] = vc.w;
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < BK; ++kk) {
+            const float4 a = *reinterpret_cast<const float4*>(&As[kk][ty * 4]);
+            const float2 c = *reinterpret_cast<const float2*>(&Cs[kk][tx * 2]);
+            float d;
+            d = a.x - c.x; acc[0][0] = fmaf(d, d, acc[0][0]);
+            d = a.x - c.y; acc[0][1] = fmaf(d, d, acc[0][1]);
+            d = a.y - c.x; acc[1][0] = fmaf(d, d, acc[1][0]);
+            d = a.y - c.y; acc[1][1] = fmaf(d, d, acc[1][1]);
+            d = a.z - c.x; acc[2][0] = fmaf(d, d, acc[2][0]);
+            d = a.z - c.y; acc[2][1] = fmaf(d, d, acc[2][1]);
+            d = a.w - c.x; acc[3][0] = fmaf(d, d, acc[3][0]);
+            d = a.w - c.y; acc[3][1] = fmaf(d, d, acc[3][1]);
+        }
+        __syncthreads();
+    }
+    const float gam = (float)(2 * s.B + 32) * U32;
+    const size_t rc = (size_t)s.mstride;  // matrix row stride
+    const float2 inf2 = make_float2(__builtin_huge_valf(), __builtin_huge_valf());
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int i = ib * TILE + ty * 4 + a, j = jb * TILE + tx * 2 + c;
+            if (i >= R || j >= R || (ib == jb && j < i)) continue;
+            float2 e = inf2;
+            if (i != j) {
+                const float2 lu = screen_bounds(acc[a][c], s.npix[i], s.npix[j], s.norm[i], s.norm[j], gam);
+                e = make_float2(__double2float_rd((double)lu.x * (1.0 - MAT_REL)),
+                                __double2float_ru((double)lu.y * (1.0 + MAT_REL)));
+            }
+            s.dmat[(size_t)i * rc + j] = e;
+            s.dmat[(size_t)j * rc + i] = e;
+        }
+    return (unsigned long long)min(TILE, R - ib * TILE) * (unsigned long long)min(TILE, R - jb * TILE);
+}
+
 // ---------------------------------------------------------------------------
 // Several merges per step (HSWO_FLAG_MULTI_MERGE): the future-work item of
 // Section 6.2, read for identical regions. A step whose winner has the value
@@ -3020,6 +3090,8 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
     int merges = s.st[3];
     bool avalid = false;  // incremental form: the least adjacent key after the last merge is known
     KeyD anext = key_none();
+    // the row cache keeps the interval matrix (Equation 1, one-merge reading, rcap <= MAT_MAX)
+    const bool mat = row_cache && row_matrix_on(s, lp);
     // two-merge reading: step 3 (the non-adjacent merge) is due, below thr3
     int st3 = lp.two_merges ? s.st[10] : 0;
     double thr3 = st3 ? s.wd[3] : 0.0;
@@ -3064,10 +3136,41 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
         KeyD M = key_none();
         const bool spectral = lp.spectral && R <= lp.kmax;
         const double T = key_exists(A) ? lp.w2 * A.d2 : __builtin_huge_val();
-        if (spectral && row_cache) {
+        if (spectral && row_cache && mat) {
+            // interval matrix: filled when the cache starts (tile after tile), then the rows --
+            // all of them at the start, else the pending ones -- rescanned from their bounds
+            if (rcs == 0) {
+                rowcache_begin(sh, s, R, E, true);
+                rcs = 1;
+            }
+            const bool all = rcs == 1;
+            const int rows = all ? R : npend;
+            if (all) {
+                const int nT = (R + TILE - 1) / TILE;
+                unsigned long long pairs = 0;
+                for (int t = 0; t < nT * (nT + 1) / 2; ++t) pairs += mat_fill_tile<TILE + 4>(sh.u.f.As, sh.u.f.Cs, s, R, t);
+                CNT_ADD(C_W_FILL_FLOPS, 3ull * (unsigned long long)s.B * pairs);
+                __syncthreads();
+            }
+            static_assert(sizeof(RowMatLds) <= sizeof(Smem::u), "the row rescans' LDS lives in the union");
+            RowMatLds& rl = *reinterpret_cast<RowMatLds*>(&sh.u);
+            int ex = 0;
+            for (int q = 0; q < rows; ++q) ex += row_matrix_task(rl, s, R, q, all);  // block-uniform trip count
+            M = spectral_min_rows(sh, s, R, rows, all);
+            rcs = 2;
+            npend = 0;
+            CNT_ADD(C_RECHECKS, ex);
+            CNT_ADD(C_ROW_BOUNDED, (unsigned long long)rows * (unsigned long long)(R - 1));
+            CNT_ADD(C_D_BYTES, 12ull * (unsigned long long)R + 8ull * (unsigned long long)rows * (unsigned long long)R +
+                                   (unsigned long long)ex * (16ull * (unsigned long long)s.B + 16ull));
+            CNT_ADD(C_SPEC_PAIRS, (unsigned long long)R * (unsigned long long)(R - 1) / 2ull);
+            tk1 = wall_clock64();
+            CNT_ADD(C_T_SPEC32, tk1 - tk0);
+            tk0 = tk1;
+        } else if (spectral && row_cache) {
             // exact rows: all of them when the cache starts, else the pending ones
             if (rcs == 0) {
-                rowcache_begin(sh, s, R, E, row_matrix_on(s, lp));
+                rowcache_begin(sh, s, R, E, false);
                 rcs = 1;
             }
             const bool all = rcs == 1;
@@ -3208,7 +3311,7 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
         if (lp.incremental) CNT_ADD(C_D_BYTES, 16ull * (unsigned long long)E + 24ull * (unsigned long long)s.B);
         if (lp.incremental) {
             int nre = 0;
-            avalid = merge_pair_inc<8>(sh, s, win.si, win.sj, R, E, merges, kind, win.d2, rcs, anext, nre, false, 0);
+            avalid = merge_pair_inc<8>(sh, s, win.si, win.sj, R, E, merges, kind, win.d2, rcs, anext, nre, mat, 0);
             CNT_ADD(C_RECHECKS, nre);
         } else {
             merge_pair(sh, s, win.si, win.sj, R, E, merges, kind, win.d2, g_ready, prec, rcs);
@@ -3218,7 +3321,7 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
         if (rcs == 2) npend = sh.npend;
         if (s.abit && rcs) abit_merge(s, win.si, win.sj, R + 1);
         if (row_cache && rcs == 0 && lp.spectral && R <= lp.kmax && R > s.stop) {
-            rowcache_begin(sh, s, R, E, row_matrix_on(s, lp));  // the spectral stage starts with the next iteration
+            rowcache_begin(sh, s, R, E, mat);  // the spectral stage starts with the next iteration
             rcs = 1;
         }
         if (step2 && lp.spectral && R <= lp.kmax && R > s.stop) {
@@ -3400,13 +3503,8 @@ __global__ void __launch_bounds__(NT) k_mat_rows(const SecDev* __restrict__ secs
 }
 
 // Interval matrix of every section whose row cache starts in this iteration
-// (state 1 with the matrix kept): one 64 x 64 tile of pairs per workgroup
-// (blockIdx.x, upper triangle; blockIdx.y the section). Each pair's squared
-// distance of the FP32 mean rows (rebuilt from the FP64 means by
-// rowcache_begin) is summed in FP32 by a 4 x 2 register tile per thread from
-// LDS-staged 32-band slices; screen_bounds turns it into certified bounds on
-// the canonical value, which are widened to the real value and rounded
-// outward into both (i, j) and (j, i).
+// (state 1 with the matrix kept): one tile per workgroup (blockIdx.x; blockIdx.y
+// the section).
 __global__ void __launch_bounds__(NT) k_mat_fill(const SecDev* __restrict__ secs, LoopParams lp) {
     __shared__ float As[BK][TILE], Cs[BK][TILE];
     if (gated(lp.counters)) return;
@@ -3415,67 +3513,8 @@ __global__ void __launch_bounds__(NT) k_mat_fill(const SecDev* __restrict__ secs
     if (!row_matrix_on(s, lp) || s.st[6] != 1 || R <= s.stop || R > lp.kmax) return;
     const int nT = (R + TILE - 1) / TILE;
     if ((int)blockIdx.x >= nT * (nT + 1) / 2) return;
-    int ib, jb;
-    tile_coords((int)blockIdx.x, nT, ib, jb);
-    const int tid = threadIdx.x;
-    const int ty = tid >> 5, tx = tid & 31;
-    float acc[4][2];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) acc[a][0] = acc[a][1] = 0.0f;
-    const int lrow = tid >> 3, lb = (tid & 7) << 2;
-    const int ia = ib * TILE + lrow, ic = jb * TILE + lrow;
-    for (int k0 = 0; k0 < s.Bp; k0 += BK) {
-        float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vc = va;
-        if (ia < R) va = *reinterpret_cast<const float4*>(s.mean + (size_t)ia * s.Bp + k0 + lb);
-        if (ic < R) vc = *reinterpret_cast<const float4*>(s.mean + (size_t)ic * s.Bp + k0 + lb);
-        As[lb + 0][lrow] = va.x;
-        As[lb + 1][lrow] = va.y;
-        As[lb + 2][lrow] = va.z;
-        As[lb + 3][lrow] = va.w;
-        Cs[lb + 0][lrow] = vc.x;
-        Cs[lb + 1][lrow] = vc.y;
-        Cs[lb + 2][lrow] = vc.z;
-        Cs[lb + 3][lrow] = vc.w;
-        __syncthreads();
-#pragma unroll 8
-        for (int kk = 0; kk < BK; ++kk) {
-            const float4 a = *reinterpret_cast<const float4*>(&As[kk][ty * 4]);
-            const float2 c = *reinterpret_cast<const float2*>(&Cs[kk][tx * 2]);
-            float d;
-            d = a.x - c.x; acc[0][0] = fmaf(d, d, acc[0][0]);
-            d = a.x - c.y; acc[0][1] = fmaf(d, d, acc[0][1]);
-            d = a.y - c.x; acc[1][0] = fmaf(d, d, acc[1][0]);
-            d = a.y - c.y; acc[1][1] = fmaf(d, d, acc[1][1]);
-            d = a.z - c.x; acc[2][0] = fmaf(d, d, acc[2][0]);
-            d = a.z - c.y; acc[2][1] = fmaf(d, d, acc[2][1]);
-            d = a.w - c.x; acc[3][0] = fmaf(d, d, acc[3][0]);
-            d = a.w - c.y; acc[3][1] = fmaf(d, d, acc[3][1]);
-        }
-        __syncthreads();
-    }
-    const float gam = (float)(2 * s.B + 32) * U32;
-    const size_t rc = (size_t)s.rcap;
-    const float2 inf2 = make_float2(__builtin_huge_valf(), __builtin_huge_valf());
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int i = ib * TILE + ty * 4 + a, j = jb * TILE + tx * 2 + c;
-            if (i >= R || j >= R || (ib == jb && j < i)) continue;
-            float2 e = inf2;
-            if (i != j) {
-                const float2 lu = screen_bounds(acc[a][c], s.npix[i], s.npix[j], s.norm[i], s.norm[j], gam);
-                e = make_float2(__double2float_rd((double)lu.x * (1.0 - MAT_REL)),
-                                __double2float_ru((double)lu.y * (1.0 + MAT_REL)));
-            }
-            s.dmat[(size_t)i * rc + j] = e;
-            s.dmat[(size_t)j * rc + i] = e;
-        }
-    if (tid == 0 && lp.counters) {
-        const unsigned long long pairs = (unsigned long long)min(TILE, R - ib * TILE) *
-                                         (unsigned long long)min(TILE, R - jb * TILE);
-        atomicAdd(&lp.counters[C_W_FILL_FLOPS], 3ull * (unsigned long long)s.B * pairs);
-    }
+    const unsigned long long pairs = mat_fill_tile<TILE>(As, Cs, s, R, (int)blockIdx.x);
+    if (threadIdx.x == 0 && lp.counters) atomicAdd(&lp.counters[C_W_FILL_FLOPS], 3ull * (unsigned long long)s.B * pairs);
 }
 
 // Start the row caches of the sections whose pass begins inside the spectral

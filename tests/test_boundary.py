@@ -197,13 +197,13 @@ def test_spectral_angle_needs_the_incremental_form(kw):
 
 def test_spectral_angle_workspace_holds_norms_instead_of_the_interval_matrix():
     # row cache of spclust_max = 256 slots: Equation 1 keeps the interval matrix (FP32 bounds, 8 bytes
-    # per pair of slots, and a 4-byte matrix row per slot); the spectral angle each slot's squared
-    # norm (8 bytes per slot) instead
+    # per entry, rows of 272 entries: 256 rounded up to an odd multiple of 16; and a 4-byte matrix row
+    # per slot); the spectral angle each slot's squared norm (8 bytes per slot) instead
     q = hswo.make_params(**BASE, incremental=True)
     p = hswo.make_params(**BASE, incremental=True, criterion="sam")
     a, b = hswo.workspace_bytes(64, 64, 32, 0, q), hswo.workspace_bytes(64, 64, 32, 0, p)
     assert 0 < b < a
-    assert abs((a - b) - (256 * 256 * 8 + 256 * 4 - 256 * 8)) <= 512
+    assert abs((a - b) - (256 * 272 * 8 + 256 * 4 - 256 * 8)) <= 512
 
 
 @pytest.mark.parametrize("kw", [dict(), dict(precision="fp16"), dict(sequential=True)])
@@ -215,12 +215,12 @@ def test_two_merges_need_the_incremental_form(kw):
     assert rc == hswo.HSWO_E_UNSUPPORTED
     assert "TWO_MERGES" in hswo.last_error()
     # the two-merge reading keeps the row cache's adjacency bitmap (rcap^2 bits) instead of the
-    # interval matrix (8 bytes per pair of slots and 4 per slot)
+    # interval matrix (rows of 272 entries of 8 bytes, and 4 bytes per slot)
     q = hswo.make_params(**BASE, two_merges=True, incremental=True)
     r = hswo.make_params(**BASE, incremental=True)
     a, b = hswo.workspace_bytes(64, 64, 8, 0, q), hswo.workspace_bytes(64, 64, 8, 0, r)
     assert 0 < a < b
-    assert abs((b - a) - (256 * 256 * 8 + 256 * 4 - 256 * 8 * 4)) <= 512
+    assert abs((b - a) - (256 * 272 * 8 + 256 * 4 - 256 * 8 * 4)) <= 512
 
 
 def test_verify_bound_flag_checked():
@@ -290,9 +290,9 @@ def test_multi_merge_form_checked(kw, code):
 def test_multi_merge_workspace_holds_the_step_scratch_instead_of_the_interval_matrix():
     # 64 x 64 HSWO: 4096 slots, 8064 edge slots -> sort keys and payloads for 8192 entries
     # (8 + 8 bytes), a place per slot (4 bytes) and 2049 listed pairs (16 bytes); the interval
-    # matrix of the 256 row-cache slots (8 bytes per pair, 4 per slot) is not kept
+    # matrix of the 256 row-cache slots (rows of 272 entries of 8 bytes, 4 bytes per slot) is not kept
     q = hswo.make_params(**BASE, incremental=True)
     m = hswo.make_params(**BASE, incremental=True, multi_merge=True)
     a, b = hswo.workspace_bytes(64, 64, 8, 0, q), hswo.workspace_bytes(64, 64, 8, 0, m)
-    want = 16 * 8192 + 4 * 4096 + 16 * 2049 - (8 * 256 * 256 + 4 * 256)
+    want = 16 * 8192 + 4 * 4096 + 16 * 2049 - (8 * 256 * 272 + 4 * 256)
     assert abs((b - a) - want) <= 6 * 256

@@ -18,12 +18,13 @@ torch = pytest.importorskip("torch")
 
 # persistent: the section driver evaluates stale rows in full (light steps, second bounds);
 # wide: the row cache keeps the interval matrix (rescans); wide_rows: wide, rows in full as persistent
-MODES = ["persistent", "wide", "wide_rows"]
+# level modes x row stage: the interval matrix (persistent, wide) or exact rows (the *_rows modes)
+MODES = ["persistent", "persistent_rows", "wide", "wide_rows"]
 
 
 def _mode(monkeypatch, mode):
-    tu = {"wide_max_sections": 0 if mode == "persistent" else 100000}
-    if mode == "wide_rows":
+    tu = {"wide_max_sections": 0 if mode.startswith("persistent") else 100000}
+    if mode.endswith("_rows"):
         tu["row_matrix"] = 0
     monkeypatch.setattr(hswo, "DEFAULT_TUNING", tu)
 
@@ -146,7 +147,7 @@ def test_bare_bound_modes(bare, scene, variant, mode, monkeypatch):
     assert_parity(make(), p, incremental=True, tag=f"bare bounds {bare} {scene} {variant} {mode}")
 
 
-@pytest.mark.parametrize("mode", ["persistent", "wide_rows"])
+@pytest.mark.parametrize("mode", ["persistent_rows", "wide_rows"])
 def test_bare_bound_mode_reaches_the_device(mode, monkeypatch):
     """The switch is read per call: keeping every bound changes the number of
     exact evaluations (light steps replace full rows, failed ones add them).
