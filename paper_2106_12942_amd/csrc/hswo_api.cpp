@@ -299,14 +299,16 @@ Plan make_plan(int H, int W, int B, const hswo_params* p, int L) {
 
 // Per-section sizes are int32 on the device: reject a plan whose edge or
 // tile capacity would not fit (a leaf's edge slots are h*w*4 under
-// 8-connectivity, which can pass 2^31 while h*w does not).
+// 8-connectivity, which can pass 2^31 while h*w does not). The edge index
+// keeps twice an edge slot number (plus one) in an int32, hence at most 2^30
+// edge slots.
 int check_plan(const Plan& pl) {
     for (size_t d = 0; d < pl.lv.size(); ++d)
         for (const SecPlan& s : pl.lv[d]) {
-            if (s.ecap > INT32_MAX || s.cap > INT32_MAX || s.tiles > INT32_MAX)
+            if (s.ecap > ((int64_t)1 << 30) || s.cap > INT32_MAX || s.tiles > INT32_MAX)
                 return fail(HSWO_E_UNSUPPORTED,
                             "a section of recursion depth %zu needs %lld edge slots and %lld regions; "
-                            "both must fit in int32 (use more recursion levels)",
+                            "the device keeps both in int32, at most 2^30 edge slots (use more recursion levels)",
                             d, (long long)s.ecap, (long long)s.cap);
         }
     return HSWO_OK;
@@ -388,6 +390,7 @@ Layout carve(const Plan& pl, int H, int W, const hswo_params* p, int bare, void*
                 s.rmax = bp.take<int32_t>(sp.cap);
                 s.cmd2 = bp.take<double>((sp.ecap + ECH - 1) / ECH);
                 s.cme = bp.take<int32_t>((sp.ecap + ECH - 1) / ECH);
+                s.cml = bp.take<int2>((sp.ecap + ECH - 1) / ECH);
                 if (p->flags & HSWO_FLAG_MULTI_MERGE) take_multi(bp, s, sp.cap, sp.ecap);
             }
             s.tstat = bp.take<float2>(sp.tiles);
@@ -1229,6 +1232,7 @@ BatchLayout carve_batch(int n, const hswo_section* sec, const hswo_params* p, in
             s.rmax = bp.take<int32_t>(cap);
             s.cmd2 = bp.take<double>((ecap + ECH - 1) / ECH);
             s.cme = bp.take<int32_t>((ecap + ECH - 1) / ECH);
+            s.cml = bp.take<int2>((ecap + ECH - 1) / ECH);
             if (p->flags & HSWO_FLAG_MULTI_MERGE) take_multi(bp, s, cap, ecap);
         }
         s.tstat = bp.take<float2>(tiles);
@@ -1321,8 +1325,9 @@ int validate_batch(int n, const hswo_section* sec, int dtype, const hswo_params*
         if (reinterpret_cast<uintptr_t>(q.cube) % 16) return fail(HSWO_E_INVAL, "section %d: cube not 16-byte aligned", i);
         if ((p->flags & HSWO_FLAG_MERGE_LOG) && !q.merge_log)
             return fail(HSWO_E_INVAL, "section %d: MERGE_LOG flag needs merge_log", i);
-        if (grid_edges(q.H, q.W, p->connectivity) > INT32_MAX)
-            return fail(HSWO_E_UNSUPPORTED, "section %d: %dx%d needs more than 2^31 - 1 edge slots", i, q.H, q.W);
+        if (grid_edges(q.H, q.W, p->connectivity) > ((int64_t)1 << 30))
+            return fail(HSWO_E_UNSUPPORTED, "section %d: %dx%d needs more than 2^30 edge slots (int32 indices)", i,
+                        q.H, q.W);
     }
     return HSWO_OK;
 }

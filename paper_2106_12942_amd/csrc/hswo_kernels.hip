@@ -445,24 +445,48 @@ __device__ __noinline__ double exact_seg(const SecDev& s, int si, int sj, int L)
     return sam ? sam_value(t0, t1, t2) : fac * t0;
 }
 
-// exact_seg for Equation 1 from the row cache's FP64 means (m64r, the stored
-// quotients S / n), so no division per band: the same bands, tree and
-// factor, hence the same value. For slots whose means are current (row cache
-// running).
+// Segment width of exact_seg_means: lanes of 16 bands each over the bands
+// zero-padded to a power of two P (one lane for P <= 16); B <= 1024.
+__device__ __forceinline__ int mean_lanes(int B) {
+    int P = 16;
+    while (P < B) P <<= 1;
+    return P / 16;
+}
+
+// The canonical criterion of Equation 1 for pair (si, sj) by an L-lane
+// segment (L = mean_lanes(B)) from the row cache's FP64 means (m64r, the
+// stored quotients S / n, so no division per band): lane m of the segment
+// adds its aligned run of 16 bands 16m..16m+15 as a perfect binary tree in
+// registers, and the segment's butterflies join the runs in tree order -- the
+// same zero-padded pairwise tree, so the same value, as the other exact
+// evaluations. All 32 loads of a lane are independent, so a segment costs one
+// memory round trip; 64 / L pairs per wavefront. For slots whose means are
+// current (row cache running). si < 0: no pair (result meaningless).
 __device__ __noinline__ double exact_seg_means(const SecDev& s, int si, int sj, int L) {
     const int B = s.B, B8 = (B + 7) & ~7;
-    const int b = (lane_id() & (L - 1)) << 2;
+    const int b0 = (lane_id() & (L - 1)) << 4;
     double t0 = 0.0, fac = 0.0;
     if (si >= 0) {
         const double* Mi = s.m64r + (size_t)si * B8;
         const double* Mj = s.m64r + (size_t)sj * B8;
-        double q[4];
+        double x[16], y[16];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const double d = (b + k < B) ? Mi[b + k] - Mj[b + k] : 0.0;
+        for (int k = 0; k < 16; ++k) {
+            const bool in = b0 + k < B;
+            x[k] = in ? Mi[b0 + k] : 0.0;
+            y[k] = in ? Mj[b0 + k] : 0.0;
+        }
+        double q[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const double d = x[k] - y[k];
             q[k] = d * d;
         }
-        t0 = (q[0] + q[1]) + (q[2] + q[3]);
+#pragma unroll
+        for (int w = 1; w < 16; w <<= 1)
+#pragma unroll
+            for (int k = 0; k < 16; k += 2 * w) q[k] = q[k] + q[k + w];
+        t0 = q[0];
         const int n_i = s.npix[si], n_j = s.npix[sj];
         const double dni = (double)n_i, dnj = (double)n_j;
         fac = (dni * dnj) / (double)(n_i + n_j);
@@ -2045,7 +2069,7 @@ __device__ void chunk_min_wave(const SecDev& s, int c, int E) {
                 kk.d2 = v;
                 kk.lo = min(la, lb);
                 kk.hi = max(la, lb);
-                kk.si = e;  // the edge slot rides in si
+                kk.si = 2 * e + (la > lb ? 1 : 0);  // the edge slot rides in si, with which end is lo
                 kk.sj = 0;
                 if (key_less(kk, best)) best = kk;
             }
@@ -2059,6 +2083,7 @@ __device__ void chunk_min_wave(const SecDev& s, int c, int E) {
     if (lane == 0) {
         s.cmd2[c] = best.d2;
         s.cme[c] = key_exists(best) ? best.si : -1;
+        s.cml[c] = make_int2(best.lo, best.hi);
     }
 }
 
@@ -2086,28 +2111,30 @@ __device__ __noinline__ void edge_index_build(const SecDev& s, int R, int E) {
 
 // The least adjacent key over every chunk's minimum, with its slots; whole block.
 __device__ KeyD chunks_min_key(Smem& sh, const SecDev& s, int E) {
+    // each chunk's record holds its least key's labels: one round of loads, then the winner's
+    // slots from its edge
     KeyD best = key_none();
     for (int c = threadIdx.x; c < (E + ECH - 1) / ECH; c += NT) {
-        const int e = s.cme[c];
-        if (e < 0) continue;
-        const int2 ed = s.edges[e];
-        const int la = s.label[ed.x], lb = s.label[ed.y];
+        const int e2 = s.cme[c];
+        const double d2 = s.cmd2[c];
+        const int2 lab = s.cml[c];
+        if (e2 < 0) continue;
         KeyD k;
-        k.d2 = s.cmd2[c];
-        if (la < lb) {
-            k.lo = la;
-            k.hi = lb;
-            k.si = ed.x;
-            k.sj = ed.y;
-        } else {
-            k.lo = lb;
-            k.hi = la;
-            k.si = ed.y;
-            k.sj = ed.x;
-        }
+        k.d2 = d2;
+        k.lo = lab.x;
+        k.hi = lab.y;
+        k.si = e2;
+        k.sj = 0;
         if (key_less(k, best)) best = k;
     }
-    return block_min_key(sh, best);
+    best = block_min_key(sh, best);
+    if (key_exists(best)) {
+        const int2 ed = s.edges[best.si >> 1];
+        const bool flip = (best.si & 1) != 0;  // the edge's second end is lo
+        best.si = flip ? ed.y : ed.x;
+        best.sj = flip ? ed.x : ed.y;
+    }
+    return best;
 }
 
 constexpr int LCAP = CAND_CAP / 3;  // edges listed per merge by the incremental form (L, L2, neighbours)
@@ -2167,13 +2194,32 @@ __device__ __noinline__ void merge_index_scan(Smem& sh, const SecDev& s, int lo_
     __syncthreads();
 }
 
-// The index path's end of a merge: the chunk minima of [a0, a1) anew (every
-// changed edge is there), the survivor's and the moved slot's ranges, and
-// the least key over all chunks.
+// The index path's end of a merge: the chunk minima taken anew of the chunks
+// that hold an edge the merge changed -- the edges it listed in L (nL of
+// them, all inside [a0, a1)), whose chunks are flagged in LDS; the renamed
+// edges of the moved slot keep their keys -- then the survivor's and the
+// moved slot's ranges, and the least key over all chunks. A chunk range too
+// long for the flags takes every chunk of [a0, a1) anew.
 __device__ __noinline__ KeyD merge_index_finish(Smem& sh, const SecDev& s, int a0, int a1, int surv, int hi_s,
-                                                bool moved, int ua, int ub, int ma, int mb, int E) {
-    __syncthreads();  // the re-scored values are written
-    for (int c = a0 / ECH + wave_id(); c < (a1 + ECH - 1) / ECH; c += NWAVE) chunk_min_wave(s, c, E);
+                                                bool moved, int ua, int ub, int ma, int mb, int E, const int* L,
+                                                int nL) {
+    constexpr int FLAG_WORDS = (int)(sizeof(sh.u.f.As) / sizeof(unsigned));
+    const int c0 = a0 / ECH, c1 = (a1 + ECH - 1) / ECH;
+    const int nw = (c1 - c0 + 31) >> 5;
+    const bool flagged = nw <= FLAG_WORDS;  // block-uniform
+    unsigned* fl = reinterpret_cast<unsigned*>(&sh.u.f.As[0][0]);  // free during a merge
+    if (flagged)
+        for (int w = threadIdx.x; w < nw; w += NT) fl[w] = 0u;
+    __syncthreads();  // the re-scored values are written, the flags cleared
+    if (flagged) {
+        for (int k = threadIdx.x; k < nL; k += NT) {
+            const int c = L[k] / ECH - c0;
+            atomicOr(&fl[c >> 5], 1u << (c & 31));
+        }
+        __syncthreads();
+    }
+    for (int c = c0 + wave_id(); c < c1; c += NWAVE)  // wavefront-uniform
+        if (!flagged || ((fl[(c - c0) >> 5] >> ((c - c0) & 31)) & 1u)) chunk_min_wave(s, c, E);
     if (threadIdx.x == 0) {
         s.rmin[surv] = ua;
         s.rmax[surv] = ub;
@@ -2204,6 +2250,7 @@ template <int U>
 __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int& E, int stamp, int kind,
                                double d2, int rc, KeyD& anext, int& nchk, bool mat, int eidx_min) {
     const int tid = threadIdx.x;
+    const int l_surv = s.label[lo_s];  // the survivor's label, whichever slot it ends in
     merge_stats(sh, s, lo_s, hi_s, R, kind, d2, 0, 0, rc, false, mat);
     const int last = R - 1;
     const int surv = (lo_s == last) ? hi_s : lo_s;
@@ -2363,6 +2410,10 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
         __syncthreads();
     }
     int* K = L2;  // L2 is consumed: indices into L of the kept edges
+    // and the label of each kept edge's other end, read now (a slot that moves keeps its label):
+    // the staging tiles are free during a merge and hold LCAP entries
+    static_assert(sizeof(sh.u.f.As) + sizeof(sh.u.f.Cs) >= LCAP * sizeof(int), "kept-edge labels fit");
+    int* KL = reinterpret_cast<int*>(&sh.u.f.As[0][0]);
     for (int k = tid; k < n1; k += NT) {
         const int e = L[k], x = XL[k];
         bool keep = x >= 0;
@@ -2379,7 +2430,9 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
         }
         if (keep) {
             s.edges[e] = make_int2(surv, x == last ? hi_s : x);
-            K[atomicAdd(&sh.bcast_i[2], 1)] = k;
+            const int pos = atomicAdd(&sh.bcast_i[2], 1);
+            K[pos] = k;
+            KL[pos] = s.label[x];
         } else {
             s.edges[e] = make_int2(-1, -1);
             s.ed2[e] = __builtin_huge_val();
@@ -2390,11 +2443,10 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
     merge_slots(sh, s, lo_s, hi_s, R, 0, rc, false, mat, d2);  // ends with a barrier
     const int nk = sh.bcast_i[2];
     const int emptied = sh.bcast_i[3];
-    const int l_surv = s.label[surv];
-    const int Ls = nk > LANE_PAIRS_MIN ? -1 : seg_lanes(s.B);
     // with the row cache running the FP64 means of every live slot are current (the survivor's
-    // written above): Equation 1 from them, without a division per band
-    const bool means = rc != 0 && s.crit == HSWO_CRIT_BSMSE;
+    // written above): Equation 1 from them, without a division per band, in 16-band lane runs
+    const bool means = rc != 0 && s.crit == HSWO_CRIT_BSMSE && s.B <= 1024;
+    const int Ls = nk > LANE_PAIRS_MIN ? -1 : (means ? mean_lanes(s.B) : seg_lanes(s.B));
     if (Ls < 0) {
         // a survivor of high degree: one re-scored edge per lane
         for (int q0 = 0; q0 < nk; q0 += NT) {  // block-uniform trip count
@@ -2404,7 +2456,7 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
                 const int k = K[q];
                 e = L[k];
                 const int x = XL[k] == last ? hi_s : XL[k];
-                const int lx = s.label[x];
+                const int lx = KL[q];
                 a = surv;
                 b = x;
                 la = l_surv;
@@ -2433,7 +2485,7 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
             const int k = K[q];
             const int e = L[k];
             const int x = XL[k] == last ? hi_s : XL[k];
-            const int lx = s.label[x];
+            const int lx = KL[q];
             int a = surv, b = x, la = l_surv, lb = lx;
             if (la > lb) {
                 a = x;
@@ -2460,7 +2512,7 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
                 const int k = K[q];
                 e = L[k];
                 const int x = XL[k] == last ? hi_s : XL[k];
-                const int lx = s.label[x];
+                const int lx = KL[q];
                 a = surv;
                 b = x;
                 la = l_surv;
@@ -2487,7 +2539,7 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
     }
     nchk += nk;
     if (use_index) {
-        anext = merge_index_finish(sh, s, a0, a1, surv, hi_s, moved, ua, ub, ma, mb, E);
+        anext = merge_index_finish(sh, s, a0, a1, surv, hi_s, moved, ua, ub, ma, mb, E, L, n1);
     } else {
         anext = block_min_key(sh, best);  // the re-scored edges and the least of the others
         if (tid == 0) s.st[12] = 0;        // the index was not kept up to date
