@@ -24,7 +24,7 @@ Workloads
 
 Forms (--form): "incremental" (default): cached exact per-edge D2 and the
 spectral row cache; "screened": every pair screened each iteration, the
-spectral stage on matrix cores (--precision bf16, the default, or fp16);
+spectral stage on matrix cores (--precision fp16, the default, or bf16);
 "plain": every pair screened each iteration in FP32, the sections of a level
 one after another (neither the precision nor the batching form);
 "plain_batched": the same FP32 screens with the sections of a level batched.
@@ -123,8 +123,10 @@ def kernel_roofline(st, B, tag, kind=None):
     measures in the same call on an empty kernel). Algorithmic work per launch = the kind's work over the step
     divided by its launches:
       wide_decide: bytes counted on the device by the kernel (16 per edge slot
-        read for the minimum, 24 per band per merge; in the spectral stage 12
-        per live row and 32 per pending row per 64 live rows) -> HBM bound;
+        the merge reads -- every slot on a pass over the list; on the edge
+        index's path the scanned ranges, the re-minimised chunks and one per
+        chunk record -- 24 per band per merge; in the spectral stage 12 per
+        live row and 32 per pending row per 64 live rows) -> HBM bound;
       wide_rows: bytes counted on the device: exact row tasks read each
         column's FP64 mean row once per 4 rows (3 flops per band and pair, far
         below the ridge), rescans read a row of the interval matrix and the
@@ -663,8 +665,9 @@ def main():
     ap.add_argument("--workload", default="rhseg2048_f16", choices=sorted(WORKLOAD_DESC))
     ap.add_argument("--form", default="incremental", choices=["incremental", "screened", "plain", "plain_batched"],
                     help="form of the timed steps (the others run once for the comparison)")
-    ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp16"],
-                    help="matrix-core screen precision of the screened form")
+    ap.add_argument("--precision", default="fp16", choices=["fp32", "bf16", "fp16"],
+                    help="matrix-core screen precision of the screened form (fp16: its finer rounding lets fewer "
+                         "tiles through to the FP32 pass than bf16 on these workloads)")
     ap.add_argument("--criterion", default="bsmse", choices=["bsmse", "sam"],
                     help="dissimilarity: Equation 1 (bsmse) or the spectral angle (sam, incremental form only)")
     ap.add_argument("--two-merges", action="store_true",

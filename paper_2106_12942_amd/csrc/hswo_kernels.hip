@@ -140,6 +140,7 @@ struct Smem {
     int bcast_i[4];
     int idx[8];              // incremental merge: slot ranges and the chunk range scanned
     int zc[2];               // several merges per step: list counters
+    int eread;               // incremental merge: edge slots (and chunk records) it read
     unsigned long long cnt[C_COUNT];  // per-block counters and stage clocks (thread 0 only)
 };
 
@@ -2190,6 +2191,8 @@ __device__ __noinline__ void merge_index_scan(Smem& sh, const SecDev& s, int lo_
         sh.idx[3] = mb;
         sh.idx[4] = a0;
         sh.idx[5] = a1;
+        sh.idx[6] = (a1 - a0) + (b1 - b0) - max(0, min(a1, b1) - max(a0, b0));  // slots scanned
+        sh.idx[7] = 0;                                                          // chunks re-minimised
     }
     __syncthreads();
 }
@@ -2219,7 +2222,11 @@ __device__ __noinline__ KeyD merge_index_finish(Smem& sh, const SecDev& s, int a
         __syncthreads();
     }
     for (int c = c0 + wave_id(); c < c1; c += NWAVE)  // wavefront-uniform
-        if (!flagged || ((fl[(c - c0) >> 5] >> ((c - c0) & 31)) & 1u)) chunk_min_wave(s, c, E);
+        if (!flagged || ((fl[(c - c0) >> 5] >> ((c - c0) & 31)) & 1u)) {
+            chunk_min_wave(s, c, E);
+            if (lane_id() == 0) atomicAdd(&sh.idx[7], 1);
+        }
+    __syncthreads();  // the chunk count is complete
     if (threadIdx.x == 0) {
         s.rmin[surv] = ua;
         s.rmax[surv] = ub;
@@ -2227,6 +2234,8 @@ __device__ __noinline__ KeyD merge_index_finish(Smem& sh, const SecDev& s, int a
             s.rmin[hi_s] = ma;
             s.rmax[hi_s] = mb;
         }
+        // read: the scanned slots, the re-minimised chunks' slots and every chunk record
+        sh.eread = sh.idx[6] + sh.idx[7] * ECH + (E + ECH - 1) / ECH;
     }
     __syncthreads();
     return chunks_min_key(sh, s, E);
@@ -2262,6 +2271,7 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
         sh.bcast_i[1] = 0;  // |L2|
         sh.bcast_i[2] = 0;  // kept edges
         sh.bcast_i[3] = 0;  // emptied slots
+        sh.eread = E;       // a pass over every slot (the index path counts its own)
     }
     __syncthreads();
     // A long edge list goes through its index: every edge that touches the
@@ -3332,10 +3342,10 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
                 const int4 z = s.zlist[t];
                 int nre = 0;
                 CNT_ADD(C_MERGES, 1);
-                CNT_ADD(C_D_BYTES, 16ull * (unsigned long long)E + 24ull * (unsigned long long)s.B);
                 avalid = merge_pair_inc<8>(sh, s, z.x, z.y, R, E, merges, z.z + (t ? 2 : 0), 0.0, rcs, anext, nre,
                                            false, 0);
                 CNT_ADD(C_RECHECKS, nre);
+                CNT_ADD(C_D_BYTES, 16ull * (unsigned long long)sh.eread + 24ull * (unsigned long long)s.B);
                 ++merges;
                 --R;
                 if (tid == 0 && z.y != R) {  // slot R (the old last) moved into z.y
@@ -3360,11 +3370,11 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
             continue;
         }
         CNT_ADD(C_MERGES, 1);
-        if (lp.incremental) CNT_ADD(C_D_BYTES, 16ull * (unsigned long long)E + 24ull * (unsigned long long)s.B);
         if (lp.incremental) {
             int nre = 0;
             avalid = merge_pair_inc<8>(sh, s, win.si, win.sj, R, E, merges, kind, win.d2, rcs, anext, nre, mat, 0);
             CNT_ADD(C_RECHECKS, nre);
+            CNT_ADD(C_D_BYTES, 16ull * (unsigned long long)sh.eread + 24ull * (unsigned long long)s.B);
         } else {
             merge_pair(sh, s, win.si, win.sj, R, E, merges, kind, win.d2, g_ready, prec, rcs);
         }
@@ -3675,11 +3685,12 @@ __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ s
         }
         if (merge_now) {
             const int stamp = s.st[3];
-            decide_bytes += 16ull * (unsigned long long)E + 24ull * (unsigned long long)s.B;
+            if (!lp.incremental) decide_bytes += 16ull * (unsigned long long)E + 24ull * (unsigned long long)s.B;
             if (lp.incremental) {
                 KeyD an;
                 const bool av = merge_pair_inc<4>(sh, s, win.si, win.sj, R, E, stamp, kind, win.d2, rcs, an, nchk,
                                                   row_matrix_on(s, lp), EIDX_MIN);
+                decide_bytes += 16ull * (unsigned long long)sh.eread + 24ull * (unsigned long long)s.B;
                 if (tid == 0) {
                     s.st[8] = av ? 1 : 0;
                     s.wd[2] = an.d2;
