@@ -2056,24 +2056,35 @@ __device__ void compact_edges(Smem& sh, const SecDev& s, int& E) {
 
 // Least key of chunk c into cmd2[c] / cme[c]; one wavefront.
 __device__ void chunk_min_wave(const SecDev& s, int c, int E) {
+    // the chunk's values at once, their least over the wavefront, then the labels of only the
+    // slots that hold it (one round of loads each, whatever the chunk holds)
     const int lane = lane_id();
-    KeyD best = key_none();
+    constexpr int PER = ECH / 64;
+    double v[PER];
+    double m = __builtin_huge_val();
 #pragma unroll
-    for (int k = 0; k < ECH / 64; ++k) {
+    for (int k = 0; k < PER; ++k) {
         const int e = c * ECH + k * 64 + lane;
-        if (e < E) {
-            const double v = s.ed2[e];
-            if (v < __builtin_huge_val() && v <= best.d2) {  // labels only for a candidate
-                const int2 ed = s.edges[e];
-                const int la = s.label[ed.x], lb = s.label[ed.y];
-                KeyD kk;
-                kk.d2 = v;
-                kk.lo = min(la, lb);
-                kk.hi = max(la, lb);
-                kk.si = 2 * e + (la > lb ? 1 : 0);  // the edge slot rides in si, with which end is lo
-                kk.sj = 0;
-                if (key_less(kk, best)) best = kk;
-            }
+        v[k] = e < E ? s.ed2[e] : __builtin_huge_val();
+        m = fmin(m, v[k]);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m = fmin(m, __shfl_xor(m, o));
+    KeyD best = key_none();
+    if (m < __builtin_huge_val()) {  // wavefront-uniform
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            if (v[k] != m) continue;
+            const int e = c * ECH + k * 64 + lane;
+            const int2 ed = s.edges[e];
+            const int la = s.label[ed.x], lb = s.label[ed.y];
+            KeyD kk;
+            kk.d2 = m;
+            kk.lo = min(la, lb);
+            kk.hi = max(la, lb);
+            kk.si = 2 * e + (la > lb ? 1 : 0);  // the edge slot rides in si, with which end is lo
+            kk.sj = 0;
+            if (key_less(kk, best)) best = kk;
         }
     }
 #pragma unroll
