@@ -1765,7 +1765,7 @@ __device__ KeyD spectral_min_rows(Smem& sh, const SecDev& s, int R, int np, bool
 // screens: keep the FP32 mean row and its norm bound current (the screened
 // and plain forms read them; the incremental form does not).
 __device__ void merge_stats(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int kind, double d2, int g_ready,
-                            int prec, int rc, bool screens, bool mat) {
+                            int prec, int rc, bool screens, bool mat, int stamp) {
     const int tid = threadIdx.x;
     const int B = s.B, Bp = s.Bp;
     const int lo_l = s.label[lo_s], hi_l = s.label[hi_s];
@@ -1807,7 +1807,7 @@ __device__ void merge_stats(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R
         s.npix[lo_s] = n_new;
         if (screens) s.norm[lo_s] = (float)(sqrt(nrm) * (1.0 + 0x1p-20));
         s.parent[hi_l] = lo_l;
-        const int k = s.st[3];
+        const int k = stamp;  // the section's merge count (st[3])
         s.mtime[hi_l] = s.top ? k : -1;
         if (s.log) {
             hswo_merge_rec rec;
@@ -2010,7 +2010,7 @@ __device__ __noinline__ void merge_slots(Smem& sh, const SecDev& s, int lo_s, in
 // maintained, 2 rows maintained).
 __device__ __forceinline__ void merge_pair(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int& E, int stamp,
                            int kind, double d2, int g_ready, int prec, int rc) {
-    merge_stats(sh, s, lo_s, hi_s, R, kind, d2, g_ready, prec, rc, true, false);
+    merge_stats(sh, s, lo_s, hi_s, R, kind, d2, g_ready, prec, rc, true, false, stamp);
     const bool inc = s.ed2 != nullptr && s.st[5] != 0;
     merge_edges_full(sh, s, lo_s, hi_s, R, E, stamp, inc);
     merge_slots(sh, s, lo_s, hi_s, R, g_ready, rc, true, false, 0.0);
@@ -2158,13 +2158,22 @@ constexpr int LCAP = CAND_CAP / 3;  // edges listed per merge by the incremental
 // block, ends with a barrier.
 __device__ __noinline__ void merge_index_scan(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int E, int* L,
                                               int* XL, int* L2) {
-    if (s.st[12] == 0) edge_index_build(s, R, E);
     const int last = R - 1;
     const bool moved = last != lo_s && last != hi_s;
-    const int ua = min(s.rmin[lo_s], s.rmin[hi_s]);
-    const int ub = max(s.rmax[lo_s], s.rmax[hi_s]);
-    const int ma = moved ? s.rmin[last] : INT_MAX;
-    const int mb = moved ? s.rmax[last] : -1;
+    // the index's state and the three slots' ranges in one round of loads (the ranges are read
+    // again after a rebuild)
+    const int valid = s.st[12];
+    int ua = min(s.rmin[lo_s], s.rmin[hi_s]);
+    int ub = max(s.rmax[lo_s], s.rmax[hi_s]);
+    int ma = moved ? s.rmin[last] : INT_MAX;
+    int mb = moved ? s.rmax[last] : -1;
+    if (valid == 0) {  // block-uniform
+        edge_index_build(s, R, E);
+        ua = min(s.rmin[lo_s], s.rmin[hi_s]);
+        ub = max(s.rmax[lo_s], s.rmax[hi_s]);
+        ma = moved ? s.rmin[last] : INT_MAX;
+        mb = moved ? s.rmax[last] : -1;
+    }
     const int tid = threadIdx.x;
     int a0 = 0, a1 = 0, b0 = 0, b1 = 0;  // chunk-aligned [a0, a1) and [b0, b1)
     if (ua <= ub) {
@@ -2268,10 +2277,10 @@ template <int U>
 // persistent driver, whose merges follow one another in one launch, gains
 // from it at any length; a wide-mode decision launch only on long lists).
 __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int& E, int stamp, int kind,
-                               double d2, int rc, KeyD& anext, int& nchk, bool mat, int eidx_min) {
+                               double d2, int rc, KeyD& anext, int& nchk, bool mat, int eidx_min, int& empty_slots) {
     const int tid = threadIdx.x;
     const int l_surv = s.label[lo_s];  // the survivor's label, whichever slot it ends in
-    merge_stats(sh, s, lo_s, hi_s, R, kind, d2, 0, 0, rc, false, mat);
+    merge_stats(sh, s, lo_s, hi_s, R, kind, d2, 0, 0, rc, false, mat, stamp);
     const int last = R - 1;
     const int surv = (lo_s == last) ? hi_s : lo_s;
     int* L = sh.u.f.cand;
@@ -2408,6 +2417,7 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
             s.st[9] = 0;
             s.st[12] = 0;  // the edge list was compacted: ranges and chunk minima are rebuilt
         }
+        empty_slots = 0;
         return false;
     }
     // rename the moved slot in L2 (the edges of L carry their neighbour in XL)
@@ -2565,16 +2575,17 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
         anext = block_min_key(sh, best);  // the re-scored edges and the least of the others
         if (tid == 0) s.st[12] = 0;        // the index was not kept up to date
     }
-    const int empty = s.st[9] + emptied;
-    __syncthreads();  // every thread has read st[9]
+    const int empty = empty_slots + emptied;  // st[9], kept by the caller
     if (4 * empty > E || R - 1 <= s.stop) {
         compact_edges(sh, s, E);
         if (tid == 0) {
             s.st[9] = 0;
             s.st[12] = 0;  // slot numbers changed: ranges and chunk minima are rebuilt
         }
-    } else if (tid == 0) {
-        s.st[9] = empty;
+        empty_slots = 0;
+    } else {
+        if (tid == 0) s.st[9] = empty;
+        empty_slots = empty;
     }
     return true;
 }
@@ -3161,6 +3172,7 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
     int rcs = row_cache ? s.st[6] : 0;   // row cache state, block-uniform
     int npend = row_cache ? s.st[7] : 0; // pending rows (state 2)
     int merges = s.st[3];
+    int empty_slots = s.st[9];  // empty edge slots left by incremental merges (kept in st[9] too)
     bool avalid = false;  // incremental form: the least adjacent key after the last merge is known
     KeyD anext = key_none();
     // the row cache keeps the interval matrix (Equation 1, one-merge reading, rcap <= MAT_MAX)
@@ -3200,7 +3212,7 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
             CNT_ADD(C_SCREEN_ITERS, 1);
             CNT_ADD(C_SCREEN_FALLBACKS, nchk - c0 > lp.topk ? 1 : 0);
         }
-        CNT_ADD(C_ADJ_PAIRS, E - s.st[9]);
+        CNT_ADD(C_ADJ_PAIRS, E - empty_slots);
         unsigned long long tk1 = wall_clock64();
         CNT_ADD(C_T_ADJ, tk1 - tk0);
         tk0 = tk1;
@@ -3354,7 +3366,7 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
                 int nre = 0;
                 CNT_ADD(C_MERGES, 1);
                 avalid = merge_pair_inc<8>(sh, s, z.x, z.y, R, E, merges, z.z + (t ? 2 : 0), 0.0, rcs, anext, nre,
-                                           false, 0);
+                                           false, 0, empty_slots);
                 CNT_ADD(C_RECHECKS, nre);
                 CNT_ADD(C_D_BYTES, 16ull * (unsigned long long)sh.eread + 24ull * (unsigned long long)s.B);
                 ++merges;
@@ -3383,7 +3395,8 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
         CNT_ADD(C_MERGES, 1);
         if (lp.incremental) {
             int nre = 0;
-            avalid = merge_pair_inc<8>(sh, s, win.si, win.sj, R, E, merges, kind, win.d2, rcs, anext, nre, mat, 0);
+            avalid = merge_pair_inc<8>(sh, s, win.si, win.sj, R, E, merges, kind, win.d2, rcs, anext, nre, mat, 0,
+                                       empty_slots);
             CNT_ADD(C_RECHECKS, nre);
             CNT_ADD(C_D_BYTES, 16ull * (unsigned long long)sh.eread + 24ull * (unsigned long long)s.B);
         } else {
@@ -3640,7 +3653,8 @@ __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ s
             if (nchk > lp.topk) atomicAdd(&lp.counters[C_SCREEN_FALLBACKS], 1ull);
         }
     }
-    const int Elive = E - s.st[9];
+    int empty_slots = s.st[9];
+    const int Elive = E - empty_slots;
     const bool spectral = lp.spectral && R <= lp.kmax;
     const double T = key_exists(A) ? lp.w2 * A.d2 : __builtin_huge_val();
     const bool row_cache = lp.incremental && s.rcap > 0;
@@ -3700,7 +3714,7 @@ __global__ void __launch_bounds__(NT) k_wide_decide(const SecDev* __restrict__ s
             if (lp.incremental) {
                 KeyD an;
                 const bool av = merge_pair_inc<4>(sh, s, win.si, win.sj, R, E, stamp, kind, win.d2, rcs, an, nchk,
-                                                  row_matrix_on(s, lp), EIDX_MIN);
+                                                  row_matrix_on(s, lp), EIDX_MIN, empty_slots);
                 decide_bytes += 16ull * (unsigned long long)sh.eread + 24ull * (unsigned long long)s.B;
                 if (tid == 0) {
                     s.st[8] = av ? 1 : 0;
