@@ -2,10 +2,11 @@
 
 * rhseg1024_salt (1024 x 1024 x 220, 5% identical salt pixels, L = 5): the
   whole merge log and every label map against the oracle, for the
-  incremental form and the BF16 matrix-core screened form.
+  incremental form (default settings, and with the leaf level in the
+  persistent driver) and the BF16 matrix-core screened form.
 * rhseg2048_f16 (2048 x 2048 x 224 float16, L = 5): the whole merge log
   (4,194,288 merges) and all 8 label maps against one oracle run on the whole
-  image, for the incremental form and the BF16 matrix-core screened form.
+  image, for the same three forms.
 * batch256 (256 uneven independent sections): every section's merge log and
   label map against the oracle, for the incremental and FP16 screened forms.
 """
@@ -41,14 +42,16 @@ def _c3_reference():
     return _C3_REF["ref"]
 
 
-@pytest.mark.parametrize("form", ["incremental", "bf16"])
+@pytest.mark.parametrize("form", ["incremental", "incremental_leaves_persistent", "bf16"])
 def test_rhseg1024_salt_full_parity(form):
     sc, p, ref = _c3_reference()
     L = p["rnb_levels"]
     kw = {k: v for k, v in p.items() if k != "rnb_levels"}
     _say(f"[gpu] rhseg1024_salt full size, form {form}")
+    inc = form.startswith("incremental")
     res = hswo.rhseg_segment(torch.from_numpy(sc.cube).cuda(), rnb_levels=L, merge_log=True, stats=True,
-                             precision="fp16" if form == "incremental" else form, incremental=form == "incremental",
+                             precision="fp16" if inc else form, incremental=inc,
+                             tuning=dict(wide_max_sections=64) if form == "incremental_leaves_persistent" else None,
                              **kw)
     torch.cuda.synchronize()
     _say(f"[gpu] rhseg1024_salt stats {res.stats}")
@@ -80,19 +83,24 @@ def _c5_reference():
     return _C5["ref"]
 
 
-@pytest.mark.parametrize("form", ["incremental", "bf16"])
+@pytest.mark.parametrize("form", ["incremental", "incremental_leaves_persistent", "bf16"])
 def test_rhseg2048_f16_full_parity(form):
     """Every merge (all five recursion levels, all 256 + 64 + 16 + 4 + 1
     sections, in order, with the FP64 criterion value) and every one of the 8
-    label maps equal the oracle's: the incremental form, and the BF16
+    label maps equal the oracle's: the incremental form with its default
+    settings (every level of at most 256 sections wide), the incremental form
+    with the leaf level in the persistent driver (interval-matrix rescans on
+    one workgroup per section; the autotuner's usual choice), and the BF16
     matrix-core screened form."""
     sc, p, ref = _c5_reference()
     L = p["rnb_levels"]
     kw = {k: v for k, v in p.items() if k != "rnb_levels"}
     H, W, _ = sc.cube.shape
     _say(f"[gpu] rhseg2048_f16 full size, form {form}")
+    inc = form.startswith("incremental")
     res = hswo.rhseg_segment(torch.from_numpy(sc.cube).cuda(), rnb_levels=L, merge_log=True, stats=True,
-                             precision="fp16" if form == "incremental" else form, incremental=form == "incremental",
+                             precision="fp16" if inc else form, incremental=inc,
+                             tuning=dict(wide_max_sections=64) if form == "incremental_leaves_persistent" else None,
                              **kw)
     torch.cuda.synchronize()
     _say(f"[gpu] rhseg2048_f16 {form}: {res.stats['merges']} merges, {res.stats['ms_total']:.0f} ms")
