@@ -2938,6 +2938,84 @@ __device__ unsigned long long mat_fill_tile(float (*As)[P], float (*Cs)[P], cons
     return (unsigned long long)min(TILE, R - ib * TILE) * (unsigned long long)min(TILE, R - jb * TILE);
 }
 
+// LDS of row_matrix_wave: per wavefront, a candidate list and its values.
+constexpr int WAVE_CAND = 128;
+struct RowWaveLds {
+    int cand[NWAVE][WAVE_CAND];
+    double val[NWAVE][WAVE_CAND];
+};
+
+// row_matrix_task by one wavefront (the section's workgroup rescans several
+// pending rows at once, one per wavefront, with no block barrier): the same
+// threshold, candidates, exact evaluations, tightened bounds and least two,
+// so the same entry of rpart. Candidates go to the wavefront's LDS list in
+// rounds of at most WAVE_CAND (ballot-compacted); LDS operations of one
+// wavefront complete in order, so its lanes read what its lanes wrote.
+// Returns the number of exact evaluations (every lane).
+__device__ int row_matrix_wave(RowWaveLds& L, const SecDev& s, int R, int q, bool all) {
+    const int lane = lane_id(), w = wave_id();
+    const size_t rc = (size_t)s.mstride;
+    const int i = all ? q : s.rpend[q];
+    const int mi = s.msl[i];
+    const float2* Di = s.dmat + (size_t)mi * rc;
+    double m1 = __builtin_huge_val(), m2 = __builtin_huge_val();
+    for (int j = lane; j < R; j += 64)
+        if (j != i) least_two(m1, m2, (double)Di[s.msl[j]].y * (1.0 + MAT_REL), __builtin_huge_val());
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) least_two(m1, m2, __shfl_xor(m1, o), __shfl_xor(m2, o));
+    const double T = m2;
+    RowPart best = part_of(__builtin_huge_val(), INT_MAX, -1);
+    int nexact = 0, n = 0;
+    int* cl = L.cand[w];
+    double* vl = L.val[w];
+    for (int j0 = 0; j0 < R; j0 += 64) {  // wavefront-uniform
+        const int j = j0 + lane;
+        const float2 e = (j < R && j != i) ? Di[s.msl[j]] : make_float2(__builtin_huge_valf(), __builtin_huge_valf());
+        const bool cand = j < R && j != i && (double)e.x * (1.0 - MAT_REL) <= T;
+        if (cand && e.y == 0.0f) top2_merge(best, part_of(0.0, s.label[j], j));  // bounded by [0, 0]: exactly 0
+        const bool put = cand && e.y != 0.0f;
+        const unsigned long long mask = __ballot(put);
+        const int cnt = __popcll(mask);
+        if (n + cnt > WAVE_CAND) {  // wavefront-uniform: evaluate what the list holds first
+            for (int k = 0; k < n; ++k) {
+                const int jj = cl[k];
+                const double v = exact_wave_means(s, i, jj);
+                if (lane == 0) {
+                    vl[k] = v;
+                    const float2 me = mat_entry(v);
+                    const int mj = s.msl[jj];
+                    s.dmat[(size_t)mi * rc + mj] = me;
+                    s.dmat[(size_t)mj * rc + mi] = me;
+                }
+            }
+            for (int k = lane; k < n; k += 64) top2_merge(best, part_of(vl[k], s.label[cl[k]], cl[k]));
+            nexact += n;
+            n = 0;
+        }
+        if (put) cl[n + __popcll(mask & ((1ull << lane) - 1ull))] = j;
+        n += cnt;
+    }
+    for (int k = 0; k < n; ++k) {
+        const int jj = cl[k];
+        const double v = exact_wave_means(s, i, jj);
+        if (lane == 0) {
+            vl[k] = v;
+            const float2 me = mat_entry(v);
+            const int mj = s.msl[jj];
+            s.dmat[(size_t)mi * rc + mj] = me;
+            s.dmat[(size_t)mj * rc + mi] = me;
+        }
+    }
+    for (int k = lane; k < n; k += 64) top2_merge(best, part_of(vl[k], s.label[cl[k]], cl[k]));
+    nexact += n;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) top2_merge(best, shfl_xor_part(best, o));
+    const int nch = (R + 63) >> 6;
+    if (lane == 0) s.rpart[(size_t)q * nch] = best;
+    for (int c = 1 + lane; c < nch; c += 64) s.rpart[(size_t)q * nch + c] = part_of(__builtin_huge_val(), INT_MAX, -1);
+    return nexact;
+}
+
 // ---------------------------------------------------------------------------
 // Several merges per step (HSWO_FLAG_MULTI_MERGE): the future-work item of
 // Section 6.2, read for identical regions. A step whose winner has the value
@@ -3237,10 +3315,16 @@ __global__ void __launch_bounds__(NT) k_section_driver(const SecDev* __restrict_
                 CNT_ADD(C_W_FILL_FLOPS, 3ull * (unsigned long long)s.B * pairs);
                 __syncthreads();
             }
-            static_assert(sizeof(RowMatLds) <= sizeof(Smem::u), "the row rescans' LDS lives in the union");
-            RowMatLds& rl = *reinterpret_cast<RowMatLds*>(&sh.u);
+            // one pending row per wavefront at a time
+            static_assert(sizeof(RowWaveLds) <= sizeof(Smem::u), "the wavefronts' candidate lists live in the union");
+            RowWaveLds& wl = *reinterpret_cast<RowWaveLds*>(&sh.u);
             int ex = 0;
-            for (int q = 0; q < rows; ++q) ex += row_matrix_task(rl, s, R, q, all);  // block-uniform trip count
+            for (int q = wave_id(); q < rows; q += NWAVE) ex += row_matrix_wave(wl, s, R, q, all);
+            if (lane_id() == 0) sh.redi[wave_id()] = ex;
+            __syncthreads();  // every row's entry is written
+            if (tid == 0)
+                for (int k = 1; k < NWAVE; ++k) ex += sh.redi[k];
+            __syncthreads();  // the counts are read before the reductions below reuse redi
             M = spectral_min_rows(sh, s, R, rows, all);
             rcs = 2;
             npend = 0;
