@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhswo.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("hswo_api.cpp", "hswo_kernels.hip", "hswo_noalloc.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("hswo_api.cpp", "hswo_driver.hip", "hswo_wide.hip", "hswo_levels.hip", "hswo_noalloc.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -1,5 +1,6 @@
 // hswo_internal.h -- device-side descriptors shared by the host runtime
-// (hswo_api.cpp) and the kernels (hswo_kernels.hip). Not part of the ABI.
+// (hswo_api.cpp) and the kernels (hswo_driver.hip, hswo_wide.hip,
+// hswo_levels.hip and the dev_*.h device headers). Not part of the ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -227,7 +228,25 @@ struct KTimer {
     }
 };
 
-// kernel launchers (hswo_kernels.hip)
+// Launch, bracketed by a pair of events of the given kind (recorded on the
+// same stream right before and after it) when per-kernel timing is on.
+#define KLAUNCH(kind, kern, grid, block, ...)                                 \
+    do {                                                                   \
+        hipEvent_t a_ = nullptr, b_ = nullptr;                             \
+        if (kt) {                                                          \
+            const hipError_t r_ = kt->pair((kind), &a_, &b_);              \
+            if (r_ != hipSuccess) return r_;                               \
+            const hipError_t q_ = hipEventRecord(a_, s);                   \
+            if (q_ != hipSuccess) return q_;                               \
+        }                                                                  \
+        hipLaunchKernelGGL(kern, grid, block, 0, s, __VA_ARGS__);          \
+        if (kt) {                                                          \
+            const hipError_t q_ = hipEventRecord(b_, s);                   \
+            if (q_ != hipSuccess) return q_;                               \
+        }                                                                  \
+    } while (0)
+
+// kernel launchers (hswo_driver.hip, hswo_wide.hip, hswo_levels.hip)
 hipError_t launch_init_pixels(int32_t* parent, int32_t* mtime, int64_t n, hipStream_t s);
 hipError_t launch_init_pixels_secs(const SecDev* secs, int n, int max_pixels, hipStream_t s);
 hipError_t launch_init_leaves(const SecDev* secs, const InitDev* init, int n, int dtype, int max_pixels,

@@ -9,13 +9,20 @@ hang the GPU, so these checks keep that pattern out of the kernels.
 import os
 import re
 
-SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2106_12942_amd", "csrc",
-                   "hswo_kernels.hip")
+CSRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2106_12942_amd", "csrc")
+# the device headers in include order, then the kernel translation units
+DEVICE_FILES = ["dev_common.h", "dev_exact.h", "dev_screen.h", "dev_row_cache.h", "dev_interval_matrix.h",
+                "dev_merge.h", "dev_stages.h", "dev_multi_merge.h", "hswo_driver.hip", "hswo_wide.hip",
+                "hswo_levels.hip", "hswo_noalloc.hip"]
+
+
+def _source():
+    return "\n".join(open(os.path.join(CSRC, f)).read() for f in DEVICE_FILES)
 
 
 def _functions(src):
     out = {}
-    for m in re.finditer(r"\n(?:template <[^>]*>\n)?__device__[^\n]*?\b(\w+)\(", src):
+    for m in re.finditer(r"\n(?:template <[^>]*>\n)?(?:\[\[maybe_unused\]\] )?__device__[^\n]*?\b(\w+)\(", src):
         i = src.index("{", m.end())
         depth, j = 0, i
         while True:
@@ -48,13 +55,14 @@ def barrier_functions(src):
 
 
 def test_block_functions_are_found():
-    bar = barrier_functions(open(SRC).read())
-    for f in ("mfma_screen", "merge_pair", "adj_collect", "fp32_tiles", "spectral_collect"):
+    bar = barrier_functions(_source())
+    for f in ("mfma_screen", "merge_pair", "adj_collect", "fp32_tiles", "spectral_collect", "zero_step_list",
+              "block_min_key"):
         assert f in bar
 
 
 def test_no_barrier_function_behind_a_thread_dependent_branch():
-    src = open(SRC).read()
+    src = _source()
     bar = barrier_functions(src)
     cond = re.compile(r"if\s*\(([^{};]*\b(tid|threadIdx\.x|lane|lane_id\(\)|gl|wave_id\(\)|wi|wj)\b[^{};]*)\)\s*(\{?)")
     bad = []
@@ -80,9 +88,14 @@ def test_no_barrier_function_behind_a_thread_dependent_branch():
 
 
 def test_counter_macro_arguments_are_plain_values():
-    src = open(SRC).read()
+    src = _source()
     bar = barrier_functions(src)
     for m in re.finditer(r"CNT_ADD\(([^;]*)\);", src):
         arg = m.group(1)
         for x in bar:
             assert not _calls(arg, x), f"CNT_ADD evaluates {x}(...) in thread 0 only: {m.group(0)}"
+
+
+def test_every_device_file_is_checked():
+    have = {f for f in os.listdir(CSRC) if f.endswith(".hip") or f.startswith("dev_")}
+    assert have == set(DEVICE_FILES)
