@@ -205,6 +205,48 @@ __device__ double exact_wave_means(const SecDev& s, int si, int sj) {
     return ((dni * dnj) / (double)(n_i + n_j)) * counter_total<LV>(part, nchk);
 }
 
+// Exact values of a wavefront's row-rescan candidates (pairs (i, cand[k]),
+// k < n) into val[k], and the matrix entries of those pairs tightened to
+// them, over groups of P consecutive candidates starting at first and
+// advancing by stride (both multiples of P): P = 64 / L pairs at once in
+// L-lane segments (exact_seg_means, one memory round trip per group) for
+// B <= 1024, else P = 1 pair at a time over the whole wavefront
+// (exact_wave_means). Either way the canonical value.
+__device__ __forceinline__ int rescan_group(const SecDev& s) { return s.B <= 1024 ? 64 / mean_lanes(s.B) : 1; }
+
+__device__ void rescan_eval(const SecDev& s, int i, const int* cand, double* val, int n, int first, int stride) {
+    const int lane = lane_id();
+    const size_t rc = (size_t)s.mstride;
+    const int mi = s.msl[i];
+    if (s.B <= 1024) {
+        const int L = mean_lanes(s.B), seg = lane / L;
+        for (int k0 = first; k0 < n; k0 += stride) {  // wavefront-uniform
+            const int k = k0 + seg;
+            const int j = k < n ? cand[k] : -1;
+            const double v = exact_seg_means(s, j >= 0 ? i : -1, j, L);
+            if (j >= 0 && (lane & (L - 1)) == 0) {
+                val[k] = v;
+                const float2 me = mat_entry(v);
+                const int mj = s.msl[j];
+                s.dmat[(size_t)mi * rc + mj] = me;
+                s.dmat[(size_t)mj * rc + mi] = me;
+            }
+        }
+    } else {
+        for (int k = first; k < n; k += stride) {
+            const int j = cand[k];
+            const double v = exact_wave_means(s, i, j);
+            if (lane == 0) {
+                val[k] = v;
+                const float2 me = mat_entry(v);
+                const int mj = s.msl[j];
+                s.dmat[(size_t)mi * rc + mj] = me;
+                s.dmat[(size_t)mj * rc + mi] = me;
+            }
+        }
+    }
+}
+
 // The two least of (a1 <= a2) and (b1 <= b2), into (a1, a2).
 __device__ __forceinline__ void least_two(double& a1, double& a2, double b1, double b2) {
     const double big = fmax(a1, b1);
@@ -227,7 +269,9 @@ struct RowMatLds {
 // (widened to the canonical value); a pair whose lower bound (likewise
 // widened) exceeds T has two pairs strictly below it, so the row's least two
 // by (D2, label) are among the others. Those are evaluated exactly
-// (exact_wave_means, one wavefront per pair) -- except pairs bounded by
+// (exact_wave_means, one wavefront per pair; a call of exact_seg_means here
+// costs the kernel a call frame and twice the registers, and measured twice
+// as slow) -- except pairs bounded by
 // [0, 0], whose canonical value is 0 -- and their bounds tightened to the
 // exact value. The row's least two go to its first chunk entry of rpart and
 // +inf to the others, which is what the exact row tasks leave for the

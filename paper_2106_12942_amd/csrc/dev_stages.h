@@ -385,6 +385,7 @@ __device__ int row_matrix_wave(RowWaveLds& L, const SecDev& s, int R, int q, boo
     int nexact = 0, n = 0;
     int* cl = L.cand[w];
     double* vl = L.val[w];
+    const int P = rescan_group(s);
     for (int j0 = 0; j0 < R; j0 += 64) {  // wavefront-uniform
         const int j = j0 + lane;
         const float2 e = (j < R && j != i) ? Di[s.msl[j]] : make_float2(__builtin_huge_valf(), __builtin_huge_valf());
@@ -394,17 +395,7 @@ __device__ int row_matrix_wave(RowWaveLds& L, const SecDev& s, int R, int q, boo
         const unsigned long long mask = __ballot(put);
         const int cnt = __popcll(mask);
         if (n + cnt > WAVE_CAND) {  // wavefront-uniform: evaluate what the list holds first
-            for (int k = 0; k < n; ++k) {
-                const int jj = cl[k];
-                const double v = exact_wave_means(s, i, jj);
-                if (lane == 0) {
-                    vl[k] = v;
-                    const float2 me = mat_entry(v);
-                    const int mj = s.msl[jj];
-                    s.dmat[(size_t)mi * rc + mj] = me;
-                    s.dmat[(size_t)mj * rc + mi] = me;
-                }
-            }
+            rescan_eval(s, i, cl, vl, n, 0, P);
             for (int k = lane; k < n; k += 64) top2_merge(best, part_of(vl[k], s.label[cl[k]], cl[k]));
             nexact += n;
             n = 0;
@@ -412,17 +403,7 @@ __device__ int row_matrix_wave(RowWaveLds& L, const SecDev& s, int R, int q, boo
         if (put) cl[n + __popcll(mask & ((1ull << lane) - 1ull))] = j;
         n += cnt;
     }
-    for (int k = 0; k < n; ++k) {
-        const int jj = cl[k];
-        const double v = exact_wave_means(s, i, jj);
-        if (lane == 0) {
-            vl[k] = v;
-            const float2 me = mat_entry(v);
-            const int mj = s.msl[jj];
-            s.dmat[(size_t)mi * rc + mj] = me;
-            s.dmat[(size_t)mj * rc + mi] = me;
-        }
-    }
+    rescan_eval(s, i, cl, vl, n, 0, P);
     for (int k = lane; k < n; k += 64) top2_merge(best, part_of(vl[k], s.label[cl[k]], cl[k]));
     nexact += n;
 #pragma unroll
