@@ -305,10 +305,13 @@ __device__ void compact_edges(Smem& sh, const SecDev& s, int& E) {
 // [rmin, rmax] of edge slots that can touch it (conservative: a merge gives
 // the survivor the union of both ranges, a moving slot keeps its range), and
 // for every chunk of ECH edge slots the least key (D2, lo, hi) of its cached
-// values (cmd2, cme: value and edge slot, -1 for none). Rebuilt from scratch
-// when st[12] is 0 (pass start, compaction).
+// values (cmd2 the value, cml the labels, cme the pair's slots in label
+// order, x = -1 for none). A merge renames the slot that moves in the records
+// that name it, so the least record yields the next pair's slots without a
+// load of its edge. Rebuilt from scratch when st[12] is 0 (pass start,
+// compaction).
 
-// Least key of chunk c into cmd2[c] / cme[c]; one wavefront.
+// Least key of chunk c into cmd2[c] / cme[c] / cml[c]; one wavefront.
 __device__ void chunk_min_wave(const SecDev& s, int c, int E) {
     // the chunk's values at once, their least over the wavefront, then the labels of only the
     // slots that hold it (one round of loads each, whatever the chunk holds)
@@ -336,8 +339,8 @@ __device__ void chunk_min_wave(const SecDev& s, int c, int E) {
             kk.d2 = m;
             kk.lo = min(la, lb);
             kk.hi = max(la, lb);
-            kk.si = 2 * e + (la > lb ? 1 : 0);  // the edge slot rides in si, with which end is lo
-            kk.sj = 0;
+            kk.si = la < lb ? ed.x : ed.y;
+            kk.sj = la < lb ? ed.y : ed.x;
             if (key_less(kk, best)) best = kk;
         }
     }
@@ -348,7 +351,7 @@ __device__ void chunk_min_wave(const SecDev& s, int c, int E) {
     }
     if (lane == 0) {
         s.cmd2[c] = best.d2;
-        s.cme[c] = key_exists(best) ? best.si : -1;
+        s.cme[c] = key_exists(best) ? make_int2(best.si, best.sj) : make_int2(-1, -1);
         s.cml[c] = make_int2(best.lo, best.hi);
     }
 }
@@ -377,30 +380,22 @@ __device__ __noinline__ void edge_index_build(const SecDev& s, int R, int E) {
 
 // The least adjacent key over every chunk's minimum, with its slots; whole block.
 __device__ KeyD chunks_min_key(Smem& sh, const SecDev& s, int E) {
-    // each chunk's record holds its least key's labels: one round of loads, then the winner's
-    // slots from its edge
+    // each chunk's record holds its least key's labels and slots: one round of loads
     KeyD best = key_none();
     for (int c = threadIdx.x; c < (E + ECH - 1) / ECH; c += NT) {
-        const int e2 = s.cme[c];
+        const int2 sl = s.cme[c];
         const double d2 = s.cmd2[c];
         const int2 lab = s.cml[c];
-        if (e2 < 0) continue;
+        if (sl.x < 0) continue;
         KeyD k;
         k.d2 = d2;
         k.lo = lab.x;
         k.hi = lab.y;
-        k.si = e2;
-        k.sj = 0;
+        k.si = sl.x;
+        k.sj = sl.y;
         if (key_less(k, best)) best = k;
     }
-    best = block_min_key(sh, best);
-    if (key_exists(best)) {
-        const int2 ed = s.edges[best.si >> 1];
-        const bool flip = (best.si & 1) != 0;  // the edge's second end is lo
-        best.si = flip ? ed.y : ed.x;
-        best.sj = flip ? ed.x : ed.y;
-    }
-    return best;
+    return block_min_key(sh, best);
 }
 
 constexpr int LCAP = CAND_CAP / 3;  // edges listed per merge by the incremental form (L, L2, neighbours)
@@ -674,13 +669,20 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
         empty_slots = 0;
         return false;
     }
-    // rename the moved slot in L2 (the edges of L carry their neighbour in XL)
+    // rename the moved slot in L2 (the edges of L carry their neighbour in XL), and in the
+    // chunk records of those edges (every edge of the moved slot is in L or L2, and the chunks
+    // of L are taken anew; threads that share a chunk write the same record)
     for (int k = tid; k < n2; k += NT) {
         const int e = L2[k];
         int2 ed = s.edges[e];
         if (ed.x == last) ed.x = hi_s;
         if (ed.y == last) ed.y = hi_s;
         s.edges[e] = ed;
+        if (use_index) {
+            const int2 r = s.cme[e / ECH];
+            if (r.x == last || r.y == last)
+                s.cme[e / ECH] = make_int2(r.x == last ? hi_s : r.x, r.y == last ? hi_s : r.y);
+        }
     }
     __syncthreads();  // L2 is read through before its space is reused as K below
     // one edge per neighbour survives: the least edge slot (compared in LDS

@@ -389,7 +389,7 @@ Layout carve(const Plan& pl, int H, int W, const hswo_params* p, int bare, void*
                 s.rmin = bp.take<int32_t>(sp.cap);
                 s.rmax = bp.take<int32_t>(sp.cap);
                 s.cmd2 = bp.take<double>((sp.ecap + ECH - 1) / ECH);
-                s.cme = bp.take<int32_t>((sp.ecap + ECH - 1) / ECH);
+                s.cme = bp.take<int2>((sp.ecap + ECH - 1) / ECH);
                 s.cml = bp.take<int2>((sp.ecap + ECH - 1) / ECH);
                 if (p->flags & HSWO_FLAG_MULTI_MERGE) take_multi(bp, s, sp.cap, sp.ecap);
             }
@@ -1231,7 +1231,7 @@ BatchLayout carve_batch(int n, const hswo_section* sec, const hswo_params* p, in
             s.rmin = bp.take<int32_t>(cap);
             s.rmax = bp.take<int32_t>(cap);
             s.cmd2 = bp.take<double>((ecap + ECH - 1) / ECH);
-            s.cme = bp.take<int32_t>((ecap + ECH - 1) / ECH);
+            s.cme = bp.take<int2>((ecap + ECH - 1) / ECH);
             s.cml = bp.take<int2>((ecap + ECH - 1) / ECH);
             if (p->flags & HSWO_FLAG_MULTI_MERGE) take_multi(bp, s, cap, ecap);
         }

@@ -109,7 +109,7 @@ struct SecDev {
     int32_t* rmin;   // [R0]
     int32_t* rmax;   // [R0]
     double* cmd2;    // [ceil(Ecap / ECH)]
-    int32_t* cme;    // [ceil(Ecap / ECH)] 2 x edge slot + 1 if the edge's second end has the lower label; -1: none
+    int2* cme;       // [ceil(Ecap / ECH)] the slots of that key's pair, the lower label's first; x = -1: none
     int2* cml;       // [ceil(Ecap / ECH)] the labels (lo, hi) of that key
     // spectral row cache (incremental form), slots [0, rcap):
     double* m64;     // [B][rcap] FP64 mean spectra S/n (spectral angle: the sums S), band-major
