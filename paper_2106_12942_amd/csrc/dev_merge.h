@@ -142,6 +142,8 @@ __device__ void merge_edges_full(Smem& sh, const SecDev& s, int lo_s, int hi_s, 
 // pair's canonical value. The survivor's bounds row comes from Ward's update
 // of its and the merged region's matrix rows; matrix rows are indexed
 // through msl, so moving a slot moves no matrix entry.
+constexpr int MERGE_XB = 4;  // entries per thread and round in merge_slots' loops over the live slots
+
 __device__ __noinline__ void merge_slots(Smem& sh, const SecDev& s, int lo_s, int hi_s, int R, int g_ready, int rc,
                                          bool screens, bool mat, double d2) {
     const int tid = threadIdx.x;
@@ -159,12 +161,32 @@ __device__ __noinline__ void merge_slots(Smem& sh, const SecDev& s, int lo_s, in
         const int ml = s.msl[lo_s], mh = s.msl[hi_s];
         float2* Dl = s.dmat + (size_t)ml * rcp;
         const float2* Dh = s.dmat + (size_t)mh * rcp;
-        for (int k = tid; k < R; k += NT) {
-            if (k == lo_s || k == hi_s) continue;
-            const int mk = s.msl[k];
-            const float2 v = mat_update(Dl[mk], Dh[mk], (double)de.x, (double)de.y, n_lo, n_hi, (double)s.npix[k]);
-            Dl[mk] = v;
-            s.dmat[(size_t)mk * rcp + ml] = v;
+        // MERGE_XB entries per thread with their loads in flight together: the slot map and
+        // counts, then the two rows' bounds, then the stores (a loop over single entries waits
+        // for each entry's two dependent loads in turn, its stores ordering the next loads)
+        for (int k0 = 0; k0 < R; k0 += MERGE_XB * NT) {  // block-uniform
+            int mk[MERGE_XB];
+            double nk[MERGE_XB];
+#pragma unroll
+            for (int x = 0; x < MERGE_XB; ++x) {
+                const int k = k0 + x * NT + tid;
+                const bool on = k < R && k != lo_s && k != hi_s;
+                mk[x] = on ? s.msl[k] : -1;
+                nk[x] = on ? (double)s.npix[k] : 0.0;
+            }
+            float2 el[MERGE_XB], eh[MERGE_XB];
+#pragma unroll
+            for (int x = 0; x < MERGE_XB; ++x) {
+                el[x] = mk[x] >= 0 ? Dl[mk[x]] : make_float2(0.0f, 0.0f);
+                eh[x] = mk[x] >= 0 ? Dh[mk[x]] : make_float2(0.0f, 0.0f);
+            }
+#pragma unroll
+            for (int x = 0; x < MERGE_XB; ++x)
+                if (mk[x] >= 0) {
+                    const float2 v = mat_update(el[x], eh[x], (double)de.x, (double)de.y, n_lo, n_hi, nk[x]);
+                    Dl[mk[x]] = v;
+                    s.dmat[(size_t)mk[x] * rcp + ml] = v;
+                }
         }
         __syncthreads();  // every read of npix and msl above is done before the slot moves below
         if (tid == 0) {
@@ -208,43 +230,56 @@ __device__ __noinline__ void merge_slots(Smem& sh, const SecDev& s, int lo_s, in
     if (rc == 2) {
         if (tid == 0) sh.npend = 1;
         __syncthreads();
-        for (int i = tid; i < R; i += NT) {
-            if (i == lo_s || i == hi_s) continue;
-            const int ni = (i == last) ? hi_s : i;
-            const int p = s.rbp[i];
-            // the second bound follows a moved partner; when its partner is merged it stays as a
-            // bare bound (-3) by default only if its value is 0 (identical spectra, where the
-            // merged region usually ties again), else it is dropped (the interval matrix keeps
-            // no second bounds)
-            int np2 = -1;
-            if (!mat) {
-                const int p2 = s.rbp2[i];
-                np2 = p2 == last ? hi_s : p2;
-                if (p2 == lo_s || p2 == hi_s)  // the value is read only here
-                    np2 = (s.bare == 2 || (s.bare == 1 && s.rbd2[i] == 0.0)) ? -3 : -1;
-                if (ni != i) {
-                    s.rbd2[ni] = s.rbd2[i];
-                    s.rbl2[ni] = s.rbl2[i];
-                }
-                if (ni != i || np2 != p2) s.rbp2[ni] = np2;
+        for (int i0 = 0; i0 < R; i0 += MERGE_XB * NT) {  // block-uniform
+            // the rows' cached partners loaded together first (the loop body stores row state)
+            int pv[MERGE_XB], p2v[MERGE_XB];
+#pragma unroll
+            for (int x = 0; x < MERGE_XB; ++x) {
+                const int i = i0 + x * NT + tid;
+                const bool on = i < R && i != lo_s && i != hi_s;
+                pv[x] = on ? s.rbp[i] : -1;
+                p2v[x] = (on && !mat) ? s.rbp2[i] : -1;
             }
-            if (p == lo_s || p == hi_s) {
-                // stale: a light step (marked -2) when it has a second bound, else a full evaluation
-                // (with the interval matrix always the rescan of its bounds row)
-                if (np2 != -1 && !mat) {
-                    s.rbp[ni] = -2;
+#pragma unroll
+            for (int x = 0; x < MERGE_XB; ++x) {
+                const int i = i0 + x * NT + tid;
+                if (i >= R || i == lo_s || i == hi_s) continue;
+                const int ni = (i == last) ? hi_s : i;
+                const int p = pv[x];
+                // the second bound follows a moved partner; when its partner is merged it stays as a
+                // bare bound (-3) by default only if its value is 0 (identical spectra, where the
+                // merged region usually ties again), else it is dropped (the interval matrix keeps
+                // no second bounds)
+                int np2 = -1;
+                if (!mat) {
+                    const int p2 = p2v[x];
+                    np2 = p2 == last ? hi_s : p2;
+                    if (p2 == lo_s || p2 == hi_s)  // the value is read only here
+                        np2 = (s.bare == 2 || (s.bare == 1 && s.rbd2[i] == 0.0)) ? -3 : -1;
+                    if (ni != i) {
+                        s.rbd2[ni] = s.rbd2[i];
+                        s.rbl2[ni] = s.rbl2[i];
+                    }
+                    if (ni != i || np2 != p2) s.rbp2[ni] = np2;
+                }
+                if (p == lo_s || p == hi_s) {
+                    // stale: a light step (marked -2) when it has a second bound, else a full evaluation
+                    // (with the interval matrix always the rescan of its bounds row)
+                    if (np2 != -1 && !mat) {
+                        s.rbp[ni] = -2;
+                    } else {
+                        s.rbp[ni] = -1;
+                        s.rpend[atomicAdd(&sh.npend, 1)] = ni;
+                    }
                 } else {
-                    s.rbp[ni] = -1;
-                    s.rpend[atomicAdd(&sh.npend, 1)] = ni;
+                    // only a moved row or a moved partner changes the entry
+                    const int np = (p == last) ? hi_s : p;
+                    if (ni != i) {
+                        s.rbd[ni] = s.rbd[i];
+                        s.rbl[ni] = s.rbl[i];
+                    }
+                    if (ni != i || np != p) s.rbp[ni] = np;
                 }
-            } else {
-                // only a moved row or a moved partner changes the entry
-                const int np = (p == last) ? hi_s : p;
-                if (ni != i) {
-                    s.rbd[ni] = s.rbd[i];
-                    s.rbl[ni] = s.rbl[i];
-                }
-                if (ni != i || np != p) s.rbp[ni] = np;
             }
         }
         if (tid == 0) {
