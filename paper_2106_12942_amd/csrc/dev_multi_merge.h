@@ -8,6 +8,8 @@
 
 namespace hswo {
 
+namespace {
+
 // ---------------------------------------------------------------------------
 // Several merges per step (HSWO_FLAG_MULTI_MERGE): the future-work item of
 // Section 6.2, read for identical regions. A step whose winner has the value
@@ -221,5 +223,7 @@ __device__ void zsort(const SecDev& s, int n) {
     __syncthreads();
     return k;
 }
+
+}  // namespace
 
 }  // namespace hswo

@@ -9,6 +9,8 @@
 
 namespace hswo {
 
+namespace {
+
 // ---------------------------------------------------------------------------
 // Stages of one merge-loop iteration, as block-level functions over a range
 // of the work, shared by the persistent driver (one workgroup does all of a
@@ -369,7 +371,7 @@ struct RowWaveLds {
 // rounds of at most WAVE_CAND (ballot-compacted); LDS operations of one
 // wavefront complete in order, so its lanes read what its lanes wrote.
 // Returns the number of exact evaluations (every lane).
-__device__ int row_matrix_wave(RowWaveLds& L, const SecDev& s, int R, int q, bool all) {
+[[maybe_unused]] __device__ int row_matrix_wave(RowWaveLds& L, const SecDev& s, int R, int q, bool all) {
     const int lane = lane_id(), w = wave_id();
     const size_t rc = (size_t)s.mstride;
     const int i = all ? q : s.rpend[q];
@@ -413,5 +415,7 @@ __device__ int row_matrix_wave(RowWaveLds& L, const SecDev& s, int R, int q, boo
     for (int c = 1 + lane; c < nch; c += 64) s.rpart[(size_t)q * nch + c] = part_of(__builtin_huge_val(), INT_MAX, -1);
     return nexact;
 }
+
+}  // namespace
 
 }  // namespace hswo
