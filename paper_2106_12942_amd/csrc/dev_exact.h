@@ -234,6 +234,59 @@ __device__ __noinline__ double exact_seg_means(const SecDev& s, int si, int sj, 
     return fac * t0;
 }
 
+// exact_seg_means for the two pairs (si, sj) and (si, sk) at once: the
+// segment loads si's run once and both partners' runs together (one memory
+// round trip for two pairs). The value of (si, sk) goes to v2. The canonical
+// value does not depend on the pair's order (a difference and its negation
+// square alike, the count factor is symmetric), so si may be either end.
+// si < 0: no pair; sk < 0: no second pair (those results are meaningless).
+__device__ __noinline__ double exact_seg_means2(const SecDev& s, int si, int sj, int sk, int L, double& v2) {
+    const int B = s.B, B8 = (B + 7) & ~7;
+    const int b0 = (lane_id() & (L - 1)) << 4;
+    double t0 = 0.0, t1 = 0.0, fac0 = 0.0, fac1 = 0.0;
+    if (si >= 0) {
+        const int sk2 = sk >= 0 ? sk : sj;
+        const double* Mi = s.m64r + (size_t)si * B8;
+        const double* Mj = s.m64r + (size_t)sj * B8;
+        const double* Mk = s.m64r + (size_t)sk2 * B8;
+        double x[16], y[16], z[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const bool in = b0 + k < B;
+            x[k] = in ? Mi[b0 + k] : 0.0;
+            y[k] = in ? Mj[b0 + k] : 0.0;
+            z[k] = in ? Mk[b0 + k] : 0.0;
+        }
+        double q[16], r[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const double d = x[k] - y[k];
+            const double e = x[k] - z[k];
+            q[k] = d * d;
+            r[k] = e * e;
+        }
+#pragma unroll
+        for (int w = 1; w < 16; w <<= 1)
+#pragma unroll
+            for (int k = 0; k < 16; k += 2 * w) {
+                q[k] = q[k] + q[k + w];
+                r[k] = r[k] + r[k + w];
+            }
+        t0 = q[0];
+        t1 = r[0];
+        const int n_i = s.npix[si], n_j = s.npix[sj], n_k = s.npix[sk2];
+        const double dni = (double)n_i, dnj = (double)n_j, dnk = (double)n_k;
+        fac0 = (dni * dnj) / (double)(n_i + n_j);
+        fac1 = (dni * dnk) / (double)(n_i + n_k);
+    }
+    for (int o = 1; o < L; o <<= 1) {
+        t0 = t0 + __shfl_xor(t0, o);
+        t1 = t1 + __shfl_xor(t1, o);
+    }
+    v2 = fac1 * t1;
+    return fac0 * t0;
+}
+
 // One pair per lane, for many pairs at once (defined with the row tasks' counter).
 __device__ __noinline__ double exact_lane(const SecDev& s, int si, int sj);
 

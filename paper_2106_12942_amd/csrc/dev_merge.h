@@ -824,6 +824,43 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
             if (lane_id() == 0) s.ed2[e] = kk.d2;
             if (key_less(kk, best)) best = kk;
         }
+    } else if (means) {
+        // 2 x 64 / Ls re-scored edges per wavefront at once: two per segment, which shares the
+        // survivor's run between them (exact_seg_means2)
+        const int ppw = 64 / Ls, sub = lane_id() / Ls;
+        for (int q0 = wave_id() * 2 * ppw; q0 < nk; q0 += NWAVE * 2 * ppw) {  // wavefront-uniform trip count
+            const int qa = q0 + sub, qb = q0 + ppw + sub;  // qb < nk implies qa < nk
+            int xa = -1, xb = -1, ea = -1, eb = -1, la = 0, lb = 0;
+            if (qa < nk) {
+                const int k = K[qa];
+                ea = L[k];
+                xa = XL[k] == last ? hi_s : XL[k];
+                la = KL[qa];
+            }
+            if (qb < nk) {
+                const int k = K[qb];
+                eb = L[k];
+                xb = XL[k] == last ? hi_s : XL[k];
+                lb = KL[qb];
+            }
+            double vb;
+            const double va = exact_seg_means2(s, qa < nk ? surv : -1, xa, xb, Ls, vb);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int q = h ? qb : qa;
+                if (q < nk) {
+                    const int x = h ? xb : xa, lx = h ? lb : la;
+                    KeyD kk;
+                    kk.d2 = h ? vb : va;
+                    kk.lo = min(l_surv, lx);
+                    kk.hi = max(l_surv, lx);
+                    kk.si = l_surv < lx ? surv : x;
+                    kk.sj = l_surv < lx ? x : surv;
+                    if ((lane_id() & (Ls - 1)) == 0) s.ed2[h ? eb : ea] = kk.d2;
+                    if (key_less(kk, best)) best = kk;
+                }
+            }
+        }
     } else {
         // 64 / Ls re-scored edges per wavefront at once
         const int ppw = 64 / Ls, sub = lane_id() / Ls;
@@ -846,7 +883,7 @@ __device__ __forceinline__ bool merge_pair_inc(Smem& sh, const SecDev& s, int lo
                     lb = l_surv;
                 }
             }
-            const double v = means ? exact_seg_means(s, a, b, Ls) : exact_seg(s, a, b, Ls);
+            const double v = exact_seg(s, a, b, Ls);
             if (q < nk) {
                 KeyD kk;
                 kk.d2 = v;
