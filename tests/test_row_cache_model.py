@@ -11,8 +11,10 @@ real merge sequence (taken from the oracle), the invariant and that the
 cached minimum equals a brute-force minimum over all pairs.
 
 The second part checks that the per-thread band sum used by the row cache
-(fixed subtrees of GB bands combined through a binary counter) adds in the
-same perfect binary tree as the wavefront evaluator (4 bands per lane, lane
+(fixed subtrees of GB bands combined through a binary counter), and the
+segmented evaluators of the merge path (4 bands per lane in a segment of L
+lanes; runs of 16 bands per lane from the stored means), add in the same
+perfect binary tree as the wavefront evaluator (4 bands per lane, lane
 butterflies, then a 16-leaf tree over 256-band chunks), bit for bit.
 """
 import numpy as np
@@ -186,3 +188,58 @@ def test_counter_order_equals_wave_order(B, GB):
     a = _wave_order_sum(q)
     b = _counter_order_sum(q, GB)
     assert a.tobytes() == np.float64(b).tobytes()
+
+
+def _seg_order_sum(q):
+    """Sum of q in the segment order of exact_seg: L lanes (the least power of two
+    with 4L >= B), lane m adds bands 4m..4m+3 in pairs, butterflies join the lanes."""
+    B = len(q)
+    L = 1
+    while 4 * L < B:
+        L *= 2
+    lanes = []
+    for m in range(L):
+        v = [q[b] if b < B else 0.0 for b in range(4 * m, 4 * m + 4)]
+        lanes.append((v[0] + v[1]) + (v[2] + v[3]))
+    o = 1
+    while o < L:
+        lanes = [lanes[m] + lanes[m ^ o] for m in range(L)]
+        o *= 2
+    return lanes[0]
+
+
+def _run16_order_sum(q):
+    """Sum of q in the order of exact_seg_means and exact_seg_means2: the bands padded
+    to a power of two P >= 16, lane m adds its run 16m..16m+15 as a perfect tree,
+    butterflies join the P / 16 runs."""
+    B = len(q)
+    P = 16
+    while P < B:
+        P *= 2
+    lanes = []
+    for m in range(P // 16):
+        t = [q[b] if b < B else 0.0 for b in range(16 * m, 16 * m + 16)]
+        w = 1
+        while w < 16:
+            t = [t[k] + t[k + w] if k % (2 * w) == 0 else t[k] for k in range(16)]
+            w *= 2
+        lanes.append(t[0])
+    o = 1
+    while o < len(lanes):
+        lanes = [lanes[m] + lanes[m ^ o] for m in range(len(lanes))]
+        o *= 2
+    return lanes[0]
+
+
+@pytest.mark.parametrize("B", [1, 2, 3, 5, 16, 17, 31, 64, 100, 128, 200, 220, 224, 255, 256, 257, 300, 513, 700, 1000,
+                               1024])
+def test_segment_orders_equal_wave_order(B):
+    # the merge path's segmented evaluators must add the bands in the wavefront evaluator's tree;
+    # 16 vectors of nearby magnitudes per size, so that another association shows in the last bits
+    rng = np.random.default_rng(2000 + B)
+    for _ in range(16):
+        q = rng.random(B) * np.exp2(rng.integers(-4, 4, B))
+        a = np.float64(_wave_order_sum(q)).tobytes()
+        if B <= 256:
+            assert np.float64(_seg_order_sum(q)).tobytes() == a
+        assert np.float64(_run16_order_sum(q)).tobytes() == a
