@@ -183,11 +183,12 @@ def _counter_order_sum(q, GB):
 @pytest.mark.parametrize("GB", [4, 8, 16])
 def test_counter_order_equals_wave_order(B, GB):
     rng = np.random.default_rng(1000 + B)
-    # magnitudes spread over many binades so a different association shows
-    q = rng.random(B) * np.exp2(rng.integers(-30, 30, B))
-    a = _wave_order_sum(q)
-    b = _counter_order_sum(q, GB)
-    assert a.tobytes() == np.float64(b).tobytes()
+    # 16 vectors of nearby magnitudes per size, so that another association shows in the last bits
+    for _ in range(16):
+        q = rng.random(B) * np.exp2(rng.integers(-4, 4, B))
+        a = _wave_order_sum(q)
+        b = _counter_order_sum(q, GB)
+        assert np.float64(a).tobytes() == np.float64(b).tobytes()
 
 
 def _seg_order_sum(q):
