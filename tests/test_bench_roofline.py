@@ -1,6 +1,9 @@
 """The benchmark's roofline object (CPU): which kernel kind it prices and
 how. The kind is the longest-running one whose work the form defines; the
-event-pair overhead is taken off every launch first."""
+event-pair overhead is taken off every launch first. Also: a request for more
+than one GPU ends with a JSON line that says why."""
+import os
+
 import pytest
 
 import bench
@@ -56,3 +59,15 @@ def test_variant_tags_name_the_criterion_and_reading():
     A.criterion, A.two_merges = "sam", True
     assert bench.variant_tag(A) == "_sam_two"
     assert bench.variant_kwargs(A) == {"criterion": "sam", "two_merges": True}
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    import json
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300, cwd=root)
+    assert r.returncode != 0
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU only" in line["error"]
