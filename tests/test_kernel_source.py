@@ -99,3 +99,9 @@ def test_counter_macro_arguments_are_plain_values():
 def test_every_device_file_is_checked():
     have = {f for f in os.listdir(CSRC) if f.endswith(".hip") or f.startswith("dev_")}
     assert have == set(DEVICE_FILES)
+
+
+def test_every_translation_unit_is_built():
+    from paper_2106_12942_amd import build
+    have = {f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp"))}
+    assert have == {os.path.basename(f) for f in build.SOURCES}
