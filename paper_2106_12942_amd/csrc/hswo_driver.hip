@@ -21,6 +21,16 @@
 //                    survivor; swap-remove of the dead slot; one block pass
 //                    relabels, de-duplicates and compacts the edge list.
 //
+// That is the screened and plain forms. The incremental form (the fastest)
+// keeps instead the exact FP64 value of every edge slot and an index of
+// per-chunk least keys over the edge list, so a merge touches only the edges
+// of the merged pair and of the slot that moves; and, once the spectral
+// stage is on, per-row least pairs backed by an interval matrix of certified
+// FP32 bounds that Ward's recurrence keeps valid across merges, so only the
+// rows whose cached partner was merged are rescanned, and only the pairs
+// whose lower bound can beat a row's second least upper bound are evaluated
+// exactly.
+//
 // The spectral stage scores all pairs without masking adjacent ones: if the
 // overall minimum M is below w^2 * D2(A) (A the best adjacent pair) it cannot
 // be adjacent, because every adjacent pair has D2 >= D2(A) >= w^2 D2(A); and
