@@ -7,7 +7,10 @@ adversarial pairs and check, against the canonical FP64 value of Equation 1
 from the oracle:
   * the FP32 screen's [lower, upper] always contains the exact value;
   * the 16-bit matrix-core tile test never discards a pair whose exact value
-    is below the threshold T, whatever order the matrix core accumulates in.
+    is below the threshold T, whatever order the matrix core accumulates in;
+  * the interval matrix's bounds, kept by Ward's update over merge chains,
+    contain the canonical values, and a row rescan thresholded at the row's
+    second least upper bound finds the row's least two pairs.
 """
 import numpy as np
 import pytest
@@ -244,3 +247,66 @@ def test_exact_zero_entries_stay_exact():
     assert float(z[0]) == 0.0 and float(z[1]) == 0.0
     u = mat_update(z, z, z, 3.0, 5.0, 7.0)
     assert float(u[0]) == 0.0 and float(u[1]) == 0.0
+
+
+def _rescan(E, S, n, live, i, lab):
+    """Model of a row rescan: T is the row's second least upper bound (widened to
+    the canonical value); only the pairs whose widened lower bound reaches T are
+    evaluated (a pair bounded by [0, 0] is exactly 0); the row's least two by
+    (D2, label) among them."""
+    key = lambda a, b: (min(a, b), max(a, b))
+    ups = sorted(float(E[key(i, j)][1]) * (1 + MAT_REL) for j in live if j != i)
+    T = ups[1] if len(ups) > 1 else np.inf
+    cands = []
+    for j in live:
+        if j == i:
+            continue
+        lo, hi = E[key(i, j)]
+        if float(lo) * (1 - MAT_REL) <= T:
+            if float(hi) == 0.0:
+                v = 0.0
+            else:
+                a, b = key(i, j)
+                v = oracle.criterion_d2(S[a], S[b], int(n[a]), int(n[b]))
+            cands.append((v, lab[j]))
+    return sorted(cands)[:2], len(cands)
+
+
+@pytest.mark.parametrize("kind", ["voronoi", "salt"])
+def test_rescan_keeps_each_rows_least_two(kind):
+    """Over a merge chain whose matrix is kept by Ward's update on bounds only,
+    every row's rescan (threshold at its second least upper bound) finds the
+    row's least two pairs by (D2, label), ties and exact zeros included, and
+    evaluates fewer pairs than the row holds."""
+    rng = np.random.default_rng({"voronoi": 11, "salt": 12}[kind])
+    B, R = 24, 36
+    base = rng.uniform(0, 2000, size=(5, B))
+    cls = rng.integers(0, 5, size=R)
+    mu = base[cls] + rng.normal(0, 30.0, size=(R, B))
+    if kind == "salt":
+        mu[rng.random(R) < 0.3] = 2000.0
+    n = rng.integers(1, 20, size=R).astype(np.int64)
+    S = np.round(mu * n[:, None] * 64) / 64
+    lab = rng.permutation(R)  # labels need not follow the slots
+    live = list(range(R))
+    key = lambda a, b: (min(a, b), max(a, b))
+    E = {(i, j): mat_entry(oracle.criterion_d2(S[i], S[j], int(n[i]), int(n[j]))) for i in live for j in live
+         if i < j}
+    evaluated = held = 0
+    while len(live) > 3:
+        a, b = (int(v) for v in sorted(rng.choice(live, size=2, replace=False)))
+        d = E[(a, b)]
+        for k in live:
+            if k not in (a, b):
+                E[key(k, a)] = mat_update(E[key(k, a)], E[key(k, b)], d, float(n[a]), float(n[b]), float(n[k]))
+        S[a] = S[a] + S[b]
+        n[a] += n[b]
+        live.remove(b)
+        for i in live:
+            got, nc = _rescan(E, S, n, live, i, lab)
+            brute = sorted((oracle.criterion_d2(S[min(i, j)], S[max(i, j)], int(n[min(i, j)]), int(n[max(i, j)])),
+                            lab[j]) for j in live if j != i)[:2]
+            assert got == brute, (kind, len(live), i)
+            evaluated += nc
+            held += len(live) - 1
+    assert evaluated < held
